@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Benchmark of the block tensordot hot path on one MI355X.
+
+Workload (timed): the large pairwise contraction -- A and B rank-28 complex
+tensors, every dim 2 (2 GiB each in complex64), 14 contracted indices chosen
+as a seeded random subset of each operand's axes paired in random order,
+unblocked.  One step = plan + permute A + permute B + complex GEMM whose K
+loop walks the coupled pairs (fused reduction) + FP64 norm of C, in FP32-4M
+(complex64 operands, FP32 MFMA, FP32 accumulation).  The reported value is
+useful flops (8*M*N*K) per second of the whole step, inputs already in HBM.
+
+Beside it the same workload runs in FP64 and in split-BF16x3, each with its
+error against the oracle on sampled outputs; the sliced 20-qubit amplitude
+(4x5 grid, 12 cycles, 4 sliced bonds = 16 slices) gives amplitude latency
+percentiles; the oracle is timed on the host on the sampled outputs.
+
+Prints one JSON line on stdout.  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK = 157.3   # TFLOP/s, dense FP32 MFMA, MI355X
+FP64_PEAK = 78.6
+BF16_PEAK = 2500.0
+HBM_PEAK = 8000.0   # GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def kernel_sha():
+    with open(os.path.join(ROOT, "paper_2201_06620_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, per_launch_units):
+    """HBM bytes per launch from the committed PMC summary, if still current."""
+    path = os.path.join(ROOT, "profiles", "cgemm_f32_rank28_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernels_sha256_16") != kernel_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--side-steps", type=int, default=3,
+                    help="timed steps for the FP64 and BF16x3 side measurements")
+    ap.add_argument("--rank", type=int, default=28)
+    ap.add_argument("--k", type=int, default=14)
+    ap.add_argument("--amp-requests", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the contraction is not "
+                                   "sharded across GPUs (run with --gpus 1)"}))
+        return 2
+
+    import torch
+    import oracle
+    import paper_2201_06620_amd as rn
+    from workloads import configs
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 1
+    ctx = rn.Context(0)
+    dev = "cuda:0"
+
+    # ------------------------------------------------------------ inputs
+    t0 = time.time()
+    p = configs.config3(rank=args.rank, k=args.k)
+    log(f"inputs generated in {time.time() - t0:.1f}s: rank {args.rank}, k {args.k}, "
+        f"axes_a={p.axes_a} axes_b={p.axes_b}")
+    dims = [2] * args.rank
+    M = N = 2 ** (args.rank - args.k)
+    K = 2 ** args.k
+    flops = 8.0 * M * N * K
+
+    # Sampled outputs: four 64 x 64 blocks of C viewed as M x N (row-major C).
+    rs = np.random.default_rng(2201)
+    sample = []
+    for _ in range(4):
+        r0 = int(rs.integers(0, M // 64)) * 64
+        c0 = int(rs.integers(0, N // 64)) * 64
+        rr, cc = np.meshgrid(np.arange(r0, r0 + 64), np.arange(c0, c0 + 64), indexing="ij")
+        sample.append((rr * N + cc).reshape(-1))
+    sample = np.concatenate(sample).astype(np.int64)
+
+    def run_mode(mode, steps, warmup, profile):
+        dt = torch.complex128 if mode == "fp64" else torch.complex64
+        a = torch.from_numpy(p.a.data).to(dt).to(dev)
+        b = torch.from_numpy(p.b.data).to(dt).to(dev)
+        cd, cg, ws, fl = rn.plan_block_tensordot(dims, None, dims, None, p.axes_a, p.axes_b, mode)
+        c = torch.empty(M * N, dtype=dt, device=dev)
+        wsb = torch.empty(max(ws, 1), dtype=torch.uint8, device=dev)
+
+        def step():
+            ctx.block_tensordot(a, dims, None, b, dims, None, p.axes_a, p.axes_b, mode, out=c,
+                                workspace=wsb)
+            return ctx.norm2(c, [2] * (2 * (args.rank - args.k)))
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        if profile:
+            ctx.profile(True)
+            ctx.profile_read()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            nrm = step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        kern = ctx.profile_read() if profile else None
+        ctx.profile(False)
+        got = c[torch.from_numpy(sample).to(dev)].cpu().numpy().astype(np.complex128)
+        out = {"ms_per_step": 1e3 * el / steps, "tflops": flops * steps / el / 1e12,
+               "norm2_c": float(nrm.item()), "kernels": kern}
+        del a, b, c, wsb
+        torch.cuda.empty_cache()
+        return out, got
+
+    log("FP32-4M timed run")
+    main_res, got32 = run_mode("fp32_4m", args.steps, args.warmup, True)
+    log(f"  {main_res['ms_per_step']:.2f} ms/step, {main_res['tflops']:.2f} TFLOP/s; "
+        f"kernels {main_res['kernels']}")
+    side = {}
+    gots = {"fp32_4m": got32}
+    if not args.no_side:
+        for mode in ("bf16x3", "fp64"):
+            log(f"{mode} side run")
+            r, g = run_mode(mode, args.side_steps, 1, True)
+            side[mode] = r
+            gots[mode] = g
+            log(f"  {r['ms_per_step']:.2f} ms/step, {r['tflops']:.2f} TFLOP/s")
+
+    # ------------------------------------------------ oracle on the sample
+    cpu = None
+    ref = None
+    if not args.no_cpu_baseline:
+        A = p.a.data.reshape(dims)
+        B = p.b.data.reshape(dims)
+        log(f"oracle on {sample.size} sampled outputs (single thread)")
+        t = time.perf_counter()
+        ref = oracle.tensordot_entries(A, B, p.axes_a, p.axes_b, sample)
+        el = time.perf_counter() - t
+        cpu = {"value": 8.0 * K * sample.size / el / 1e12, "unit": "TFLOP/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{sample.size} output entries (four 64x64 blocks of C) of the same "
+                         f"rank-{args.rank} contraction, each a {K}-term complex128 sum; "
+                         f"{el:.1f} s"}
+        log(f"  {el:.1f}s -> {cpu['value'] * 1e3:.4f} GFLOP/s")
+
+    errors = {}
+    if ref is not None:
+        for mode, g in gots.items():
+            errors[mode] = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+        log(f"sampled e_F vs oracle: {errors}")
+
+    # ------------------------------------------- amplitude latency (16 slices)
+    amp = None
+    if args.amp_requests > 0:
+        w = configs.config2()
+        lat = {}
+        for mode in ("fp64", "fp32_4m"):
+            dt = torch.complex128 if mode == "fp64" else torch.complex64
+            ts = [torch.from_numpy(np.ascontiguousarray(t.reshape(-1))).to(dt).to(dev)
+                  for t in w.network.tensors]
+            ws_n, fl, mr = ctx.contract_network_plan(ts, w.network.labels, w.path, w.sliced,
+                                                     mode)
+            wsb = torch.empty(max(ws_n, 1), dtype=torch.uint8, device=dev)
+            ampt = torch.zeros(2, dtype=torch.float64, device=dev)
+            for _ in range(3):
+                ctx.contract_network(ts, w.network.labels, w.path, w.sliced, mode, amp=ampt,
+                                     workspace=wsb)
+            torch.cuda.synchronize()
+            xs = []
+            for _ in range(args.amp_requests):
+                t = time.perf_counter()
+                ctx.contract_network(ts, w.network.labels, w.path, w.sliced, mode, amp=ampt,
+                                     workspace=wsb)
+                torch.cuda.synchronize()
+                xs.append(1e3 * (time.perf_counter() - t))
+            a_ = ampt.cpu().numpy()
+            lat[mode] = {"p50_ms": percentile(xs, 50), "p99_ms": percentile(xs, 99),
+                         "amplitudes_per_s": 1e3 / float(np.mean(xs)),
+                         "amplitude": [float(a_[0]), float(a_[1])],
+                         "flops_per_amplitude": fl}
+        amp = {"workload": "one amplitude of a 20-qubit random circuit (4x5 grid, 12 cycles), "
+                           "greedy path, 4 sliced bonds = 16 slices batched, FP64 slice sum; "
+                           "one request at a time", **lat}
+        log(f"amplitude latency: {amp}")
+
+    k = main_res["kernels"]
+    gemm_ms = k["gemm"][0] / max(k["gemm"][1], 1)
+    achieved = flops / (gemm_ms * 1e-3) / 1e12
+    traffic = traffic_from_profiles("cgemm_f32_4m", 1)
+    modes = {"fp32_4m": {"tflops": main_res["tflops"], "ms_per_step": main_res["ms_per_step"],
+                         "e_F_sampled": errors.get("fp32_4m"), "tolerance": 1e-5,
+                         "frac_of_fp32_peak": main_res["tflops"] / FP32_PEAK}}
+    for mode, r in side.items():
+        modes[mode] = {"tflops": r["tflops"], "ms_per_step": r["ms_per_step"],
+                       "e_F_sampled": errors.get(mode),
+                       "tolerance": 1e-12 if mode == "fp64" else 1e-3}
+    if "fp64" in side:
+        modes["fp64"]["frac_of_fp64_peak"] = side["fp64"]["tflops"] / FP64_PEAK
+        modes["speedup_fp32_vs_fp64"] = main_res["tflops"] / side["fp64"]["tflops"]
+    if "bf16x3" in side:
+        modes["bf16x3"]["executed_frac_of_bf16_peak"] = 3 * side["bf16x3"]["tflops"] / BF16_PEAK
+        if "fp64" in side:
+            modes["speedup_bf16x3_vs_fp64"] = side["bf16x3"]["tflops"] / side["fp64"]["tflops"]
+
+    line = {
+        "metric": "block-tensordot TFLOP/s (FP64 vs FP32 vs split-BF16) + p50/p99 amplitude "
+                  "latency",
+        "value": main_res["tflops"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"pairwise contraction of two rank-{args.rank} complex64 tensors "
+                               f"(all dims 2), {args.k} contracted indices in seeded random "
+                               f"order, unblocked; FP32-4M; step = permute A, permute B, "
+                               f"fused-pair complex GEMM, FP64 norm of C",
+                   "M": M, "N": N, "K": K, "useful_flops_per_step": flops},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
+                     "kernel": "cgemm_f32_4m", "kernel_ms": gemm_ms},
+        "cpu_baseline": cpu,
+        "modes": modes,
+        "amplitude_latency": amp,
+        "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in k.items()},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

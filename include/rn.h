@@ -1,0 +1,196 @@
+/*
+ * rn.h - C ABI of the MI355X (gfx950) block tensor contraction library.
+ *
+ * A block tensor is a dense complex tensor split into a uniform grid of
+ * equal sub-tensors ("blocks") along each axis; the paper's block tensor
+ * algebra (Section II.C) contracts two such tensors pair of blocks by pair of
+ * blocks and sums the partial blocks into the output blocks.  This library
+ * runs that contraction on one GPU: an index permutation of each operand
+ * into a GEMM-ready layout, one complex GEMM whose K loop walks the coupled
+ * block pairs, and the reduction of the partials into C, all in HIP kernels.
+ *
+ * Conventions shared by every entry point:
+ *   - Every dim and every grid count is a power of two (tensors of quantum
+ *     circuits have dim 2; a dim 2^a is handled as a axes of dim 2 fused);
+ *     other values give RN_ERR_UNSUPPORTED.
+ *   - Element layout: complex values interleaved (re, im), row-major.
+ *     A tensor whose grid is not all ones is stored block-major: blocks in
+ *     row-major order of their block coordinates, each block contiguous and
+ *     row-major inside.  Grid all ones is the plain dense layout.
+ *   - Pairing follows tensordot: axesA[i] is contracted with axesB[i], and
+ *     the output lists A's free axes in A's order, then B's free axes in B's
+ *     order (the pairwise contraction formula, Section II.A).
+ *   - When the two operands split a contracted pair of axes into different
+ *     numbers of blocks, both are viewed on the finer grid (the common
+ *     refinement), which does not change the result.  C's grid is A's
+ *     free-axis grid followed by B's free-axis grid.
+ *   - Ownership: the caller allocates and owns every device buffer (tensor
+ *     data, workspace, results) and keeps it alive until the stream has
+ *     finished the enqueued work.  The library never frees caller memory.
+ *   - Asynchrony: compute calls enqueue kernels on `stream` (a hipStream_t,
+ *     NULL for the default stream) and return; they do not synchronise.
+ *   - Errors: every call returns rn_status and never throws.  On failure
+ *     nothing has been enqueued (argument checks run before any launch) and
+ *     rn_last_error() gives a message for the calling thread.
+ *   - Modes and dtypes: RN_FP64 computes in double with RN_C128 tensors;
+ *     RN_FP32_4M, RN_FP32_3M and RN_BF16X3 take RN_C64 tensors and
+ *     accumulate in float.
+ */
+#ifndef RN_H
+#define RN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RN_MAX_RANK 64
+#define RN_MAX_SLICED 15
+
+typedef enum {
+  RN_OK = 0,
+  RN_ERR_INVALID = 1,     /* null pointer, bad rank/axis/label, mode-dtype mismatch */
+  RN_ERR_SHAPE = 2,       /* paired dims differ, or C's dims are not the derived ones */
+  RN_ERR_GRID = 3,        /* a grid count does not divide its dim, or C's grid differs */
+  RN_ERR_WORKSPACE = 4,   /* workspace smaller than the plan requires */
+  RN_ERR_OOM = 5,         /* a request can never fit the memory budget */
+  RN_ERR_HIP = 6,         /* a HIP runtime call failed */
+  RN_ERR_UNSUPPORTED = 7  /* dims or grids that are not powers of two, sizes over limits */
+} rn_status;
+
+typedef enum { RN_C64 = 1, RN_C128 = 2 } rn_dtype;
+
+/* Arithmetic of the per-pair complex GEMM:
+ *   RN_FP64    complex128, 4 real products per complex product, FP64 MFMA;
+ *   RN_FP32_4M complex64, 4 real products, FP32 MFMA, FP32 accumulation;
+ *   RN_FP32_3M complex64, 3 real products (Gauss), FP32 MFMA;
+ *   RN_BF16X3  complex64 operands split as x = hi + lo (both bfloat16),
+ *              products lo*hi + hi*lo + hi*hi on BF16 MFMA, FP32 accumulation. */
+typedef enum { RN_FP64 = 0, RN_FP32_4M = 1, RN_FP32_3M = 2, RN_BF16X3 = 3 } rn_mode;
+
+typedef struct rn_ctx* rn_handle;
+
+/* Tensor descriptor.  data is a device pointer owned by the caller. */
+typedef struct {
+  int32_t rank;                /* 0 .. RN_MAX_RANK */
+  int32_t dtype;               /* rn_dtype */
+  int64_t dims[RN_MAX_RANK];   /* powers of two, >= 1 */
+  int32_t grid[RN_MAX_RANK];   /* blocks per axis; power of two dividing dims[j] */
+  void* data;
+} rn_tensor;
+
+/* Library context bound to one HIP device.  Holds plan caches only. */
+rn_status rn_create(rn_handle* h, int device);
+rn_status rn_destroy(rn_handle h);
+const char* rn_status_str(rn_status s);
+const char* rn_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Block tensordot (Section II.C, the four steps; tensordot semantics of the
+ * commutative task in Section III).
+ *
+ * plan: validates A, B, k, axes and mode, and fills C's rank, dims, grid
+ * and dtype (C->data is left untouched), the workspace the call needs, and
+ * the useful flop count 8*M*N*K (M, N, K = products of A-free, B-free and
+ * contracted dims).  Any output pointer may be NULL.
+ *
+ * rn_block_tensordot: C = sum over coupled block pairs of A_blk . B_blk,
+ * written block-major into C->data (which must not alias A or B).  C must
+ * carry exactly the rank, dims and grid the plan derives.  ws must be a
+ * device buffer of at least the planned bytes (NULL allowed when 0).
+ * ------------------------------------------------------------------------ */
+rn_status rn_block_tensordot_plan(rn_handle h, const rn_tensor* A, const rn_tensor* B, int32_t k,
+                                  const int32_t* axesA, const int32_t* axesB, rn_mode mode,
+                                  rn_tensor* C, size_t* ws_bytes, double* flops);
+rn_status rn_block_tensordot(rn_handle h, const rn_tensor* A, const rn_tensor* B, int32_t k,
+                             const int32_t* axesA, const int32_t* axesB, rn_tensor* C,
+                             rn_mode mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Pair list of one output block (step 2 of Section II.C): for C block
+ * `cblock` (row-major linear block index) writes up to `cap` pairs
+ * (A block index, B block index), each a row-major linear index into the
+ * operand's own stored grid, in the order the GEMM K loop visits them
+ * (ascending contracted block coordinates on the refined grid).  When a
+ * stored block is finer-split by the refinement, the same stored block index
+ * appears for each of its refined pieces.  *npairs receives the count. */
+rn_status rn_block_pairs(rn_handle h, const rn_tensor* A, const rn_tensor* B, int32_t k,
+                         const int32_t* axesA, const int32_t* axesB, int64_t cblock,
+                         int64_t* pairs, int64_t cap, int64_t* npairs);
+
+/* Memory models of Section IV.A in elements: sequential reduction
+ * B_k k_b (m_b + n_b) + m_b n_b (Eq. 1) and one pair plus accumulator
+ * k_b (m_b + n_b) + m_b n_b (Eq. 2), for the blocks of this contraction on
+ * the refined grid.  Host only; either output may be NULL. */
+rn_status rn_block_footprint(const rn_tensor* A, const rn_tensor* B, int32_t k,
+                             const int32_t* axesA, const int32_t* axesB, double* eq1_elems,
+                             double* eq2_elems);
+
+/* Many independent block tensordots in one call (same mode).  Plans every
+ * problem first (any invalid problem fails the whole call before anything is
+ * enqueued), then enqueues them on the stream; each problem gets its own
+ * 256-byte aligned slice of the workspace.  ws_bytes from
+ * rn_block_tensordot_batch_plan. */
+rn_status rn_block_tensordot_batch_plan(rn_handle h, int32_t n, const rn_tensor* A,
+                                        const rn_tensor* B, const int32_t* k,
+                                        const int32_t* const* axesA,
+                                        const int32_t* const* axesB, rn_mode mode, rn_tensor* C,
+                                        size_t* ws_bytes, double* flops);
+rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
+                                   const rn_tensor* B, const int32_t* k,
+                                   const int32_t* const* axesA, const int32_t* const* axesB,
+                                   rn_tensor* C, rn_mode mode, void* ws, size_t ws_bytes,
+                                   void* stream);
+
+/* ------------------------------------------------------------------------
+ * Sliced network contraction (Sections II.A and II.B).
+ *
+ * T[0..nt-1]: the network's tensors (every dim 2, grid all ones, dtype
+ * matching the mode).  labels[i][j] is the integer bond label of axis j of
+ * tensor i; a label carried by two tensors is a bond, and every label must
+ * be a bond (the network closes to a scalar).  path: nt-1 pairs in
+ * single-static-assignment form (ids >= nt name step results in order).  A
+ * step sums over the labels its two operands share.  sliced: nsliced
+ * (<= RN_MAX_SLICED) bond labels projected onto both basis values; slice s
+ * fixes sliced[i] to bit (nsliced-1-i) of s.  All 2^nsliced slices run
+ * batched through every step, and their scalar results are summed in FP64
+ * in ascending s on the GPU.  amp_dev (device, 2 doubles) receives
+ * (re, im) of the amplitude; slices_dev (device, 2*2^nsliced doubles, may be
+ * NULL) receives each slice's value.
+ * ------------------------------------------------------------------------ */
+rn_status rn_contract_network_plan(rn_handle h, int32_t nt, const rn_tensor* T,
+                                   const int32_t* const* labels, int32_t nsteps,
+                                   const int32_t* path, int32_t nsliced, const int32_t* sliced,
+                                   rn_mode mode, size_t* ws_bytes, double* flops,
+                                   int32_t* max_rank);
+rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
+                              const int32_t* const* labels, int32_t nsteps, const int32_t* path,
+                              int32_t nsliced, const int32_t* sliced, rn_mode mode, void* ws,
+                              size_t ws_bytes, void* stream, double* amp_dev, double* slices_dev);
+
+/* ------------------------------------------------------------------------
+ * FP64 reductions on the GPU (slice sums and norms, Section II.B).
+ * rn_norm2: out_dev[0] = sum |x|^2 over all elements of T, in FP64.
+ * rn_sum_c128: out_dev[0..1] = sum of n complex128 values (device, n <= 2^20),
+ * in a fixed order that does not depend on the launch.
+ * ------------------------------------------------------------------------ */
+rn_status rn_norm2(rn_handle h, const rn_tensor* T, double* out_dev, void* stream);
+rn_status rn_sum_c128(rn_handle h, int64_t n, const double* vals_dev, double* out_dev,
+                      void* stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (measurement support).  While enabled, every kernel this
+ * handle enqueues is bracketed by two HIP events recorded on the stream it
+ * runs on.  rn_profile_read waits for those events, returns the summed
+ * milliseconds and launch counts per kernel class -- [0] permute, [1] complex
+ * GEMM, [2] split-K reduction, [3] FP64 sums and norms -- and clears them.
+ * Timing adds an event pair per launch; leave it off in production.
+ * ------------------------------------------------------------------------ */
+rn_status rn_profile_enable(rn_handle h, int on);
+rn_status rn_profile_read(rn_handle h, double ms[4], int64_t count[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RN_H */

@@ -1,0 +1,352 @@
+"""Python binding of the MI355X block tensor contraction library (librosnet.so).
+
+Argument marshalling only: every step of the contraction runs in the HIP
+kernels behind the C ABI declared in include/rn.h.  PyTorch supplies device
+memory and the current stream; there is no CPU fallback, and loading fails
+loudly when the built library is missing.
+
+Operand tensors are torch complex tensors on a GPU holding the stored
+(block-major) buffer; their logical dims and grid are passed separately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librosnet.so")
+RN_MAX_RANK = 64
+RN_MAX_SLICED = 15
+
+MODES = {"fp64": 0, "fp32_4m": 1, "fp32_3m": 2, "bf16x3": 3}
+C64, C128 = 1, 2
+STATUS = {0: "RN_OK", 1: "RN_ERR_INVALID", 2: "RN_ERR_SHAPE", 3: "RN_ERR_GRID",
+          4: "RN_ERR_WORKSPACE", 5: "RN_ERR_OOM", 6: "RN_ERR_HIP", 7: "RN_ERR_UNSUPPORTED"}
+
+EXPORTS = ["rn_create", "rn_destroy", "rn_status_str", "rn_last_error",
+           "rn_block_tensordot_plan", "rn_block_tensordot", "rn_block_pairs",
+           "rn_block_footprint", "rn_block_tensordot_batch_plan", "rn_block_tensordot_batch",
+           "rn_contract_network_plan", "rn_contract_network", "rn_norm2", "rn_sum_c128",
+           "rn_profile_enable", "rn_profile_read"]
+
+
+class RnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class RnTensor(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("dims", ctypes.c_int64 * RN_MAX_RANK), ("grid", ctypes.c_int32 * RN_MAX_RANK),
+                ("data", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_2201_06620_amd/build.py` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        p, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        T = ctypes.POINTER(RnTensor)
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        L.rn_create.argtypes = [ctypes.POINTER(p), ctypes.c_int]
+        L.rn_destroy.argtypes = [p]
+        L.rn_status_str.argtypes = [ctypes.c_int]
+        L.rn_status_str.restype = ctypes.c_char_p
+        L.rn_last_error.argtypes = []
+        L.rn_last_error.restype = ctypes.c_char_p
+        L.rn_block_tensordot_plan.argtypes = [p, T, T, i32, p, p, ctypes.c_int, T,
+                                              ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_double)]
+        L.rn_block_tensordot.argtypes = [p, T, T, i32, p, p, T, ctypes.c_int, p, sz, p]
+        L.rn_block_pairs.argtypes = [p, T, T, i32, p, p, i64, p, i64, ctypes.POINTER(i64)]
+        L.rn_block_footprint.argtypes = [T, T, i32, p, p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
+        L.rn_block_tensordot_batch_plan.argtypes = [p, i32, T, T, p, pp, pp, ctypes.c_int, T,
+                                                    ctypes.POINTER(sz),
+                                                    ctypes.POINTER(ctypes.c_double)]
+        L.rn_block_tensordot_batch.argtypes = [p, i32, T, T, p, pp, pp, T, ctypes.c_int, p, sz, p]
+        L.rn_contract_network_plan.argtypes = [p, i32, T, pp, i32, p, i32, p, ctypes.c_int,
+                                               ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(i32)]
+        L.rn_contract_network.argtypes = [p, i32, T, pp, i32, p, i32, p, ctypes.c_int, p, sz, p,
+                                          p, p]
+        L.rn_norm2.argtypes = [p, T, p, p]
+        L.rn_sum_c128.argtypes = [p, i64, p, p, p]
+        L.rn_profile_enable.argtypes = [p, ctypes.c_int]
+        L.rn_profile_read.argtypes = [p, p, p]
+        for name in EXPORTS:
+            getattr(L, name).restype = getattr(L, name).restype if name in (
+                "rn_status_str", "rn_last_error") else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str = "") -> None:
+    if status != 0:
+        msg = lib().rn_last_error().decode()
+        raise RnError(status, f"{what}: {msg}" if what else msg)
+
+
+def descriptor(dims, grid=None, dtype=C128, data=None) -> RnTensor:
+    t = RnTensor()
+    dims = [int(d) for d in dims]
+    if len(dims) > RN_MAX_RANK:
+        raise ValueError("rank above RN_MAX_RANK")
+    grid = [1] * len(dims) if grid is None else [int(g) for g in grid]
+    t.rank = len(dims)
+    t.dtype = dtype
+    for j, (d, g) in enumerate(zip(dims, grid)):
+        t.dims[j] = d
+        t.grid[j] = g
+    t.data = data
+    return t
+
+
+def _arr32(x):
+    a = np.ascontiguousarray(np.asarray(list(x), dtype=np.int32).reshape(-1))
+    return a, (a.ctypes.data if a.size else None)
+
+
+def mode_id(mode) -> int:
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def dtype_of_mode(mode) -> int:
+    return C128 if mode_id(mode) == 0 else C64
+
+
+# ------------------------------------------------------------- host-only
+
+def plan_block_tensordot(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, mode="fp64"):
+    """(C dims, C grid, workspace bytes, useful flops) of a block tensordot."""
+    dt = dtype_of_mode(mode)
+    A, B, C = descriptor(dims_a, grid_a, dt), descriptor(dims_b, grid_b, dt), RnTensor()
+    aa, pa = _arr32(axes_a)
+    ab, pb = _arr32(axes_b)
+    ws, fl = ctypes.c_size_t(), ctypes.c_double()
+    check(lib().rn_block_tensordot_plan(None, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb,
+                                        mode_id(mode), ctypes.byref(C), ctypes.byref(ws),
+                                        ctypes.byref(fl)), "plan")
+    return ([C.dims[j] for j in range(C.rank)], [C.grid[j] for j in range(C.rank)],
+            ws.value, fl.value)
+
+
+def block_pairs(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, cblock, dtype=C128):
+    """Coupled (A block, B block) pairs of one C block, in K-loop order."""
+    A, B = descriptor(dims_a, grid_a, dtype), descriptor(dims_b, grid_b, dtype)
+    aa, pa = _arr32(axes_a)
+    ab, pb = _arr32(axes_b)
+    n = ctypes.c_int64()
+    check(lib().rn_block_pairs(None, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb, cblock,
+                               None, 0, ctypes.byref(n)), "pairs")
+    out = np.zeros(2 * max(n.value, 1), dtype=np.int64)
+    check(lib().rn_block_pairs(None, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb, cblock,
+                               out.ctypes.data, n.value, ctypes.byref(n)), "pairs")
+    return [(int(out[2 * i]), int(out[2 * i + 1])) for i in range(n.value)]
+
+
+def block_footprint(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, dtype=C64):
+    """(Eq. 1, Eq. 2) element counts of Section IV.A for this contraction."""
+    A, B = descriptor(dims_a, grid_a, dtype), descriptor(dims_b, grid_b, dtype)
+    aa, pa = _arr32(axes_a)
+    ab, pb = _arr32(axes_b)
+    e1, e2 = ctypes.c_double(), ctypes.c_double()
+    check(lib().rn_block_footprint(ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb,
+                                   ctypes.byref(e1), ctypes.byref(e2)), "footprint")
+    return e1.value, e2.value
+
+
+# ------------------------------------------------------------- GPU calls
+
+class Context:
+    """One library handle bound to a HIP device (torch device index)."""
+
+    def __init__(self, device: int = 0):
+        import torch  # noqa: F401  (device memory and streams come from torch)
+        self.device = device
+        h = ctypes.c_void_p()
+        check(lib().rn_create(ctypes.byref(h), device), "rn_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().rn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -----------------------------------------------------------
+    @staticmethod
+    def _stream():
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def _workspace(self, nbytes, workspace=None):
+        import torch
+        if nbytes == 0:
+            return None, 0
+        if workspace is not None:
+            if workspace.numel() * workspace.element_size() < nbytes:
+                raise RnError(4, "workspace too small")
+            return workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._last_ws = ws
+        return ws.data_ptr(), nbytes
+
+    # -- block tensordot -----------------------------------------------------
+    def block_tensordot(self, a, dims_a, grid_a, b, dims_b, grid_b, axes_a, axes_b,
+                        mode="fp64", out=None, workspace=None):
+        """C (stored block-major, flat torch tensor), C dims, C grid."""
+        import torch
+        dt = dtype_of_mode(mode)
+        want = torch.complex128 if dt == C128 else torch.complex64
+        for x in (a, b):
+            if x.dtype != want or not x.is_cuda or not x.is_contiguous():
+                raise RnError(1, f"operands must be contiguous {want} tensors on the GPU")
+        A = descriptor(dims_a, grid_a, dt, a.data_ptr())
+        B = descriptor(dims_b, grid_b, dt, b.data_ptr())
+        C = RnTensor()
+        aa, pa = _arr32(axes_a)
+        ab, pb = _arr32(axes_b)
+        ws_n, fl = ctypes.c_size_t(), ctypes.c_double()
+        check(lib().rn_block_tensordot_plan(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
+                                            pa, pb, mode_id(mode), ctypes.byref(C),
+                                            ctypes.byref(ws_n), ctypes.byref(fl)), "plan")
+        cdims = [C.dims[j] for j in range(C.rank)]
+        cgrid = [C.grid[j] for j in range(C.rank)]
+        n = int(np.prod(cdims, dtype=np.int64)) if cdims else 1
+        if out is None:
+            out = torch.empty(n, dtype=want, device=a.device)
+        C.data = out.data_ptr()
+        wp, wn = self._workspace(ws_n.value, workspace)
+        check(lib().rn_block_tensordot(self.h, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb,
+                                       ctypes.byref(C), mode_id(mode), wp, wn, self._stream()),
+              "block_tensordot")
+        return out, cdims, cgrid
+
+    def block_tensordot_batch(self, problems, mode="fp32_4m", outs=None, workspace=None):
+        """problems: list of (a, dims_a, grid_a, b, dims_b, grid_b, axes_a, axes_b)."""
+        import torch
+        n = len(problems)
+        dt = dtype_of_mode(mode)
+        want = torch.complex128 if dt == C128 else torch.complex64
+        As, Bs, Cs = (RnTensor * n)(), (RnTensor * n)(), (RnTensor * n)()
+        ks = np.zeros(max(n, 1), dtype=np.int32)
+        keep = []
+        pa_arr = (ctypes.c_void_p * max(n, 1))()
+        pb_arr = (ctypes.c_void_p * max(n, 1))()
+        for i, (a, da, ga, b, db, gb, axa, axb) in enumerate(problems):
+            As[i] = descriptor(da, ga, dt, a.data_ptr())
+            Bs[i] = descriptor(db, gb, dt, b.data_ptr())
+            x, px = _arr32(axa)
+            y, py = _arr32(axb)
+            keep += [x, y]
+            ks[i] = len(x)
+            pa_arr[i] = px
+            pb_arr[i] = py
+        ws_n, fl = ctypes.c_size_t(), ctypes.c_double()
+        check(lib().rn_block_tensordot_batch_plan(self.h, n, As, Bs, ks.ctypes.data, pa_arr,
+                                                  pb_arr, mode_id(mode), Cs, ctypes.byref(ws_n),
+                                                  ctypes.byref(fl)), "batch plan")
+        results = []
+        for i in range(n):
+            cd = [Cs[i].dims[j] for j in range(Cs[i].rank)]
+            cg = [Cs[i].grid[j] for j in range(Cs[i].rank)]
+            o = outs[i] if outs is not None else torch.empty(
+                int(np.prod(cd, dtype=np.int64)) if cd else 1, dtype=want,
+                device=problems[i][0].device)
+            Cs[i].data = o.data_ptr()
+            results.append((o, cd, cg))
+        wp, wn = self._workspace(ws_n.value, workspace)
+        check(lib().rn_block_tensordot_batch(self.h, n, As, Bs, ks.ctypes.data, pa_arr, pb_arr,
+                                             Cs, mode_id(mode), wp, wn, self._stream()), "batch")
+        return results, fl.value
+
+    # -- networks ------------------------------------------------------------
+    def _net_args(self, tensors, labels, mode):
+        n = len(tensors)
+        dt = dtype_of_mode(mode)
+        Ts = (RnTensor * n)()
+        lab_arr = (ctypes.c_void_p * n)()
+        keep = []
+        for i, (t, l) in enumerate(zip(tensors, labels)):
+            Ts[i] = descriptor([2] * len(l), None, dt, t.data_ptr())
+            x, px = _arr32(l)
+            keep.append(x)
+            lab_arr[i] = px
+        return Ts, lab_arr, keep
+
+    def contract_network_plan(self, tensors, labels, path, sliced, mode="fp64"):
+        Ts, lab_arr, keep = self._net_args(tensors, labels, mode)
+        pth, pp = _arr32([x for st in path for x in st])
+        sl, ps = _arr32(sliced)
+        ws_n, fl, mr = ctypes.c_size_t(), ctypes.c_double(), ctypes.c_int32()
+        check(lib().rn_contract_network_plan(self.h, len(tensors), Ts, lab_arr, len(path), pp,
+                                             len(sl), ps, mode_id(mode), ctypes.byref(ws_n),
+                                             ctypes.byref(fl), ctypes.byref(mr)), "network plan")
+        return ws_n.value, fl.value, mr.value
+
+    def contract_network(self, tensors, labels, path, sliced=(), mode="fp64", amp=None,
+                         slices=None, workspace=None):
+        """Amplitude (device tensor of 2 doubles, re and im) of a sliced network."""
+        import torch
+        Ts, lab_arr, keep = self._net_args(tensors, labels, mode)
+        pth, pp = _arr32([x for st in path for x in st])
+        sl, ps = _arr32(sliced)
+        ws_n, fl, mr = ctypes.c_size_t(), ctypes.c_double(), ctypes.c_int32()
+        check(lib().rn_contract_network_plan(self.h, len(tensors), Ts, lab_arr, len(path), pp,
+                                             len(sl), ps, mode_id(mode), ctypes.byref(ws_n),
+                                             ctypes.byref(fl), ctypes.byref(mr)), "network plan")
+        dev = tensors[0].device
+        if amp is None:
+            amp = torch.zeros(2, dtype=torch.float64, device=dev)
+        wp, wn = self._workspace(ws_n.value, workspace)
+        check(lib().rn_contract_network(self.h, len(tensors), Ts, lab_arr, len(path), pp,
+                                        len(sl), ps, mode_id(mode), wp, wn, self._stream(),
+                                        amp.data_ptr(),
+                                        slices.data_ptr() if slices is not None else None),
+              "contract_network")
+        return amp
+
+    # -- kernel timing -------------------------------------------------------
+    KERNEL_CLASSES = ("permute", "gemm", "splitk_reduce", "fp64_reduce")
+
+    def profile(self, on: bool = True) -> None:
+        check(lib().rn_profile_enable(self.h, 1 if on else 0), "profile")
+
+    def profile_read(self):
+        """{class: (total ms, launches)} since the last read; clears the record."""
+        ms = np.zeros(4, dtype=np.float64)
+        cnt = np.zeros(4, dtype=np.int64)
+        check(lib().rn_profile_read(self.h, ms.ctypes.data, cnt.ctypes.data), "profile_read")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.KERNEL_CLASSES)}
+
+    # -- reductions ----------------------------------------------------------
+    def norm2(self, t, dims=None):
+        import torch
+        dt = C128 if t.dtype == torch.complex128 else C64
+        dims = [t.numel()] if dims is None else dims
+        T = descriptor(dims, None, dt, t.data_ptr())
+        out = torch.zeros(1, dtype=torch.float64, device=t.device)
+        check(lib().rn_norm2(self.h, ctypes.byref(T), out.data_ptr(), self._stream()), "norm2")
+        return out
+
+    def sum_c128(self, vals):
+        import torch
+        out = torch.zeros(2, dtype=torch.float64, device=vals.device)
+        check(lib().rn_sum_c128(self.h, vals.numel(), vals.data_ptr(), out.data_ptr(),
+                                self._stream()), "sum_c128")
+        return out

@@ -1,0 +1,1036 @@
+// HIP kernels for gfx950 (MI355X): index permutation, complex GEMM on MFMA,
+// split-K reduction and FP64 reductions.
+//
+// Terminology: a "complex column" is one complex output element per row; in
+// the 4M real embedding a complex m x k matrix A is the real m x 2k matrix of
+// its interleaved (re, im) values, and a complex k x n matrix B becomes the
+// real 2k x 2n matrix whose 2x2 cell for b is [[b_r, b_i], [-b_i, b_r]].  One
+// real GEMM then yields C already interleaved, with 8*M*N*K real flops.  The
+// embedding of B is never stored: each lane builds its B operand from the
+// complex value in LDS (select re or im, flip a sign).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "rn_internal.hpp"
+
+namespace rn {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+// ===========================================================================
+// Index permutation (TTGT relayout).  Output bit o of the linear element
+// index reads input bit src[o]; input bits outside src are fixed by in_base
+// (slice projection).  A workgroup moves one tile: the set S of bits made of
+// the lowest output bits and the lowest input bits, so both the global reads
+// (input order) and the global writes (output order) run over contiguous
+// runs of >= 512 bytes, while the transpose between the two orders happens
+// in LDS.  The remaining bits index the tiles.
+// ===========================================================================
+struct PermParams {
+  const void* in;
+  void* out;
+  void* out2;
+  int64_t in_base;
+  int64_t ntiles;
+  int nS;        // tile bits
+  int nO;        // outer bits
+  int8_t ls_in[16];   // load order q -> input bit
+  int8_t ss_out[16];  // store order q -> output bit
+  int8_t ss_lds[16];  // store order q -> load-order position
+  int8_t os_in[64];   // outer bit q -> input bit
+  int8_t os_out[64];  // outer bit q -> output bit
+};
+
+__device__ __forceinline__ int lds_pad(int x) { return x + (x >> 5); }
+
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// hi = nearest bfloat16 of x; lo = nearest bfloat16 of the exact residual
+// x - hi (Henry, Tang and Heinecke, "Leveraging the bfloat16 artificial
+// intelligence datatype for higher-precision computations", ARITH 2019).
+__device__ __forceinline__ void bf16_split(float x, uint32_t& hi, uint32_t& lo) {
+  hi = bf16_rne(x);
+  float r = x - __uint_as_float(hi << 16);
+  lo = bf16_rne(r);
+}
+
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);
+  const T* __restrict__ in = reinterpret_cast<const T*>(p.in);
+  const int tid = threadIdx.x;
+  const int tsize = 1 << p.nS;
+  const int lo_bits = p.nS < 8 ? p.nS : 8;
+  // Thread-fixed low parts of the tile-local index u = tid + 256 * j.
+  int64_t in_lo = 0;
+  int64_t out_lo = 0;
+  int lds_lo = 0;
+  for (int q = 0; q < lo_bits; ++q) {
+    if ((tid >> q) & 1) {
+      in_lo += int64_t(1) << p.ls_in[q];
+      out_lo += int64_t(1) << p.ss_out[q];
+      lds_lo += 1 << p.ss_lds[q];
+    }
+  }
+  const bool active = tid < tsize;
+  for (int64_t t = blockIdx.x; t < p.ntiles; t += gridDim.x) {
+    int64_t ib = p.in_base, ob = 0;
+    for (int q = 0; q < p.nO; ++q) {
+      if ((t >> q) & 1) {
+        ib += int64_t(1) << p.os_in[q];
+        ob += int64_t(1) << p.os_out[q];
+      }
+    }
+    if (active) {
+      for (int j = 0; (j << 8) < tsize; ++j) {
+        int64_t io = ib + in_lo;
+        for (int q = 8; q < p.nS; ++q)
+          if ((j >> (q - 8)) & 1) io += int64_t(1) << p.ls_in[q];
+        tile[lds_pad(tid + (j << 8))] = in[io];
+      }
+    }
+    __syncthreads();
+    if (active) {
+      for (int j = 0; (j << 8) < tsize; ++j) {
+        int64_t oo = ob + out_lo;
+        int li = lds_lo;
+        for (int q = 8; q < p.nS; ++q) {
+          if ((j >> (q - 8)) & 1) {
+            oo += int64_t(1) << p.ss_out[q];
+            li += 1 << p.ss_lds[q];
+          }
+        }
+        T v = tile[lds_pad(li)];
+        if constexpr (KIND == 0) {
+          reinterpret_cast<T*>(p.out)[oo] = v;
+        } else {
+          uint32_t hr, lr, hi_, li_;
+          bf16_split(v.x, hr, lr);
+          bf16_split(v.y, hi_, li_);
+          reinterpret_cast<uint32_t*>(p.out)[oo] = hr | (hi_ << 16);
+          reinterpret_cast<uint32_t*>(p.out2)[oo] = lr | (li_ << 16);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_permute(const PermLaunch& L, hipStream_t s) {
+  const int R = L.perm.nbits;
+  PermParams p{};
+  p.in = L.in;
+  p.out = L.out;
+  p.out2 = L.out2;
+  p.in_base = L.in_base;
+  const int tlow = (L.in_es == 16) ? 5 : 6;
+  bool inS[64] = {false};
+  if (R <= 2 * tlow) {
+    for (int o = 0; o < R; ++o) inS[o] = true;
+  } else {
+    for (int o = 0; o < tlow; ++o) inS[o] = true;
+    // Output bits ordered by their input position: the lowest tlow of them
+    // are the input-contiguous bits.
+    int ord[64];
+    for (int o = 0; o < R; ++o) ord[o] = o;
+    std::sort(ord, ord + R, [&](int a, int b) { return L.perm.src[a] < L.perm.src[b]; });
+    for (int q = 0; q < tlow; ++q) inS[ord[q]] = true;
+  }
+  int ls[16], ss[16], nS = 0, nO = 0;
+  for (int o = 0; o < R; ++o) {
+    if (inS[o]) {
+      ss[nS++] = o;
+    } else {
+      p.os_in[nO] = L.perm.src[o];
+      p.os_out[nO] = (int8_t)o;
+      ++nO;
+    }
+  }
+  for (int q = 0; q < nS; ++q) ls[q] = ss[q];
+  std::sort(ls, ls + nS, [&](int a, int b) { return L.perm.src[a] < L.perm.src[b]; });
+  for (int q = 0; q < nS; ++q) {
+    p.ls_in[q] = L.perm.src[ls[q]];
+    p.ss_out[q] = (int8_t)ss[q];
+    for (int r = 0; r < nS; ++r)
+      if (ls[r] == ss[q]) p.ss_lds[q] = (int8_t)r;
+  }
+  p.nS = nS;
+  p.nO = nO;
+  p.ntiles = int64_t(1) << nO;
+  const int tsize = 1 << nS;
+  size_t lds = size_t(tsize + (tsize >> 5) + 1) * L.in_es;
+  int64_t grid = std::min<int64_t>(p.ntiles, 256 * 8);
+  if (L.kind == 1) {
+    permute_kernel<float2, 1><<<dim3((unsigned)grid), dim3(256), lds, s>>>(p);
+  } else if (L.in_es == 16) {
+    permute_kernel<double2, 0><<<dim3((unsigned)grid), dim3(256), lds, s>>>(p);
+  } else {
+    permute_kernel<float2, 0><<<dim3((unsigned)grid), dim3(256), lds, s>>>(p);
+  }
+  return hipGetLastError();
+}
+
+// ===========================================================================
+// Complex GEMM: C[M x N] = A[M x K] * B[N x K]^T (both operands K-contiguous),
+// batched over slices, optionally split along K into partial sums.
+// ===========================================================================
+struct GemmParams {
+  const void* A;
+  const void* B;
+  const void* A2;
+  const void* B2;
+  void* C;
+  void* partial;
+  int64_t M, N, K, lda, ldb;
+  int64_t crh, crl, cch, ccl;
+  int crs, ccs;
+  int nbb;
+  int splitk;
+  int64_t kchunk;
+  int tiles_m, tiles_n;
+  int64_t a_bs[RN_MAX_SLICED], b_bs[RN_MAX_SLICED], c_bs[RN_MAX_SLICED];
+};
+
+__device__ __forceinline__ int64_t batch_off(const int64_t* st, int nbb, int b) {
+  int64_t o = 0;
+  for (int i = 0; i < nbb; ++i)
+    if ((b >> i) & 1) o += st[i];
+  return o;
+}
+
+__device__ __forceinline__ int64_t map2(int64_t x, int sh, int64_t hi, int64_t lo) {
+  return (x >> sh) * hi + (x & ((int64_t(1) << sh) - 1)) * lo;
+}
+
+// Output element (row, col, part) of tile results: either straight into C
+// through the two-level maps, or into the split-K partial buffer.
+template <typename R>
+__device__ __forceinline__ void store_out(const GemmParams& p, int b, int split, int64_t row,
+                                          int64_t col, int part, R v) {
+  if (row >= p.M || col >= p.N) return;
+  if (p.splitk > 1) {
+    int64_t nb = int64_t(1) << p.nbb;
+    int64_t idx = ((int64_t(split) * nb + b) * p.M + row) * p.N + col;
+    reinterpret_cast<R*>(p.partial)[2 * idx + part] = v;
+  } else {
+    int64_t off = batch_off(p.c_bs, p.nbb, b) + map2(row, p.crs, p.crh, p.crl) +
+                  map2(col, p.ccs, p.cch, p.ccl);
+    reinterpret_cast<R*>(p.C)[2 * off + part] = v;
+  }
+}
+
+// Workgroup -> output tile.  Hardware hands consecutive workgroups to the 8
+// XCDs round-robin; renumbering them so each XCD receives one contiguous run
+// of logical tiles, and walking tiles in column groups of GROUP_M row tiles,
+// keeps the A row panels and B column panels a group shares inside one L2.
+__device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
+  int nwg = gridDim.x;
+  int bid = blockIdx.x;
+  if ((nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
+  const int GROUP_M = 8;
+  int group_size = GROUP_M * tiles_n;
+  int g = bid / group_size;
+  int first_m = g * GROUP_M;
+  int gm = min(tiles_m - first_m, GROUP_M);
+  int r = bid % group_size;
+  tm = first_m + r % gm;
+  tn = r / gm;
+}
+
+// ---------------------------------------------------------------------------
+// FP32, 4M embedding, v_mfma_f32_32x32x2_f32.
+// WM x WN waves; each wave owns TM x TN MFMA tiles of 32 x 32 real outputs.
+// ---------------------------------------------------------------------------
+template <int WM, int WN, int TM, int TN, int BK>
+__global__ __launch_bounds__(256) void cgemm_f32_4m(GemmParams p) {
+  static_assert(WM * WN == 4, "four waves");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 16;  // complex columns
+  constexpr int LDK = BK + 1;       // padded LDS row, complex elements
+  constexpr int AV = BM * BK / 2;   // float4 (two complex) loads per A chunk
+  constexpr int BV = BN * BK / 2;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  __shared__ float2 As[2][BM * LDK];
+  __shared__ float2 Bs[2][BN * LDK];
+
+  int tm, tn;
+  tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+  const int split = blockIdx.y;
+  const int b = blockIdx.z;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const float2* __restrict__ Ag =
+      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const float2* __restrict__ Bg =
+      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+
+  float4 ra[NA], rb[NB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = row0 + r, gk = k0 + c;
+        if (gr < p.M) {
+          const float2* src = Ag + gr * p.lda + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = col0 + r, gk = k0 + c;
+        if (gr < p.N) {
+          const float2* src = Bg + gr * p.ldb + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      rb[j] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        As[buf][r * LDK + c] = make_float2(ra[j].x, ra[j].y);
+        As[buf][r * LDK + c + 1] = make_float2(ra[j].z, ra[j].w);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        Bs[buf][r * LDK + c] = make_float2(rb[j].x, rb[j].y);
+        Bs[buf][r * LDK + c + 1] = make_float2(rb[j].z, rb[j].w);
+      }
+    }
+  };
+
+  v16f acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  // Lane roles in the 32x32x2 MFMA: A operand row = lane % 32, k = lane / 32
+  // (k 0 = real part, k 1 = imaginary part of the complex a); B operand real
+  // column n = lane % 32 (complex column n / 2, part n & 1), same k.
+  const int khalf = lane >> 5;
+  const int par = lane & 1;
+  const bool b_take_re = (khalf == par);
+  const uint32_t b_sign = (khalf == 1 && par == 0) ? 0x80000000u : 0u;
+  const int arow = wm * TM * 32 + (lane & 31);
+  const int bcol = wn * TN * 16 + ((lane & 31) >> 1);
+
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      float af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        float2 a = As[buf][(arow + i * 32) * LDK + kk];
+        af[i] = khalf ? a.y : a.x;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        float2 bv = Bs[buf][(bcol + j * 16) * LDK + kk];
+        float v = b_take_re ? bv.x : bv.y;
+        bf[j] = __uint_as_float(__float_as_uint(v) ^ b_sign);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // 32x32 accumulator layout: lane holds real column lane % 32 and rows
+  // 8*(e/4) + 4*(lane/32) + e%4 for e = 0..15.
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * khalf + (e & 3);
+        int n = wn * TN * 32 + j * 32 + (lane & 31);
+        store_out<float>(p, b, split, row, col0 + (n >> 1), n & 1, acc[i][j][e]);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// FP64, 4M embedding, v_mfma_f64_16x16x4_f64 (4 real k = 2 complex k).
+// ---------------------------------------------------------------------------
+template <int WM, int WN, int TM, int TN, int BK>
+__global__ __launch_bounds__(256) void cgemm_f64_4m(GemmParams p) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK % 2 == 0, "two complex k per MFMA");
+  constexpr int BM = WM * TM * 16;
+  constexpr int BN = WN * TN * 8;  // complex columns
+  constexpr int LDK = BK + 1;
+  constexpr int AV = BM * BK;  // double2 loads
+  constexpr int BV = BN * BK;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  __shared__ double2 As[2][BM * LDK];
+  __shared__ double2 Bs[2][BN * LDK];
+
+  int tm, tn;
+  tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+  const int split = blockIdx.y;
+  const int b = blockIdx.z;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const double2* __restrict__ Ag =
+      reinterpret_cast<const double2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const double2* __restrict__ Bg =
+      reinterpret_cast<const double2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+
+  double2 ra[NA], rb[NB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      double2 v = make_double2(0.0, 0.0);
+      if (idx < AV) {
+        int r = idx / BK, c = idx % BK;
+        int64_t gr = row0 + r, gk = k0 + c;
+        if (gr < p.M && gk < kend) v = Ag[gr * p.lda + gk];
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      double2 v = make_double2(0.0, 0.0);
+      if (idx < BV) {
+        int r = idx / BK, c = idx % BK;
+        int64_t gr = col0 + r, gk = k0 + c;
+        if (gr < p.N && gk < kend) v = Bg[gr * p.ldb + gk];
+      }
+      rb[j] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < AV) As[buf][(idx / BK) * LDK + idx % BK] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < BV) Bs[buf][(idx / BK) * LDK + idx % BK] = rb[j];
+    }
+  };
+
+  v4d acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.0;
+
+  // 16x16x4 f64 roles: A row = lane % 16, real k = lane / 16, i.e. complex k
+  // lane / 32 and part (lane / 16) & 1; B real column n = lane % 16 (complex
+  // column n / 2, part n & 1), same real k.
+  const int kc = lane >> 5;
+  const int kpart = (lane >> 4) & 1;
+  const int par = lane & 1;
+  const bool b_take_re = (kpart == par);
+  const bool b_neg = (kpart == 1 && par == 0);
+  const int arow = wm * TM * 16 + (lane & 15);
+  const int bcol = wn * TN * 8 + ((lane & 15) >> 1);
+
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      double af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        double2 a = As[buf][(arow + i * 16) * LDK + kk + kc];
+        af[i] = kpart ? a.y : a.x;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        double2 bv = Bs[buf][(bcol + j * 8) * LDK + kk + kc];
+        double v = b_take_re ? bv.x : bv.y;
+        bf[j] = b_neg ? -v : v;
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // 16x16 f64 accumulator layout (unlike the f32 16x16 one): lane holds
+  // real column lane % 16 and rows 4*e + lane/16 for e = 0..3.
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t row = row0 + wm * TM * 16 + i * 16 + 4 * e + (lane >> 4);
+        int n = wn * TN * 16 + j * 16 + (lane & 15);
+        store_out<double>(p, b, split, row, col0 + (n >> 1), n & 1, acc[i][j][e]);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Split BF16 x3, 4M embedding, v_mfma_f32_32x32x16_bf16.
+// Operands are bf16 complex pairs packed as uint32 (re low, im high), hi and
+// lo parts in separate arrays.  Per 16 real k: lo*hi + hi*lo + hi*hi into
+// one FP32 accumulator.
+// ---------------------------------------------------------------------------
+template <int WM, int WN, int TM, int TN, int BK>
+__global__ __launch_bounds__(256) void cgemm_bf16x3(GemmParams p) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK % 8 == 0, "eight complex k per MFMA");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 16;
+  constexpr int LDK = BK + 4;       // uint32 per padded row
+  constexpr int AV = BM * BK / 4;   // uint4 loads (4 complex) per array
+  constexpr int BV = BN * BK / 4;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  __shared__ __align__(16) uint32_t Ah[2][BM * LDK];
+  __shared__ __align__(16) uint32_t Al[2][BM * LDK];
+  __shared__ __align__(16) uint32_t Bh[2][BN * LDK];
+  __shared__ __align__(16) uint32_t Bl[2][BN * LDK];
+
+  int tm, tn;
+  tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+  const int split = blockIdx.y;
+  const int b = blockIdx.z;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const int64_t ao = batch_off(p.a_bs, p.nbb, b), bo = batch_off(p.b_bs, p.nbb, b);
+  const uint32_t* __restrict__ Agh = reinterpret_cast<const uint32_t*>(p.A) + ao;
+  const uint32_t* __restrict__ Agl = reinterpret_cast<const uint32_t*>(p.A2) + ao;
+  const uint32_t* __restrict__ Bgh = reinterpret_cast<const uint32_t*>(p.B) + bo;
+  const uint32_t* __restrict__ Bgl = reinterpret_cast<const uint32_t*>(p.B2) + bo;
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+
+  uint4 rah[NA], ral[NA], rbh[NB], rbl[NB];
+  auto ld4 = [&](const uint32_t* src, int64_t gk) -> uint4 {
+    if (gk + 3 < kend) return *reinterpret_cast<const uint4*>(src);
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gk < kend) v.x = src[0];
+    if (gk + 1 < kend) v.y = src[1];
+    if (gk + 2 < kend) v.z = src[2];
+    return v;
+  };
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
+      if (idx < AV) {
+        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
+        int64_t gr = row0 + r, gk = k0 + c;
+        if (gr < p.M && gk < kend) {
+          h = ld4(Agh + gr * p.lda + gk, gk);
+          l = ld4(Agl + gr * p.lda + gk, gk);
+        }
+      }
+      rah[j] = h;
+      ral[j] = l;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
+      if (idx < BV) {
+        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
+        int64_t gr = col0 + r, gk = k0 + c;
+        if (gr < p.N && gk < kend) {
+          h = ld4(Bgh + gr * p.ldb + gk, gk);
+          l = ld4(Bgl + gr * p.ldb + gk, gk);
+        }
+      }
+      rbh[j] = h;
+      rbl[j] = l;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < AV) {
+        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
+        *reinterpret_cast<uint4*>(&Ah[buf][r * LDK + c]) = rah[j];
+        *reinterpret_cast<uint4*>(&Al[buf][r * LDK + c]) = ral[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < BV) {
+        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
+        *reinterpret_cast<uint4*>(&Bh[buf][r * LDK + c]) = rbh[j];
+        *reinterpret_cast<uint4*>(&Bl[buf][r * LDK + c]) = rbl[j];
+      }
+    }
+  };
+
+  v16f acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  // 32x32x16 bf16 roles: A row = lane % 32, real k = 8*(lane/32) + 0..7,
+  // i.e. complex k 4*(lane/32) + 0..3 in interleaved (re, im) order; B real
+  // column n = lane % 32 reads the same four complex b's of complex column
+  // n / 2 and turns each packed (b_r, b_i) into (b_r, -b_i) for n even or
+  // (b_i, b_r) for n odd.
+  const int kq = (lane >> 5) * 4;
+  const bool odd = lane & 1;
+  const int arow = wm * TM * 32 + (lane & 31);
+  const int bcol = wn * TN * 16 + ((lane & 31) >> 1);
+  auto bfix = [&](v4u w) -> v4u {
+    if (odd) return (w >> 16) | (w << 16);
+    return w ^ 0x80000000u;
+  };
+
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 8) {
+      v8bf ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        int o = (arow + i * 32) * LDK + kk + kq;
+        ah[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(&Ah[buf][o]));
+        al[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(&Al[buf][o]));
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        int o = (bcol + j * 16) * LDK + kk + kq;
+        bh[j] = __builtin_bit_cast(v8bf, bfix(*reinterpret_cast<const v4u*>(&Bh[buf][o])));
+        bl[j] = __builtin_bit_cast(v8bf, bfix(*reinterpret_cast<const v4u*>(&Bl[buf][o])));
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  const int khalf = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * khalf + (e & 3);
+        int n = wn * TN * 32 + j * 32 + (lane & 31);
+        store_out<float>(p, b, split, row, col0 + (n >> 1), n & 1, acc[i][j][e]);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Small problems: one thread per complex output, sequential K loop (FP64,
+// FP32 or split BF16 products).  Used when a tile would be mostly empty.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+template <int MODE>
+__global__ __launch_bounds__(256) void cgemm_small(GemmParams p) {
+  const int split = blockIdx.y;
+  const int b = blockIdx.z;
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= p.M * p.N) return;
+  const int64_t row = e / p.N, col = e % p.N;
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int64_t ao = batch_off(p.a_bs, p.nbb, b) + row * p.lda;
+  const int64_t bo = batch_off(p.b_bs, p.nbb, b) + col * p.ldb;
+  if constexpr (MODE == RN_FP64) {
+    const double2* A = reinterpret_cast<const double2*>(p.A) + ao;
+    const double2* B = reinterpret_cast<const double2*>(p.B) + bo;
+    double re = 0.0, im = 0.0;
+    for (int64_t k = kbeg; k < kend; ++k) {
+      double2 a = A[k], bb = B[k];
+      re = fma(a.x, bb.x, re);
+      re = fma(-a.y, bb.y, re);
+      im = fma(a.x, bb.y, im);
+      im = fma(a.y, bb.x, im);
+    }
+    store_out<double>(p, b, split, row, col, 0, re);
+    store_out<double>(p, b, split, row, col, 1, im);
+  } else if constexpr (MODE == RN_FP32_4M) {
+    const float2* A = reinterpret_cast<const float2*>(p.A) + ao;
+    const float2* B = reinterpret_cast<const float2*>(p.B) + bo;
+    float re = 0.f, im = 0.f;
+    for (int64_t k = kbeg; k < kend; ++k) {
+      float2 a = A[k], bb = B[k];
+      re = fmaf(a.x, bb.x, re);
+      re = fmaf(-a.y, bb.y, re);
+      im = fmaf(a.x, bb.y, im);
+      im = fmaf(a.y, bb.x, im);
+    }
+    store_out<float>(p, b, split, row, col, 0, re);
+    store_out<float>(p, b, split, row, col, 1, im);
+  } else {
+    const uint32_t* Ah = reinterpret_cast<const uint32_t*>(p.A) + ao;
+    const uint32_t* Al = reinterpret_cast<const uint32_t*>(p.A2) + ao;
+    const uint32_t* Bh = reinterpret_cast<const uint32_t*>(p.B) + bo;
+    const uint32_t* Bl = reinterpret_cast<const uint32_t*>(p.B2) + bo;
+    float re = 0.f, im = 0.f;
+    for (int64_t k = kbeg; k < kend; ++k) {
+      uint32_t ah = Ah[k], al = Al[k], bh = Bh[k], bl = Bl[k];
+      float ahr = bf_lo(ah), ahi = bf_hi(ah), alr = bf_lo(al), ali = bf_hi(al);
+      float bhr = bf_lo(bh), bhi = bf_hi(bh), blr = bf_lo(bl), bli = bf_hi(bl);
+      // lo*hi + hi*lo + hi*hi, each a complex product of bf16 values (exact
+      // in FP32), accumulated in FP32.
+      re = fmaf(alr, bhr, re); re = fmaf(-ali, bhi, re);
+      im = fmaf(alr, bhi, im); im = fmaf(ali, bhr, im);
+      re = fmaf(ahr, blr, re); re = fmaf(-ahi, bli, re);
+      im = fmaf(ahr, bli, im); im = fmaf(ahi, blr, im);
+      re = fmaf(ahr, bhr, re); re = fmaf(-ahi, bhi, re);
+      im = fmaf(ahr, bhi, im); im = fmaf(ahi, bhr, im);
+    }
+    store_out<float>(p, b, split, row, col, 0, re);
+    store_out<float>(p, b, split, row, col, 1, im);
+  }
+}
+
+// Split-K reduction: C = sum over splits of the partials, in ascending split
+// order, written through the two-level maps.
+template <typename R>
+__global__ __launch_bounds__(256) void splitk_reduce(GemmParams p) {
+  const int64_t nb = int64_t(1) << p.nbb;
+  const int64_t total = nb * p.M * p.N;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * 256) {
+    const int64_t b = e / (p.M * p.N);
+    const int64_t rc = e % (p.M * p.N);
+    const int64_t row = rc / p.N, col = rc % p.N;
+    const R* part = reinterpret_cast<const R*>(p.partial);
+    R re = 0, im = 0;
+    for (int s = 0; s < p.splitk; ++s) {
+      int64_t idx = (int64_t(s) * nb + b) * p.M * p.N + rc;
+      re += part[2 * idx];
+      im += part[2 * idx + 1];
+    }
+    int64_t off = batch_off(p.c_bs, p.nbb, (int)b) + map2(row, p.crs, p.crh, p.crl) +
+                  map2(col, p.ccs, p.cch, p.ccl);
+    reinterpret_cast<R*>(p.C)[2 * off] = re;
+    reinterpret_cast<R*>(p.C)[2 * off + 1] = im;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile configurations and dispatch.
+// ---------------------------------------------------------------------------
+struct TileCfg {
+  int bm, bn;  // rows, complex columns
+  int bk;      // complex k per LDS stage
+};
+
+// Index 0 = small-problem kernel; the rest are MFMA tile shapes per mode.
+static const TileCfg kF32Tiles[] = {
+    {1, 1, 1}, {128, 64, 16}, {64, 32, 16}, {256, 64, 8}, {128, 128, 8}};
+static const TileCfg kF64Tiles[] = {{1, 1, 1}, {128, 64, 8}, {64, 32, 8}};
+static const TileCfg kBF16Tiles[] = {{1, 1, 1}, {128, 64, 16}, {64, 32, 16}};
+
+static const TileCfg& tile_of(rn_mode mode, int t) {
+  if (mode == RN_FP64) return kF64Tiles[t];
+  if (mode == RN_BF16X3) return kBF16Tiles[t];
+  return kF32Tiles[t];
+}
+
+static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
+  if (M * N * K <= (int64_t(1) << 15) || M < 16 || N < 8) return 0;
+  if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) return 1;
+  return 2;
+}
+
+int choose_splitk(rn_mode mode, int64_t M, int64_t N, int64_t K, int64_t batch) {
+  int t = choose_tile(mode, M, N, K);
+  const TileCfg& c = tile_of(mode, t);
+  int64_t tiles = ((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn) * batch;
+  int64_t minchunk = (t == 0) ? 64 : 4 * c.bk;
+  int s = 1;
+  while (s < 64 && tiles * s < 1024 && K / (2 * s) >= minchunk) s *= 2;
+  return s;
+}
+
+hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
+  GemmParams p{};
+  p.A = g.A;
+  p.B = g.B;
+  p.A2 = g.A2;
+  p.B2 = g.B2;
+  p.C = g.C;
+  p.partial = g.partial;
+  p.M = g.M;
+  p.N = g.N;
+  p.K = g.K;
+  p.lda = g.lda;
+  p.ldb = g.ldb;
+  p.crs = g.crow.shift;
+  p.crh = g.crow.hi;
+  p.crl = g.crow.lo;
+  p.ccs = g.ccol.shift;
+  p.cch = g.ccol.hi;
+  p.ccl = g.ccol.lo;
+  p.nbb = g.nbb;
+  for (int i = 0; i < g.nbb; ++i) {
+    p.a_bs[i] = g.a_bstride[i];
+    p.b_bs[i] = g.b_bstride[i];
+    p.c_bs[i] = g.c_bstride[i];
+  }
+  p.splitk = g.splitk;
+  p.kchunk = (g.K + g.splitk - 1) / g.splitk;
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  const int tile = g.tile >= 0 ? g.tile : choose_tile(g.mode, g.M, g.N, g.K);
+  const TileCfg& c = tile_of(g.mode, tile);
+  const unsigned nbatch = 1u << g.nbb;
+  const int ev = prof ? prof->begin(1, s) : -1;
+  if (tile == 0) {
+    dim3 grid((unsigned)((g.M * g.N + 255) / 256), (unsigned)g.splitk, nbatch);
+    if (g.mode == RN_FP64)
+      cgemm_small<RN_FP64><<<grid, 256, 0, s>>>(p);
+    else if (g.mode == RN_BF16X3)
+      cgemm_small<RN_BF16X3><<<grid, 256, 0, s>>>(p);
+    else
+      cgemm_small<RN_FP32_4M><<<grid, 256, 0, s>>>(p);
+  } else {
+    p.tiles_m = (int)((g.M + c.bm - 1) / c.bm);
+    p.tiles_n = (int)((g.N + c.bn - 1) / c.bn);
+    dim3 grid((unsigned)(p.tiles_m * p.tiles_n), (unsigned)g.splitk, nbatch);
+    if (g.mode == RN_FP64) {
+      if (tile == 1)
+        cgemm_f64_4m<2, 2, 4, 4, 8><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_f64_4m<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
+    } else if (g.mode == RN_BF16X3) {
+      if (tile == 1)
+        cgemm_bf16x3<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_bf16x3<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
+    } else {
+      if (tile == 1)
+        cgemm_f32_4m<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
+      else if (tile == 2)
+        cgemm_f32_4m<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
+      else if (tile == 3)
+        cgemm_f32_4m<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_f32_4m<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(p);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (prof) prof->end(ev, s);
+  if (e != hipSuccess || g.splitk <= 1) return e;
+  int64_t total = int64_t(nbatch) * g.M * g.N;
+  unsigned rg = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  const int ev2 = prof ? prof->begin(2, s) : -1;
+  if (g.mode == RN_FP64)
+    splitk_reduce<double><<<rg, 256, 0, s>>>(p);
+  else
+    splitk_reduce<float><<<rg, 256, 0, s>>>(p);
+  e = hipGetLastError();
+  if (prof) prof->end(ev2, s);
+  return e;
+}
+
+// ===========================================================================
+// FP64 reductions.  Deterministic: every element goes to a fixed lane, lanes
+// combine in a fixed butterfly order (cross-lane shuffles), waves in a fixed
+// order through LDS, blocks in ascending order in a second pass.
+// ===========================================================================
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  return t;
+}
+
+constexpr int kRedBlocks = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(256) void norm2_partial(const T* x, int64_t n, double* part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(kRedBlocks) * 256) {
+    double re = (double)x[i].x, im = (double)x[i].y;
+    s += re * re + im * im;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void sum_partials(const double* part, int n, double* out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+hipError_t launch_norm2(const void* x, int64_t n, int dtype, double* out, double* scratch,
+                        hipStream_t s) {
+  if (dtype == RN_C128)
+    norm2_partial<double2><<<kRedBlocks, 256, 0, s>>>(reinterpret_cast<const double2*>(x), n,
+                                                     scratch);
+  else
+    norm2_partial<float2><<<kRedBlocks, 256, 0, s>>>(reinterpret_cast<const float2*>(x), n,
+                                                    scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  sum_partials<<<1, 256, 0, s>>>(scratch, kRedBlocks, out);
+  return hipGetLastError();
+}
+
+// Complex sum of n values in FP64 by one workgroup: lane t accumulates
+// values t, t + 256, ... in ascending order, then the fixed tree.
+template <typename T>
+__global__ __launch_bounds__(256) void csum_kernel(const T* v, int64_t n, double* out,
+                                                   double* each) {
+  __shared__ double sh[4];
+  double re = 0.0, im = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    double r = (double)v[i].x, m = (double)v[i].y;
+    re += r;
+    im += m;
+    if (each) {
+      each[2 * i] = r;
+      each[2 * i + 1] = m;
+    }
+  }
+  re = block_sum(re, sh);
+  __syncthreads();
+  im = block_sum(im, sh);
+  if (threadIdx.x == 0) {
+    out[0] = re;
+    out[1] = im;
+  }
+}
+
+hipError_t launch_sum_c128(const double* vals, int64_t n, double* out, hipStream_t s) {
+  csum_kernel<double2><<<1, 256, 0, s>>>(reinterpret_cast<const double2*>(vals), n, out,
+                                         nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_slices(const void* vals, int es, int64_t n, double* out_sum,
+                             double* out_each, hipStream_t s) {
+  if (es == 16)
+    csum_kernel<double2><<<1, 256, 0, s>>>(reinterpret_cast<const double2*>(vals), n, out_sum,
+                                           out_each);
+  else
+    csum_kernel<float2><<<1, 256, 0, s>>>(reinterpret_cast<const float2*>(vals), n, out_sum,
+                                          out_each);
+  return hipGetLastError();
+}
+
+}  // namespace rn

@@ -1,0 +1,416 @@
+// Sliced tensor-network contraction on one GPU (Sections II.A and II.B).
+//
+// Every slice of a sliced network has the same shapes, so the slices run as
+// one batch through every step of the path: each step is one batched
+// block tensordot (permute A, permute B, batched complex GEMM).  A tensor
+// carries a batch dimension only over the sliced labels it depends on, so a
+// sub-network that touches no sliced bond is contracted once and broadcast
+// (batch stride 0) into the steps that use it.  Slice projection is fused
+// into the permute: a sliced axis of an input tensor becomes a batch bit.
+// The per-slice scalars are summed in FP64 on the GPU at the end.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "rn_internal.hpp"
+
+namespace rn {
+
+namespace {
+
+struct Arena {
+  std::vector<std::pair<int64_t, int64_t>> free_list;  // (offset, size), sorted
+  int64_t top = 0;
+  int64_t peak = 0;
+  int64_t alloc(int64_t size) {
+    size = (size + 255) & ~int64_t(255);
+    for (size_t i = 0; i < free_list.size(); ++i) {
+      if (free_list[i].second >= size) {
+        int64_t off = free_list[i].first;
+        free_list[i].first += size;
+        free_list[i].second -= size;
+        if (free_list[i].second == 0) free_list.erase(free_list.begin() + i);
+        return off;
+      }
+    }
+    int64_t off = top;
+    top += size;
+    peak = std::max(peak, top);
+    return off;
+  }
+  void release(int64_t off, int64_t size) {
+    size = (size + 255) & ~int64_t(255);
+    free_list.push_back({off, size});
+    std::sort(free_list.begin(), free_list.end());
+    std::vector<std::pair<int64_t, int64_t>> merged;
+    for (auto& f : free_list) {
+      if (!merged.empty() && merged.back().first + merged.back().second == f.first)
+        merged.back().second += f.second;
+      else
+        merged.push_back(f);
+    }
+    if (!merged.empty() && merged.back().first + merged.back().second == top) {
+      top = merged.back().first;
+      merged.pop_back();
+    }
+    free_list = merged;
+  }
+};
+
+struct NTensor {
+  std::vector<int> labels;     // stored axis labels, outermost first (sliced excluded
+                               // for intermediates; raw for inputs)
+  uint32_t dmask = 0;          // slice indices this tensor depends on
+  bool input = false;
+  int input_idx = -1;
+  int64_t off = -1;            // workspace offset (intermediates)
+  int64_t bytes = 0;
+};
+
+struct NStep {
+  int a = 0, b = 0;
+  int64_t M = 1, N = 1, K = 1;
+  BitPerm permA, permB;
+  bool permuteA = false, permuteB = false;
+  int64_t offA = -1, offA2 = -1, offB = -1, offB2 = -1, offPart = -1;
+  int nbb = 0;
+  int64_t a_bs[RN_MAX_SLICED] = {0}, b_bs[RN_MAX_SLICED] = {0}, c_bs[RN_MAX_SLICED] = {0};
+  int splitk = 1;
+};
+
+struct NetPlan {
+  rn_mode mode;
+  int es;
+  int nsliced;
+  std::vector<NTensor> T;
+  std::vector<NStep> steps;
+  int64_t ws_bytes = 0;
+  double flops = 0;
+  int max_rank = 0;
+};
+
+int popc(uint32_t x) { return __builtin_popcount(x); }
+
+// Sorted slice indices of a mask; the highest index is the batch LSB.
+std::vector<int> mask_list(uint32_t m) {
+  std::vector<int> v;
+  for (int i = 0; i < 32; ++i)
+    if ((m >> i) & 1) v.push_back(i);
+  return v;
+}
+
+// Physical bit position of `label` (or of slice index `sidx`) in a stored
+// tensor.  Inputs: raw labels, axis j at bit rank-1-j.  Intermediates:
+// [batch bits | labels], label j at bit r-1-j, batch of slice index i at
+// r + (number of indices in dmask greater than i).
+int pos_of_label(const NTensor& t, int label) {
+  int r = (int)t.labels.size();
+  for (int j = 0; j < r; ++j)
+    if (t.labels[j] == label) return r - 1 - j;
+  return -1;
+}
+
+int pos_of_slice(const NTensor& t, int sidx, const std::vector<int>& sliced) {
+  if (t.input) return pos_of_label(t, sliced[sidx]);
+  int r = (int)t.labels.size();
+  int above = 0;
+  for (int i = sidx + 1; i < 32; ++i) above += (t.dmask >> i) & 1;
+  return r + above;
+}
+
+rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                       int32_t nsteps, const int32_t* path, int32_t nsliced,
+                       const int32_t* sliced, rn_mode mode, NetPlan* NP) {
+  if (nt < 1 || !T || !labels) return fail(RN_ERR_INVALID, "empty network");
+  if (nsteps != nt - 1 || (nsteps > 0 && !path))
+    return fail(RN_ERR_INVALID, "path must have nt-1 steps");
+  if (nsliced < 0 || nsliced > RN_MAX_SLICED || (nsliced > 0 && !sliced))
+    return fail(RN_ERR_INVALID, "bad sliced labels");
+  if (mode != RN_FP64 && mode != RN_FP32_4M && mode != RN_BF16X3)
+    return fail(RN_ERR_UNSUPPORTED, "network mode must be RN_FP64, RN_FP32_4M or RN_BF16X3");
+  const int want = mode == RN_FP64 ? RN_C128 : RN_C64;
+  NetPlan P;
+  P.mode = mode;
+  P.es = mode == RN_FP64 ? 16 : 8;
+  P.nsliced = nsliced;
+  std::vector<int> sl(sliced, sliced + nsliced);
+  std::map<int, int> count, slice_index;
+  for (int i = 0; i < nsliced; ++i) {
+    if (slice_index.count(sl[i])) return fail(RN_ERR_INVALID, "repeated sliced label");
+    slice_index[sl[i]] = i;
+  }
+  for (int i = 0; i < nt; ++i) {
+    const rn_tensor& t = T[i];
+    if (t.rank < 0 || t.rank > 40) return fail(RN_ERR_INVALID, "tensor rank out of range");
+    if (t.dtype != want) return fail(RN_ERR_INVALID, "tensor dtype does not match the mode");
+    if (!t.data) return fail(RN_ERR_INVALID, "null tensor data");
+    if (t.rank > 0 && !labels[i]) return fail(RN_ERR_INVALID, "null labels");
+    NTensor nt_;
+    nt_.input = true;
+    nt_.input_idx = i;
+    for (int j = 0; j < t.rank; ++j) {
+      if (t.dims[j] != 2) return fail(RN_ERR_UNSUPPORTED, "network tensors need dims of 2");
+      if (t.grid[j] != 1) return fail(RN_ERR_UNSUPPORTED, "network tensors must be unblocked");
+      int l = labels[i][j];
+      for (int q = 0; q < j; ++q)
+        if (labels[i][q] == l) return fail(RN_ERR_INVALID, "label repeated within a tensor");
+      nt_.labels.push_back(l);
+      count[l]++;
+      auto it = slice_index.find(l);
+      if (it != slice_index.end()) nt_.dmask |= 1u << it->second;
+    }
+    P.T.push_back(nt_);
+  }
+  for (auto& kv : count)
+    if (kv.second != 2)
+      return fail(RN_ERR_INVALID, "label " + std::to_string(kv.first) +
+                                      " is not a bond between two tensors");
+  for (int i = 0; i < nsliced; ++i)
+    if (!count.count(sl[i])) return fail(RN_ERR_INVALID, "sliced label is not a bond");
+
+  std::vector<bool> alive(nt + nsteps, false);
+  for (int i = 0; i < nt; ++i) alive[i] = true;
+  Arena arena;
+  auto eff = [&](const NTensor& t) {
+    std::vector<int> v;
+    for (int l : t.labels)
+      if (!slice_index.count(l)) v.push_back(l);
+    return v;
+  };
+  for (int i = 0; i < nt; ++i) P.max_rank = std::max(P.max_rank, (int)eff(P.T[i]).size());
+  const bool split_prec = (mode == RN_BF16X3);
+  for (int s = 0; s < nsteps; ++s) {
+    int a = path[2 * s], b = path[2 * s + 1];
+    if (a < 0 || b < 0 || a >= nt + s || b >= nt + s || a == b || !alive[a] || !alive[b])
+      return fail(RN_ERR_INVALID, "path step " + std::to_string(s) + " uses a dead tensor");
+    alive[a] = alive[b] = false;
+    const NTensor& ta = P.T[a];
+    const NTensor& tb = P.T[b];
+    std::vector<int> la = eff(ta), lb = eff(tb);
+    // Contracted labels in the order of the larger operand.
+    std::vector<int> shared;
+    const std::vector<int>& ord = (lb.size() > la.size()) ? lb : la;
+    const std::vector<int>& oth = (lb.size() > la.size()) ? la : lb;
+    for (int l : ord)
+      if (std::find(oth.begin(), oth.end(), l) != oth.end()) shared.push_back(l);
+    std::vector<int> fa, fb;
+    for (int l : la)
+      if (std::find(shared.begin(), shared.end(), l) == shared.end()) fa.push_back(l);
+    for (int l : lb)
+      if (std::find(shared.begin(), shared.end(), l) == shared.end()) fb.push_back(l);
+    NStep st;
+    st.a = a;
+    st.b = b;
+    int kb = (int)shared.size(), mb = (int)fa.size(), nbits = (int)fb.size();
+    if (mb + nbits > 34) return fail(RN_ERR_UNSUPPORTED, "intermediate over 2^34 elements");
+    st.M = int64_t(1) << mb;
+    st.N = int64_t(1) << nbits;
+    st.K = int64_t(1) << kb;
+    uint32_t dc = ta.dmask | tb.dmask;
+    std::vector<int> dcl = mask_list(dc);
+    st.nbb = (int)dcl.size();
+    // Operand permutations: [batch over own dmask | free | contracted].
+    auto build = [&](const NTensor& t, const std::vector<int>& fr, BitPerm& bp) {
+      bp.nbits = 0;
+      for (int q = kb - 1; q >= 0; --q) bp.src[bp.nbits++] = (int8_t)pos_of_label(t, shared[q]);
+      for (int q = (int)fr.size() - 1; q >= 0; --q)
+        bp.src[bp.nbits++] = (int8_t)pos_of_label(t, fr[q]);
+      std::vector<int> dl = mask_list(t.dmask);
+      for (int q = (int)dl.size() - 1; q >= 0; --q)
+        bp.src[bp.nbits++] = (int8_t)pos_of_slice(t, dl[q], sl);
+    };
+    build(ta, fa, st.permA);
+    build(tb, fb, st.permB);
+    st.permuteA = split_prec || !st.permA.identity();
+    st.permuteB = split_prec || !st.permB.identity();
+    // Batch strides.  Bit q of the GEMM batch index is slice index
+    // dcl[nbb-1-q]; an operand not depending on it has stride 0.
+    for (int q = 0; q < st.nbb; ++q) {
+      int sidx = dcl[st.nbb - 1 - q];
+      auto stride = [&](const NTensor& t, int64_t body) -> int64_t {
+        if (!((t.dmask >> sidx) & 1)) return 0;
+        int above = 0;
+        for (int i = sidx + 1; i < 32; ++i) above += (t.dmask >> i) & 1;
+        return (int64_t(1) << above) * body;
+      };
+      st.a_bs[q] = stride(ta, st.M * st.K);
+      st.b_bs[q] = stride(tb, st.N * st.K);
+      st.c_bs[q] = (int64_t(1) << q) * st.M * st.N;
+    }
+    int64_t nbatch = int64_t(1) << st.nbb;
+    int64_t abytes = (st.M * st.K << popc(ta.dmask)) * (split_prec ? 4 : P.es);
+    int64_t bbytes = (st.N * st.K << popc(tb.dmask)) * (split_prec ? 4 : P.es);
+    if (st.permuteA) {
+      st.offA = arena.alloc(abytes);
+      if (split_prec) st.offA2 = arena.alloc(abytes);
+    }
+    if (st.permuteB) {
+      st.offB = arena.alloc(bbytes);
+      if (split_prec) st.offB2 = arena.alloc(bbytes);
+    }
+    st.splitk = choose_splitk(mode, st.M, st.N, st.K, nbatch);
+    int64_t pbytes = int64_t(st.splitk) * nbatch * st.M * st.N * P.es;
+    if (st.splitk > 1) st.offPart = arena.alloc(pbytes);
+    NTensor tc;
+    for (int l : fa) tc.labels.push_back(l);
+    for (int l : fb) tc.labels.push_back(l);
+    tc.dmask = dc;
+    tc.bytes = nbatch * st.M * st.N * P.es;
+    tc.off = arena.alloc(tc.bytes);
+    P.max_rank = std::max(P.max_rank, mb + nbits);
+    P.flops += 8.0 * double(st.M) * double(st.N) * double(st.K) * double(nbatch);
+    // Temporaries die with the step; operands that are intermediates die too.
+    if (st.permuteA) {
+      arena.release(st.offA, abytes);
+      if (split_prec) arena.release(st.offA2, abytes);
+    }
+    if (st.permuteB) {
+      arena.release(st.offB, bbytes);
+      if (split_prec) arena.release(st.offB2, bbytes);
+    }
+    if (st.splitk > 1) arena.release(st.offPart, pbytes);
+    if (!ta.input) arena.release(ta.off, ta.bytes);
+    if (!tb.input) arena.release(tb.off, tb.bytes);
+    P.T.push_back(tc);
+    P.steps.push_back(st);
+    alive[nt + s] = true;
+  }
+  const NTensor& fin = P.T.back();
+  if (!eff(fin).empty()) return fail(RN_ERR_INVALID, "network does not close to a scalar");
+  P.ws_bytes = arena.peak;
+  *NP = std::move(P);
+  return RN_OK;
+}
+
+}  // namespace
+
+static rn_status enqueue_network(const NetPlan& P, const rn_tensor* T, void* ws, hipStream_t s,
+                                 double* amp_dev, double* slices_dev, Profiler* prof) {
+  char* w = static_cast<char*>(ws);
+  const bool split_prec = (P.mode == RN_BF16X3);
+  auto ptr = [&](int id) -> const void* {
+    const NTensor& t = P.T[id];
+    return t.input ? T[t.input_idx].data : static_cast<const void*>(w + t.off);
+  };
+  hipError_t e;
+  const int nt = (int)P.T.size() - (int)P.steps.size();
+  for (size_t si = 0; si < P.steps.size(); ++si) {
+    const NStep& st = P.steps[si];
+    const void* am = ptr(st.a);
+    const void* bm = ptr(st.b);
+    const void* am2 = nullptr;
+    const void* bm2 = nullptr;
+    if (st.permuteA) {
+      PermLaunch L;
+      L.in = am;
+      L.out = w + st.offA;
+      L.out2 = split_prec ? w + st.offA2 : nullptr;
+      L.perm = st.permA;
+      L.in_es = P.es;
+      L.kind = split_prec ? 1 : 0;
+      int ev = prof->begin(0, s);
+      e = launch_permute(L, s);
+      prof->end(ev, s);
+      if (e != hipSuccess)
+        return fail(RN_ERR_HIP, std::string("network permute: ") + hipGetErrorString(e));
+      am = L.out;
+      am2 = L.out2;
+    }
+    if (st.permuteB) {
+      PermLaunch L;
+      L.in = bm;
+      L.out = w + st.offB;
+      L.out2 = split_prec ? w + st.offB2 : nullptr;
+      L.perm = st.permB;
+      L.in_es = P.es;
+      L.kind = split_prec ? 1 : 0;
+      int ev = prof->begin(0, s);
+      e = launch_permute(L, s);
+      prof->end(ev, s);
+      if (e != hipSuccess)
+        return fail(RN_ERR_HIP, std::string("network permute: ") + hipGetErrorString(e));
+      bm = L.out;
+      bm2 = L.out2;
+    }
+    GemmLaunch g;
+    g.mode = P.mode;
+    g.A = am;
+    g.B = bm;
+    g.A2 = am2;
+    g.B2 = bm2;
+    g.C = w + P.T[nt + si].off;
+    g.M = st.M;
+    g.N = st.N;
+    g.K = st.K;
+    g.lda = st.K;
+    g.ldb = st.K;
+    g.crow.shift = 62;
+    g.crow.hi = 0;
+    g.crow.lo = st.N;
+    g.ccol.shift = 62;
+    g.ccol.hi = 0;
+    g.ccol.lo = 1;
+    g.nbb = st.nbb;
+    for (int q = 0; q < st.nbb; ++q) {
+      g.a_bstride[q] = st.a_bs[q];
+      g.b_bstride[q] = st.b_bs[q];
+      g.c_bstride[q] = st.c_bs[q];
+    }
+    g.splitk = st.splitk;
+    g.partial = st.splitk > 1 ? w + st.offPart : nullptr;
+    if ((e = launch_gemm(g, s, prof)) != hipSuccess)
+      return fail(RN_ERR_HIP, std::string("network GEMM: ") + hipGetErrorString(e));
+  }
+  const NTensor& fin = P.T.back();
+  int64_t nvals = int64_t(1) << popc(fin.dmask);
+  int ev = prof->begin(3, s);
+  e = launch_sum_slices(ptr((int)P.T.size() - 1), P.es, nvals, amp_dev, slices_dev, s);
+  prof->end(ev, s);
+  if (e != hipSuccess) return fail(RN_ERR_HIP, std::string("slice sum: ") + hipGetErrorString(e));
+  return RN_OK;
+}
+
+}  // namespace rn
+
+using namespace rn;
+
+extern "C" {
+
+rn_status rn_contract_network_plan(rn_handle h, int32_t nt, const rn_tensor* T,
+                                   const int32_t* const* labels, int32_t nsteps,
+                                   const int32_t* path, int32_t nsliced, const int32_t* sliced,
+                                   rn_mode mode, size_t* ws_bytes, double* flops,
+                                   int32_t* max_rank) {
+  (void)h;
+  NetPlan P;
+  rn_status st = plan_network(nt, T, labels, nsteps, path, nsliced, sliced, mode, &P);
+  if (st != RN_OK) return st;
+  if (ws_bytes) *ws_bytes = (size_t)P.ws_bytes;
+  if (flops) *flops = P.flops;
+  if (max_rank) *max_rank = P.max_rank;
+  return RN_OK;
+}
+
+rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
+                              const int32_t* const* labels, int32_t nsteps, const int32_t* path,
+                              int32_t nsliced, const int32_t* sliced, rn_mode mode, void* ws,
+                              size_t ws_bytes, void* stream, double* amp_dev,
+                              double* slices_dev) {
+  if (!h) return fail(RN_ERR_INVALID, "null handle");
+  if (!amp_dev) return fail(RN_ERR_INVALID, "null amplitude buffer");
+  NetPlan P;
+  rn_status st = plan_network(nt, T, labels, nsteps, path, nsliced, sliced, mode, &P);
+  if (st != RN_OK) return st;
+  if ((int64_t)ws_bytes < P.ws_bytes || (P.ws_bytes > 0 && !ws))
+    return fail(RN_ERR_WORKSPACE, "workspace smaller than planned (" +
+                                      std::to_string(P.ws_bytes) + " bytes needed)");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return fail(RN_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  return enqueue_network(P, T, ws, static_cast<hipStream_t>(stream), amp_dev, slices_dev,
+                         &h->prof);
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal declarations of the block tensordot library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rn.h"
+
+namespace rn {
+
+// Thread-local error message behind rn_last_error().
+void set_error(const std::string& msg);
+rn_status fail(rn_status s, const std::string& msg);
+
+// ---------------------------------------------------------------------------
+// Bit-level view of tensors.  Every dim is 2^a, every grid count 2^c, so a
+// tensor of R = sum(a_j) index bits is a 2^R array and every relayout is a
+// permutation of the R bits of the linear element index.  Logical bit
+// (axis j, t) is bit t of coordinate x_j; its physical position in the
+// block-major buffer is given by phys_pos().
+// ---------------------------------------------------------------------------
+struct Layout {
+  int rank = 0;
+  int abits[RN_MAX_RANK] = {0};  // log2 dims
+  int cbits[RN_MAX_RANK] = {0};  // log2 grid
+  int total = 0;                 // sum of abits
+  int phys_pos(int axis, int t) const;
+};
+
+rn_status make_layout(const rn_tensor* T, const char* name, Layout* L);
+
+// A bit permutation: output bit o (LSB = 0) reads input bit src[o].
+// Input bits not listed are fixed by `in_base` (slice projections).
+struct BitPerm {
+  int nbits = 0;
+  int8_t src[64] = {0};
+  bool identity() const;
+};
+
+// Two-level index map for one GEMM dimension:
+//   off(x) = (x >> shift) * hi + (x & ((1 << shift) - 1)) * lo   (elements).
+struct Map2 {
+  int shift = 62;
+  int64_t hi = 0;
+  int64_t lo = 1;
+};
+
+// Plan of one block tensordot (a GEMM C[M x N] = A[M x K] * B[N x K]^T).
+struct TdPlan {
+  rn_mode mode = RN_FP64;
+  int es = 16;                      // bytes per complex element of A, B and C
+  int mbits = 0, nbits = 0, kbits = 0;
+  int64_t M = 1, N = 1, K = 1;
+  int Mb = 0, Mi = 0, Nb = 0, Ni = 0;  // block / inner bit counts of C's layout
+  int pairbits = 0;                     // contracted block bits on the refined grid
+  BitPerm permA, permB;                 // storage -> GEMM layout
+  bool permuteA = false, permuteB = false;
+  Map2 crow, ccol;                      // GEMM (row, col) -> C offset
+  // Derived C descriptor.
+  int crank = 0;
+  int64_t cdims[RN_MAX_RANK];
+  int32_t cgrid[RN_MAX_RANK];
+  // Refined-grid bookkeeping for pair lists.
+  int k = 0;
+  int32_t axA[RN_MAX_RANK], axB[RN_MAX_RANK];
+  int pair_cbits[RN_MAX_RANK];  // refined contracted grid bits, pair order
+  // Workspace sub-buffers (byte offsets; -1 when unused).
+  int64_t off_a = -1, off_b = -1, off_a2 = -1, off_b2 = -1, off_part = -1;
+  int splitk = 1;
+  size_t ws_bytes = 0;
+  double flops = 0;
+};
+
+rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
+                         const int32_t* axesA, const int32_t* axesB, rn_mode mode,
+                         TdPlan* P);
+rn_status check_c(const TdPlan& P, const rn_tensor* C);
+
+// Optional per-launch event timing (rn_profile_enable).
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  // Record the start event of a launch of class `cls`; returns its index or -1.
+  int begin(int cls, hipStream_t s);
+  void end(int idx, hipStream_t s);
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels.hip).
+// ---------------------------------------------------------------------------
+struct PermLaunch {
+  const void* in = nullptr;
+  void* out = nullptr;
+  void* out2 = nullptr;      // lo part for the bfloat16 split
+  int64_t in_base = 0;       // element offset added to every input index
+  BitPerm perm;              // output bit -> input bit
+  int in_es = 8;             // input element bytes (8 or 16)
+  int kind = 0;              // 0 copy, 1 split complex64 -> bf16 hi/lo
+};
+hipError_t launch_permute(const PermLaunch& p, hipStream_t s);
+
+// Batched GEMM over slices: batch index b has `nbb` bits; operand X is
+// offset by sum over set bits i of b of X_bstride[i] elements.
+struct GemmLaunch {
+  rn_mode mode = RN_FP64;
+  const void* A = nullptr;   // M x K, row stride lda (complex elements)
+  const void* B = nullptr;   // N x K, row stride ldb
+  const void* A2 = nullptr;  // bf16 lo parts (RN_BF16X3)
+  const void* B2 = nullptr;
+  void* C = nullptr;
+  int64_t M = 0, N = 0, K = 0, lda = 0, ldb = 0;
+  Map2 crow, ccol;
+  int nbb = 0;
+  int64_t a_bstride[RN_MAX_SLICED] = {0}, b_bstride[RN_MAX_SLICED] = {0},
+          c_bstride[RN_MAX_SLICED] = {0};
+  int splitk = 1;
+  void* partial = nullptr;   // splitk > 1: [splitk][batch][M][N] complex, fp32/fp64
+  int tile = -1;             // tile config index, -1 = choose
+};
+hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof = nullptr);
+int choose_splitk(rn_mode mode, int64_t M, int64_t N, int64_t K, int64_t batch);
+
+rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor* B,
+                            const rn_tensor* C, void* ws, hipStream_t s, Profiler* prof);
+
+hipError_t launch_norm2(const void* x, int64_t n, int dtype, double* out, double* scratch,
+                        hipStream_t s);
+hipError_t launch_sum_c128(const double* vals, int64_t n, double* out, hipStream_t s);
+hipError_t launch_sum_slices(const void* vals, int es, int64_t n, double* out_sum,
+                             double* out_each, hipStream_t s);
+
+}  // namespace rn
+
+// Opaque handle.
+struct rn_ctx {
+  int device = 0;
+  void* red_scratch = nullptr;  // 4096 doubles of device memory for reductions
+  rn::Profiler prof;
+};

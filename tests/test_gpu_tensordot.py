@@ -1,0 +1,174 @@
+"""GPU parity: block tensordot through the C ABI against the CPU oracle.
+
+Tolerances (relative Frobenius error e_F over the compared entries): 1e-12
+for FP64, 1e-5 for FP32, 1e-3 for split BF16.  The FP32 and BF16 modes take
+the complex128 inputs rounded once to complex64 and are compared with the
+oracle on the original complex128 inputs.  Gaussian-integer inputs make
+every mode exact, so those cases compare bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import configs, rng
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32_4m": 1e-5, "bf16x3": 1e-3}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2201_06620_amd as rn
+    assert torch.cuda.is_available()
+    return rn.Context(0)
+
+
+def dev(x, mode):
+    import torch
+    dt = torch.complex128 if mode == "fp64" else torch.complex64
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dt).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def e_f(x, ref):
+    return np.linalg.norm(x - ref) / max(np.linalg.norm(ref), 1e-300)
+
+
+def run_problem(ctx, p, mode):
+    import torch
+    a, b = dev(p.a.data, mode), dev(p.b.data, mode)
+    c, cd, cg = ctx.block_tensordot(a, p.a.dims, p.a.grid, b, p.b.dims, p.b.grid,
+                                    p.axes_a, p.axes_b, mode)
+    torch.cuda.synchronize()
+    return host(c), cd, cg
+
+
+def oracle_problem(p):
+    return oracle.block_tensordot(p.a.data, p.a.dims, p.a.grid, p.b.data, p.b.dims, p.b.grid,
+                                  p.axes_a, p.axes_b)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "bf16x3"])
+def test_config1(ctx, mode):
+    log(f"config1 mode={mode}")
+    p = configs.config1()
+    c, cd, cg = run_problem(ctx, p, mode)
+    ref, rd, rg = oracle_problem(p)
+    assert cd == rd and cg == rg
+    err = e_f(c, ref)
+    log(f"  e_F={err:.3e}")
+    assert err < TOL[mode]
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "bf16x3"])
+def test_config1_integers_bitwise(ctx, mode):
+    log(f"config1 integers mode={mode}")
+    p = configs.config1(integer=True)
+    c, _, _ = run_problem(ctx, p, mode)
+    ref, _, _ = oracle_problem(p)
+    assert np.array_equal(c, ref)
+
+
+def random_problem(seed, ra, rb, k, blocked=True, integer=False):
+    r = rng.SplitMix64(seed)
+    axa, axb = r.sample(ra, k), r.sample(rb, k)
+    ga = [2 if (blocked and r.below(3) == 0) else 1 for _ in range(ra)]
+    gb = [2 if (blocked and r.below(3) == 0) else 1 for _ in range(rb)]
+    return configs.make_problem(ra, rb, axa, axb, ga, gb, seed, integer)
+
+
+# Shapes that span several tiles and leave ragged edges, small and
+# degenerate cases: k = 0 (outer product), full contraction (scalar), M or
+# N of 1, K of 1.
+SHAPES = [(12, 12, 5), (13, 11, 6), (14, 13, 7), (10, 9, 0), (7, 7, 7), (9, 4, 4),
+          (4, 9, 4), (1, 12, 1), (12, 1, 1), (16, 10, 3), (11, 15, 9), (15, 15, 2)]
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "bf16x3"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_random_shapes(ctx, mode, shape):
+    ra, rb, k = shape
+    seed = 7000 + 97 * ra + 13 * rb + k
+    log(f"random shape={shape} mode={mode} seed={seed}")
+    p = random_problem(seed, ra, rb, k)
+    c, cd, cg = run_problem(ctx, p, mode)
+    ref, rd, rg = oracle_problem(p)
+    assert cd == rd and cg == rg
+    assert e_f(c, ref) < TOL[mode]
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "bf16x3"])
+@pytest.mark.parametrize("shape", [(12, 12, 5), (10, 9, 0), (7, 7, 7), (16, 10, 3)])
+def test_random_shapes_integers_bitwise(ctx, mode, shape):
+    ra, rb, k = shape
+    p = random_problem(9100 + ra * 31 + rb + k, ra, rb, k, integer=True)
+    log(f"integer shape={shape} mode={mode}")
+    c, _, _ = run_problem(ctx, p, mode)
+    ref, _, _ = oracle_problem(p)
+    assert np.array_equal(c, ref)
+
+
+def test_rank0_operand(ctx):
+    # A scalar times a tensor (rank-0 A, k = 0).
+    import torch
+    a = np.array([1.5 - 0.5j])
+    b = rng.complex_normal(5, 2 ** 6)
+    c, cd, cg = ctx.block_tensordot(dev(a, "fp64"), [], [], dev(b, "fp64"), [2] * 6, [2] * 6,
+                                    [], [], "fp64")
+    torch.cuda.synchronize()
+    assert cd == [2] * 6 and cg == [2] * 6
+    assert np.allclose(host(c), a[0] * b, rtol=1e-15, atol=0)
+
+
+def test_block_layout_permute_exact(ctx):
+    # Contracting with identity matrices only moves data: the permute and the
+    # GEMM must then reproduce the relabelled input bit for bit in FP64.
+    import torch
+    A = rng.complex_normal(33, 2 ** 10).reshape((2,) * 10)
+    eye = np.eye(4, dtype=np.complex128).reshape(2, 2, 2, 2)
+    ga = [2, 1, 2, 1, 1, 2, 1, 1, 2, 1]
+    ab = oracle.to_blocked(A, ga)
+    c, cd, cg = ctx.block_tensordot(dev(ab, "fp64"), [2] * 10, ga, dev(eye, "fp64"), [2] * 4,
+                                    [1] * 4, [3, 7], [2, 3], "fp64")
+    torch.cuda.synchronize()
+    ref, rd, rg = oracle.block_tensordot(ab, [2] * 10, ga, eye.reshape(-1), [2] * 4, [1] * 4,
+                                         [3, 7], [2, 3])
+    assert np.array_equal(host(c), ref)
+
+
+def test_workspace_error_leaves_output(ctx):
+    import torch
+    import paper_2201_06620_amd as rn
+    p = configs.config1()
+    a, b = dev(p.a.data, "fp64"), dev(p.b.data, "fp64")
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(rn.RnError) as e:
+        ctx.block_tensordot(a, p.a.dims, p.a.grid, b, p.b.dims, p.b.grid, p.axes_a, p.axes_b,
+                            "fp64", workspace=small)
+    assert e.value.status == 4
+
+
+def test_norm2_and_sum(ctx):
+    import torch
+    x = rng.complex_normal(44, 2 ** 18)
+    for mode in ("fp64", "fp32_4m"):
+        t = dev(x, mode)
+        got = ctx.norm2(t).item()
+        ref = oracle.norm2(host(t))
+        assert abs(got - ref) <= 1e-12 * ref
+    v = rng.complex_normal(45, 1000)
+    s = ctx.sum_c128(dev(v, "fp64")).cpu().numpy()
+    ref = np.sum(v)
+    assert abs(complex(s[0], s[1]) - ref) < 1e-12 * abs(ref) + 1e-13
