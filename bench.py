@@ -80,6 +80,8 @@ def main() -> int:
     ap.add_argument("--amp-requests", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one plain 1 GiB copy kernel first (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -152,6 +154,14 @@ def main() -> int:
         del a, b, c, wsb
         torch.cuda.empty_cache()
         return out, got
+
+    if args.copy_calib:
+        x = torch.ones(2 ** 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written by one elementwise kernel")
+        del x, y
 
     log("FP32-4M timed run")
     main_res, got32 = run_mode("fp32_4m", args.steps, args.warmup, True)

@@ -43,8 +43,12 @@ struct PermParams {
   int8_t ls_in[16];   // load order q -> input bit
   int8_t ss_out[16];  // store order q -> output bit
   int8_t ss_lds[16];  // store order q -> load-order position
-  int8_t os_in[64];   // outer bit q -> input bit
-  int8_t os_out[64];  // outer bit q -> output bit
+  int8_t os_in[48];   // outer bit q -> input bit
+  int8_t os_out[48];  // outer bit q -> output bit
+  // Offsets of element j * 256 of a tile (bits >= 8 of the tile index).
+  int64_t hi_in[16];
+  int64_t hi_out[16];
+  int32_t hi_lds[16];
 };
 
 __device__ __forceinline__ int lds_pad(int x) { return x + (x >> 5); }
@@ -65,7 +69,10 @@ __device__ __forceinline__ void bf16_split(float x, uint32_t& hi, uint32_t& lo) 
   lo = bf16_rne(r);
 }
 
-template <typename T, int KIND>
+// E elements per thread per tile (tile = 256 * E elements, or fewer for a
+// tile smaller than one workgroup).  All E loads of a tile are issued before
+// any is consumed, so each thread keeps E global reads in flight.
+template <typename T, int KIND, int E>
 __global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
@@ -73,9 +80,7 @@ __global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
   const int tid = threadIdx.x;
   const int tsize = 1 << p.nS;
   const int lo_bits = p.nS < 8 ? p.nS : 8;
-  // Thread-fixed low parts of the tile-local index u = tid + 256 * j.
-  int64_t in_lo = 0;
-  int64_t out_lo = 0;
+  int64_t in_lo = 0, out_lo = 0;
   int lds_lo = 0;
   for (int q = 0; q < lo_bits; ++q) {
     if ((tid >> q) & 1) {
@@ -93,32 +98,26 @@ __global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
         ob += int64_t(1) << p.os_out[q];
       }
     }
+    T v[E];
     if (active) {
-      for (int j = 0; (j << 8) < tsize; ++j) {
-        int64_t io = ib + in_lo;
-        for (int q = 8; q < p.nS; ++q)
-          if ((j >> (q - 8)) & 1) io += int64_t(1) << p.ls_in[q];
-        tile[lds_pad(tid + (j << 8))] = in[io];
-      }
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = in[ib + in_lo + p.hi_in[j]];
+#pragma unroll
+      for (int j = 0; j < E; ++j) tile[lds_pad(tid + (j << 8))] = v[j];
     }
     __syncthreads();
     if (active) {
-      for (int j = 0; (j << 8) < tsize; ++j) {
-        int64_t oo = ob + out_lo;
-        int li = lds_lo;
-        for (int q = 8; q < p.nS; ++q) {
-          if ((j >> (q - 8)) & 1) {
-            oo += int64_t(1) << p.ss_out[q];
-            li += 1 << p.ss_lds[q];
-          }
-        }
-        T v = tile[lds_pad(li)];
+#pragma unroll
+      for (int j = 0; j < E; ++j) v[j] = tile[lds_pad(lds_lo + p.hi_lds[j])];
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int64_t oo = ob + out_lo + p.hi_out[j];
         if constexpr (KIND == 0) {
-          reinterpret_cast<T*>(p.out)[oo] = v;
+          reinterpret_cast<T*>(p.out)[oo] = v[j];
         } else {
           uint32_t hr, lr, hi_, li_;
-          bf16_split(v.x, hr, lr);
-          bf16_split(v.y, hi_, li_);
+          bf16_split(v[j].x, hr, lr);
+          bf16_split(v[j].y, hi_, li_);
           reinterpret_cast<uint32_t*>(p.out)[oo] = hr | (hi_ << 16);
           reinterpret_cast<uint32_t*>(p.out2)[oo] = lr | (li_ << 16);
         }
@@ -128,8 +127,20 @@ __global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
   }
 }
 
+template <typename T, int KIND>
+static void launch_perm_e(const PermParams& p, int e, unsigned grid, size_t lds, hipStream_t s) {
+  switch (e) {
+    case 1: permute_kernel<T, KIND, 1><<<grid, 256, lds, s>>>(p); break;
+    case 2: permute_kernel<T, KIND, 2><<<grid, 256, lds, s>>>(p); break;
+    case 4: permute_kernel<T, KIND, 4><<<grid, 256, lds, s>>>(p); break;
+    case 8: permute_kernel<T, KIND, 8><<<grid, 256, lds, s>>>(p); break;
+    default: permute_kernel<T, KIND, 16><<<grid, 256, lds, s>>>(p); break;
+  }
+}
+
 hipError_t launch_permute(const PermLaunch& L, hipStream_t s) {
   const int R = L.perm.nbits;
+  if (R > 48) return hipErrorInvalidValue;
   PermParams p{};
   p.in = L.in;
   p.out = L.out;
@@ -170,15 +181,29 @@ hipError_t launch_permute(const PermLaunch& L, hipStream_t s) {
   p.nO = nO;
   p.ntiles = int64_t(1) << nO;
   const int tsize = 1 << nS;
-  size_t lds = size_t(tsize + (tsize >> 5) + 1) * L.in_es;
-  int64_t grid = std::min<int64_t>(p.ntiles, 256 * 8);
-  if (L.kind == 1) {
-    permute_kernel<float2, 1><<<dim3((unsigned)grid), dim3(256), lds, s>>>(p);
-  } else if (L.in_es == 16) {
-    permute_kernel<double2, 0><<<dim3((unsigned)grid), dim3(256), lds, s>>>(p);
-  } else {
-    permute_kernel<float2, 0><<<dim3((unsigned)grid), dim3(256), lds, s>>>(p);
+  const int E = tsize >= 256 ? tsize / 256 : 1;
+  for (int j = 0; j < E; ++j) {
+    int64_t hi = 0, ho = 0;
+    int hl = 0;
+    for (int q = 8; q < nS; ++q) {
+      if ((j >> (q - 8)) & 1) {
+        hi += int64_t(1) << p.ls_in[q];
+        ho += int64_t(1) << p.ss_out[q];
+        hl += 1 << p.ss_lds[q];
+      }
+    }
+    p.hi_in[j] = hi;
+    p.hi_out[j] = ho;
+    p.hi_lds[j] = hl;
   }
+  size_t lds = size_t(tsize + (tsize >> 5) + 1) * L.in_es;
+  unsigned grid = (unsigned)std::min<int64_t>(p.ntiles, 256 * 16);
+  if (L.kind == 1)
+    launch_perm_e<float2, 1>(p, E, grid, lds, s);
+  else if (L.in_es == 16)
+    launch_perm_e<double2, 0>(p, E, grid, lds, s);
+  else
+    launch_perm_e<float2, 0>(p, E, grid, lds, s);
   return hipGetLastError();
 }
 
