@@ -129,8 +129,10 @@ rn_status rn_block_footprint(const rn_tensor* A, const rn_tensor* B, int32_t k,
 
 /* Many independent block tensordots in one call (same mode).  Plans every
  * problem first (any invalid problem fails the whole call before anything is
- * enqueued), then enqueues them on the stream; each problem gets its own
- * 256-byte aligned slice of the workspace.  ws_bytes from
+ * enqueued).  Then one grouped launch relayouts every operand that needs it
+ * and one grouped launch per GEMM tile shape contracts all problems, the
+ * problems ordered by decreasing flops; no split-K.  Per-problem parameters
+ * are copied into the end of the workspace first.  ws_bytes from
  * rn_block_tensordot_batch_plan. */
 rn_status rn_block_tensordot_batch_plan(rn_handle h, int32_t n, const rn_tensor* A,
                                         const rn_tensor* B, const int32_t* k,
@@ -142,6 +144,31 @@ rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
                                    const int32_t* const* axesA, const int32_t* const* axesB,
                                    rn_tensor* C, rn_mode mode, void* ws, size_t ws_bytes,
                                    void* stream);
+
+/* Tile-shape autotuner for batches.  For every problem shape (mode,
+ * log2 M, log2 N, log2 K) of the batch that is not tuned yet, times each GEMM
+ * tile configuration on that problem (one warm-up and three timed launches,
+ * HIP events) and keeps the fastest.  Runs synchronously on `stream` and
+ * writes C (arguments as rn_block_tensordot_batch).  The choices live in the
+ * handle and are used by every later call on it; they never change during a
+ * call, so results are reproducible.  When the environment variable
+ * RN_TUNE_CACHE names a file, rn_create loads it and every autotune run
+ * rewrites it.  save/load/clear manage the table explicitly. */
+rn_status rn_autotune_batch(rn_handle h, int32_t n, const rn_tensor* A, const rn_tensor* B,
+                            const int32_t* k, const int32_t* const* axesA,
+                            const int32_t* const* axesB, rn_tensor* C, rn_mode mode, void* ws,
+                            size_t ws_bytes, void* stream);
+rn_status rn_tune_save(rn_handle h, const char* path);
+rn_status rn_tune_load(rn_handle h, const char* path);
+rn_status rn_tune_clear(rn_handle h);
+
+/* Graph replay.  When on (the default; RN_GRAPHS=0 in the environment turns
+ * it off at rn_create), rn_block_tensordot_batch and rn_contract_network
+ * record their launch sequence as a HIP graph the first time they run with a
+ * given set of arguments on a non-default stream, and replay the graph when
+ * the identical call repeats.  Never used on the NULL stream, inside a
+ * caller's own stream capture, or while kernel timing is on. */
+rn_status rn_set_graphs(rn_handle h, int on);
 
 /* ------------------------------------------------------------------------
  * Sliced network contraction (Sections II.A and II.B).

@@ -29,7 +29,8 @@ EXPORTS = ["rn_create", "rn_destroy", "rn_status_str", "rn_last_error",
            "rn_block_tensordot_plan", "rn_block_tensordot", "rn_block_pairs",
            "rn_block_footprint", "rn_block_tensordot_batch_plan", "rn_block_tensordot_batch",
            "rn_contract_network_plan", "rn_contract_network", "rn_norm2", "rn_sum_c128",
-           "rn_profile_enable", "rn_profile_read"]
+           "rn_profile_enable", "rn_profile_read", "rn_autotune_batch", "rn_tune_save",
+           "rn_tune_load", "rn_tune_clear", "rn_set_graphs"]
 
 
 class RnError(RuntimeError):
@@ -82,6 +83,11 @@ def lib():
         L.rn_norm2.argtypes = [p, T, p, p]
         L.rn_sum_c128.argtypes = [p, i64, p, p, p]
         L.rn_profile_enable.argtypes = [p, ctypes.c_int]
+        L.rn_autotune_batch.argtypes = [p, i32, T, T, p, pp, pp, T, ctypes.c_int, p, sz, p]
+        L.rn_tune_save.argtypes = [p, ctypes.c_char_p]
+        L.rn_tune_load.argtypes = [p, ctypes.c_char_p]
+        L.rn_tune_clear.argtypes = [p]
+        L.rn_set_graphs.argtypes = [p, ctypes.c_int]
         L.rn_profile_read.argtypes = [p, p, p]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype if name in (
@@ -165,6 +171,31 @@ def block_footprint(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, dtype=C64):
     return e1.value, e2.value
 
 
+def plan_batch_workspace(ctx, problems, mode="fp32_4m"):
+    """Workspace bytes of rn_block_tensordot_batch for these problems."""
+    n = len(problems)
+    dt = dtype_of_mode(mode)
+    As, Bs = (RnTensor * n)(), (RnTensor * n)()
+    ks = np.zeros(max(n, 1), dtype=np.int32)
+    keep = []
+    pa_arr = (ctypes.c_void_p * max(n, 1))()
+    pb_arr = (ctypes.c_void_p * max(n, 1))()
+    for i, (a, da, ga, b, db, gb, axa, axb) in enumerate(problems):
+        As[i] = descriptor(da, ga, dt, None)
+        Bs[i] = descriptor(db, gb, dt, None)
+        x, px = _arr32(axa)
+        y, py = _arr32(axb)
+        keep += [x, y]
+        ks[i] = len(x)
+        pa_arr[i] = px
+        pb_arr[i] = py
+    ws_n = ctypes.c_size_t()
+    check(lib().rn_block_tensordot_batch_plan(ctx.h if ctx else None, n, As, Bs, ks.ctypes.data,
+                                              pa_arr, pb_arr, mode_id(mode), None,
+                                              ctypes.byref(ws_n), None), "batch plan")
+    return ws_n.value
+
+
 # ------------------------------------------------------------- GPU calls
 
 class Context:
@@ -237,8 +268,12 @@ class Context:
               "block_tensordot")
         return out, cdims, cgrid
 
-    def block_tensordot_batch(self, problems, mode="fp32_4m", outs=None, workspace=None):
-        """problems: list of (a, dims_a, grid_a, b, dims_b, grid_b, axes_a, axes_b)."""
+    def block_tensordot_batch(self, problems, mode="fp32_4m", outs=None, workspace=None,
+                              autotune=False):
+        """problems: list of (a, dims_a, grid_a, b, dims_b, grid_b, axes_a, axes_b).
+
+        autotune=True first times the tile shapes of every untuned problem
+        shape (synchronously), then runs the batch with the chosen tiles."""
         import torch
         n = len(problems)
         dt = dtype_of_mode(mode)
@@ -271,9 +306,24 @@ class Context:
             Cs[i].data = o.data_ptr()
             results.append((o, cd, cg))
         wp, wn = self._workspace(ws_n.value, workspace)
+        if autotune:
+            check(lib().rn_autotune_batch(self.h, n, As, Bs, ks.ctypes.data, pa_arr, pb_arr, Cs,
+                                          mode_id(mode), wp, wn, self._stream()), "autotune")
         check(lib().rn_block_tensordot_batch(self.h, n, As, Bs, ks.ctypes.data, pa_arr, pb_arr,
                                              Cs, mode_id(mode), wp, wn, self._stream()), "batch")
         return results, fl.value
+
+    def set_graphs(self, on: bool) -> None:
+        check(lib().rn_set_graphs(self.h, 1 if on else 0), "set_graphs")
+
+    def tune_save(self, path: str) -> None:
+        check(lib().rn_tune_save(self.h, path.encode()), "tune_save")
+
+    def tune_load(self, path: str) -> None:
+        check(lib().rn_tune_load(self.h, path.encode()), "tune_load")
+
+    def tune_clear(self) -> None:
+        check(lib().rn_tune_clear(self.h), "tune_clear")
 
     # -- networks ------------------------------------------------------------
     def _net_args(self, tensors, labels, mode):

@@ -1,6 +1,8 @@
 // C ABI entry points: argument checks, planning, and kernel enqueue.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -128,6 +130,17 @@ rn_status rn_create(rn_handle* h, int device) {
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   rn_ctx* c = new rn_ctx();
   c->device = device;
+  const char* g = getenv("RN_GRAPHS");
+  c->graphs_enabled = !(g && g[0] == '0');
+  const char* tp = getenv("RN_TUNE_CACHE");
+  if (tp && tp[0]) {
+    c->tune_path = tp;
+    FILE* f = fopen(tp, "r");
+    if (f) {
+      fclose(f);
+      rn_tune_load(c, tp);
+    }
+  }
   e = hipMalloc(&c->red_scratch, 4096 * sizeof(double));
   if (e != hipSuccess) {
     delete c;
@@ -146,6 +159,15 @@ rn_status rn_destroy(rn_handle h) {
     hipEventDestroy(r.b);
   }
   for (hipEvent_t e : h->prof.pool) hipEventDestroy(e);
+  for (auto& g : h->graphs) {
+    hipGraphExecDestroy(g.exec);
+    if (g.pinned) hipHostFree(g.pinned);
+  }
+  if (h->pinned_done) {
+    hipEventSynchronize(h->pinned_done);
+    hipEventDestroy(h->pinned_done);
+  }
+  if (h->pinned) hipHostFree(h->pinned);
   delete h;
   return RN_OK;
 }
@@ -270,61 +292,6 @@ rn_status rn_block_footprint(const rn_tensor* A, const rn_tensor* B, int32_t k,
   double bk = double(int64_t(1) << P.pairbits);
   if (eq1_elems) *eq1_elems = bk * kb * (mb + nb) + mb * nb;
   if (eq2_elems) *eq2_elems = kb * (mb + nb) + mb * nb;
-  return RN_OK;
-}
-
-rn_status rn_block_tensordot_batch_plan(rn_handle h, int32_t n, const rn_tensor* A,
-                                        const rn_tensor* B, const int32_t* k,
-                                        const int32_t* const* axesA,
-                                        const int32_t* const* axesB, rn_mode mode, rn_tensor* C,
-                                        size_t* ws_bytes, double* flops) {
-  (void)h;
-  if (n < 0 || (n > 0 && (!A || !B || !k || !axesA || !axesB)))
-    return fail(RN_ERR_INVALID, "bad batch arguments");
-  size_t ws = 0;
-  double fl = 0;
-  for (int i = 0; i < n; ++i) {
-    TdPlan P;
-    rn_status st = plan_tensordot(&A[i], &B[i], k[i], axesA[i], axesB[i], mode, &P);
-    if (st != RN_OK) return fail(st, "problem " + std::to_string(i) + ": " + last_error());
-    if (C) fill_c(P, A[i].dtype, &C[i]);
-    ws += (P.ws_bytes + 255) & ~size_t(255);
-    fl += P.flops;
-  }
-  if (ws_bytes) *ws_bytes = ws;
-  if (flops) *flops = fl;
-  return RN_OK;
-}
-
-rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
-                                   const rn_tensor* B, const int32_t* k,
-                                   const int32_t* const* axesA, const int32_t* const* axesB,
-                                   rn_tensor* C, rn_mode mode, void* ws, size_t ws_bytes,
-                                   void* stream) {
-  if (!h) return fail(RN_ERR_INVALID, "null handle");
-  rn_status st;
-  if (n < 0 || (n > 0 && (!A || !B || !k || !axesA || !axesB || !C)))
-    return fail(RN_ERR_INVALID, "bad batch arguments");
-  std::vector<TdPlan> plans(n);
-  size_t need = 0;
-  for (int i = 0; i < n; ++i) {
-    st = plan_tensordot(&A[i], &B[i], k[i], axesA[i], axesB[i], mode, &plans[i]);
-    if (st == RN_OK) st = check_c(plans[i], &C[i]);
-    if (st != RN_OK) return fail(st, "problem " + std::to_string(i) + ": " + last_error());
-    if (!A[i].data || !B[i].data) return fail(RN_ERR_INVALID, "null operand data");
-    need += (plans[i].ws_bytes + 255) & ~size_t(255);
-  }
-  if (ws_bytes < need || (need > 0 && !ws))
-    return fail(RN_ERR_WORKSPACE, "workspace smaller than planned (" + std::to_string(need) +
-                                      " bytes needed)");
-  if ((st = bind_device(h)) != RN_OK) return st;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  size_t off = 0;
-  for (int i = 0; i < n; ++i) {
-    st = enqueue_tensordot(plans[i], &A[i], &B[i], &C[i], ws_at(ws, (int64_t)off), s, &h->prof);
-    if (st != RN_OK) return st;
-    off += (plans[i].ws_bytes + 255) & ~size_t(255);
-  }
   return RN_OK;
 }
 

@@ -1,0 +1,511 @@
+// Many block tensordots in one call: grouped launches, graph replay, and the
+// tile autotuner.
+//
+// A batch of independent contractions (the uneven-problem workload) is run
+// as one grouped permute launch over every operand that needs a relayout
+// and one grouped GEMM launch per tile shape, with problems ordered by
+// decreasing work so the largest start first.  The per-problem parameters
+// travel in a small table copied into the workspace.  When the same call is
+// repeated on a non-default stream, the recorded sequence (table copy plus
+// launches) is replayed as a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+
+#include "rn_internal.hpp"
+
+namespace rn {
+const std::string& last_error();
+
+uint64_t hash_bytes(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;  // FNV-1a
+  }
+  return h;
+}
+
+int tuned_tile(const rn_ctx* h, rn_mode mode, int mbits, int nbits, int kbits) {
+  if (!h) return -1;
+  auto it = h->tune.find(std::make_tuple((int)mode, mbits, nbits, kbits));
+  return it == h->tune.end() ? -1 : it->second;
+}
+
+static rn_status hipf(hipError_t e, const char* what) {
+  return fail(RN_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+rn_status upload_table(rn_ctx* h, const std::vector<char>& table, void* dev, hipStream_t s) {
+  if (table.empty()) return RN_OK;
+  hipError_t e;
+  if (h->pinned_done && (e = hipEventSynchronize(h->pinned_done)) != hipSuccess)
+    return hipf(e, "hipEventSynchronize");
+  if (h->pinned_bytes < table.size()) {
+    if (h->pinned) hipHostFree(h->pinned);
+    h->pinned = nullptr;
+    h->pinned_bytes = 0;
+    if ((e = hipHostMalloc(&h->pinned, table.size(), hipHostMallocDefault)) != hipSuccess)
+      return hipf(e, "hipHostMalloc");
+    h->pinned_bytes = table.size();
+  }
+  memcpy(h->pinned, table.data(), table.size());
+  if ((e = hipMemcpyAsync(dev, h->pinned, table.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hipf(e, "hipMemcpyAsync");
+  if (!h->pinned_done &&
+      (e = hipEventCreateWithFlags(&h->pinned_done, hipEventDisableTiming)) != hipSuccess)
+    return hipf(e, "hipEventCreate");
+  if ((e = hipEventRecord(h->pinned_done, s)) != hipSuccess) return hipf(e, "hipEventRecord");
+  return RN_OK;
+}
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct BatchPlan {
+  std::vector<TdPlan> plans;
+  std::vector<size_t> region;   // workspace offset of each problem's temporaries
+  std::vector<int> order;       // problems by decreasing work
+  size_t table_off = 0;
+  size_t ws_bytes = 0;
+  double flops = 0;
+};
+
+struct Launches {
+  std::vector<char> table;
+  GroupedLaunch perm;
+  std::vector<GroupedLaunch> gemms;
+};
+
+rn_status plan_batch(int32_t n, const rn_tensor* A, const rn_tensor* B, const int32_t* k,
+                     const int32_t* const* axesA, const int32_t* const* axesB, rn_mode mode,
+                     BatchPlan* bp) {
+  if (n < 0 || (n > 0 && (!A || !B || !k || !axesA || !axesB)))
+    return fail(RN_ERR_INVALID, "bad batch arguments");
+  bp->plans.resize(n);
+  bp->region.resize(n);
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    rn_status st = plan_tensordot(&A[i], &B[i], k[i], axesA[i], axesB[i], mode, &bp->plans[i],
+                                  /*allow_splitk=*/false);
+    if (st != RN_OK) return fail(st, "problem " + std::to_string(i) + ": " + last_error());
+    bp->region[i] = off;
+    off += align256(bp->plans[i].ws_bytes);
+    bp->flops += bp->plans[i].flops;
+  }
+  bp->order.resize(n);
+  std::iota(bp->order.begin(), bp->order.end(), 0);
+  std::stable_sort(bp->order.begin(), bp->order.end(), [&](int a, int b) {
+    return bp->plans[a].flops > bp->plans[b].flops;
+  });
+  bp->table_off = off;
+  return RN_OK;
+}
+
+// Parameter tables for the grouped launches; pointers refer to `ws`.
+void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, const rn_tensor* B,
+                    const rn_tensor* C, char* ws, Launches* L) {
+  const int n = (int)bp.plans.size();
+  std::vector<PermLaunch> jobs;
+  std::vector<GemmLaunch> gl(n);
+  for (int i : bp.order) {
+    const TdPlan& P = bp.plans[i];
+    const bool split_prec = (P.mode == RN_BF16X3);
+    char* base = ws ? ws + bp.region[i] : nullptr;
+    GemmLaunch& g = gl[i];
+    g.mode = P.mode;
+    g.A = A[i].data;
+    g.B = B[i].data;
+    if (P.permuteA) {
+      PermLaunch pl;
+      pl.in = A[i].data;
+      pl.out = base ? base + P.off_a : nullptr;
+      pl.out2 = (split_prec && base) ? base + P.off_a2 : nullptr;
+      pl.perm = P.permA;
+      pl.in_es = P.es;
+      pl.kind = split_prec ? 1 : 0;
+      jobs.push_back(pl);
+      g.A = pl.out;
+      g.A2 = pl.out2;
+    }
+    if (P.permuteB) {
+      PermLaunch pl;
+      pl.in = B[i].data;
+      pl.out = base ? base + P.off_b : nullptr;
+      pl.out2 = (split_prec && base) ? base + P.off_b2 : nullptr;
+      pl.perm = P.permB;
+      pl.in_es = P.es;
+      pl.kind = split_prec ? 1 : 0;
+      jobs.push_back(pl);
+      g.B = pl.out;
+      g.B2 = pl.out2;
+    }
+    g.C = C ? C[i].data : nullptr;
+    g.M = P.M;
+    g.N = P.N;
+    g.K = P.K;
+    g.lda = P.K;
+    g.ldb = P.K;
+    g.crow = P.crow;
+    g.ccol = P.ccol;
+    g.splitk = 1;
+    int t = tuned_tile(h, P.mode, P.mbits, P.nbits, P.kbits);
+    g.tile = t >= 0 ? t : gemm_default_tile(P.mode, P.M, P.N, P.K);
+  }
+  L->table.clear();
+  std::vector<char> part;
+  if (grouped_perm_build(jobs, part, L->perm) > 0) L->table = part;
+  std::map<int, std::vector<GemmLaunch>> by_tile;
+  for (int i : bp.order) by_tile[gl[i].tile].push_back(gl[i]);
+  L->gemms.clear();
+  for (auto& kv : by_tile) {
+    GroupedLaunch G;
+    size_t base = L->table.size();
+    if (grouped_gemm_build(kv.second, kv.first, part, G) == 0) continue;
+    G.params_off += base;
+    G.prefix_off += base;
+    L->table.insert(L->table.end(), part.begin(), part.end());
+    L->gemms.push_back(G);
+  }
+}
+
+rn_status launch_all(rn_ctx* h, const Launches& L, char* table_dev, hipStream_t s, bool prof) {
+  hipError_t e;
+  int ev = prof ? h->prof.begin(0, s) : -1;
+  e = launch_permute_grouped(L.perm, table_dev, s);
+  if (prof) h->prof.end(ev, s);
+  if (e != hipSuccess) return hipf(e, "grouped permute");
+  for (const GroupedLaunch& G : L.gemms) {
+    ev = prof ? h->prof.begin(1, s) : -1;
+    e = launch_gemm_grouped(G, table_dev, s);
+    if (prof) h->prof.end(ev, s);
+    if (e != hipSuccess) return hipf(e, "grouped GEMM");
+  }
+  return RN_OK;
+}
+
+bool graphs_wanted(const rn_ctx* h, hipStream_t s) {
+  if (!h->graphs_enabled || h->prof.on || s == nullptr) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+  return true;
+}
+
+GraphEntry* find_graph(rn_ctx* h, uint64_t key) {
+  for (auto& g : h->graphs)
+    if (g.key == key) {
+      g.last_use = ++h->use_clock;
+      return &g;
+    }
+  return nullptr;
+}
+
+void evict_graphs(rn_ctx* h, size_t keep) {
+  // A graph may still run on some stream: drain the device before freeing.
+  if (h->graphs.size() > keep) hipDeviceSynchronize();
+  while (h->graphs.size() > keep) {
+    auto it = std::min_element(h->graphs.begin(), h->graphs.end(),
+                               [](const GraphEntry& a, const GraphEntry& b) {
+                                 return a.last_use < b.last_use;
+                               });
+    hipGraphExecDestroy(it->exec);
+    if (it->pinned) hipHostFree(it->pinned);
+    h->graphs.erase(it);
+  }
+}
+
+}  // namespace
+
+// Record `enqueue` on stream s as a graph (with the table copied from a
+// pinned buffer owned by the cache entry), keep it under `key`, launch it.
+rn_status capture_and_launch(rn_ctx* h, uint64_t key, const std::vector<char>& table,
+                             void* table_dev, hipStream_t s,
+                             const std::function<rn_status(hipStream_t)>& enqueue) {
+  GraphEntry ent;
+  ent.key = key;
+  hipError_t e;
+  if (!table.empty()) {
+    if ((e = hipHostMalloc(&ent.pinned, table.size(), hipHostMallocDefault)) != hipSuccess)
+      return hipf(e, "hipHostMalloc");
+    memcpy(ent.pinned, table.data(), table.size());
+  }
+  if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    if (ent.pinned) hipHostFree(ent.pinned);
+    return hipf(e, "hipStreamBeginCapture");
+  }
+  rn_status st = RN_OK;
+  if (!table.empty()) {
+    e = hipMemcpyAsync(table_dev, ent.pinned, table.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) st = hipf(e, "hipMemcpyAsync (capture)");
+  }
+  if (st == RN_OK) st = enqueue(s);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(s, &graph);
+  if (st == RN_OK && e != hipSuccess) st = hipf(e, "hipStreamEndCapture");
+  if (st == RN_OK) {
+    e = hipGraphInstantiate(&ent.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) st = hipf(e, "hipGraphInstantiate");
+  }
+  if (graph) hipGraphDestroy(graph);
+  if (st != RN_OK) {
+    if (ent.pinned) hipHostFree(ent.pinned);
+    return st;
+  }
+  if ((e = hipGraphLaunch(ent.exec, s)) != hipSuccess) {
+    hipGraphExecDestroy(ent.exec);
+    if (ent.pinned) hipHostFree(ent.pinned);
+    return hipf(e, "hipGraphLaunch");
+  }
+  ent.last_use = ++h->use_clock;
+  h->graphs.push_back(ent);
+  evict_graphs(h, 32);
+  return RN_OK;
+}
+
+rn_status replay_graph(rn_ctx* h, uint64_t key, hipStream_t s, bool* done) {
+  *done = false;
+  GraphEntry* g = find_graph(h, key);
+  if (!g) return RN_OK;
+  hipError_t e = hipGraphLaunch(g->exec, s);
+  if (e != hipSuccess) return hipf(e, "hipGraphLaunch");
+  *done = true;
+  return RN_OK;
+}
+
+bool use_graphs(const rn_ctx* h, hipStream_t s) { return graphs_wanted(h, s); }
+
+bool seen_before(rn_ctx* h, uint64_t key) {
+  if (std::find(h->seen.begin(), h->seen.end(), key) != h->seen.end()) return true;
+  h->seen.push_back(key);
+  if (h->seen.size() > 256) h->seen.erase(h->seen.begin());
+  return false;
+}
+
+uint64_t hash_tensor(uint64_t x, const rn_tensor& t) {
+  x = hash_bytes(x, &t.rank, sizeof(t.rank));
+  x = hash_bytes(x, &t.dtype, sizeof(t.dtype));
+  x = hash_bytes(x, t.dims, sizeof(int64_t) * (size_t)std::max(0, t.rank));
+  x = hash_bytes(x, t.grid, sizeof(int32_t) * (size_t)std::max(0, t.rank));
+  x = hash_bytes(x, &t.data, sizeof(t.data));
+  return x;
+}
+
+static uint64_t g_tune_version = 0;
+
+}  // namespace rn
+
+using namespace rn;
+
+extern "C" {
+
+rn_status rn_block_tensordot_batch_plan(rn_handle h, int32_t n, const rn_tensor* A,
+                                        const rn_tensor* B, const int32_t* k,
+                                        const int32_t* const* axesA,
+                                        const int32_t* const* axesB, rn_mode mode, rn_tensor* C,
+                                        size_t* ws_bytes, double* flops) {
+  BatchPlan bp;
+  rn_status st = plan_batch(n, A, B, k, axesA, axesB, mode, &bp);
+  if (st != RN_OK) return st;
+  if (C) {
+    for (int i = 0; i < n; ++i) {
+      const TdPlan& P = bp.plans[i];
+      C[i].rank = P.crank;
+      C[i].dtype = A[i].dtype;
+      for (int j = 0; j < RN_MAX_RANK; ++j) {
+        C[i].dims[j] = j < P.crank ? P.cdims[j] : 0;
+        C[i].grid[j] = j < P.crank ? P.cgrid[j] : 0;
+      }
+    }
+  }
+  if (ws_bytes) *ws_bytes = bp.table_off + grouped_table_bound(mode, n);
+  if (flops) *flops = bp.flops;
+  return RN_OK;
+}
+
+rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
+                                   const rn_tensor* B, const int32_t* k,
+                                   const int32_t* const* axesA, const int32_t* const* axesB,
+                                   rn_tensor* C, rn_mode mode, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  if (!h) return fail(RN_ERR_INVALID, "null handle");
+  if (n > 0 && !C) return fail(RN_ERR_INVALID, "null C descriptors");
+  BatchPlan bp;
+  rn_status st = plan_batch(n, A, B, k, axesA, axesB, mode, &bp);
+  if (st != RN_OK) return st;
+  for (int i = 0; i < n; ++i) {
+    if ((st = check_c(bp.plans[i], &C[i])) != RN_OK)
+      return fail(st, "problem " + std::to_string(i) + ": " + last_error());
+    if (!A[i].data || !B[i].data) return fail(RN_ERR_INVALID, "null operand data");
+  }
+  Launches L;
+  build_launches(h, bp, A, B, C, static_cast<char*>(ws), &L);
+  size_t need = bp.table_off + grouped_table_bound(mode, n);
+  if (ws_bytes < need || (need > 0 && !ws))
+    return fail(RN_ERR_WORKSPACE, "workspace smaller than planned (" + std::to_string(need) +
+                                      " bytes needed)");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hipf(e, "hipSetDevice");
+  if (n == 0) return RN_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* table_dev = static_cast<char*>(ws) + bp.table_off;
+  if (use_graphs(h, s)) {
+    uint64_t key = 1469598103934665603ull;
+    key = hash_bytes(key, "batch", 5);
+    key = hash_bytes(key, &mode, sizeof(mode));
+    key = hash_bytes(key, &n, sizeof(n));
+    for (int i = 0; i < n; ++i) {
+      key = hash_tensor(key, A[i]);
+      key = hash_tensor(key, B[i]);
+      key = hash_tensor(key, C[i]);
+      key = hash_bytes(key, &k[i], sizeof(int32_t));
+      key = hash_bytes(key, axesA[i], sizeof(int32_t) * (size_t)k[i]);
+      key = hash_bytes(key, axesB[i], sizeof(int32_t) * (size_t)k[i]);
+    }
+    key = hash_bytes(key, &ws, sizeof(ws));
+    key = hash_bytes(key, &s, sizeof(s));
+    key = hash_bytes(key, &g_tune_version, sizeof(g_tune_version));
+    bool done = false;
+    if ((st = replay_graph(h, key, s, &done)) != RN_OK || done) return st;
+    if (seen_before(h, key))
+      return capture_and_launch(h, key, L.table, table_dev, s, [&](hipStream_t cs) {
+        return launch_all(h, L, table_dev, cs, false);
+      });
+  }
+  if ((st = upload_table(h, L.table, table_dev, s)) != RN_OK) return st;
+  return launch_all(h, L, table_dev, s, h->prof.on);
+}
+
+// Autotuner: for every shape (mode, log2 M, log2 N, log2 K) of the batch not
+// yet tuned, time each tile configuration of the GEMM on that problem's
+// permuted operands (one warm-up, three timed launches, HIP events) and keep
+// the fastest.  Runs synchronously on `stream`; results persist in the handle
+// and, when RN_TUNE_CACHE names a file, on disk.
+rn_status rn_autotune_batch(rn_handle h, int32_t n, const rn_tensor* A, const rn_tensor* B,
+                            const int32_t* k, const int32_t* const* axesA,
+                            const int32_t* const* axesB, rn_tensor* C, rn_mode mode, void* ws,
+                            size_t ws_bytes, void* stream) {
+  if (!h) return fail(RN_ERR_INVALID, "null handle");
+  if (n > 0 && !C) return fail(RN_ERR_INVALID, "null C descriptors");
+  BatchPlan bp;
+  rn_status st = plan_batch(n, A, B, k, axesA, axesB, mode, &bp);
+  if (st != RN_OK) return st;
+  for (int i = 0; i < n; ++i)
+    if ((st = check_c(bp.plans[i], &C[i])) != RN_OK) return st;
+  if (ws_bytes < bp.table_off || (bp.table_off > 0 && !ws))
+    return fail(RN_ERR_WORKSPACE, "workspace smaller than planned");
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hipf(e, "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hipf(e, "hipEventCreate");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    hipEventDestroy(e0);
+    return hipf(e, "hipEventCreate");
+  }
+  const bool saved_prof = h->prof.on;
+  h->prof.on = false;
+  for (int i : bp.order) {
+    const TdPlan& P = bp.plans[i];
+    auto key = std::make_tuple((int)P.mode, P.mbits, P.nbits, P.kbits);
+    if (h->tune.count(key)) continue;
+    char* base = static_cast<char*>(ws) + bp.region[i];
+    // Permute once (same as the batch would), then time GEMM candidates.
+    st = enqueue_tensordot(P, &A[i], &B[i], &C[i], base, s, nullptr);
+    if (st != RN_OK) break;
+    GemmLaunch g;
+    g.mode = P.mode;
+    const bool split_prec = (P.mode == RN_BF16X3);
+    g.A = P.permuteA ? base + P.off_a : A[i].data;
+    g.A2 = (P.permuteA && split_prec) ? base + P.off_a2 : nullptr;
+    g.B = P.permuteB ? base + P.off_b : B[i].data;
+    g.B2 = (P.permuteB && split_prec) ? base + P.off_b2 : nullptr;
+    g.C = C[i].data;
+    g.M = P.M;
+    g.N = P.N;
+    g.K = P.K;
+    g.lda = g.ldb = P.K;
+    g.crow = P.crow;
+    g.ccol = P.ccol;
+    g.splitk = 1;
+    int best = -1;
+    float best_ms = 0.f;
+    for (int t = 0; t < gemm_tile_count(P.mode) && st == RN_OK; ++t) {
+      g.tile = t;
+      if ((e = launch_gemm(g, s)) != hipSuccess) { st = hipf(e, "autotune launch"); break; }
+      hipEventRecord(e0, s);
+      for (int r = 0; r < 3; ++r)
+        if ((e = launch_gemm(g, s)) != hipSuccess) break;
+      hipEventRecord(e1, s);
+      if (e != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+        st = hipf(e, "autotune timing");
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (best < 0 || ms < best_ms) {
+        best = t;
+        best_ms = ms;
+      }
+    }
+    if (st != RN_OK) break;
+    h->tune[key] = best;
+  }
+  h->prof.on = saved_prof;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  ++g_tune_version;
+  if (st == RN_OK && !h->tune_path.empty()) rn_tune_save(h, h->tune_path.c_str());
+  return st;
+}
+
+rn_status rn_tune_save(rn_handle h, const char* path) {
+  if (!h || !path) return fail(RN_ERR_INVALID, "null argument");
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(RN_ERR_INVALID, std::string("cannot write ") + path);
+  fprintf(f, "rn_tune 1\n");
+  for (auto& kv : h->tune)
+    fprintf(f, "%d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
+            std::get<2>(kv.first), std::get<3>(kv.first), kv.second);
+  fclose(f);
+  return RN_OK;
+}
+
+rn_status rn_tune_load(rn_handle h, const char* path) {
+  if (!h || !path) return fail(RN_ERR_INVALID, "null argument");
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(RN_ERR_INVALID, std::string("cannot read ") + path);
+  int ver = 0;
+  if (fscanf(f, "rn_tune %d", &ver) != 1 || ver != 1) {
+    fclose(f);
+    return fail(RN_ERR_INVALID, "not a tune file");
+  }
+  int m, a, b, c, t;
+  while (fscanf(f, "%d %d %d %d %d", &m, &a, &b, &c, &t) == 5) {
+    if (m < RN_FP64 || m > RN_BF16X3 || t < 0 || t >= gemm_tile_count((rn_mode)m)) continue;
+    h->tune[std::make_tuple(m, a, b, c)] = t;
+  }
+  fclose(f);
+  ++g_tune_version;
+  return RN_OK;
+}
+
+rn_status rn_tune_clear(rn_handle h) {
+  if (!h) return fail(RN_ERR_INVALID, "null handle");
+  h->tune.clear();
+  ++g_tune_version;
+  return RN_OK;
+}
+
+rn_status rn_set_graphs(rn_handle h, int on) {
+  if (!h) return fail(RN_ERR_INVALID, "null handle");
+  h->graphs_enabled = on != 0;
+  return RN_OK;
+}
+
+}  // extern "C"

@@ -12,6 +12,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
+#include <vector>
 
 #include "rn_internal.hpp"
 
@@ -69,19 +71,12 @@ __device__ __forceinline__ void bf16_split(float x, uint32_t& hi, uint32_t& lo) 
   lo = bf16_rne(r);
 }
 
-// E elements per thread per tile (tile = 256 * E elements, or fewer for a
-// tile smaller than one workgroup).  All E loads of a tile are issued before
-// any is consumed, so each thread keeps E global reads in flight.
-template <typename T, int KIND, int E>
-__global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);
-  const T* __restrict__ in = reinterpret_cast<const T*>(p.in);
-  const int tid = threadIdx.x;
-  const int tsize = 1 << p.nS;
+// Thread-fixed low parts of the tile-local index u = tid + 256 * j.
+__device__ __forceinline__ void perm_lo(const PermParams& p, int tid, int64_t& in_lo,
+                                        int64_t& out_lo, int& lds_lo) {
   const int lo_bits = p.nS < 8 ? p.nS : 8;
-  int64_t in_lo = 0, out_lo = 0;
-  int lds_lo = 0;
+  in_lo = out_lo = 0;
+  lds_lo = 0;
   for (int q = 0; q < lo_bits; ++q) {
     if ((tid >> q) & 1) {
       in_lo += int64_t(1) << p.ls_in[q];
@@ -89,42 +84,93 @@ __global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
       lds_lo += 1 << p.ss_lds[q];
     }
   }
+}
+
+// One tile t of a permutation.  E elements per thread (tile = 256 * E
+// elements, or fewer for a tile smaller than one workgroup); with PRED the
+// tile may hold fewer than 256 * E elements.  All loads of a tile are
+// issued before any is consumed, so each thread keeps E reads in flight.
+template <typename T, int KIND, int E, bool PRED>
+__device__ __forceinline__ void permute_tile(const PermParams& p, int64_t t, T* tile,
+                                             int64_t in_lo, int64_t out_lo, int lds_lo) {
+  const T* __restrict__ in = reinterpret_cast<const T*>(p.in);
+  const int tid = threadIdx.x;
+  const int tsize = 1 << p.nS;
   const bool active = tid < tsize;
-  for (int64_t t = blockIdx.x; t < p.ntiles; t += gridDim.x) {
-    int64_t ib = p.in_base, ob = 0;
-    for (int q = 0; q < p.nO; ++q) {
-      if ((t >> q) & 1) {
-        ib += int64_t(1) << p.os_in[q];
-        ob += int64_t(1) << p.os_out[q];
-      }
+  int64_t ib = p.in_base, ob = 0;
+  for (int q = 0; q < p.nO; ++q) {
+    if ((t >> q) & 1) {
+      ib += int64_t(1) << p.os_in[q];
+      ob += int64_t(1) << p.os_out[q];
     }
-    T v[E];
-    if (active) {
-#pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = in[ib + in_lo + p.hi_in[j]];
-#pragma unroll
-      for (int j = 0; j < E; ++j) tile[lds_pad(tid + (j << 8))] = v[j];
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = tile[lds_pad(lds_lo + p.hi_lds[j])];
-#pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const int64_t oo = ob + out_lo + p.hi_out[j];
-        if constexpr (KIND == 0) {
-          reinterpret_cast<T*>(p.out)[oo] = v[j];
-        } else {
-          uint32_t hr, lr, hi_, li_;
-          bf16_split(v[j].x, hr, lr);
-          bf16_split(v[j].y, hi_, li_);
-          reinterpret_cast<uint32_t*>(p.out)[oo] = hr | (hi_ << 16);
-          reinterpret_cast<uint32_t*>(p.out2)[oo] = lr | (li_ << 16);
-        }
-      }
-    }
-    __syncthreads();
   }
+  T v[E];
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+      if (!PRED || (j << 8) < tsize) v[j] = in[ib + in_lo + p.hi_in[j]];
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+      if (!PRED || (j << 8) < tsize) tile[lds_pad(tid + (j << 8))] = v[j];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+      if (!PRED || (j << 8) < tsize) v[j] = tile[lds_pad(lds_lo + p.hi_lds[j])];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if (PRED && (j << 8) >= tsize) continue;
+      const int64_t oo = ob + out_lo + p.hi_out[j];
+      if constexpr (KIND == 0) {
+        reinterpret_cast<T*>(p.out)[oo] = v[j];
+      } else {
+        uint32_t hr, lr, hi_, li_;
+        bf16_split(v[j].x, hr, lr);
+        bf16_split(v[j].y, hi_, li_);
+        reinterpret_cast<uint32_t*>(p.out)[oo] = hr | (hi_ << 16);
+        reinterpret_cast<uint32_t*>(p.out2)[oo] = lr | (li_ << 16);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int KIND, int E>
+__global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);
+  int64_t in_lo, out_lo;
+  int lds_lo;
+  perm_lo(p, threadIdx.x, in_lo, out_lo, lds_lo);
+  for (int64_t t = blockIdx.x; t < p.ntiles; t += gridDim.x)
+    permute_tile<T, KIND, E, false>(p, t, tile, in_lo, out_lo, lds_lo);
+}
+
+// Many permutations in one launch: workgroup w moves one tile of job i,
+// prefix[i] <= w < prefix[i+1].
+struct PermTable {
+  const PermParams* jobs;
+  const int32_t* prefix;
+  int n;
+};
+
+template <typename T, int KIND, int E>
+__global__ __launch_bounds__(256) void permute_grouped(PermTable g) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);
+  int lo = 0, hi = g.n - 1;
+  const int bid = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (g.prefix[mid] <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  const PermParams& p = g.jobs[lo];
+  int64_t in_lo, out_lo;
+  int lds_lo;
+  perm_lo(p, threadIdx.x, in_lo, out_lo, lds_lo);
+  permute_tile<T, KIND, E, true>(p, bid - g.prefix[lo], tile, in_lo, out_lo, lds_lo);
 }
 
 template <typename T, int KIND>
@@ -138,10 +184,10 @@ static void launch_perm_e(const PermParams& p, int e, unsigned grid, size_t lds,
   }
 }
 
-hipError_t launch_permute(const PermLaunch& L, hipStream_t s) {
+// Tile choice and offset tables of one permutation (host).
+static void perm_setup(const PermLaunch& L, PermParams& p) {
   const int R = L.perm.nbits;
-  if (R > 48) return hipErrorInvalidValue;
-  PermParams p{};
+  p = PermParams{};
   p.in = L.in;
   p.out = L.out;
   p.out2 = L.out2;
@@ -196,6 +242,14 @@ hipError_t launch_permute(const PermLaunch& L, hipStream_t s) {
     p.hi_out[j] = ho;
     p.hi_lds[j] = hl;
   }
+}
+
+hipError_t launch_permute(const PermLaunch& L, hipStream_t s) {
+  if (L.perm.nbits > 48) return hipErrorInvalidValue;
+  PermParams p;
+  perm_setup(L, p);
+  const int tsize = 1 << p.nS;
+  const int E = tsize >= 256 ? tsize / 256 : 1;
   size_t lds = size_t(tsize + (tsize >> 5) + 1) * L.in_es;
   unsigned grid = (unsigned)std::min<int64_t>(p.ntiles, 256 * 16);
   if (L.kind == 1)
@@ -204,6 +258,47 @@ hipError_t launch_permute(const PermLaunch& L, hipStream_t s) {
     launch_perm_e<double2, 0>(p, E, grid, lds, s);
   else
     launch_perm_e<float2, 0>(p, E, grid, lds, s);
+  return hipGetLastError();
+}
+
+size_t grouped_perm_build(const std::vector<PermLaunch>& jobs, std::vector<char>& table,
+                          GroupedLaunch& G) {
+  G = GroupedLaunch{};
+  G.n = (int)jobs.size();
+  if (jobs.empty()) return 0;
+  G.kind = jobs[0].kind;
+  G.es = jobs[0].in_es;
+  std::vector<PermParams> ps(jobs.size());
+  std::vector<int32_t> prefix(jobs.size() + 1, 0);
+  int max_tsize = 1;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    perm_setup(jobs[i], ps[i]);
+    max_tsize = std::max(max_tsize, 1 << ps[i].nS);
+    prefix[i + 1] = prefix[i] + (int32_t)ps[i].ntiles;
+  }
+  G.blocks = prefix.back();
+  G.lds = size_t(max_tsize + (max_tsize >> 5) + 1) * G.es;
+  G.params_off = 0;
+  G.prefix_off = (jobs.size() * sizeof(PermParams) + 255) & ~size_t(255);
+  size_t bytes = (G.prefix_off + prefix.size() * sizeof(int32_t) + 255) & ~size_t(255);
+  table.resize(bytes);
+  memcpy(table.data(), ps.data(), jobs.size() * sizeof(PermParams));
+  memcpy(table.data() + G.prefix_off, prefix.data(), prefix.size() * sizeof(int32_t));
+  return bytes;
+}
+
+hipError_t launch_permute_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s) {
+  if (G.n == 0 || G.blocks == 0) return hipSuccess;
+  PermTable t;
+  t.jobs = reinterpret_cast<const PermParams*>(static_cast<const char*>(table_dev) + G.params_off);
+  t.prefix = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.prefix_off);
+  t.n = G.n;
+  if (G.kind == 1)
+    permute_grouped<float2, 1, 16><<<G.blocks, 256, G.lds, s>>>(t);
+  else if (G.es == 16)
+    permute_grouped<double2, 0, 4><<<G.blocks, 256, G.lds, s>>>(t);
+  else
+    permute_grouped<float2, 0, 16><<<G.blocks, 256, G.lds, s>>>(t);
   return hipGetLastError();
 }
 
@@ -279,7 +374,8 @@ __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, i
 // WM x WN waves; each wave owns TM x TN MFMA tiles of 32 x 32 real outputs.
 // ---------------------------------------------------------------------------
 template <int WM, int WN, int TM, int TN, int BK>
-__global__ __launch_bounds__(256) void cgemm_f32_4m(GemmParams p) {
+__device__ __forceinline__ void cgemm_f32_4m_body(const GemmParams& p, int tm, int tn, int split,
+                                                int b) {
   static_assert(WM * WN == 4, "four waves");
   constexpr int BM = WM * TM * 32;
   constexpr int BN = WN * TN * 16;  // complex columns
@@ -291,10 +387,6 @@ __global__ __launch_bounds__(256) void cgemm_f32_4m(GemmParams p) {
   __shared__ float2 As[2][BM * LDK];
   __shared__ float2 Bs[2][BN * LDK];
 
-  int tm, tn;
-  tile_coords(p.tiles_m, p.tiles_n, tm, tn);
-  const int split = blockIdx.y;
-  const int b = blockIdx.z;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -438,10 +530,176 @@ __global__ __launch_bounds__(256) void cgemm_f32_4m(GemmParams p) {
 }
 
 // ---------------------------------------------------------------------------
+// FP32, 3M (Gauss): T1 = Ar.Br, T2 = Ai.Bi, T3 = (Ar + Ai).(Br + Bi);
+// Re C = T1 - T2, Im C = (T3 - T1) - T2.  v_mfma_f32_32x32x2_f32 with the
+// two k of one instruction = two consecutive complex k: lane halves read
+// different complex elements and use both parts, so the operands stay
+// interleaved in memory and LDS (no planar copy) and each 32x32 tile is 32
+// complex columns.  6 real flops per complex multiply-add are executed.
+// ---------------------------------------------------------------------------
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f32_3m_body(const GemmParams& p, int tm, int tn, int split,
+                                                int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK % 2 == 0, "two complex k per MFMA");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 32;  // complex columns
+  constexpr int LDK = BK + 1;
+  constexpr int AV = BM * BK / 2;
+  constexpr int BV = BN * BK / 2;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  __shared__ float2 As[2][BM * LDK];
+  __shared__ float2 Bs[2][BN * LDK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const float2* __restrict__ Ag =
+      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const float2* __restrict__ Bg =
+      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+
+  float4 ra[NA], rb[NB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = row0 + r, gk = k0 + c;
+        if (gr < p.M) {
+          const float2* src = Ag + gr * p.lda + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = col0 + r, gk = k0 + c;
+        if (gr < p.N) {
+          const float2* src = Bg + gr * p.ldb + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      rb[j] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        As[buf][r * LDK + c] = make_float2(ra[j].x, ra[j].y);
+        As[buf][r * LDK + c + 1] = make_float2(ra[j].z, ra[j].w);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        Bs[buf][r * LDK + c] = make_float2(rb[j].x, rb[j].y);
+        Bs[buf][r * LDK + c + 1] = make_float2(rb[j].z, rb[j].w);
+      }
+    }
+  };
+
+  v16f t1[TM][TN], t2[TM][TN], t3[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) t1[i][j][e] = t2[i][j][e] = t3[i][j][e] = 0.f;
+
+  const int kh = lane >> 5;
+  const int arow = wm * TM * 32 + (lane & 31);
+  const int bcol = wn * TN * 32 + (lane & 31);
+
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      float ar[TM], ai[TM], as[TM], br[TN], bi[TN], bs[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        float2 a = As[buf][(arow + i * 32) * LDK + kk + kh];
+        ar[i] = a.x;
+        ai[i] = a.y;
+        as[i] = a.x + a.y;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        float2 v = Bs[buf][(bcol + j * 32) * LDK + kk + kh];
+        br[j] = v.x;
+        bi[j] = v.y;
+        bs[j] = v.x + v.y;
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], t1[i][j], 0, 0, 0);
+          t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], bi[j], t2[i][j], 0, 0, 0);
+          t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[i], bs[j], t3[i][j], 0, 0, 0);
+        }
+    }
+    if (it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
+        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
+        float a = t1[i][j][e], c = t2[i][j][e];
+        store_out<float>(p, b, split, row, col, 0, a - c);
+        store_out<float>(p, b, split, row, col, 1, (t3[i][j][e] - a) - c);
+      }
+}
+
+// ---------------------------------------------------------------------------
 // FP64, 4M embedding, v_mfma_f64_16x16x4_f64 (4 real k = 2 complex k).
 // ---------------------------------------------------------------------------
 template <int WM, int WN, int TM, int TN, int BK>
-__global__ __launch_bounds__(256) void cgemm_f64_4m(GemmParams p) {
+__device__ __forceinline__ void cgemm_f64_4m_body(const GemmParams& p, int tm, int tn, int split,
+                                                int b) {
   static_assert(WM * WN == 4, "four waves");
   static_assert(BK % 2 == 0, "two complex k per MFMA");
   constexpr int BM = WM * TM * 16;
@@ -454,10 +712,6 @@ __global__ __launch_bounds__(256) void cgemm_f64_4m(GemmParams p) {
   __shared__ double2 As[2][BM * LDK];
   __shared__ double2 Bs[2][BN * LDK];
 
-  int tm, tn;
-  tile_coords(p.tiles_m, p.tiles_n, tm, tn);
-  const int split = blockIdx.y;
-  const int b = blockIdx.z;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -582,7 +836,8 @@ __global__ __launch_bounds__(256) void cgemm_f64_4m(GemmParams p) {
 // one FP32 accumulator.
 // ---------------------------------------------------------------------------
 template <int WM, int WN, int TM, int TN, int BK>
-__global__ __launch_bounds__(256) void cgemm_bf16x3(GemmParams p) {
+__device__ __forceinline__ void cgemm_bf16x3_body(const GemmParams& p, int tm, int tn, int split,
+                                                int b) {
   static_assert(WM * WN == 4, "four waves");
   static_assert(BK % 8 == 0, "eight complex k per MFMA");
   constexpr int BM = WM * TM * 32;
@@ -597,10 +852,6 @@ __global__ __launch_bounds__(256) void cgemm_bf16x3(GemmParams p) {
   __shared__ __align__(16) uint32_t Bh[2][BN * LDK];
   __shared__ __align__(16) uint32_t Bl[2][BN * LDK];
 
-  int tm, tn;
-  tile_coords(p.tiles_m, p.tiles_n, tm, tn);
-  const int split = blockIdx.y;
-  const int b = blockIdx.z;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -757,10 +1008,9 @@ __device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w <<
 __device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void cgemm_small(GemmParams p) {
-  const int split = blockIdx.y;
-  const int b = blockIdx.z;
-  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+__device__ __forceinline__ void cgemm_small_body(const GemmParams& p, int64_t blk, int split,
+                                                 int b) {
+  const int64_t e = blk * 256 + threadIdx.x;
   if (e >= p.M * p.N) return;
   const int64_t row = e / p.N, col = e % p.N;
   const int64_t kbeg = int64_t(split) * p.kchunk;
@@ -780,6 +1030,18 @@ __global__ __launch_bounds__(256) void cgemm_small(GemmParams p) {
     }
     store_out<double>(p, b, split, row, col, 0, re);
     store_out<double>(p, b, split, row, col, 1, im);
+  } else if constexpr (MODE == RN_FP32_3M) {
+    const float2* A = reinterpret_cast<const float2*>(p.A) + ao;
+    const float2* B = reinterpret_cast<const float2*>(p.B) + bo;
+    float t1 = 0.f, t2 = 0.f, t3 = 0.f;
+    for (int64_t k = kbeg; k < kend; ++k) {
+      float2 a = A[k], bb = B[k];
+      t1 = fmaf(a.x, bb.x, t1);
+      t2 = fmaf(a.y, bb.y, t2);
+      t3 = fmaf(a.x + a.y, bb.x + bb.y, t3);
+    }
+    store_out<float>(p, b, split, row, col, 0, t1 - t2);
+    store_out<float>(p, b, split, row, col, 1, (t3 - t1) - t2);
   } else if constexpr (MODE == RN_FP32_4M) {
     const float2* A = reinterpret_cast<const float2*>(p.A) + ao;
     const float2* B = reinterpret_cast<const float2*>(p.B) + bo;
@@ -815,6 +1077,59 @@ __global__ __launch_bounds__(256) void cgemm_small(GemmParams p) {
     store_out<float>(p, b, split, row, col, 0, re);
     store_out<float>(p, b, split, row, col, 1, im);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel entry points.  Single problem: the grid is (tiles, splits, slice
+// batch).  Grouped: many problems in one launch; workgroup w serves problem
+// i with prefix[i] <= w < prefix[i+1] (problems ordered by decreasing work,
+// so the largest start first) and takes that problem's local tile.
+// ---------------------------------------------------------------------------
+struct GroupTable {
+  const GemmParams* probs;
+  const int32_t* prefix;  // n + 1 entries
+  int n;
+};
+
+__device__ __forceinline__ int group_find(const GroupTable& g, int bid) {
+  int lo = 0, hi = g.n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (g.prefix[mid] <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+#define RN_GEMM_ENTRY(NAME)                                                              \
+  template <int WM, int WN, int TM, int TN, int BK>                                     \
+  __global__ __launch_bounds__(256) void NAME(GemmParams p) {                           \
+    int tm, tn;                                                                         \
+    tile_coords(p.tiles_m, p.tiles_n, tm, tn);                                          \
+    NAME##_body<WM, WN, TM, TN, BK>(p, tm, tn, blockIdx.y, blockIdx.z);                 \
+  }                                                                                     \
+  template <int WM, int WN, int TM, int TN, int BK>                                     \
+  __global__ __launch_bounds__(256) void NAME##_grouped(GroupTable g) {                 \
+    const int i = group_find(g, blockIdx.x);                                            \
+    const GemmParams& p = g.probs[i];                                                   \
+    const int local = blockIdx.x - g.prefix[i];                                         \
+    NAME##_body<WM, WN, TM, TN, BK>(p, local / p.tiles_n, local % p.tiles_n, 0, 0);     \
+  }
+
+RN_GEMM_ENTRY(cgemm_f32_4m)
+RN_GEMM_ENTRY(cgemm_f32_3m)
+RN_GEMM_ENTRY(cgemm_f64_4m)
+RN_GEMM_ENTRY(cgemm_bf16x3)
+
+template <int MODE>
+__global__ __launch_bounds__(256) void cgemm_small(GemmParams p) {
+  cgemm_small_body<MODE>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void cgemm_small_grouped(GroupTable g) {
+  const int i = group_find(g, blockIdx.x);
+  cgemm_small_body<MODE>(g.probs[i], blockIdx.x - g.prefix[i], 0, 0);
 }
 
 // Split-K reduction: C = sum over splits of the partials, in ascending split
@@ -855,10 +1170,12 @@ static const TileCfg kF32Tiles[] = {
     {1, 1, 1}, {128, 64, 16}, {64, 32, 16}, {256, 64, 8}, {128, 128, 8}};
 static const TileCfg kF64Tiles[] = {{1, 1, 1}, {128, 64, 8}, {64, 32, 8}};
 static const TileCfg kBF16Tiles[] = {{1, 1, 1}, {128, 64, 16}, {64, 32, 16}};
+static const TileCfg k3MTiles[] = {{1, 1, 1}, {128, 64, 16}, {64, 64, 16}};
 
 static const TileCfg& tile_of(rn_mode mode, int t) {
   if (mode == RN_FP64) return kF64Tiles[t];
   if (mode == RN_BF16X3) return kBF16Tiles[t];
+  if (mode == RN_FP32_3M) return k3MTiles[t];
   return kF32Tiles[t];
 }
 
@@ -878,8 +1195,8 @@ int choose_splitk(rn_mode mode, int64_t M, int64_t N, int64_t K, int64_t batch) 
   return s;
 }
 
-hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
-  GemmParams p{};
+static void fill_params(const GemmLaunch& g, GemmParams& p) {
+  p = GemmParams{};
   p.A = g.A;
   p.B = g.B;
   p.A2 = g.A2;
@@ -905,6 +1222,22 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
   }
   p.splitk = g.splitk;
   p.kchunk = (g.K + g.splitk - 1) / g.splitk;
+}
+
+int gemm_tile_count(rn_mode mode) {
+  if (mode == RN_FP64) return (int)(sizeof(kF64Tiles) / sizeof(kF64Tiles[0]));
+  if (mode == RN_BF16X3) return (int)(sizeof(kBF16Tiles) / sizeof(kBF16Tiles[0]));
+  if (mode == RN_FP32_3M) return (int)(sizeof(k3MTiles) / sizeof(k3MTiles[0]));
+  return (int)(sizeof(kF32Tiles) / sizeof(kF32Tiles[0]));
+}
+
+int gemm_default_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
+  return choose_tile(mode, M, N, K);
+}
+
+hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
+  GemmParams p;
+  fill_params(g, p);
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int tile = g.tile >= 0 ? g.tile : choose_tile(g.mode, g.M, g.N, g.K);
   const TileCfg& c = tile_of(g.mode, tile);
@@ -914,6 +1247,8 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
     dim3 grid((unsigned)((g.M * g.N + 255) / 256), (unsigned)g.splitk, nbatch);
     if (g.mode == RN_FP64)
       cgemm_small<RN_FP64><<<grid, 256, 0, s>>>(p);
+    else if (g.mode == RN_FP32_3M)
+      cgemm_small<RN_FP32_3M><<<grid, 256, 0, s>>>(p);
     else if (g.mode == RN_BF16X3)
       cgemm_small<RN_BF16X3><<<grid, 256, 0, s>>>(p);
     else
@@ -927,6 +1262,11 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f64_4m<2, 2, 4, 4, 8><<<grid, 256, 0, s>>>(p);
       else
         cgemm_f64_4m<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
+    } else if (g.mode == RN_FP32_3M) {
+      if (tile == 1)
+        cgemm_f32_3m<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_f32_3m<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
     } else if (g.mode == RN_BF16X3) {
       if (tile == 1)
         cgemm_bf16x3<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
@@ -956,6 +1296,85 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
   e = hipGetLastError();
   if (prof) prof->end(ev2, s);
   return e;
+}
+
+// Upper bound of the parameter tables of one grouped batch of n problems,
+// whatever the tile choice (at most one GEMM group per tile shape).
+size_t grouped_table_bound(rn_mode mode, int n) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t b = al(2 * size_t(n) * sizeof(PermParams)) + al((2 * size_t(n) + 1) * sizeof(int32_t));
+  b += size_t(gemm_tile_count(mode)) *
+       (al(size_t(n) * sizeof(GemmParams)) + al((size_t(n) + 1) * sizeof(int32_t)));
+  return b;
+}
+
+size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
+                          std::vector<char>& table, GroupedLaunch& G) {
+  G = GroupedLaunch{};
+  G.n = (int)probs.size();
+  G.tile = tile;
+  if (probs.empty()) return 0;
+  G.mode = probs[0].mode;
+  const TileCfg& c = tile_of(G.mode, tile);
+  std::vector<GemmParams> ps(probs.size());
+  std::vector<int32_t> prefix(probs.size() + 1, 0);
+  for (size_t i = 0; i < probs.size(); ++i) {
+    fill_params(probs[i], ps[i]);
+    ps[i].splitk = 1;
+    ps[i].kchunk = probs[i].K;
+    int64_t blocks;
+    if (tile == 0) {
+      blocks = (probs[i].M * probs[i].N + 255) / 256;
+    } else {
+      ps[i].tiles_m = (int)((probs[i].M + c.bm - 1) / c.bm);
+      ps[i].tiles_n = (int)((probs[i].N + c.bn - 1) / c.bn);
+      blocks = int64_t(ps[i].tiles_m) * ps[i].tiles_n;
+    }
+    prefix[i + 1] = prefix[i] + (int32_t)blocks;
+  }
+  G.blocks = prefix.back();
+  G.params_off = 0;
+  G.prefix_off = (probs.size() * sizeof(GemmParams) + 255) & ~size_t(255);
+  size_t bytes = (G.prefix_off + prefix.size() * sizeof(int32_t) + 255) & ~size_t(255);
+  table.resize(bytes);
+  memcpy(table.data(), ps.data(), probs.size() * sizeof(GemmParams));
+  memcpy(table.data() + G.prefix_off, prefix.data(), prefix.size() * sizeof(int32_t));
+  return bytes;
+}
+
+hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s) {
+  if (G.n == 0 || G.blocks == 0) return hipSuccess;
+  GroupTable t;
+  t.probs = reinterpret_cast<const GemmParams*>(static_cast<const char*>(table_dev) + G.params_off);
+  t.prefix = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.prefix_off);
+  t.n = G.n;
+  const dim3 grid((unsigned)G.blocks);
+  const int tile = G.tile;
+  switch (G.mode) {
+    case RN_FP64:
+      if (tile == 0) cgemm_small_grouped<RN_FP64><<<grid, 256, 0, s>>>(t);
+      else if (tile == 1) cgemm_f64_4m_grouped<2, 2, 4, 4, 8><<<grid, 256, 0, s>>>(t);
+      else cgemm_f64_4m_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
+      break;
+    case RN_FP32_3M:
+      if (tile == 0) cgemm_small_grouped<RN_FP32_3M><<<grid, 256, 0, s>>>(t);
+      else if (tile == 1) cgemm_f32_3m_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
+      else cgemm_f32_3m_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
+      break;
+    case RN_BF16X3:
+      if (tile == 0) cgemm_small_grouped<RN_BF16X3><<<grid, 256, 0, s>>>(t);
+      else if (tile == 1) cgemm_bf16x3_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
+      else cgemm_bf16x3_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
+      break;
+    default:
+      if (tile == 0) cgemm_small_grouped<RN_FP32_4M><<<grid, 256, 0, s>>>(t);
+      else if (tile == 1) cgemm_f32_4m_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 2) cgemm_f32_4m_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 3) cgemm_f32_4m_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
+      else cgemm_f32_4m_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
+      break;
+  }
+  return hipGetLastError();
 }
 
 // ===========================================================================

@@ -129,8 +129,7 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
     return fail(RN_ERR_INVALID, "path must have nt-1 steps");
   if (nsliced < 0 || nsliced > RN_MAX_SLICED || (nsliced > 0 && !sliced))
     return fail(RN_ERR_INVALID, "bad sliced labels");
-  if (mode != RN_FP64 && mode != RN_FP32_4M && mode != RN_BF16X3)
-    return fail(RN_ERR_UNSUPPORTED, "network mode must be RN_FP64, RN_FP32_4M or RN_BF16X3");
+  if (mode < RN_FP64 || mode > RN_BF16X3) return fail(RN_ERR_INVALID, "unknown mode");
   const int want = mode == RN_FP64 ? RN_C128 : RN_C64;
   NetPlan P;
   P.mode = mode;
@@ -409,8 +408,31 @@ rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
                                       std::to_string(P.ws_bytes) + " bytes needed)");
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return fail(RN_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
-  return enqueue_network(P, T, ws, static_cast<hipStream_t>(stream), amp_dev, slices_dev,
-                         &h->prof);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (use_graphs(h, s)) {
+    uint64_t key = 1469598103934665603ull;
+    key = hash_bytes(key, "network", 7);
+    key = hash_bytes(key, &mode, sizeof(mode));
+    key = hash_bytes(key, &nt, sizeof(nt));
+    for (int i = 0; i < nt; ++i) {
+      key = hash_tensor(key, T[i]);
+      key = hash_bytes(key, labels[i], sizeof(int32_t) * (size_t)T[i].rank);
+    }
+    key = hash_bytes(key, path, sizeof(int32_t) * 2 * (size_t)nsteps);
+    key = hash_bytes(key, &nsliced, sizeof(nsliced));
+    key = hash_bytes(key, sliced, sizeof(int32_t) * (size_t)nsliced);
+    key = hash_bytes(key, &ws, sizeof(ws));
+    key = hash_bytes(key, &amp_dev, sizeof(amp_dev));
+    key = hash_bytes(key, &slices_dev, sizeof(slices_dev));
+    key = hash_bytes(key, &s, sizeof(s));
+    bool done = false;
+    if ((st = replay_graph(h, key, s, &done)) != RN_OK || done) return st;
+    if (seen_before(h, key))
+      return capture_and_launch(h, key, std::vector<char>(), nullptr, s, [&](hipStream_t cs) {
+        return enqueue_network(P, T, ws, cs, amp_dev, slices_dev, &h->prof);
+      });
+  }
+  return enqueue_network(P, T, ws, s, amp_dev, slices_dev, &h->prof);
 }
 
 }  // extern "C"

@@ -83,7 +83,7 @@ static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
                          const int32_t* axesA, const int32_t* axesB, rn_mode mode,
-                         TdPlan* P) {
+                         TdPlan* P, bool allow_splitk) {
   Layout LA, LB;
   rn_status st;
   if ((st = make_layout(A, "A", &LA)) != RN_OK) return st;
@@ -195,7 +195,7 @@ rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
   }
 
   // Workspace.
-  bool split_prec = (mode == RN_BF16X3 || mode == RN_FP32_3M);
+  bool split_prec = (mode == RN_BF16X3);
   p.permuteA = split_prec || !p.permA.identity();
   p.permuteB = split_prec || !p.permB.identity();
   int64_t off = 0;
@@ -217,7 +217,7 @@ rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
       off = align256(off + bbytes);
     }
   }
-  p.splitk = choose_splitk(mode, p.M, p.N, p.K, 1);
+  p.splitk = allow_splitk ? choose_splitk(mode, p.M, p.N, p.K, 1) : 1;
   if (p.splitk > 1) {
     p.off_part = off;
     off = align256(off + int64_t(p.splitk) * p.M * p.N * (mode == RN_FP64 ? 16 : 8));

@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/rn.h"
@@ -76,7 +79,7 @@ struct TdPlan {
 
 rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
                          const int32_t* axesA, const int32_t* axesB, rn_mode mode,
-                         TdPlan* P);
+                         TdPlan* P, bool allow_splitk = true);
 rn_status check_c(const TdPlan& P, const rn_tensor* C);
 
 // Optional per-launch event timing (rn_profile_enable).
@@ -126,6 +129,28 @@ struct GemmLaunch {
   int tile = -1;             // tile config index, -1 = choose
 };
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof = nullptr);
+int gemm_tile_count(rn_mode mode);
+int gemm_default_tile(rn_mode mode, int64_t M, int64_t N, int64_t K);
+
+// Grouped launches: many problems (or permutations) in one kernel launch.
+// The host builds a parameter table plus a prefix sum of workgroups per
+// problem; the table is copied to device memory before the launch.
+struct GroupedLaunch {
+  int n = 0;
+  int kind = 0, es = 8;       // permutes
+  rn_mode mode = RN_FP64;     // GEMMs
+  int tile = 0;
+  int blocks = 0;
+  size_t lds = 0;
+  size_t params_off = 0, prefix_off = 0;
+};
+size_t grouped_perm_build(const std::vector<PermLaunch>& jobs, std::vector<char>& table,
+                          GroupedLaunch& G);
+hipError_t launch_permute_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s);
+size_t grouped_table_bound(rn_mode mode, int n);
+size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
+                          std::vector<char>& table, GroupedLaunch& G);
+hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s);
 int choose_splitk(rn_mode mode, int64_t M, int64_t N, int64_t K, int64_t batch);
 
 rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor* B,
@@ -139,9 +164,49 @@ hipError_t launch_sum_slices(const void* vals, int es, int64_t n, double* out_su
 
 }  // namespace rn
 
+// Captured launch sequences, replayed when a call repeats with identical
+// arguments.  `pinned` holds the parameter tables the graph's copy node reads.
+struct GraphEntry {
+  uint64_t key = 0;
+  hipGraphExec_t exec = nullptr;
+  void* pinned = nullptr;
+  uint64_t last_use = 0;
+};
+
 // Opaque handle.
 struct rn_ctx {
   int device = 0;
   void* red_scratch = nullptr;  // 4096 doubles of device memory for reductions
   rn::Profiler prof;
+  // Tile choices from the autotuner: (mode, log2 M, log2 N, log2 K) -> tile.
+  std::map<std::tuple<int, int, int, int>, int> tune;
+  std::string tune_path;
+  // Pinned staging for parameter tables of direct (not captured) launches.
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t pinned_done = nullptr;
+  bool graphs_enabled = true;
+  std::vector<GraphEntry> graphs;
+  std::vector<uint64_t> seen;  // keys run once directly; a repeat is captured
+  uint64_t use_clock = 0;
 };
+
+namespace rn {
+int tuned_tile(const rn_ctx* h, rn_mode mode, int mbits, int nbits, int kbits);
+// Stage `bytes` of host table data and copy them to `dev` on stream s.
+rn_status upload_table(rn_ctx* h, const std::vector<char>& table, void* dev, hipStream_t s);
+uint64_t hash_bytes(uint64_t h, const void* p, size_t n);
+uint64_t hash_tensor(uint64_t x, const rn_tensor& t);
+// Graph cache: replay_graph launches the graph stored under `key` if any
+// (*done = true); capture_and_launch records `enqueue` (preceded by a copy of
+// `table` to `table_dev` from a pinned buffer the entry owns), stores and
+// launches it.  use_graphs: graphs are enabled, the stream is not the null
+// stream, not already capturing, and kernel timing is off.
+bool use_graphs(const rn_ctx* h, hipStream_t s);
+rn_status replay_graph(rn_ctx* h, uint64_t key, hipStream_t s, bool* done);
+// True when `key` was run before (directly); otherwise remembers it.
+bool seen_before(rn_ctx* h, uint64_t key);
+rn_status capture_and_launch(rn_ctx* h, uint64_t key, const std::vector<char>& table,
+                             void* table_dev, hipStream_t s,
+                             const std::function<rn_status(hipStream_t)>& enqueue);
+}  // namespace rn

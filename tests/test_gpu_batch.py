@@ -1,0 +1,177 @@
+"""GPU parity of batched block tensordots, autotuned tiles and graph replay.
+
+The uneven batch (256 problems, operand ranks 8-24, 2-10 contracted axes,
+output rank <= 24, blocked on the first three axes) is checked on sampled
+outputs of every problem against the oracle; a smaller batch is checked
+whole.  Graph replays are compared bit for bit with the eager run.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import circuits, configs, paths, rng
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_2201_06620_amd as rn
+    assert torch.cuda.is_available()
+    return rn.Context(0)
+
+
+def to_dev(x, mode):
+    import torch
+    dt = torch.complex128 if mode == "fp64" else torch.complex64
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dt).to("cuda")
+
+
+def dense(op):
+    return oracle.from_blocked(op.data, op.dims, op.grid)
+
+
+def blocked_flat_index(dims, grid, flat_dense):
+    # Position in C's block-major buffer of dense (row-major) index flat_dense.
+    flat_dense = np.asarray(flat_dense, dtype=np.int64)
+    if len(dims) == 0:
+        return np.zeros_like(flat_dense)
+    idx = np.array(np.unravel_index(flat_dense, dims)).T
+    ext = np.array(dims) // np.array(grid)
+    bcoord, icoord = idx // ext, idx % ext
+    blin = np.ravel_multi_index(tuple(bcoord.T), grid)
+    ilin = np.ravel_multi_index(tuple(icoord.T), tuple(ext))
+    return blin * int(np.prod(ext)) + ilin
+
+
+def small_batch(count=24, seed=5150, integer=False):
+    r = rng.SplitMix64(seed)
+    probs = []
+    while len(probs) < count:
+        ra, rb, k = r.randint(3, 12), r.randint(3, 12), r.randint(0, 6)
+        if k > min(ra, rb) or ra + rb - 2 * k > 14:
+            continue
+        axa, axb = r.sample(ra, k), r.sample(rb, k)
+        probs.append(configs.make_problem(ra, rb, axa, axb, configs.split_first(ra),
+                                          configs.split_first(rb), seed + 31 * len(probs),
+                                          integer))
+    return probs
+
+
+def run_batch(ctx, probs, mode, autotune=False, workspace=None, outs=None):
+    import torch
+    items = [(to_dev(p.a.data, mode), p.a.dims, p.a.grid, to_dev(p.b.data, mode), p.b.dims,
+              p.b.grid, p.axes_a, p.axes_b) for p in probs]
+    res, fl = ctx.block_tensordot_batch(items, mode, autotune=autotune, workspace=workspace,
+                                        outs=outs)
+    torch.cuda.synchronize()
+    return items, res
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "fp32_3m", "bf16x3"])
+def test_small_batch_full(ctx, mode):
+    tol = {"fp64": 1e-12, "fp32_4m": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3}[mode]
+    probs = small_batch()
+    _, res = run_batch(ctx, probs, mode)
+    for p, (c, cd, cg) in zip(probs, res):
+        ref, rd, rg = oracle.block_tensordot(p.a.data, p.a.dims, p.a.grid, p.b.data, p.b.dims,
+                                             p.b.grid, p.axes_a, p.axes_b)
+        assert cd == rd and cg == rg
+        got = c.cpu().numpy().astype(np.complex128)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err < tol, (mode, err)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "bf16x3"])
+def test_small_batch_integers_bitwise_and_autotune(ctx, mode, tmp_path):
+    probs = small_batch(16, seed=6161, integer=True)
+    _, res = run_batch(ctx, probs, mode, autotune=True)
+    for p, (c, _, _) in zip(probs, res):
+        ref, _, _ = oracle.block_tensordot(p.a.data, p.a.dims, p.a.grid, p.b.data, p.b.dims,
+                                           p.b.grid, p.axes_a, p.axes_b)
+        assert np.array_equal(c.cpu().numpy().astype(np.complex128), ref)
+    f = str(tmp_path / "tune.txt")
+    ctx.tune_save(f)
+    text = open(f).read()
+    assert text.startswith("rn_tune 1") and len(text.splitlines()) > 1
+    ctx.tune_clear()
+    ctx.tune_load(f)
+
+
+def test_config4_sampled(ctx):
+    import torch
+    log("config4: generating 256 problems")
+    probs = configs.config4()
+    assert len(probs) == 256
+    _, res = run_batch(ctx, probs, "fp32_4m", autotune=True)
+    rs = np.random.default_rng(44)
+    worst = 0.0
+    for i, (p, (c, cd, cg)) in enumerate(zip(probs, res)):
+        n = int(np.prod(cd)) if cd else 1
+        idx = np.unique(rs.integers(0, n, size=min(n, 48)))
+        ref = oracle.tensordot_entries(dense(p.a), dense(p.b), p.axes_a, p.axes_b, idx)
+        pos = torch.from_numpy(blocked_flat_index(cd, cg, idx)).to("cuda")
+        got = c[pos].cpu().numpy().astype(np.complex128)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        worst = max(worst, err)
+        assert err < 1e-5, (i, err)
+    log(f"config4 worst sampled e_F = {worst:.3e}")
+
+
+def test_batch_graph_replay_matches_eager(ctx):
+    import torch
+    probs = small_batch(20, seed=777)
+    items = [(to_dev(p.a.data, "fp32_4m"), p.a.dims, p.a.grid, to_dev(p.b.data, "fp32_4m"),
+              p.b.dims, p.b.grid, p.axes_a, p.axes_b) for p in probs]
+    side = torch.cuda.Stream()
+    ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    ctx.set_graphs(False)
+    eager, _ = ctx.block_tensordot_batch(items, "fp32_4m", workspace=ws)
+    torch.cuda.synchronize()
+    eager = [c.clone() for c, _, _ in eager]
+    ctx.set_graphs(True)
+    outs = [torch.empty_like(c) for c in eager]
+    for rep in range(4):      # direct, capture, then replays
+        for o in outs:
+            o.zero_()
+        with torch.cuda.stream(side):
+            ctx.block_tensordot_batch(items, "fp32_4m", workspace=ws, outs=outs)
+        side.synchronize()
+        scratch = torch.randn(1 << 20, device="cuda").sum()   # eager work in between
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), rep
+
+
+def test_network_graph_replay_matches_eager(ctx):
+    import torch
+    circ = circuits.random_circuit(3, 4, 8, seed=91)
+    net = circuits.circuit_network(circ, circuits.random_bitstring(12, 92))
+    path = paths.greedy_path(net.labels, 93, restarts=2)
+    sliced = paths.greedy_slices(net.labels, path, 94, n_slices=3)
+    ts = [torch.from_numpy(np.ascontiguousarray(t.reshape(-1))).to("cuda")
+          for t in net.tensors]
+    ws_n, _, _ = ctx.contract_network_plan(ts, net.labels, path, sliced, "fp64")
+    ws = torch.empty(max(ws_n, 1), dtype=torch.uint8, device="cuda")
+    ctx.set_graphs(False)
+    eager = ctx.contract_network(ts, net.labels, path, sliced, "fp64", workspace=ws).clone()
+    torch.cuda.synchronize()
+    ctx.set_graphs(True)
+    side = torch.cuda.Stream()
+    amp = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        amp.zero_()
+        with torch.cuda.stream(side):
+            ctx.contract_network(ts, net.labels, path, sliced, "fp64", amp=amp, workspace=ws)
+        side.synchronize()
+        torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.equal(amp, eager), rep

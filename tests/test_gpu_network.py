@@ -14,7 +14,7 @@ from workloads import circuits, configs, paths
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32_4m": 1e-5, "bf16x3": 1e-3}
+TOL = {"fp64": 1e-12, "fp32_4m": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3}
 
 
 def log(msg):
@@ -45,7 +45,7 @@ def amp_err(a, ref, n):
     return abs(a - ref) / max(abs(ref), 2.0 ** (-n / 2))
 
 
-@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "bf16x3"])
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "fp32_3m", "bf16x3"])
 def test_config2_amplitude(ctx, mode):
     log(f"config2 network mode={mode}")
     w = configs.config2()
