@@ -68,6 +68,75 @@ def traffic_from_profiles(kernel, per_launch_units):
         return None
 
 
+def _make_request(i):
+    from workloads import configs
+    return configs.config5_request(0, i)
+
+
+def run_serving(args, torch, rn, log):
+    """Requests of the serving workload: seeded random circuits on 30-53-site
+    grids, 8-14 cycles, sliced until the largest intermediate has rank <= 30
+    (at most 6 sliced bonds), complex64 with FP64 slice sums.  First all
+    requests are queued at once (saturated throughput), then the same requests
+    arrive as a Poisson stream at a fraction of that rate."""
+    import threading
+    from concurrent.futures import ProcessPoolExecutor
+
+    t0 = time.time()
+    with ProcessPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+        reqs = list(ex.map(_make_request, range(args.serve_requests)))
+    log(f"serving: {len(reqs)} requests planned in {time.time() - t0:.1f}s; sites "
+        f"{[w.meta['sites'] for w in reqs]}")
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.9 * free)
+    srv = rn.Server(0, hbm_budget=budget, max_active=4)
+    tensors = [[t.astype(np.complex64) for t in w.network.tensors] for w in reqs]
+
+    def submit(i):
+        w = reqs[i]
+        return srv.submit(tensors[i], w.network.labels, w.path, w.sliced, "fp32_4m")
+
+    # Warm-up (kernel first use), not counted.
+    srv.wait(submit(0))
+    t = time.perf_counter()
+    tickets = [submit(i) for i in range(len(reqs))]
+    sat = [srv.wait(tk) for tk in tickets]
+    sat_s = time.perf_counter() - t
+    thr = len(reqs) / sat_s
+    lam = args.serve_load * thr
+    gaps = np.random.default_rng(2201).exponential(1.0 / lam, size=len(reqs))
+    tk2 = [None] * len(reqs)
+
+    def client():
+        for i, g in enumerate(gaps):
+            time.sleep(float(g))
+            tk2[i] = submit(i)
+
+    t = time.perf_counter()
+    th = threading.Thread(target=client)
+    th.start()
+    th.join()
+    res = [srv.wait(tk) for tk in tk2]
+    el = time.perf_counter() - t
+    srv.close()
+    lat = [1e3 * r["latency_s"] for r in res]
+    same = sum(1 for a, b in zip(sat, res) if a["amp"] == b["amp"] and a["status"] == 0)
+    out = {"workload": "amplitude requests for seeded random circuits on 30-53-site grids, 8-14 "
+                       "cycles, sliced to largest intermediate rank <= 30 (<= 6 sliced bonds), "
+                       "complex64 FP32-4M with FP64 slice sums; HBM-footprint admission, 4 "
+                       "concurrent slots",
+           "requests": len(reqs), "saturated_amplitudes_per_s": thr,
+           "arrival_rate_per_s": lam, "load": args.serve_load,
+           "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+           "amplitudes_per_s": len(reqs) / el,
+           "mean_queue_ms": 1e3 * float(np.mean([r["queue_s"] for r in res])),
+           "identical_to_saturated_run": same,
+           "total_flops": float(sum(w.meta["total_flops"] for w in reqs)),
+           "statuses": sorted(set(r["status"] for r in res))}
+    log(f"serving: {out}")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +150,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true")
     ap.add_argument("--no-batch", dest="batch", action="store_false")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-load", type=float, default=0.75,
+                    help="Poisson arrival rate as a fraction of the saturated throughput")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 1 GiB copy kernel first (HBM counter calibration)")
     args = ap.parse_args()
@@ -287,6 +359,11 @@ def main() -> int:
         del items, res, outs, wsb
         torch.cuda.empty_cache()
 
+    # ------------------------------- serving: Poisson stream of requests
+    serving = None
+    if args.serve_requests > 0:
+        serving = run_serving(args, torch, rn, log)
+
     k = main_res["kernels"]
     gemm_ms = k["gemm"][0] / max(k["gemm"][1], 1)
     achieved = flops / (gemm_ms * 1e-3) / 1e12
@@ -334,6 +411,7 @@ def main() -> int:
         "modes": modes,
         "amplitude_latency": amp,
         "batch": batch,
+        "serving": serving,
         "kernel_ms_per_step": {kk: v[0] / args.steps for kk, v in k.items()},
     }
     print(json.dumps(line), flush=True)

@@ -197,6 +197,44 @@ rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
                               size_t ws_bytes, void* stream, double* amp_dev, double* slices_dev);
 
 /* ------------------------------------------------------------------------
+ * Amplitude server (continuous admission of sliced-network requests).
+ *
+ * rn_server_create binds a server to a device with its own library handle,
+ * a device arena of hbm_budget bytes (allocated once) and max_active slots
+ * (HIP streams, 1..16).  rn_server_submit copies a request -- a network as
+ * for rn_contract_network but with HOST tensor data -- into the server's
+ * queue and returns a ticket; it never blocks on the GPU.  A worker thread
+ * admits queued requests in arrival order whenever a slot is free and the
+ * request's footprint (its tensors + the planned workspace + 256 bytes)
+ * fits the free arena; admitted requests run concurrently on their slots
+ * and keep their tensors resident until they finish.  A request whose
+ * footprint exceeds the whole budget completes with status RN_ERR_OOM.
+ * Results: amplitude, latency = completion - submit, and its split into
+ * queueing and running time.  A request's amplitude does not depend on what
+ * else runs (every kernel is deterministic and per-request).
+ * rn_server_destroy waits for all submitted requests, then frees everything.
+ * ------------------------------------------------------------------------ */
+typedef struct rn_server* rn_server_t;
+typedef struct {
+  double amp[2];          /* (re, im) of the amplitude, FP64 slice sum */
+  double latency_s;       /* completion - submit */
+  double queue_s;         /* admission - submit */
+  double run_s;           /* completion - admission */
+  double footprint_bytes; /* arena bytes the request held */
+  int32_t status;         /* RN_OK, RN_ERR_OOM, or the error of the enqueue */
+} rn_result;
+rn_status rn_server_create(int device, size_t hbm_budget, int32_t max_active, rn_server_t* srv);
+rn_status rn_server_submit(rn_server_t srv, int32_t nt, const rn_tensor* T,
+                           const int32_t* const* labels, int32_t nsteps, const int32_t* path,
+                           int32_t nsliced, const int32_t* sliced, rn_mode mode,
+                           uint64_t* ticket);
+rn_status rn_server_poll(rn_server_t srv, uint64_t ticket, int32_t* done, rn_result* res);
+rn_status rn_server_wait(rn_server_t srv, uint64_t ticket, rn_result* res);
+rn_status rn_server_stats(rn_server_t srv, int64_t* queued, int64_t* active, int64_t* completed,
+                          size_t* bytes_in_use);
+rn_status rn_server_destroy(rn_server_t srv);
+
+/* ------------------------------------------------------------------------
  * FP64 reductions on the GPU (slice sums and norms, Section II.B).
  * rn_norm2: out_dev[0] = sum |x|^2 over all elements of T, in FP64.
  * rn_sum_c128: out_dev[0..1] = sum of n complex128 values (device, n <= 2^20),

@@ -30,13 +30,21 @@ EXPORTS = ["rn_create", "rn_destroy", "rn_status_str", "rn_last_error",
            "rn_block_footprint", "rn_block_tensordot_batch_plan", "rn_block_tensordot_batch",
            "rn_contract_network_plan", "rn_contract_network", "rn_norm2", "rn_sum_c128",
            "rn_profile_enable", "rn_profile_read", "rn_autotune_batch", "rn_tune_save",
-           "rn_tune_load", "rn_tune_clear", "rn_set_graphs"]
+           "rn_tune_load", "rn_tune_clear", "rn_set_graphs", "rn_server_create",
+           "rn_server_submit", "rn_server_poll", "rn_server_wait", "rn_server_stats",
+           "rn_server_destroy"]
 
 
 class RnError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class RnResult(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double * 2), ("latency_s", ctypes.c_double),
+                ("queue_s", ctypes.c_double), ("run_s", ctypes.c_double),
+                ("footprint_bytes", ctypes.c_double), ("status", ctypes.c_int32)]
 
 
 class RnTensor(ctypes.Structure):
@@ -88,6 +96,15 @@ def lib():
         L.rn_tune_load.argtypes = [p, ctypes.c_char_p]
         L.rn_tune_clear.argtypes = [p]
         L.rn_set_graphs.argtypes = [p, ctypes.c_int]
+        L.rn_server_create.argtypes = [ctypes.c_int, sz, i32, ctypes.POINTER(p)]
+        L.rn_server_submit.argtypes = [p, i32, T, pp, i32, p, i32, p, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_uint64)]
+        L.rn_server_poll.argtypes = [p, ctypes.c_uint64, ctypes.POINTER(i32),
+                                     ctypes.POINTER(RnResult)]
+        L.rn_server_wait.argtypes = [p, ctypes.c_uint64, ctypes.POINTER(RnResult)]
+        L.rn_server_stats.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64), ctypes.POINTER(sz)]
+        L.rn_server_destroy.argtypes = [p]
         L.rn_profile_read.argtypes = [p, p, p]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype if name in (
@@ -400,3 +417,73 @@ class Context:
         check(lib().rn_sum_c128(self.h, vals.numel(), vals.data_ptr(), out.data_ptr(),
                                 self._stream()), "sum_c128")
         return out
+
+
+class Server:
+    """Amplitude server (rn_server_*): submit networks with host tensors,
+    collect amplitudes and latencies.  All GPU work runs in the library's
+    worker thread."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_active: int = 4):
+        s = ctypes.c_void_p()
+        check(lib().rn_server_create(device, hbm_budget, max_active, ctypes.byref(s)),
+              "rn_server_create")
+        self.s = s
+
+    def submit(self, tensors, labels, path, sliced=(), mode="fp64") -> int:
+        """tensors: numpy complex arrays (complex128 for fp64, complex64 otherwise)."""
+        dt = dtype_of_mode(mode)
+        want = np.complex128 if dt == C128 else np.complex64
+        n = len(tensors)
+        Ts = (RnTensor * n)()
+        lab = (ctypes.c_void_p * n)()
+        keep = []
+        for i, (t, l) in enumerate(zip(tensors, labels)):
+            a = np.ascontiguousarray(np.asarray(t).reshape(-1), dtype=want)
+            keep.append(a)
+            Ts[i] = descriptor([2] * len(l), None, dt, a.ctypes.data)
+            x, px = _arr32(l)
+            keep.append(x)
+            lab[i] = px
+        pth, pp = _arr32([x for st in path for x in st])
+        sl, ps = _arr32(sliced)
+        tk = ctypes.c_uint64()
+        check(lib().rn_server_submit(self.s, n, Ts, lab, len(path), pp, len(sl), ps,
+                                     mode_id(mode), ctypes.byref(tk)), "submit")
+        return tk.value
+
+    @staticmethod
+    def _res(r):
+        return {"amp": complex(r.amp[0], r.amp[1]), "latency_s": r.latency_s,
+                "queue_s": r.queue_s, "run_s": r.run_s, "footprint": r.footprint_bytes,
+                "status": r.status}
+
+    def poll(self, ticket):
+        d = ctypes.c_int32()
+        r = RnResult()
+        check(lib().rn_server_poll(self.s, ticket, ctypes.byref(d), ctypes.byref(r)), "poll")
+        return self._res(r) if d.value else None
+
+    def wait(self, ticket):
+        r = RnResult()
+        check(lib().rn_server_wait(self.s, ticket, ctypes.byref(r)), "wait")
+        return self._res(r)
+
+    def stats(self):
+        q, a, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        b = ctypes.c_size_t()
+        check(lib().rn_server_stats(self.s, ctypes.byref(q), ctypes.byref(a), ctypes.byref(c),
+                                    ctypes.byref(b)), "stats")
+        return {"queued": q.value, "active": a.value, "completed": c.value,
+                "bytes_in_use": b.value}
+
+    def close(self):
+        if self.s:
+            lib().rn_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librosnet.so")
-SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "network.cpp", "batch.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "network.cpp", "batch.cpp", "serve.cpp"]
 ARCH = os.environ.get("RN_OFFLOAD_ARCH", "gfx950")
 
 
@@ -17,7 +17,7 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Wall", "-Wno-unused-result",
+           "-Wall", "-Wno-unused-result", "-pthread",
            # Packed FP32 instructions stay off: hipcc would otherwise form
            # v_pk_* ops from plain float code.
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

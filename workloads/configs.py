@@ -157,7 +157,7 @@ def config5_request(trial: int, index: int, max_rank: int = 30, max_sliced: int 
         cyc = rng.randint(*cycles)
         rows, cols = circuits.grid_shape(n)
         wl = circuit_workload(rows, cols, cyc, substream_seed(seed, attempt),
-                              max_rank=max_rank, n_sites=n, restarts=4)
+                              max_rank=max_rank, n_sites=n, restarts=2)
         total = wl.meta["flops_per_slice"] * (1 << len(wl.sliced))
         if len(wl.sliced) <= max_sliced and total <= flops_cap and len(wl.sliced) >= 0:
             wl.meta.update({"sites": n, "cycles": cyc, "attempt": attempt,
