@@ -1378,6 +1378,155 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
 }
 
 // ===========================================================================
+// Small network steps, evaluated straight from the stored layouts.  One
+// workgroup computes 256 consecutive outputs of one slice batch; the K-part
+// offsets of both operands are tabulated in LDS once per workgroup.  All
+// independent small steps of one dependency level of the path share one
+// launch.
+// ===========================================================================
+struct DirectTable {
+  const DirectStep* steps;
+  const int32_t* prefix;
+  int n;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
+  __shared__ int32_t koa[kDirectMaxK];
+  __shared__ int32_t kob[kDirectMaxK];
+  int lo = 0, hi = g.n - 1;
+  const int bid = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (g.prefix[mid] <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  const DirectStep& d = g.steps[lo];
+  const int local = bid - g.prefix[lo];
+  const int b = local / d.blocks_per_batch;
+  const int64_t e = int64_t(local % d.blocks_per_batch) * 256 + threadIdx.x;
+  for (int k = threadIdx.x; k < d.K; k += 256) {
+    int32_t oa = 0, ob = 0;
+    for (int i = 0; i < d.kbits; ++i)
+      if ((k >> i) & 1) {
+        oa += int32_t(1) << d.ak[i];
+        ob += int32_t(1) << d.bk[i];
+      }
+    koa[k] = oa;
+    kob[k] = ob;
+  }
+  __syncthreads();
+  if (e >= d.M * d.N) return;
+  const int64_t m = e >> d.nbits, n = e & (d.N - 1);
+  int64_t ao = 0, bo = 0;
+  for (int i = 0; i < d.nbb; ++i)
+    if ((b >> i) & 1) {
+      ao += d.a_bs[i];
+      bo += d.b_bs[i];
+    }
+  for (int i = 0; i < d.mbits; ++i)
+    if ((m >> i) & 1) ao += int64_t(1) << d.am[i];
+  for (int i = 0; i < d.nbits; ++i)
+    if ((n >> i) & 1) bo += int64_t(1) << d.bn[i];
+  const int64_t co = int64_t(b) * d.M * d.N + e;
+  if constexpr (MODE == RN_FP64) {
+    const double2* A = reinterpret_cast<const double2*>(d.A) + ao;
+    const double2* B = reinterpret_cast<const double2*>(d.B) + bo;
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < d.K; ++k) {
+      double2 a = A[koa[k]], bb = B[kob[k]];
+      re = fma(a.x, bb.x, re);
+      re = fma(-a.y, bb.y, re);
+      im = fma(a.x, bb.y, im);
+      im = fma(a.y, bb.x, im);
+    }
+    reinterpret_cast<double2*>(d.C)[co] = make_double2(re, im);
+  } else {
+    const float2* A = reinterpret_cast<const float2*>(d.A) + ao;
+    const float2* B = reinterpret_cast<const float2*>(d.B) + bo;
+    float re = 0.f, im = 0.f;
+    if constexpr (MODE == RN_FP32_3M) {
+      float t1 = 0.f, t2 = 0.f, t3 = 0.f;
+      for (int k = 0; k < d.K; ++k) {
+        float2 a = A[koa[k]], bb = B[kob[k]];
+        t1 = fmaf(a.x, bb.x, t1);
+        t2 = fmaf(a.y, bb.y, t2);
+        t3 = fmaf(a.x + a.y, bb.x + bb.y, t3);
+      }
+      re = t1 - t2;
+      im = (t3 - t1) - t2;
+    } else if constexpr (MODE == RN_BF16X3) {
+      for (int k = 0; k < d.K; ++k) {
+        float2 a = A[koa[k]], bb = B[kob[k]];
+        uint32_t h0, l0, h1, l1, h2, l2, h3, l3;
+        bf16_split(a.x, h0, l0);
+        bf16_split(a.y, h1, l1);
+        bf16_split(bb.x, h2, l2);
+        bf16_split(bb.y, h3, l3);
+        const float ahr = __uint_as_float(h0 << 16), alr = __uint_as_float(l0 << 16);
+        const float ahi = __uint_as_float(h1 << 16), ali = __uint_as_float(l1 << 16);
+        const float bhr = __uint_as_float(h2 << 16), blr = __uint_as_float(l2 << 16);
+        const float bhi = __uint_as_float(h3 << 16), bli = __uint_as_float(l3 << 16);
+        re = fmaf(alr, bhr, re); re = fmaf(-ali, bhi, re);
+        im = fmaf(alr, bhi, im); im = fmaf(ali, bhr, im);
+        re = fmaf(ahr, blr, re); re = fmaf(-ahi, bli, re);
+        im = fmaf(ahr, bli, im); im = fmaf(ahi, blr, im);
+        re = fmaf(ahr, bhr, re); re = fmaf(-ahi, bhi, re);
+        im = fmaf(ahr, bhi, im); im = fmaf(ahi, bhr, im);
+      }
+    } else {
+      for (int k = 0; k < d.K; ++k) {
+        float2 a = A[koa[k]], bb = B[kob[k]];
+        re = fmaf(a.x, bb.x, re);
+        re = fmaf(-a.y, bb.y, re);
+        im = fmaf(a.x, bb.y, im);
+        im = fmaf(a.y, bb.x, im);
+      }
+    }
+    reinterpret_cast<float2*>(d.C)[co] = make_float2(re, im);
+  }
+}
+
+size_t grouped_direct_bound(int n) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  return al(size_t(n) * sizeof(DirectStep)) + al((size_t(n) + 1) * sizeof(int32_t));
+}
+
+size_t grouped_direct_build(const std::vector<DirectStep>& steps, rn_mode mode,
+                            std::vector<char>& table, GroupedLaunch& G) {
+  G = GroupedLaunch{};
+  G.n = (int)steps.size();
+  G.mode = mode;
+  if (steps.empty()) return 0;
+  std::vector<int32_t> prefix(steps.size() + 1, 0);
+  for (size_t i = 0; i < steps.size(); ++i)
+    prefix[i + 1] = prefix[i] + steps[i].blocks_per_batch * (1 << steps[i].nbb);
+  G.blocks = prefix.back();
+  G.params_off = 0;
+  G.prefix_off = (steps.size() * sizeof(DirectStep) + 255) & ~size_t(255);
+  size_t bytes = (G.prefix_off + prefix.size() * sizeof(int32_t) + 255) & ~size_t(255);
+  table.assign(bytes, 0);
+  memcpy(table.data(), steps.data(), steps.size() * sizeof(DirectStep));
+  memcpy(table.data() + G.prefix_off, prefix.data(), prefix.size() * sizeof(int32_t));
+  return bytes;
+}
+
+hipError_t launch_direct_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s) {
+  if (G.n == 0 || G.blocks == 0) return hipSuccess;
+  DirectTable t;
+  t.steps = reinterpret_cast<const DirectStep*>(static_cast<const char*>(table_dev) + G.params_off);
+  t.prefix = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.prefix_off);
+  t.n = G.n;
+  switch (G.mode) {
+    case RN_FP64: direct_grouped<RN_FP64><<<G.blocks, 256, 0, s>>>(t); break;
+    case RN_FP32_3M: direct_grouped<RN_FP32_3M><<<G.blocks, 256, 0, s>>>(t); break;
+    case RN_BF16X3: direct_grouped<RN_BF16X3><<<G.blocks, 256, 0, s>>>(t); break;
+    default: direct_grouped<RN_FP32_4M><<<G.blocks, 256, 0, s>>>(t); break;
+  }
+  return hipGetLastError();
+}
+
+// ===========================================================================
 // FP64 reductions.  Deterministic: every element goes to a fixed lane, lanes
 // combine in a fixed butterfly order (cross-lane shuffles), waves in a fixed
 // order through LDS, blocks in ascending order in a second pass.

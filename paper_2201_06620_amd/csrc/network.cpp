@@ -79,6 +79,10 @@ struct NStep {
   int nbb = 0;
   int64_t a_bs[RN_MAX_SLICED] = {0}, b_bs[RN_MAX_SLICED] = {0}, c_bs[RN_MAX_SLICED] = {0};
   int splitk = 1;
+  int64_t abytes = 0, bbytes = 0, pbytes = 0;  // temporaries
+  bool direct = false;  // small step: evaluated from the stored layouts
+  DirectStep dstep;     // its bit maps (pointers filled at enqueue time)
+  int level = 0;        // 1 + max level of its operands (inputs: 0)
 };
 
 struct NetPlan {
@@ -90,6 +94,8 @@ struct NetPlan {
   int64_t ws_bytes = 0;
   double flops = 0;
   int max_rank = 0;
+  std::vector<std::vector<int>> levels;  // step indices per dependency level
+  int64_t table_off = 0;                 // grouped small-step tables in ws
 };
 
 int popc(uint32_t x) { return __builtin_popcount(x); }
@@ -181,6 +187,7 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
   };
   for (int i = 0; i < nt; ++i) P.max_rank = std::max(P.max_rank, (int)eff(P.T[i]).size());
   const bool split_prec = (mode == RN_BF16X3);
+  std::vector<int> level(nt, 0);
   for (int s = 0; s < nsteps; ++s) {
     int a = path[2 * s], b = path[2 * s + 1];
     if (a < 0 || b < 0 || a >= nt + s || b >= nt + s || a == b || !alive[a] || !alive[b])
@@ -240,54 +247,148 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
       st.c_bs[q] = (int64_t(1) << q) * st.M * st.N;
     }
     int64_t nbatch = int64_t(1) << st.nbb;
-    int64_t abytes = (st.M * st.K << popc(ta.dmask)) * (split_prec ? 4 : P.es);
-    int64_t bbytes = (st.N * st.K << popc(tb.dmask)) * (split_prec ? 4 : P.es);
-    if (st.permuteA) {
-      st.offA = arena.alloc(abytes);
-      if (split_prec) st.offA2 = arena.alloc(abytes);
+    auto stored_bits = [&](const NTensor& t) {
+      return t.input ? (int)t.labels.size() : (int)t.labels.size() + popc(t.dmask);
+    };
+    st.direct = st.K <= kDirectMaxK && st.M * st.N * st.K * nbatch <= (int64_t(1) << 24) &&
+                stored_bits(ta) < 31 && stored_bits(tb) < 31 && st.nbb <= 15;
+    if (st.direct) {
+      DirectStep& d = st.dstep;
+      d.M = st.M;
+      d.N = st.N;
+      d.K = st.K;
+      d.mbits = mb;
+      d.nbits = nbits;
+      d.kbits = kb;
+      d.nbb = st.nbb;
+      d.blocks_per_batch = (int)((st.M * st.N + 255) / 256);
+      for (int i = 0; i < mb; ++i) d.am[i] = (int8_t)pos_of_label(ta, fa[mb - 1 - i]);
+      for (int i = 0; i < nbits; ++i) d.bn[i] = (int8_t)pos_of_label(tb, fb[nbits - 1 - i]);
+      for (int i = 0; i < kb; ++i) {
+        d.ak[i] = (int8_t)pos_of_label(ta, shared[kb - 1 - i]);
+        d.bk[i] = (int8_t)pos_of_label(tb, shared[kb - 1 - i]);
+      }
+      for (int q = 0; q < st.nbb; ++q) {
+        int sidx = dcl[st.nbb - 1 - q];
+        d.a_bs[q] = ((ta.dmask >> sidx) & 1) ? int64_t(1) << pos_of_slice(ta, sidx, sl) : 0;
+        d.b_bs[q] = ((tb.dmask >> sidx) & 1) ? int64_t(1) << pos_of_slice(tb, sidx, sl) : 0;
+      }
+      st.permuteA = st.permuteB = false;
     }
-    if (st.permuteB) {
-      st.offB = arena.alloc(bbytes);
-      if (split_prec) st.offB2 = arena.alloc(bbytes);
-    }
-    st.splitk = choose_splitk(mode, st.M, st.N, st.K, nbatch);
-    int64_t pbytes = int64_t(st.splitk) * nbatch * st.M * st.N * P.es;
-    if (st.splitk > 1) st.offPart = arena.alloc(pbytes);
+    st.abytes = (st.M * st.K << popc(ta.dmask)) * (split_prec ? 4 : P.es);
+    st.bbytes = (st.N * st.K << popc(tb.dmask)) * (split_prec ? 4 : P.es);
+    st.splitk = st.direct ? 1 : choose_splitk(mode, st.M, st.N, st.K, nbatch);
+    st.pbytes = st.splitk > 1 ? int64_t(st.splitk) * nbatch * st.M * st.N * P.es : 0;
     NTensor tc;
     for (int l : fa) tc.labels.push_back(l);
     for (int l : fb) tc.labels.push_back(l);
     tc.dmask = dc;
     tc.bytes = nbatch * st.M * st.N * P.es;
-    tc.off = arena.alloc(tc.bytes);
     P.max_rank = std::max(P.max_rank, mb + nbits);
     P.flops += 8.0 * double(st.M) * double(st.N) * double(st.K) * double(nbatch);
-    // Temporaries die with the step; operands that are intermediates die too.
-    if (st.permuteA) {
-      arena.release(st.offA, abytes);
-      if (split_prec) arena.release(st.offA2, abytes);
-    }
-    if (st.permuteB) {
-      arena.release(st.offB, bbytes);
-      if (split_prec) arena.release(st.offB2, bbytes);
-    }
-    if (st.splitk > 1) arena.release(st.offPart, pbytes);
-    if (!ta.input) arena.release(ta.off, ta.bytes);
-    if (!tb.input) arena.release(tb.off, tb.bytes);
+    st.level = 1 + std::max(level[a], level[b]);
+    level.push_back(st.level);
+    if ((int)P.levels.size() < st.level) P.levels.resize(st.level);
+    P.levels[st.level - 1].push_back(s);
     P.T.push_back(tc);
     P.steps.push_back(st);
     alive[nt + s] = true;
   }
   const NTensor& fin = P.T.back();
   if (!eff(fin).empty()) return fail(RN_ERR_INVALID, "network does not close to a scalar");
-  P.ws_bytes = arena.peak;
+  // Workspace in execution order: level by level; the small steps of a
+  // level run together in one launch, so their results are all live at once
+  // and their operands are released only after that launch; the large steps
+  // of the level then run one after another.
+  auto release_operand = [&](int id) {
+    if (!P.T[id].input) arena.release(P.T[id].off, P.T[id].bytes);
+  };
+  for (auto& lv : P.levels) {
+    for (int si : lv)
+      if (P.steps[si].direct) P.T[nt + si].off = arena.alloc(P.T[nt + si].bytes);
+    for (int si : lv)
+      if (P.steps[si].direct) {
+        release_operand(P.steps[si].a);
+        release_operand(P.steps[si].b);
+      }
+    for (int si : lv) {
+      NStep& st = P.steps[si];
+      if (st.direct) continue;
+      if (st.permuteA) {
+        st.offA = arena.alloc(st.abytes);
+        if (split_prec) st.offA2 = arena.alloc(st.abytes);
+      }
+      if (st.permuteB) {
+        st.offB = arena.alloc(st.bbytes);
+        if (split_prec) st.offB2 = arena.alloc(st.bbytes);
+      }
+      if (st.splitk > 1) st.offPart = arena.alloc(st.pbytes);
+      P.T[nt + si].off = arena.alloc(P.T[nt + si].bytes);
+      if (st.permuteA) {
+        arena.release(st.offA, st.abytes);
+        if (split_prec) arena.release(st.offA2, st.abytes);
+      }
+      if (st.permuteB) {
+        arena.release(st.offB, st.bbytes);
+        if (split_prec) arena.release(st.offB2, st.bbytes);
+      }
+      if (st.splitk > 1) arena.release(st.offPart, st.pbytes);
+      release_operand(st.a);
+      release_operand(st.b);
+    }
+  }
+  P.table_off = (arena.peak + 255) & ~int64_t(255);
+  int64_t tbytes = 0;
+  for (auto& lv : P.levels) {
+    int nd = 0;
+    for (int si : lv) nd += P.steps[si].direct ? 1 : 0;
+    if (nd) tbytes += (int64_t)grouped_direct_bound(nd);
+  }
+  P.ws_bytes = P.table_off + tbytes;
   *NP = std::move(P);
   return RN_OK;
 }
 
 }  // namespace
 
+// Parameter tables of the grouped small-step launches, one per level, with
+// operand pointers resolved for this call.
+static void build_net_tables(const NetPlan& P, const rn_tensor* T, void* ws,
+                             std::vector<char>& blob, std::vector<GroupedLaunch>& per_level) {
+  char* w = static_cast<char*>(ws);
+  const int nt = (int)P.T.size() - (int)P.steps.size();
+  auto ptr = [&](int id) -> const void* {
+    const NTensor& t = P.T[id];
+    return t.input ? T[t.input_idx].data : static_cast<const void*>(w + t.off);
+  };
+  blob.clear();
+  per_level.assign(P.levels.size(), GroupedLaunch{});
+  std::vector<char> part;
+  for (size_t L = 0; L < P.levels.size(); ++L) {
+    std::vector<DirectStep> ds;
+    for (int si : P.levels[L]) {
+      const NStep& st = P.steps[si];
+      if (!st.direct) continue;
+      DirectStep d = st.dstep;
+      d.A = ptr(st.a);
+      d.B = ptr(st.b);
+      d.C = w + P.T[nt + si].off;
+      ds.push_back(d);
+    }
+    if (ds.empty()) continue;
+    GroupedLaunch G;
+    size_t base = blob.size();
+    grouped_direct_build(ds, P.mode, part, G);
+    G.params_off += base;
+    G.prefix_off += base;
+    blob.insert(blob.end(), part.begin(), part.end());
+    per_level[L] = G;
+  }
+}
+
 static rn_status enqueue_network(const NetPlan& P, const rn_tensor* T, void* ws, hipStream_t s,
-                                 double* amp_dev, double* slices_dev, Profiler* prof) {
+                                 double* amp_dev, double* slices_dev, Profiler* prof,
+                                 const std::vector<GroupedLaunch>& per_level) {
   char* w = static_cast<char*>(ws);
   const bool split_prec = (P.mode == RN_BF16X3);
   auto ptr = [&](int id) -> const void* {
@@ -296,72 +397,83 @@ static rn_status enqueue_network(const NetPlan& P, const rn_tensor* T, void* ws,
   };
   hipError_t e;
   const int nt = (int)P.T.size() - (int)P.steps.size();
-  for (size_t si = 0; si < P.steps.size(); ++si) {
-    const NStep& st = P.steps[si];
-    const void* am = ptr(st.a);
-    const void* bm = ptr(st.b);
-    const void* am2 = nullptr;
-    const void* bm2 = nullptr;
-    if (st.permuteA) {
-      PermLaunch L;
-      L.in = am;
-      L.out = w + st.offA;
-      L.out2 = split_prec ? w + st.offA2 : nullptr;
-      L.perm = st.permA;
-      L.in_es = P.es;
-      L.kind = split_prec ? 1 : 0;
-      int ev = prof->begin(0, s);
-      e = launch_permute(L, s);
+  for (size_t L = 0; L < P.levels.size(); ++L) {
+    // All small steps of this level in one launch, then the large ones.
+    if (per_level[L].n > 0) {
+      int ev = prof->begin(1, s);
+      e = launch_direct_grouped(per_level[L], w + P.table_off, s);
       prof->end(ev, s);
       if (e != hipSuccess)
-        return fail(RN_ERR_HIP, std::string("network permute: ") + hipGetErrorString(e));
-      am = L.out;
-      am2 = L.out2;
+        return fail(RN_ERR_HIP, std::string("network small steps: ") + hipGetErrorString(e));
     }
-    if (st.permuteB) {
-      PermLaunch L;
-      L.in = bm;
-      L.out = w + st.offB;
-      L.out2 = split_prec ? w + st.offB2 : nullptr;
-      L.perm = st.permB;
-      L.in_es = P.es;
-      L.kind = split_prec ? 1 : 0;
-      int ev = prof->begin(0, s);
-      e = launch_permute(L, s);
-      prof->end(ev, s);
-      if (e != hipSuccess)
-        return fail(RN_ERR_HIP, std::string("network permute: ") + hipGetErrorString(e));
-      bm = L.out;
-      bm2 = L.out2;
+    for (int si : P.levels[L]) {
+      const NStep& st = P.steps[si];
+      if (st.direct) continue;
+      const void* am = ptr(st.a);
+      const void* bm = ptr(st.b);
+      const void* am2 = nullptr;
+      const void* bm2 = nullptr;
+      if (st.permuteA) {
+        PermLaunch pl;
+        pl.in = am;
+        pl.out = w + st.offA;
+        pl.out2 = split_prec ? w + st.offA2 : nullptr;
+        pl.perm = st.permA;
+        pl.in_es = P.es;
+        pl.kind = split_prec ? 1 : 0;
+        int ev = prof->begin(0, s);
+        e = launch_permute(pl, s);
+        prof->end(ev, s);
+        if (e != hipSuccess)
+          return fail(RN_ERR_HIP, std::string("network permute: ") + hipGetErrorString(e));
+        am = pl.out;
+        am2 = pl.out2;
+      }
+      if (st.permuteB) {
+        PermLaunch pl;
+        pl.in = bm;
+        pl.out = w + st.offB;
+        pl.out2 = split_prec ? w + st.offB2 : nullptr;
+        pl.perm = st.permB;
+        pl.in_es = P.es;
+        pl.kind = split_prec ? 1 : 0;
+        int ev = prof->begin(0, s);
+        e = launch_permute(pl, s);
+        prof->end(ev, s);
+        if (e != hipSuccess)
+          return fail(RN_ERR_HIP, std::string("network permute: ") + hipGetErrorString(e));
+        bm = pl.out;
+        bm2 = pl.out2;
+      }
+      GemmLaunch g;
+      g.mode = P.mode;
+      g.A = am;
+      g.B = bm;
+      g.A2 = am2;
+      g.B2 = bm2;
+      g.C = w + P.T[nt + si].off;
+      g.M = st.M;
+      g.N = st.N;
+      g.K = st.K;
+      g.lda = st.K;
+      g.ldb = st.K;
+      g.crow.shift = 62;
+      g.crow.hi = 0;
+      g.crow.lo = st.N;
+      g.ccol.shift = 62;
+      g.ccol.hi = 0;
+      g.ccol.lo = 1;
+      g.nbb = st.nbb;
+      for (int q = 0; q < st.nbb; ++q) {
+        g.a_bstride[q] = st.a_bs[q];
+        g.b_bstride[q] = st.b_bs[q];
+        g.c_bstride[q] = st.c_bs[q];
+      }
+      g.splitk = st.splitk;
+      g.partial = st.splitk > 1 ? w + st.offPart : nullptr;
+      if ((e = launch_gemm(g, s, prof)) != hipSuccess)
+        return fail(RN_ERR_HIP, std::string("network GEMM: ") + hipGetErrorString(e));
     }
-    GemmLaunch g;
-    g.mode = P.mode;
-    g.A = am;
-    g.B = bm;
-    g.A2 = am2;
-    g.B2 = bm2;
-    g.C = w + P.T[nt + si].off;
-    g.M = st.M;
-    g.N = st.N;
-    g.K = st.K;
-    g.lda = st.K;
-    g.ldb = st.K;
-    g.crow.shift = 62;
-    g.crow.hi = 0;
-    g.crow.lo = st.N;
-    g.ccol.shift = 62;
-    g.ccol.hi = 0;
-    g.ccol.lo = 1;
-    g.nbb = st.nbb;
-    for (int q = 0; q < st.nbb; ++q) {
-      g.a_bstride[q] = st.a_bs[q];
-      g.b_bstride[q] = st.b_bs[q];
-      g.c_bstride[q] = st.c_bs[q];
-    }
-    g.splitk = st.splitk;
-    g.partial = st.splitk > 1 ? w + st.offPart : nullptr;
-    if ((e = launch_gemm(g, s, prof)) != hipSuccess)
-      return fail(RN_ERR_HIP, std::string("network GEMM: ") + hipGetErrorString(e));
   }
   const NTensor& fin = P.T.back();
   int64_t nvals = int64_t(1) << popc(fin.dmask);
@@ -427,12 +539,21 @@ rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
     key = hash_bytes(key, &s, sizeof(s));
     bool done = false;
     if ((st = replay_graph(h, key, s, &done)) != RN_OK || done) return st;
-    if (seen_before(h, key))
-      return capture_and_launch(h, key, std::vector<char>(), nullptr, s, [&](hipStream_t cs) {
-        return enqueue_network(P, T, ws, cs, amp_dev, slices_dev, &h->prof);
+    if (seen_before(h, key)) {
+      std::vector<char> blob;
+      std::vector<GroupedLaunch> per_level;
+      build_net_tables(P, T, ws, blob, per_level);
+      char* tdev = static_cast<char*>(ws) + P.table_off;
+      return capture_and_launch(h, key, blob, tdev, s, [&](hipStream_t cs) {
+        return enqueue_network(P, T, ws, cs, amp_dev, slices_dev, &h->prof, per_level);
       });
+    }
   }
-  return enqueue_network(P, T, ws, s, amp_dev, slices_dev, &h->prof);
+  std::vector<char> blob;
+  std::vector<GroupedLaunch> per_level;
+  build_net_tables(P, T, ws, blob, per_level);
+  if ((st = upload_table(h, blob, static_cast<char*>(ws) + P.table_off, s)) != RN_OK) return st;
+  return enqueue_network(P, T, ws, s, amp_dev, slices_dev, &h->prof, per_level);
 }
 
 }  // extern "C"

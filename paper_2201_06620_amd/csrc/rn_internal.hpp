@@ -148,6 +148,25 @@ size_t grouped_perm_build(const std::vector<PermLaunch>& jobs, std::vector<char>
                           GroupedLaunch& G);
 hipError_t launch_permute_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s);
 size_t grouped_table_bound(rn_mode mode, int n);
+
+// One small contraction step evaluated directly from the stored layouts
+// (no relayout): C[b][m][n] = sum_k A[a_off(b) + amap(m, k)] * B[...], where
+// amap scatters the bits of m and k to their physical positions in A.
+struct DirectStep {
+  const void* A = nullptr;
+  const void* B = nullptr;
+  void* C = nullptr;
+  int64_t M = 1, N = 1, K = 1;
+  int mbits = 0, nbits = 0, kbits = 0, nbb = 0;
+  int blocks_per_batch = 1;
+  int8_t am[40] = {0}, ak[40] = {0}, bn[40] = {0}, bk[40] = {0};
+  int64_t a_bs[RN_MAX_SLICED] = {0}, b_bs[RN_MAX_SLICED] = {0};
+};
+constexpr int64_t kDirectMaxK = 4096;
+size_t grouped_direct_bound(int n);
+size_t grouped_direct_build(const std::vector<DirectStep>& steps, rn_mode mode,
+                            std::vector<char>& table, GroupedLaunch& G);
+hipError_t launch_direct_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s);
 size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
                           std::vector<char>& table, GroupedLaunch& G);
 hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s);

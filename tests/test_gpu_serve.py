@@ -95,8 +95,11 @@ def test_alone_equals_in_mix(requests_):
 
 def test_request_over_budget_is_rejected():
     import paper_2201_06620_amd as rn
-    srv = rn.Server(0, hbm_budget=1 << 20, max_active=2)
     w = configs.circuit_workload(4, 4, 8, 123, max_rank=30, restarts=1)
+    big = rn.Server(0, hbm_budget=1 << 30, max_active=1)
+    fp = big.wait(submit(big, w, "fp64"))["footprint"]
+    big.close()
+    srv = rn.Server(0, hbm_budget=int(fp) // 2, max_active=2)
     res = srv.wait(submit(srv, w, "fp64"))
     assert res["status"] == 5  # RN_ERR_OOM: can never fit the budget
     small = configs.circuit_workload(2, 3, 4, 124, restarts=1)

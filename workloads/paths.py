@@ -137,6 +137,12 @@ def greedy_slices(labels, path, seed: int, n_slices: int | None = None,
 
     Stops after exactly ``n_slices`` bonds, or once the largest intermediate
     rank is <= ``max_rank`` (whichever is given), or at ``max_sliced`` bonds.
+    Each round scores every unsliced bond x by (largest rank with x sliced
+    too, total flops over all slices, seeded random key) and takes the least.
+    Scores come from per-bond tallies: slicing x lowers the rank of exactly
+    the tensors carrying x, so the largest rank drops by one iff x is carried
+    by every tensor of the current largest rank, and a step's flops halve iff
+    x is among its operands' labels.
     """
     rng = SplitMix64(seed * 104729 + 17)
     sliced: list[int] = []
@@ -157,13 +163,27 @@ def greedy_slices(labels, path, seed: int, n_slices: int | None = None,
 
     while not done() and len(sliced) < max_sliced:
         cur = frozenset(sliced)
+        ranks = [len(t - cur) for t in sets]
+        top = max(ranks)
+        n_top = sum(1 for r in ranks if r == top)
+        in_top: dict[int, int] = {}
+        for t, r in zip(sets, ranks):
+            if r == top:
+                for x in t:
+                    in_top[x] = in_top.get(x, 0) + 1
+        weights = [1 << len(u - cur) for u in unions]
+        total = sum(weights)
+        with_x: dict[int, int] = {}
+        for u, wgt in zip(unions, weights):
+            for x in u:
+                with_x[x] = with_x.get(x, 0) + wgt
         best, best_key = None, None
         for x in cands:
             if x in cur:
                 continue
-            s = cur | {x}
-            mr = max(len(t - s) for t in sets)
-            fl = sum(1 << len(u - s) for u in unions) << len(s)
+            mr = top - 1 if in_top.get(x, 0) == n_top else top
+            # Flops over all 2^(|S|+1) slices; halves for steps carrying x.
+            fl = (2 * total - with_x.get(x, 0)) << len(cur)
             key = (mr, fl, rng.uniform())
             if best_key is None or key < best_key:
                 best, best_key = x, key
