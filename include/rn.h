@@ -158,6 +158,9 @@ rn_status rn_autotune_batch(rn_handle h, int32_t n, const rn_tensor* A, const rn
                             const int32_t* k, const int32_t* const* axesA,
                             const int32_t* const* axesB, rn_tensor* C, rn_mode mode, void* ws,
                             size_t ws_bytes, void* stream);
+/* Number of GEMM tile shapes of a mode (indices 0 .. n-1 in tune files;
+ * index 0 is the one-thread-per-output kernel for tiny problems). */
+int32_t rn_tile_count(rn_mode mode);
 rn_status rn_tune_save(rn_handle h, const char* path);
 rn_status rn_tune_load(rn_handle h, const char* path);
 rn_status rn_tune_clear(rn_handle h);

@@ -30,7 +30,7 @@ EXPORTS = ["rn_create", "rn_destroy", "rn_status_str", "rn_last_error",
            "rn_block_footprint", "rn_block_tensordot_batch_plan", "rn_block_tensordot_batch",
            "rn_contract_network_plan", "rn_contract_network", "rn_norm2", "rn_sum_c128",
            "rn_profile_enable", "rn_profile_read", "rn_autotune_batch", "rn_tune_save",
-           "rn_tune_load", "rn_tune_clear", "rn_set_graphs", "rn_server_create",
+           "rn_tune_load", "rn_tune_clear", "rn_tile_count", "rn_set_graphs", "rn_server_create",
            "rn_server_submit", "rn_server_poll", "rn_server_wait", "rn_server_stats",
            "rn_server_destroy"]
 
@@ -63,6 +63,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python paper_2201_06620_amd/build.py` (no CPU fallback exists)")
+        # PyTorch brings its own HIP runtime; load it first so that the
+        # library binds to that same runtime instead of a second copy.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         p, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         T = ctypes.POINTER(RnTensor)
@@ -95,6 +98,7 @@ def lib():
         L.rn_tune_save.argtypes = [p, ctypes.c_char_p]
         L.rn_tune_load.argtypes = [p, ctypes.c_char_p]
         L.rn_tune_clear.argtypes = [p]
+        L.rn_tile_count.argtypes = [ctypes.c_int]
         L.rn_set_graphs.argtypes = [p, ctypes.c_int]
         L.rn_server_create.argtypes = [ctypes.c_int, sz, i32, ctypes.POINTER(p)]
         L.rn_server_submit.argtypes = [p, i32, T, pp, i32, p, i32, p, ctypes.c_int,
@@ -137,6 +141,11 @@ def descriptor(dims, grid=None, dtype=C128, data=None) -> RnTensor:
 def _arr32(x):
     a = np.ascontiguousarray(np.asarray(list(x), dtype=np.int32).reshape(-1))
     return a, (a.ctypes.data if a.size else None)
+
+
+def tile_count(mode) -> int:
+    """Number of GEMM tile shapes of a mode (the autotuner's candidates)."""
+    return int(lib().rn_tile_count(mode_id(mode)))
 
 
 def mode_id(mode) -> int:

@@ -41,7 +41,8 @@ void Profiler::end(int idx, hipStream_t s) {
 }
 
 rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor* B,
-                            const rn_tensor* C, void* ws, hipStream_t s, Profiler* prof) {
+                            const rn_tensor* C, void* ws, hipStream_t s, Profiler* prof,
+                            int tile) {
   const bool split_prec = (P.mode == RN_BF16X3);
   const void* am = A->data;
   const void* bm = B->data;
@@ -94,6 +95,7 @@ rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor
   g.ccol = P.ccol;
   g.splitk = P.splitk;
   g.partial = P.splitk > 1 ? ws_at(ws, P.off_part) : nullptr;
+  g.tile = tile;
   if ((e = launch_gemm(g, s, prof)) != hipSuccess) return hip_fail(e, "complex GEMM");
   return RN_OK;
 }
@@ -215,7 +217,8 @@ rn_status rn_block_tensordot(rn_handle h, const rn_tensor* A, const rn_tensor* B
     return fail(RN_ERR_WORKSPACE, "workspace smaller than planned (" +
                                       std::to_string(P.ws_bytes) + " bytes needed)");
   if ((st = bind_device(h)) != RN_OK) return st;
-  return enqueue_tensordot(P, A, B, C, ws, static_cast<hipStream_t>(stream), &h->prof);
+  return enqueue_tensordot(P, A, B, C, ws, static_cast<hipStream_t>(stream), &h->prof,
+                           tuned_tile(h, P.mode, P.mbits, P.nbits, P.kbits));
 }
 
 rn_status rn_block_pairs(rn_handle h, const rn_tensor* A, const rn_tensor* B, int32_t k,

@@ -435,7 +435,13 @@ rn_status rn_autotune_batch(rn_handle h, int32_t n, const rn_tensor* A, const rn
     g.splitk = 1;
     int best = -1;
     float best_ms = 0.f;
+    std::vector<float> times;
     for (int t = 0; t < gemm_tile_count(P.mode) && st == RN_OK; ++t) {
+      // The one-thread-per-output kernel only competes on small problems.
+      if (t == 0 && double(P.M) * double(P.N) * double(P.K) > double(int64_t(1) << 26)) {
+        times.push_back(-1.f);
+        continue;
+      }
       g.tile = t;
       if ((e = launch_gemm(g, s)) != hipSuccess) { st = hipf(e, "autotune launch"); break; }
       hipEventRecord(e0, s);
@@ -448,6 +454,8 @@ rn_status rn_autotune_batch(rn_handle h, int32_t n, const rn_tensor* A, const rn
       }
       float ms = 0.f;
       hipEventElapsedTime(&ms, e0, e1);
+      ms /= 3.f;
+      times.push_back(ms);
       if (best < 0 || ms < best_ms) {
         best = t;
         best_ms = ms;
@@ -455,6 +463,7 @@ rn_status rn_autotune_batch(rn_handle h, int32_t n, const rn_tensor* A, const rn
     }
     if (st != RN_OK) break;
     h->tune[key] = best;
+    h->tune_ms[key] = times;
   }
   h->prof.on = saved_prof;
   hipEventDestroy(e0);
@@ -464,14 +473,26 @@ rn_status rn_autotune_batch(rn_handle h, int32_t n, const rn_tensor* A, const rn
   return st;
 }
 
+int32_t rn_tile_count(rn_mode mode) {
+  if (mode < RN_FP64 || mode > RN_BF16X3) return 0;
+  return gemm_tile_count(mode);
+}
+
 rn_status rn_tune_save(rn_handle h, const char* path) {
   if (!h || !path) return fail(RN_ERR_INVALID, "null argument");
   FILE* f = fopen(path, "w");
   if (!f) return fail(RN_ERR_INVALID, std::string("cannot write ") + path);
   fprintf(f, "rn_tune 1\n");
-  for (auto& kv : h->tune)
+  for (auto& kv : h->tune) {
     fprintf(f, "%d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
             std::get<2>(kv.first), std::get<3>(kv.first), kv.second);
+    auto it = h->tune_ms.find(kv.first);
+    if (it != h->tune_ms.end()) {
+      fprintf(f, "#");
+      for (float ms : it->second) fprintf(f, " %.4f", ms);
+      fprintf(f, "\n");
+    }
+  }
   fclose(f);
   return RN_OK;
 }
@@ -485,8 +506,11 @@ rn_status rn_tune_load(rn_handle h, const char* path) {
     fclose(f);
     return fail(RN_ERR_INVALID, "not a tune file");
   }
-  int m, a, b, c, t;
-  while (fscanf(f, "%d %d %d %d %d", &m, &a, &b, &c, &t) == 5) {
+  char line[1024];
+  if (!fgets(line, sizeof(line), f)) line[0] = 0;  // rest of the header line
+  while (fgets(line, sizeof(line), f)) {
+    int m, a, b, c, t;
+    if (line[0] == '#' || sscanf(line, "%d %d %d %d %d", &m, &a, &b, &c, &t) != 5) continue;
     if (m < RN_FP64 || m > RN_BF16X3 || t < 0 || t >= gemm_tile_count((rn_mode)m)) continue;
     h->tune[std::make_tuple(m, a, b, c)] = t;
   }

@@ -1001,6 +1001,334 @@ __device__ __forceinline__ void cgemm_bf16x3_body(const GemmParams& p, int tm, i
 }
 
 // ---------------------------------------------------------------------------
+// Re/Im-split variants of the 4M kernels.  Each 32x32 MFMA tile covers 32
+// complex columns and comes in a pair: one accumulates the real parts and
+// one the imaginary parts of C.  For the real part, B's embedded rows are
+// (b_r, -b_i) per complex k; for the imaginary part (b_i, b_r).  All lanes
+// of one MFMA then apply the same transform to the same complex B values,
+// so a B fragment is read from LDS once for both tiles and no lane diverges.
+// ---------------------------------------------------------------------------
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f32_ri_body(const GemmParams& p, int tm, int tn, int split,
+                                                  int b) {
+  static_assert(WM * WN == 4, "four waves");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 32;  // complex columns
+  constexpr int LDK = BK + 1;
+  constexpr int AV = BM * BK / 2;
+  constexpr int BV = BN * BK / 2;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  __shared__ float2 As[2][BM * LDK];
+  __shared__ float2 Bs[2][BN * LDK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const float2* __restrict__ Ag =
+      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const float2* __restrict__ Bg =
+      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+
+  float4 ra[NA], rb[NB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = row0 + r, gk = k0 + c;
+        if (gr < p.M) {
+          const float2* src = Ag + gr * p.lda + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = col0 + r, gk = k0 + c;
+        if (gr < p.N) {
+          const float2* src = Bg + gr * p.ldb + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      rb[j] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        As[buf][r * LDK + c] = make_float2(ra[j].x, ra[j].y);
+        As[buf][r * LDK + c + 1] = make_float2(ra[j].z, ra[j].w);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        Bs[buf][r * LDK + c] = make_float2(rb[j].x, rb[j].y);
+        Bs[buf][r * LDK + c + 1] = make_float2(rb[j].z, rb[j].w);
+      }
+    }
+  };
+
+  v16f cr[TM][TN], ci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
+
+  // Lane roles: A row = lane % 32, real k = lane / 32 (0: re, 1: im part of
+  // complex a); B complex column = lane % 32, same real k.
+  const int kh = lane >> 5;
+  const uint32_t neg = kh ? 0x80000000u : 0u;
+  const int arow = wm * TM * 32 + (lane & 31);
+  const int bcol = wn * TN * 32 + (lane & 31);
+
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      float af[TM], br[TN], bi[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        float2 a = As[buf][(arow + i * 32) * LDK + kk];
+        af[i] = kh ? a.y : a.x;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        float2 v = Bs[buf][(bcol + j * 32) * LDK + kk];
+        // Real-part row: (b_r, -b_i); imaginary-part row: (b_i, b_r).
+        br[j] = __uint_as_float(__float_as_uint(kh ? v.y : v.x) ^ neg);
+        bi[j] = kh ? v.x : v.y;
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], br[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bi[j], ci[i][j], 0, 0, 0);
+        }
+    }
+    if (it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
+        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
+        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
+        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
+      }
+}
+
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm, int tn,
+                                                     int split, int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK % 8 == 0, "eight complex k per MFMA");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 32;  // complex columns
+  constexpr int LDK = BK + 4;
+  constexpr int AV = BM * BK / 4;
+  constexpr int BV = BN * BK / 4;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  __shared__ __align__(16) uint32_t Ah[2][BM * LDK];
+  __shared__ __align__(16) uint32_t Al[2][BM * LDK];
+  __shared__ __align__(16) uint32_t Bh[2][BN * LDK];
+  __shared__ __align__(16) uint32_t Bl[2][BN * LDK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const int64_t ao = batch_off(p.a_bs, p.nbb, b), bo = batch_off(p.b_bs, p.nbb, b);
+  const uint32_t* __restrict__ Agh = reinterpret_cast<const uint32_t*>(p.A) + ao;
+  const uint32_t* __restrict__ Agl = reinterpret_cast<const uint32_t*>(p.A2) + ao;
+  const uint32_t* __restrict__ Bgh = reinterpret_cast<const uint32_t*>(p.B) + bo;
+  const uint32_t* __restrict__ Bgl = reinterpret_cast<const uint32_t*>(p.B2) + bo;
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+
+  uint4 rah[NA], ral[NA], rbh[NB], rbl[NB];
+  auto ld4 = [&](const uint32_t* src, int64_t gk) -> uint4 {
+    if (gk + 3 < kend) return *reinterpret_cast<const uint4*>(src);
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gk < kend) v.x = src[0];
+    if (gk + 1 < kend) v.y = src[1];
+    if (gk + 2 < kend) v.z = src[2];
+    return v;
+  };
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
+      if (idx < AV) {
+        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
+        int64_t gr = row0 + r, gk = k0 + c;
+        if (gr < p.M && gk < kend) {
+          h = ld4(Agh + gr * p.lda + gk, gk);
+          l = ld4(Agl + gr * p.lda + gk, gk);
+        }
+      }
+      rah[j] = h;
+      ral[j] = l;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
+      if (idx < BV) {
+        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
+        int64_t gr = col0 + r, gk = k0 + c;
+        if (gr < p.N && gk < kend) {
+          h = ld4(Bgh + gr * p.ldb + gk, gk);
+          l = ld4(Bgl + gr * p.ldb + gk, gk);
+        }
+      }
+      rbh[j] = h;
+      rbl[j] = l;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < AV) {
+        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
+        *reinterpret_cast<uint4*>(&Ah[buf][r * LDK + c]) = rah[j];
+        *reinterpret_cast<uint4*>(&Al[buf][r * LDK + c]) = ral[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < BV) {
+        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
+        *reinterpret_cast<uint4*>(&Bh[buf][r * LDK + c]) = rbh[j];
+        *reinterpret_cast<uint4*>(&Bl[buf][r * LDK + c]) = rbl[j];
+      }
+    }
+  };
+
+  v16f cr[TM][TN], ci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
+
+  // A row = lane % 32 and complex k 4*(lane/32) + 0..3 (interleaved re, im
+  // = 8 real k); B complex column = lane % 32, same complex k.  Packed b
+  // (b_r | b_i << 16) becomes (b_r, -b_i) for the real-part tile and
+  // (b_i, b_r) for the imaginary-part tile.
+  const int kq = (lane >> 5) * 4;
+  const int arow = wm * TM * 32 + (lane & 31);
+  const int bcol = wn * TN * 32 + (lane & 31);
+
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 8) {
+      v8bf ah[TM], al[TM];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        int o = (arow + i * 32) * LDK + kk + kq;
+        ah[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(&Ah[buf][o]));
+        al[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(&Al[buf][o]));
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        int o = (bcol + j * 32) * LDK + kk + kq;
+        const v4u wh = *reinterpret_cast<const v4u*>(&Bh[buf][o]);
+        const v4u wl = *reinterpret_cast<const v4u*>(&Bl[buf][o]);
+        const v8bf bhr = __builtin_bit_cast(v8bf, wh ^ 0x80000000u);
+        const v8bf blr = __builtin_bit_cast(v8bf, wl ^ 0x80000000u);
+        const v8bf bhi = __builtin_bit_cast(v8bf, (wh >> 16) | (wh << 16));
+        const v8bf bli = __builtin_bit_cast(v8bf, (wl >> 16) | (wl << 16));
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhr, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhi, ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], blr, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bli, ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhr, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhi, ci[i][j], 0, 0, 0);
+        }
+      }
+    }
+    if (it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  const int khalf = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * khalf + (e & 3);
+        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
+        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
+        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Small problems: one thread per complex output, sequential K loop (FP64,
 // FP32 or split BF16 products).  Used when a tile would be mostly empty.
 // ---------------------------------------------------------------------------
@@ -1120,6 +1448,8 @@ RN_GEMM_ENTRY(cgemm_f32_4m)
 RN_GEMM_ENTRY(cgemm_f32_3m)
 RN_GEMM_ENTRY(cgemm_f64_4m)
 RN_GEMM_ENTRY(cgemm_bf16x3)
+RN_GEMM_ENTRY(cgemm_f32_ri)
+RN_GEMM_ENTRY(cgemm_bf16x3_ri)
 
 template <int MODE>
 __global__ __launch_bounds__(256) void cgemm_small(GemmParams p) {
@@ -1166,10 +1496,13 @@ struct TileCfg {
 };
 
 // Index 0 = small-problem kernel; the rest are MFMA tile shapes per mode.
-static const TileCfg kF32Tiles[] = {
-    {1, 1, 1}, {128, 64, 16}, {64, 32, 16}, {256, 64, 8}, {128, 128, 8}};
+static const TileCfg kF32Tiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 32, 16},
+                                    {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
+                                    {128, 128, 8}};
 static const TileCfg kF64Tiles[] = {{1, 1, 1}, {128, 64, 8}, {64, 32, 8}};
-static const TileCfg kBF16Tiles[] = {{1, 1, 1}, {128, 64, 16}, {64, 32, 16}};
+static const TileCfg kBF16Tiles[] = {{1, 1, 1},     {128, 64, 16}, {64, 32, 16},
+                                     {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
+                                     {128, 128, 8}, {256, 64, 8}};
 static const TileCfg k3MTiles[] = {{1, 1, 1}, {128, 64, 16}, {64, 64, 16}};
 
 static const TileCfg& tile_of(rn_mode mode, int t) {
@@ -1179,9 +1512,16 @@ static const TileCfg& tile_of(rn_mode mode, int t) {
   return kF32Tiles[t];
 }
 
+// Default tile shape when the autotuner has no entry: the one-thread kernel
+// for tiny problems, otherwise the largest tile the output fills (the
+// Re/Im-split tiles for FP32-4M and BF16x3 measured fastest on large pairs).
 static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
   if (M * N * K <= (int64_t(1) << 15) || M < 16 || N < 8) return 0;
-  if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) return 1;
+  if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) {
+    if (mode == RN_FP32_4M) return 5;
+    if (mode == RN_BF16X3) return N >= 128 ? 6 : 5;
+    return 1;
+  }
   return 2;
 }
 
@@ -1270,8 +1610,18 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
     } else if (g.mode == RN_BF16X3) {
       if (tile == 1)
         cgemm_bf16x3<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 2)
         cgemm_bf16x3<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
+      else if (tile == 3)
+        cgemm_bf16x3<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
+      else if (tile == 4)
+        cgemm_bf16x3<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(p);
+      else if (tile == 5)
+        cgemm_bf16x3_ri<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
+      else if (tile == 6)
+        cgemm_bf16x3_ri<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_bf16x3_ri<2, 2, 4, 1, 8><<<grid, 256, 0, s>>>(p);
     } else {
       if (tile == 1)
         cgemm_f32_4m<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
@@ -1279,8 +1629,12 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f32_4m<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
       else if (tile == 3)
         cgemm_f32_4m<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 4)
         cgemm_f32_4m<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(p);
+      else if (tile == 5)
+        cgemm_f32_ri<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_f32_ri<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
     }
   }
   hipError_t e = hipGetLastError();
@@ -1364,14 +1718,21 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
     case RN_BF16X3:
       if (tile == 0) cgemm_small_grouped<RN_BF16X3><<<grid, 256, 0, s>>>(t);
       else if (tile == 1) cgemm_bf16x3_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
-      else cgemm_bf16x3_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 2) cgemm_bf16x3_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 3) cgemm_bf16x3_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 4) cgemm_bf16x3_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 5) cgemm_bf16x3_ri_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 6) cgemm_bf16x3_ri_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
+      else cgemm_bf16x3_ri_grouped<2, 2, 4, 1, 8><<<grid, 256, 0, s>>>(t);
       break;
     default:
       if (tile == 0) cgemm_small_grouped<RN_FP32_4M><<<grid, 256, 0, s>>>(t);
       else if (tile == 1) cgemm_f32_4m_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
       else if (tile == 2) cgemm_f32_4m_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
       else if (tile == 3) cgemm_f32_4m_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
-      else cgemm_f32_4m_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 4) cgemm_f32_4m_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 5) cgemm_f32_ri_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
+      else cgemm_f32_ri_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
       break;
   }
   return hipGetLastError();

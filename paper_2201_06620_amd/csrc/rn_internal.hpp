@@ -173,7 +173,8 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
 int choose_splitk(rn_mode mode, int64_t M, int64_t N, int64_t K, int64_t batch);
 
 rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor* B,
-                            const rn_tensor* C, void* ws, hipStream_t s, Profiler* prof);
+                            const rn_tensor* C, void* ws, hipStream_t s, Profiler* prof,
+                            int tile = -1);
 
 hipError_t launch_norm2(const void* x, int64_t n, int dtype, double* out, double* scratch,
                         hipStream_t s);
@@ -199,6 +200,8 @@ struct rn_ctx {
   rn::Profiler prof;
   // Tile choices from the autotuner: (mode, log2 M, log2 N, log2 K) -> tile.
   std::map<std::tuple<int, int, int, int>, int> tune;
+  // Milliseconds per launch of every tile shape timed for that key.
+  std::map<std::tuple<int, int, int, int>, std::vector<float>> tune_ms;
   std::string tune_path;
   // Pinned staging for parameter tables of direct (not captured) launches.
   void* pinned = nullptr;
