@@ -1329,6 +1329,307 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
 }
 
 // ---------------------------------------------------------------------------
+// Re/Im-split tiles with planar LDS rows.  While staging a chunk into LDS,
+// each row of A is stored as [a_r(0..BK-1) | a_i(0..BK-1)] and each row of B
+// as [b_r(0..BK-1) | -b_i(0..BK-1)], so the MFMA lane whose real k is the
+// imaginary half reads the second half directly: no per-fragment select.
+// The real-part tile uses B rows as stored; the imaginary-part tile needs
+// (b_i, b_r), read from the other half with one sign flip on the first.
+// ---------------------------------------------------------------------------
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f32_rp_body(const GemmParams& p, int tm, int tn, int split,
+                                                  int b) {
+  static_assert(WM * WN == 4, "four waves");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 32;  // complex columns
+  constexpr int LDR = 2 * BK + 1;   // floats per padded LDS row
+  constexpr int AV = BM * BK / 2;
+  constexpr int BV = BN * BK / 2;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  __shared__ float As[2][BM * LDR];
+  __shared__ float Bs[2][BN * LDR];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const float2* __restrict__ Ag =
+      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const float2* __restrict__ Bg =
+      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+
+  float4 ra[NA], rb[NB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = row0 + r, gk = k0 + c;
+        if (gr < p.M) {
+          const float2* src = Ag + gr * p.lda + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = col0 + r, gk = k0 + c;
+        if (gr < p.N) {
+          const float2* src = Bg + gr * p.ldb + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      rb[j] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        float* row = &As[buf][r * LDR];
+        row[c] = ra[j].x;
+        row[c + 1] = ra[j].z;
+        row[BK + c] = ra[j].y;
+        row[BK + c + 1] = ra[j].w;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        float* row = &Bs[buf][r * LDR];
+        row[c] = rb[j].x;
+        row[c + 1] = rb[j].z;
+        row[BK + c] = -rb[j].y;
+        row[BK + c + 1] = -rb[j].w;
+      }
+    }
+  };
+
+  v16f cr[TM][TN], ci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
+
+  const int kh = lane >> 5;
+  const int aoff = (wm * TM * 32 + (lane & 31)) * LDR + kh * BK;
+  const int boff_r = (wn * TN * 32 + (lane & 31)) * LDR + kh * BK;
+  const int boff_i = (wn * TN * 32 + (lane & 31)) * LDR + (1 - kh) * BK;
+  const uint32_t flip = kh ? 0u : 0x80000000u;  // Im row: (-(-b_i), b_r)
+
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      float af[TM], br[TN], bi[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = As[buf][aoff + i * 32 * LDR + kk];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        br[j] = Bs[buf][boff_r + j * 32 * LDR + kk];
+        bi[j] = __uint_as_float(__float_as_uint(Bs[buf][boff_i + j * 32 * LDR + kk]) ^ flip);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], br[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bi[j], ci[i][j], 0, 0, 0);
+        }
+    }
+    if (it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
+        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
+        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
+        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
+      }
+}
+
+// FP64 counterpart: v_mfma_f64_16x16x4_f64, 16 complex columns per tile
+// pair, 2 complex k per instruction (real k = lane / 16: complex k lane / 32,
+// half (lane / 16) & 1).
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f64_rp_body(const GemmParams& p, int tm, int tn, int split,
+                                                  int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK % 2 == 0, "two complex k per MFMA");
+  constexpr int BM = WM * TM * 16;
+  constexpr int BN = WN * TN * 16;  // complex columns
+  constexpr int LDR = 2 * BK + 1;   // doubles per padded LDS row
+  constexpr int AV = BM * BK;
+  constexpr int BV = BN * BK;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  __shared__ double As[2][BM * LDR];
+  __shared__ double Bs[2][BN * LDR];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const double2* __restrict__ Ag =
+      reinterpret_cast<const double2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const double2* __restrict__ Bg =
+      reinterpret_cast<const double2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+
+  double2 ra[NA], rb[NB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      double2 v = make_double2(0.0, 0.0);
+      if (idx < AV) {
+        int r = idx / BK, c = idx % BK;
+        int64_t gr = row0 + r, gk = k0 + c;
+        if (gr < p.M && gk < kend) v = Ag[gr * p.lda + gk];
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      double2 v = make_double2(0.0, 0.0);
+      if (idx < BV) {
+        int r = idx / BK, c = idx % BK;
+        int64_t gr = col0 + r, gk = k0 + c;
+        if (gr < p.N && gk < kend) v = Bg[gr * p.ldb + gk];
+      }
+      rb[j] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < AV) {
+        int r = idx / BK, c = idx % BK;
+        As[buf][r * LDR + c] = ra[j].x;
+        As[buf][r * LDR + BK + c] = ra[j].y;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (idx < BV) {
+        int r = idx / BK, c = idx % BK;
+        Bs[buf][r * LDR + c] = rb[j].x;
+        Bs[buf][r * LDR + BK + c] = -rb[j].y;
+      }
+    }
+  };
+
+  v4d cr[TM][TN], ci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cr[i][j][e] = ci[i][j][e] = 0.0;
+
+  const int kc = lane >> 5;
+  const int half = (lane >> 4) & 1;
+  const int aoff = (wm * TM * 16 + (lane & 15)) * LDR + half * BK + kc;
+  const int boff_r = (wn * TN * 16 + (lane & 15)) * LDR + half * BK + kc;
+  const int boff_i = (wn * TN * 16 + (lane & 15)) * LDR + (1 - half) * BK + kc;
+  const bool negi = (half == 0);
+
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      double af[TM], br[TN], bi[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = As[buf][aoff + i * 16 * LDR + kk];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        br[j] = Bs[buf][boff_r + j * 16 * LDR + kk];
+        double v = Bs[buf][boff_i + j * 16 * LDR + kk];
+        bi[j] = negi ? -v : v;
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], br[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bi[j], ci[i][j], 0, 0, 0);
+        }
+    }
+    if (it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // 16x16 f64 accumulator layout: column lane % 16, rows 4*e + lane/16.
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t row = row0 + wm * TM * 16 + i * 16 + 4 * e + (lane >> 4);
+        int64_t col = col0 + wn * TN * 16 + j * 16 + (lane & 15);
+        store_out<double>(p, b, split, row, col, 0, cr[i][j][e]);
+        store_out<double>(p, b, split, row, col, 1, ci[i][j][e]);
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Small problems: one thread per complex output, sequential K loop (FP64,
 // FP32 or split BF16 products).  Used when a tile would be mostly empty.
 // ---------------------------------------------------------------------------
@@ -1450,6 +1751,8 @@ RN_GEMM_ENTRY(cgemm_f64_4m)
 RN_GEMM_ENTRY(cgemm_bf16x3)
 RN_GEMM_ENTRY(cgemm_f32_ri)
 RN_GEMM_ENTRY(cgemm_bf16x3_ri)
+RN_GEMM_ENTRY(cgemm_f32_rp)
+RN_GEMM_ENTRY(cgemm_f64_rp)
 
 template <int MODE>
 __global__ __launch_bounds__(256) void cgemm_small(GemmParams p) {
@@ -1498,8 +1801,9 @@ struct TileCfg {
 // Index 0 = small-problem kernel; the rest are MFMA tile shapes per mode.
 static const TileCfg kF32Tiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 32, 16},
                                     {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
-                                    {128, 128, 8}};
-static const TileCfg kF64Tiles[] = {{1, 1, 1}, {128, 64, 8}, {64, 32, 8}};
+                                    {128, 128, 8}, {128, 64, 16}, {128, 128, 8}};
+static const TileCfg kF64Tiles[] = {{1, 1, 1}, {128, 64, 8}, {64, 32, 8}, {128, 64, 8},
+                                    {64, 64, 8}};
 static const TileCfg kBF16Tiles[] = {{1, 1, 1},     {128, 64, 16}, {64, 32, 16},
                                      {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
                                      {128, 128, 8}, {256, 64, 8}};
@@ -1514,12 +1818,14 @@ static const TileCfg& tile_of(rn_mode mode, int t) {
 
 // Default tile shape when the autotuner has no entry: the one-thread kernel
 // for tiny problems, otherwise the largest tile the output fills (the
-// Re/Im-split tiles for FP32-4M and BF16x3 measured fastest on large pairs).
+// Re/Im-split tiles -- planar LDS rows for FP32-4M and FP64 -- measured
+// fastest on large pairs).
 static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
   if (M * N * K <= (int64_t(1) << 15) || M < 16 || N < 8) return 0;
   if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) {
-    if (mode == RN_FP32_4M) return 5;
+    if (mode == RN_FP32_4M) return 7;
     if (mode == RN_BF16X3) return N >= 128 ? 6 : 5;
+    if (mode == RN_FP64) return 3;
     return 1;
   }
   return 2;
@@ -1600,8 +1906,12 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
     if (g.mode == RN_FP64) {
       if (tile == 1)
         cgemm_f64_4m<2, 2, 4, 4, 8><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 2)
         cgemm_f64_4m<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
+      else if (tile == 3)
+        cgemm_f64_rp<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_f64_rp<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
     } else if (g.mode == RN_FP32_3M) {
       if (tile == 1)
         cgemm_f32_3m<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
@@ -1633,8 +1943,12 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f32_4m<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(p);
       else if (tile == 5)
         cgemm_f32_ri<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 6)
         cgemm_f32_ri<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
+      else if (tile == 7)
+        cgemm_f32_rp<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_f32_rp<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
     }
   }
   hipError_t e = hipGetLastError();
@@ -1708,7 +2022,9 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
     case RN_FP64:
       if (tile == 0) cgemm_small_grouped<RN_FP64><<<grid, 256, 0, s>>>(t);
       else if (tile == 1) cgemm_f64_4m_grouped<2, 2, 4, 4, 8><<<grid, 256, 0, s>>>(t);
-      else cgemm_f64_4m_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 2) cgemm_f64_4m_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 3) cgemm_f64_rp_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
+      else cgemm_f64_rp_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
       break;
     case RN_FP32_3M:
       if (tile == 0) cgemm_small_grouped<RN_FP32_3M><<<grid, 256, 0, s>>>(t);
@@ -1732,7 +2048,9 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
       else if (tile == 3) cgemm_f32_4m_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
       else if (tile == 4) cgemm_f32_4m_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
       else if (tile == 5) cgemm_f32_ri_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      else cgemm_f32_ri_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 6) cgemm_f32_ri_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 7) cgemm_f32_rp_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
+      else cgemm_f32_rp_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
       break;
   }
   return hipGetLastError();
