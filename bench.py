@@ -406,7 +406,8 @@ def main() -> int:
                    "M": M, "N": N, "K": K, "useful_flops_per_step": flops},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
-                     "kernel": "cgemm_f32_4m", "kernel_ms": gemm_ms},
+                     "kernel": "FP32-4M complex GEMM (cgemm_f32_rp, default large tile)",
+                     "kernel_ms": gemm_ms},
         "cpu_baseline": cpu,
         "modes": modes,
         "amplitude_latency": amp,
