@@ -165,6 +165,42 @@ rn_status rn_tune_save(rn_handle h, const char* path);
 rn_status rn_tune_load(rn_handle h, const char* path);
 rn_status rn_tune_clear(rn_handle h);
 
+/* Handle options.
+ *   RN_OPT_GRAPHS: 1 (default) or 0; same as rn_set_graphs.
+ *   RN_OPT_PAIR_SPLIT_THRESHOLD: number of coupled block pairs B_k at or above
+ *     which a block tensordot splits its K loop at block-pair boundaries into
+ *     separate partial sums, reduced afterwards in ascending order (the GPU form
+ *     of the reduction strategy switch of Section IV.B: below the threshold the
+ *     pairs stream through one accumulator, Eq. 2 memory; at or above it the
+ *     pairs' partials exist side by side, as in the tree reduction).  0 (the
+ *     default) leaves the choice to the built-in heuristic.
+ *   RN_OPT_SPLIT_FOOTPRINT: bytes the partial sums of one split may occupy
+ *     (default 1 GiB); the split count is lowered until it fits.
+ *   RN_OPT_SLICE_SUM: 0 (default): sliced networks keep one result per slice
+ *     to the end and sum them in FP64 (Section II.B); 1: a sliced bond is
+ *     summed inside the step that contracts it (the slices viewed as blocks of
+ *     one contraction), so later steps run once instead of once per value of
+ *     that bond; the sum then happens in the mode's accumulation precision,
+ *     and per-slice values do not exist (slices_dev must be NULL).
+ *   RN_OPT_BATCHED_SLICE_BITS: at most this many sliced bonds (the last ones
+ *     of `sliced`) run batched in one pass; the values of the others are fixed
+ *     per pass (projection by a base offset) and the passes run one after
+ *     another in the same workspace.  Default 64 (all batched).
+ *   RN_OPT_NETWORK_FOOTPRINT: workspace cap in bytes for a network; the
+ *     planner lowers the batched-slice count until the workspace fits, and
+ *     fails with RN_ERR_OOM if it cannot.  0 (default): no cap.
+ * Options affect plans and calls made on the handle afterwards. */
+typedef enum {
+  RN_OPT_GRAPHS = 0,
+  RN_OPT_PAIR_SPLIT_THRESHOLD = 1,
+  RN_OPT_SPLIT_FOOTPRINT = 2,
+  RN_OPT_SLICE_SUM = 3,
+  RN_OPT_BATCHED_SLICE_BITS = 4,
+  RN_OPT_NETWORK_FOOTPRINT = 5
+} rn_option;
+rn_status rn_set_option(rn_handle h, rn_option opt, int64_t value);
+rn_status rn_get_option(rn_handle h, rn_option opt, int64_t* value);
+
 /* Graph replay.  When on (the default; RN_GRAPHS=0 in the environment turns
  * it off at rn_create), rn_block_tensordot_batch and rn_contract_network
  * record their launch sequence as a HIP graph the first time they run with a

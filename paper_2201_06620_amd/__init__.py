@@ -32,7 +32,11 @@ EXPORTS = ["rn_create", "rn_destroy", "rn_status_str", "rn_last_error",
            "rn_profile_enable", "rn_profile_read", "rn_autotune_batch", "rn_tune_save",
            "rn_tune_load", "rn_tune_clear", "rn_tile_count", "rn_set_graphs", "rn_server_create",
            "rn_server_submit", "rn_server_poll", "rn_server_wait", "rn_server_stats",
-           "rn_server_destroy"]
+           "rn_server_destroy", "rn_set_option", "rn_get_option"]
+
+# Handle options (rn_option).
+OPTIONS = {"graphs": 0, "pair_split_threshold": 1, "split_footprint": 2, "slice_sum": 3,
+           "batched_slice_bits": 4, "network_footprint": 5}
 
 
 class RnError(RuntimeError):
@@ -100,6 +104,8 @@ def lib():
         L.rn_tune_clear.argtypes = [p]
         L.rn_tile_count.argtypes = [ctypes.c_int]
         L.rn_set_graphs.argtypes = [p, ctypes.c_int]
+        L.rn_set_option.argtypes = [p, ctypes.c_int, i64]
+        L.rn_get_option.argtypes = [p, ctypes.c_int, ctypes.POINTER(i64)]
         L.rn_server_create.argtypes = [ctypes.c_int, sz, i32, ctypes.POINTER(p)]
         L.rn_server_submit.argtypes = [p, i32, T, pp, i32, p, i32, p, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_uint64)]
@@ -264,6 +270,20 @@ class Context:
         return ws.data_ptr(), nbytes
 
     # -- block tensordot -----------------------------------------------------
+    def plan_block_tensordot(self, dims_a, grid_a, dims_b, grid_b, axes_a, axes_b,
+                             mode="fp64"):
+        """As the module-level plan, under this handle's options (split policy)."""
+        dt = dtype_of_mode(mode)
+        A, B, C = descriptor(dims_a, grid_a, dt), descriptor(dims_b, grid_b, dt), RnTensor()
+        aa, pa = _arr32(axes_a)
+        bb, pb = _arr32(axes_b)
+        ws, fl = ctypes.c_size_t(), ctypes.c_double()
+        check(lib().rn_block_tensordot_plan(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
+                                            pa, pb, mode_id(mode), ctypes.byref(C),
+                                            ctypes.byref(ws), ctypes.byref(fl)), "plan")
+        return ([C.dims[j] for j in range(C.rank)], [C.grid[j] for j in range(C.rank)],
+                ws.value, fl.value)
+
     def block_tensordot(self, a, dims_a, grid_a, b, dims_b, grid_b, axes_a, axes_b,
                         mode="fp64", out=None, workspace=None):
         """C (stored block-major, flat torch tensor), C dims, C grid."""
@@ -341,6 +361,15 @@ class Context:
 
     def set_graphs(self, on: bool) -> None:
         check(lib().rn_set_graphs(self.h, 1 if on else 0), "set_graphs")
+
+    def set_option(self, name: str, value: int) -> None:
+        """Handle option by name: graphs, pair_split_threshold, split_footprint, slice_sum."""
+        check(lib().rn_set_option(self.h, OPTIONS[name], int(value)), f"set_option {name}")
+
+    def get_option(self, name: str) -> int:
+        v = ctypes.c_int64()
+        check(lib().rn_get_option(self.h, OPTIONS[name], ctypes.byref(v)), f"get_option {name}")
+        return v.value
 
     def tune_save(self, path: str) -> None:
         check(lib().rn_tune_save(self.h, path.encode()), "tune_save")

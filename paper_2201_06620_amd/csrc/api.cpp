@@ -1,6 +1,7 @@
 // C ABI entry points: argument checks, planning, and kernel enqueue.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -193,9 +194,8 @@ const char* rn_last_error(void) { return last_error().c_str(); }
 rn_status rn_block_tensordot_plan(rn_handle h, const rn_tensor* A, const rn_tensor* B, int32_t k,
                                   const int32_t* axesA, const int32_t* axesB, rn_mode mode,
                                   rn_tensor* C, size_t* ws_bytes, double* flops) {
-  (void)h;
   TdPlan P;
-  rn_status st = plan_tensordot(A, B, k, axesA, axesB, mode, &P);
+  rn_status st = plan_tensordot(A, B, k, axesA, axesB, mode, &P, true, h ? &h->split : nullptr);
   if (st != RN_OK) return st;
   if (C) fill_c(P, A->dtype, C);
   if (ws_bytes) *ws_bytes = P.ws_bytes;
@@ -209,7 +209,7 @@ rn_status rn_block_tensordot(rn_handle h, const rn_tensor* A, const rn_tensor* B
   if (!h) return fail(RN_ERR_INVALID, "null handle");
   TdPlan P;
   rn_status st;
-  if ((st = plan_tensordot(A, B, k, axesA, axesB, mode, &P)) != RN_OK) return st;
+  if ((st = plan_tensordot(A, B, k, axesA, axesB, mode, &P, true, &h->split)) != RN_OK) return st;
   if ((st = check_c(P, C)) != RN_OK) return st;
   if (!A->data || !B->data) return fail(RN_ERR_INVALID, "null operand data");
   if (C->data == A->data || C->data == B->data) return fail(RN_ERR_INVALID, "C aliases an operand");
@@ -324,6 +324,47 @@ rn_status rn_sum_c128(rn_handle h, int64_t n, const double* vals_dev, double* ou
   hipError_t e = launch_sum_c128(vals_dev, n, out_dev, s);
   h->prof.end(ev, s);
   return e == hipSuccess ? RN_OK : hip_fail(e, "sum");
+}
+
+rn_status rn_set_option(rn_handle h, rn_option opt, int64_t value) {
+  if (!h) return fail(RN_ERR_INVALID, "null handle");
+  switch (opt) {
+    case RN_OPT_GRAPHS: h->graphs_enabled = value != 0; return RN_OK;
+    case RN_OPT_PAIR_SPLIT_THRESHOLD:
+      if (value < 0) return fail(RN_ERR_INVALID, "threshold must be >= 0");
+      h->split.pair_threshold = value;
+      return RN_OK;
+    case RN_OPT_SPLIT_FOOTPRINT:
+      if (value < 0) return fail(RN_ERR_INVALID, "footprint must be >= 0");
+      h->split.footprint = value;
+      return RN_OK;
+    case RN_OPT_SLICE_SUM:
+      if (value != 0 && value != 1) return fail(RN_ERR_INVALID, "slice sum mode is 0 or 1");
+      h->net.slice_sum = value != 0;
+      return RN_OK;
+    case RN_OPT_BATCHED_SLICE_BITS:
+      if (value < 0) return fail(RN_ERR_INVALID, "batched slice bits must be >= 0");
+      h->net.batch_bits = (int)std::min<int64_t>(value, 64);
+      return RN_OK;
+    case RN_OPT_NETWORK_FOOTPRINT:
+      if (value < 0) return fail(RN_ERR_INVALID, "footprint must be >= 0");
+      h->net.footprint = value;
+      return RN_OK;
+  }
+  return fail(RN_ERR_INVALID, "unknown option");
+}
+
+rn_status rn_get_option(rn_handle h, rn_option opt, int64_t* value) {
+  if (!h || !value) return fail(RN_ERR_INVALID, "null argument");
+  switch (opt) {
+    case RN_OPT_GRAPHS: *value = h->graphs_enabled ? 1 : 0; return RN_OK;
+    case RN_OPT_PAIR_SPLIT_THRESHOLD: *value = h->split.pair_threshold; return RN_OK;
+    case RN_OPT_SPLIT_FOOTPRINT: *value = h->split.footprint; return RN_OK;
+    case RN_OPT_SLICE_SUM: *value = h->net.slice_sum ? 1 : 0; return RN_OK;
+    case RN_OPT_BATCHED_SLICE_BITS: *value = h->net.batch_bits; return RN_OK;
+    case RN_OPT_NETWORK_FOOTPRINT: *value = h->net.footprint; return RN_OK;
+  }
+  return fail(RN_ERR_INVALID, "unknown option");
 }
 
 rn_status rn_profile_enable(rn_handle h, int on) {

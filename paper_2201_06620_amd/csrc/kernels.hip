@@ -2067,6 +2067,8 @@ struct DirectTable {
   const DirectStep* steps;
   const int32_t* prefix;
   int n;
+  int nout;
+  int64_t pass;
 };
 
 template <int MODE>
@@ -2102,6 +2104,11 @@ __global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
     if ((b >> i) & 1) {
       ao += d.a_bs[i];
       bo += d.b_bs[i];
+    }
+  for (int i = 0; i < g.nout; ++i)
+    if ((g.pass >> (g.nout - 1 - i)) & 1) {
+      if (d.a_pp[i]) ao += int64_t(1) << (d.a_pp[i] - 1);
+      if (d.b_pp[i]) bo += int64_t(1) << (d.b_pp[i] - 1);
     }
   for (int i = 0; i < d.mbits; ++i)
     if ((m >> i) & 1) ao += int64_t(1) << d.am[i];
@@ -2190,9 +2197,13 @@ size_t grouped_direct_build(const std::vector<DirectStep>& steps, rn_mode mode,
   return bytes;
 }
 
-hipError_t launch_direct_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s) {
+hipError_t launch_direct_grouped(const GroupedLaunch& G, const void* table_dev, int64_t pass,
+                                 int nout, hipStream_t s) {
   if (G.n == 0 || G.blocks == 0) return hipSuccess;
+  if (nout < 0 || nout > RN_MAX_SLICED) return hipErrorInvalidValue;
   DirectTable t;
+  t.pass = pass;
+  t.nout = nout;
   t.steps = reinterpret_cast<const DirectStep*>(static_cast<const char*>(table_dev) + G.params_off);
   t.prefix = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.prefix_off);
   t.n = G.n;

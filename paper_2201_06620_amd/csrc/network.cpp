@@ -8,6 +8,16 @@
 // (batch stride 0) into the steps that use it.  Slice projection is fused
 // into the permute: a sliced axis of an input tensor becomes a batch bit.
 // The per-slice scalars are summed in FP64 on the GPU at the end.
+//
+// Slice-sum mode views the slices as blocks of the unsliced network instead
+// (Section II.B): the step where both dependents of a sliced bond meet is the
+// step that contracts that bond, so there the slice index becomes a
+// contracted bit rather than a batch bit, and later steps run once for it.
+//
+// To bound memory, only the last `batch_bits` sliced bonds run batched; the
+// values of the others are fixed per pass (projection = a base offset on the
+// inputs carrying that bond, its bit dropped from every map), and the passes
+// run one after another in the same workspace.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -89,6 +99,12 @@ struct NetPlan {
   rn_mode mode;
   int es;
   int nsliced;
+  int nout = 0;          // sliced bonds fixed per pass (slice indices 0..nout-1)
+  bool slice_sum = false;
+  // Per input: (outer slice index, stored bit) of each sliced axis it carries
+  // whose value a pass fixes.
+  std::vector<std::vector<std::pair<int, int>>> proj;
+  int64_t sums_off = 0;  // per-pass FP64 sums when there is more than one pass
   std::vector<NTensor> T;
   std::vector<NStep> steps;
   int64_t ws_bytes = 0;
@@ -129,7 +145,8 @@ int pos_of_slice(const NTensor& t, int sidx, const std::vector<int>& sliced) {
 
 rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* labels,
                        int32_t nsteps, const int32_t* path, int32_t nsliced,
-                       const int32_t* sliced, rn_mode mode, NetPlan* NP) {
+                       const int32_t* sliced, rn_mode mode, bool slice_sum, int batch_bits,
+                       NetPlan* NP) {
   if (nt < 1 || !T || !labels) return fail(RN_ERR_INVALID, "empty network");
   if (nsteps != nt - 1 || (nsteps > 0 && !path))
     return fail(RN_ERR_INVALID, "path must have nt-1 steps");
@@ -141,6 +158,9 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
   P.mode = mode;
   P.es = mode == RN_FP64 ? 16 : 8;
   P.nsliced = nsliced;
+  P.slice_sum = slice_sum;
+  P.nout = std::max(0, nsliced - std::max(0, batch_bits));
+  P.proj.assign(nt, {});
   std::vector<int> sl(sliced, sliced + nsliced);
   std::map<int, int> count, slice_index;
   for (int i = 0; i < nsliced; ++i) {
@@ -165,7 +185,12 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
       nt_.labels.push_back(l);
       count[l]++;
       auto it = slice_index.find(l);
-      if (it != slice_index.end()) nt_.dmask |= 1u << it->second;
+      if (it != slice_index.end()) {
+        if (it->second >= P.nout)
+          nt_.dmask |= 1u << it->second;
+        else
+          P.proj[i].push_back({it->second, t.rank - 1 - j});
+      }
     }
     P.T.push_back(nt_);
   }
@@ -210,21 +235,31 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
     NStep st;
     st.a = a;
     st.b = b;
-    int kb = (int)shared.size(), mb = (int)fa.size(), nbits = (int)fb.size();
+    // Slice indices summed in this step (slice-sum mode): those both
+    // operands depend on.  They are the outermost contracted bits.
+    const uint32_t cmask = slice_sum ? (ta.dmask & tb.dmask) : 0u;
+    const std::vector<int> csl = mask_list(cmask);
+    const int ncs = (int)csl.size();
+    int kb = (int)shared.size() + ncs, mb = (int)fa.size(), nbits = (int)fb.size();
     if (mb + nbits > 34) return fail(RN_ERR_UNSUPPORTED, "intermediate over 2^34 elements");
     st.M = int64_t(1) << mb;
     st.N = int64_t(1) << nbits;
     st.K = int64_t(1) << kb;
-    uint32_t dc = ta.dmask | tb.dmask;
+    uint32_t dc = (ta.dmask | tb.dmask) & ~cmask;
     std::vector<int> dcl = mask_list(dc);
     st.nbb = (int)dcl.size();
+    // Stored bit of contracted bit q (0 = innermost) in an operand.
+    auto kpos = [&](const NTensor& t, int q) {
+      const int ns = (int)shared.size();
+      return q < ns ? pos_of_label(t, shared[ns - 1 - q]) : pos_of_slice(t, csl[q - ns], sl);
+    };
     // Operand permutations: [batch over own dmask | free | contracted].
     auto build = [&](const NTensor& t, const std::vector<int>& fr, BitPerm& bp) {
       bp.nbits = 0;
-      for (int q = kb - 1; q >= 0; --q) bp.src[bp.nbits++] = (int8_t)pos_of_label(t, shared[q]);
+      for (int q = 0; q < kb; ++q) bp.src[bp.nbits++] = (int8_t)kpos(t, q);
       for (int q = (int)fr.size() - 1; q >= 0; --q)
         bp.src[bp.nbits++] = (int8_t)pos_of_label(t, fr[q]);
-      std::vector<int> dl = mask_list(t.dmask);
+      std::vector<int> dl = mask_list(t.dmask & ~cmask);
       for (int q = (int)dl.size() - 1; q >= 0; --q)
         bp.src[bp.nbits++] = (int8_t)pos_of_slice(t, dl[q], sl);
     };
@@ -237,9 +272,10 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
     for (int q = 0; q < st.nbb; ++q) {
       int sidx = dcl[st.nbb - 1 - q];
       auto stride = [&](const NTensor& t, int64_t body) -> int64_t {
-        if (!((t.dmask >> sidx) & 1)) return 0;
+        const uint32_t bm = t.dmask & ~cmask;
+        if (!((bm >> sidx) & 1)) return 0;
         int above = 0;
-        for (int i = sidx + 1; i < 32; ++i) above += (t.dmask >> i) & 1;
+        for (int i = sidx + 1; i < 32; ++i) above += (bm >> i) & 1;
         return (int64_t(1) << above) * body;
       };
       st.a_bs[q] = stride(ta, st.M * st.K);
@@ -265,18 +301,28 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
       for (int i = 0; i < mb; ++i) d.am[i] = (int8_t)pos_of_label(ta, fa[mb - 1 - i]);
       for (int i = 0; i < nbits; ++i) d.bn[i] = (int8_t)pos_of_label(tb, fb[nbits - 1 - i]);
       for (int i = 0; i < kb; ++i) {
-        d.ak[i] = (int8_t)pos_of_label(ta, shared[kb - 1 - i]);
-        d.bk[i] = (int8_t)pos_of_label(tb, shared[kb - 1 - i]);
+        d.ak[i] = (int8_t)kpos(ta, i);
+        d.bk[i] = (int8_t)kpos(tb, i);
       }
       for (int q = 0; q < st.nbb; ++q) {
         int sidx = dcl[st.nbb - 1 - q];
         d.a_bs[q] = ((ta.dmask >> sidx) & 1) ? int64_t(1) << pos_of_slice(ta, sidx, sl) : 0;
         d.b_bs[q] = ((tb.dmask >> sidx) & 1) ? int64_t(1) << pos_of_slice(tb, sidx, sl) : 0;
       }
+      for (int i = 0; i < P.nout; ++i) {
+        auto pp = [&](const NTensor& t) -> int8_t {
+          if (!t.input) return 0;
+          for (auto& pr : P.proj[t.input_idx])
+            if (pr.first == i) return (int8_t)(pr.second + 1);
+          return 0;
+        };
+        d.a_pp[i] = pp(ta);
+        d.b_pp[i] = pp(tb);
+      }
       st.permuteA = st.permuteB = false;
     }
-    st.abytes = (st.M * st.K << popc(ta.dmask)) * (split_prec ? 4 : P.es);
-    st.bbytes = (st.N * st.K << popc(tb.dmask)) * (split_prec ? 4 : P.es);
+    st.abytes = (st.M * st.K << popc(ta.dmask & ~cmask)) * (split_prec ? 4 : P.es);
+    st.bbytes = (st.N * st.K << popc(tb.dmask & ~cmask)) * (split_prec ? 4 : P.es);
     st.splitk = st.direct ? 1 : choose_splitk(mode, st.M, st.N, st.K, nbatch);
     st.pbytes = st.splitk > 1 ? int64_t(st.splitk) * nbatch * st.M * st.N * P.es : 0;
     NTensor tc;
@@ -337,7 +383,9 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
       release_operand(st.b);
     }
   }
-  P.table_off = (arena.peak + 255) & ~int64_t(255);
+  P.sums_off = (arena.peak + 255) & ~int64_t(255);
+  const int64_t npass = int64_t(1) << P.nout;
+  P.table_off = P.sums_off + (npass > 1 ? ((16 * npass + 255) & ~int64_t(255)) : 0);
   int64_t tbytes = 0;
   for (auto& lv : P.levels) {
     int nd = 0;
@@ -351,19 +399,29 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
 
 }  // namespace
 
+// Address of tensor `id` in pass `pass`: an input carrying a sliced bond
+// whose value the pass fixes starts at that value's half.
+static const void* tensor_ptr(const NetPlan& P, const rn_tensor* T, char* w, int id, int64_t pass) {
+  const NTensor& t = P.T[id];
+  if (!t.input) return w + t.off;
+  int64_t off = 0;
+  for (auto& pr : P.proj[t.input_idx])
+    if ((pass >> (P.nout - 1 - pr.first)) & 1) off += int64_t(1) << pr.second;
+  return static_cast<const char*>(T[t.input_idx].data) + off * P.es;
+}
+
 // Parameter tables of the grouped small-step launches, one per level, with
-// operand pointers resolved for this call.
+// operand pointers resolved for this call (pass 0; the kernel adds the
+// projection offsets of later passes).
+using LevelLaunches = std::vector<GroupedLaunch>;
 static void build_net_tables(const NetPlan& P, const rn_tensor* T, void* ws,
-                             std::vector<char>& blob, std::vector<GroupedLaunch>& per_level) {
+                             std::vector<char>& blob, LevelLaunches& per_level) {
   char* w = static_cast<char*>(ws);
   const int nt = (int)P.T.size() - (int)P.steps.size();
-  auto ptr = [&](int id) -> const void* {
-    const NTensor& t = P.T[id];
-    return t.input ? T[t.input_idx].data : static_cast<const void*>(w + t.off);
-  };
   blob.clear();
   per_level.assign(P.levels.size(), GroupedLaunch{});
   std::vector<char> part;
+  auto ptr = [&](int id) { return tensor_ptr(P, T, w, id, 0); };
   for (size_t L = 0; L < P.levels.size(); ++L) {
     std::vector<DirectStep> ds;
     for (int si : P.levels[L]) {
@@ -386,22 +444,19 @@ static void build_net_tables(const NetPlan& P, const rn_tensor* T, void* ws,
   }
 }
 
-static rn_status enqueue_network(const NetPlan& P, const rn_tensor* T, void* ws, hipStream_t s,
-                                 double* amp_dev, double* slices_dev, Profiler* prof,
-                                 const std::vector<GroupedLaunch>& per_level) {
+static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hipStream_t s,
+                              int64_t pass, double* sum_dev, double* slices_dev, Profiler* prof,
+                              const std::vector<GroupedLaunch>& per_level) {
   char* w = static_cast<char*>(ws);
   const bool split_prec = (P.mode == RN_BF16X3);
-  auto ptr = [&](int id) -> const void* {
-    const NTensor& t = P.T[id];
-    return t.input ? T[t.input_idx].data : static_cast<const void*>(w + t.off);
-  };
+  auto ptr = [&](int id) { return tensor_ptr(P, T, w, id, pass); };
   hipError_t e;
   const int nt = (int)P.T.size() - (int)P.steps.size();
   for (size_t L = 0; L < P.levels.size(); ++L) {
     // All small steps of this level in one launch, then the large ones.
     if (per_level[L].n > 0) {
       int ev = prof->begin(1, s);
-      e = launch_direct_grouped(per_level[L], w + P.table_off, s);
+      e = launch_direct_grouped(per_level[L], w + P.table_off, pass, P.nout, s);
       prof->end(ev, s);
       if (e != hipSuccess)
         return fail(RN_ERR_HIP, std::string("network small steps: ") + hipGetErrorString(e));
@@ -478,53 +533,90 @@ static rn_status enqueue_network(const NetPlan& P, const rn_tensor* T, void* ws,
   const NTensor& fin = P.T.back();
   int64_t nvals = int64_t(1) << popc(fin.dmask);
   int ev = prof->begin(3, s);
-  e = launch_sum_slices(ptr((int)P.T.size() - 1), P.es, nvals, amp_dev, slices_dev, s);
+  e = launch_sum_slices(ptr((int)P.T.size() - 1), P.es, nvals, sum_dev,
+                        slices_dev ? slices_dev + 2 * pass * nvals : nullptr, s);
   prof->end(ev, s);
   if (e != hipSuccess) return fail(RN_ERR_HIP, std::string("slice sum: ") + hipGetErrorString(e));
   return RN_OK;
 }
 
-}  // namespace rn
-
-using namespace rn;
-
-extern "C" {
-
-rn_status rn_contract_network_plan(rn_handle h, int32_t nt, const rn_tensor* T,
-                                   const int32_t* const* labels, int32_t nsteps,
-                                   const int32_t* path, int32_t nsliced, const int32_t* sliced,
-                                   rn_mode mode, size_t* ws_bytes, double* flops,
-                                   int32_t* max_rank) {
-  (void)h;
-  NetPlan P;
-  rn_status st = plan_network(nt, T, labels, nsteps, path, nsliced, sliced, mode, &P);
-  if (st != RN_OK) return st;
-  if (ws_bytes) *ws_bytes = (size_t)P.ws_bytes;
-  if (flops) *flops = P.flops;
-  if (max_rank) *max_rank = P.max_rank;
+// Every pass in order; with several passes each writes its own FP64 sum and
+// one more launch adds those in ascending pass order.
+static rn_status enqueue_network(const NetPlan& P, const rn_tensor* T, void* ws, hipStream_t s,
+                                 double* amp_dev, double* slices_dev, Profiler* prof,
+                                 const LevelLaunches& launches) {
+  const int64_t npass = int64_t(1) << P.nout;
+  char* w = static_cast<char*>(ws);
+  double* sums = reinterpret_cast<double*>(w + P.sums_off);
+  rn_status st;
+  for (int64_t pass = 0; pass < npass; ++pass) {
+    double* out = npass > 1 ? sums + 2 * pass : amp_dev;
+    if ((st = enqueue_pass(P, T, ws, s, pass, out, slices_dev, prof, launches)) != RN_OK)
+      return st;
+  }
+  if (npass > 1) {
+    int ev = prof->begin(3, s);
+    hipError_t e = launch_sum_c128(sums, npass, amp_dev, s);
+    prof->end(ev, s);
+    if (e != hipSuccess)
+      return fail(RN_ERR_HIP, std::string("pass sum: ") + hipGetErrorString(e));
+  }
   return RN_OK;
 }
 
-rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
-                              const int32_t* const* labels, int32_t nsteps, const int32_t* path,
-                              int32_t nsliced, const int32_t* sliced, rn_mode mode, void* ws,
-                              size_t ws_bytes, void* stream, double* amp_dev,
-                              double* slices_dev) {
-  if (!h) return fail(RN_ERR_INVALID, "null handle");
+// Plan under the options: the largest batched-slice count whose workspace
+// fits the cap.
+static rn_status plan_fitting(int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                              int32_t nsteps, const int32_t* path, int32_t nsliced,
+                              const int32_t* sliced, rn_mode mode, const NetOpts& o,
+                              NetPlan* P) {
+  int bb = std::min(std::max(o.batch_bits, 0), std::max(nsliced, 0));
+  for (;; --bb) {
+    rn_status st = plan_network(nt, T, labels, nsteps, path, nsliced, sliced, mode, o.slice_sum,
+                                bb, P);
+    if (st != RN_OK) return st;
+    if (o.footprint <= 0 || P->ws_bytes <= o.footprint) return RN_OK;
+    if (bb == 0)
+      return fail(RN_ERR_OOM, "network workspace " + std::to_string(P->ws_bytes) +
+                                  " bytes exceeds the cap even with every slice in its own pass");
+  }
+}
+
+rn_status network_plan(int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                       int32_t nsteps, const int32_t* path, int32_t nsliced,
+                       const int32_t* sliced, rn_mode mode, const NetOpts& o, size_t* ws_bytes,
+                       double* flops, int32_t* max_rank, int* batch_bits) {
+  NetPlan P;
+  rn_status st = plan_fitting(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &P);
+  if (st != RN_OK) return st;
+  if (ws_bytes) *ws_bytes = (size_t)P.ws_bytes;
+  if (flops) *flops = P.flops * double(int64_t(1) << P.nout);
+  if (max_rank) *max_rank = P.max_rank;
+  if (batch_bits) *batch_bits = P.nsliced - P.nout;
+  return RN_OK;
+}
+
+rn_status network_run(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                      int32_t nsteps, const int32_t* path, int32_t nsliced,
+                      const int32_t* sliced, rn_mode mode, const NetOpts& o, void* ws,
+                      size_t ws_bytes, hipStream_t s, double* amp_dev, double* slices_dev) {
   if (!amp_dev) return fail(RN_ERR_INVALID, "null amplitude buffer");
   NetPlan P;
-  rn_status st = plan_network(nt, T, labels, nsteps, path, nsliced, sliced, mode, &P);
+  rn_status st = plan_fitting(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &P);
   if (st != RN_OK) return st;
+  if (P.slice_sum && slices_dev && nsliced > 0)
+    return fail(RN_ERR_INVALID, "per-slice values do not exist in slice-sum mode");
   if ((int64_t)ws_bytes < P.ws_bytes || (P.ws_bytes > 0 && !ws))
     return fail(RN_ERR_WORKSPACE, "workspace smaller than planned (" +
                                       std::to_string(P.ws_bytes) + " bytes needed)");
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return fail(RN_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
-  hipStream_t s = static_cast<hipStream_t>(stream);
   if (use_graphs(h, s)) {
     uint64_t key = 1469598103934665603ull;
     key = hash_bytes(key, "network", 7);
     key = hash_bytes(key, &mode, sizeof(mode));
+    key = hash_bytes(key, &P.slice_sum, sizeof(P.slice_sum));
+    key = hash_bytes(key, &P.nout, sizeof(P.nout));
     key = hash_bytes(key, &nt, sizeof(nt));
     for (int i = 0; i < nt; ++i) {
       key = hash_tensor(key, T[i]);
@@ -541,19 +633,45 @@ rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
     if ((st = replay_graph(h, key, s, &done)) != RN_OK || done) return st;
     if (seen_before(h, key)) {
       std::vector<char> blob;
-      std::vector<GroupedLaunch> per_level;
-      build_net_tables(P, T, ws, blob, per_level);
+      LevelLaunches launches;
+      build_net_tables(P, T, ws, blob, launches);
       char* tdev = static_cast<char*>(ws) + P.table_off;
       return capture_and_launch(h, key, blob, tdev, s, [&](hipStream_t cs) {
-        return enqueue_network(P, T, ws, cs, amp_dev, slices_dev, &h->prof, per_level);
+        return enqueue_network(P, T, ws, cs, amp_dev, slices_dev, &h->prof, launches);
       });
     }
   }
   std::vector<char> blob;
-  std::vector<GroupedLaunch> per_level;
-  build_net_tables(P, T, ws, blob, per_level);
+  LevelLaunches launches;
+  build_net_tables(P, T, ws, blob, launches);
   if ((st = upload_table(h, blob, static_cast<char*>(ws) + P.table_off, s)) != RN_OK) return st;
-  return enqueue_network(P, T, ws, s, amp_dev, slices_dev, &h->prof, per_level);
+  return enqueue_network(P, T, ws, s, amp_dev, slices_dev, &h->prof, launches);
+}
+
+}  // namespace rn
+
+using namespace rn;
+
+extern "C" {
+
+rn_status rn_contract_network_plan(rn_handle h, int32_t nt, const rn_tensor* T,
+                                   const int32_t* const* labels, int32_t nsteps,
+                                   const int32_t* path, int32_t nsliced, const int32_t* sliced,
+                                   rn_mode mode, size_t* ws_bytes, double* flops,
+                                   int32_t* max_rank) {
+  const NetOpts o = h ? h->net : NetOpts{};
+  return network_plan(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, ws_bytes, flops,
+                      max_rank, nullptr);
+}
+
+rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
+                              const int32_t* const* labels, int32_t nsteps, const int32_t* path,
+                              int32_t nsliced, const int32_t* sliced, rn_mode mode, void* ws,
+                              size_t ws_bytes, void* stream, double* amp_dev,
+                              double* slices_dev) {
+  if (!h) return fail(RN_ERR_INVALID, "null handle");
+  return network_run(h, nt, T, labels, nsteps, path, nsliced, sliced, mode, h->net, ws, ws_bytes,
+                     static_cast<hipStream_t>(stream), amp_dev, slices_dev);
 }
 
 }  // extern "C"

@@ -83,7 +83,7 @@ static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
                          const int32_t* axesA, const int32_t* axesB, rn_mode mode,
-                         TdPlan* P, bool allow_splitk) {
+                         TdPlan* P, bool allow_splitk, const SplitPolicy* policy) {
   Layout LA, LB;
   rn_status st;
   if ((st = make_layout(A, "A", &LA)) != RN_OK) return st;
@@ -218,6 +218,21 @@ rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
     }
   }
   p.splitk = allow_splitk ? choose_splitk(mode, p.M, p.N, p.K, 1) : 1;
+  const int64_t bk = int64_t(1) << p.pairbits;
+  if (allow_splitk && policy && policy->pair_threshold > 0) {
+    if (bk >= policy->pair_threshold && bk >= 2) {
+      // One partial per group of pairs: split count a power of two <= B_k,
+      // so every split boundary is a pair boundary; chunks of at least 64
+      // keep each split's K range a whole number of MFMA K-steps.
+      const int64_t part = p.M * p.N * (mode == RN_FP64 ? 16 : 8);
+      int s = 1;
+      while (s < 64 && 2 * s <= bk && p.K / (2 * s) >= 64 && 2 * s * part <= policy->footprint)
+        s *= 2;
+      p.splitk = s;
+    } else {
+      p.splitk = 1;
+    }
+  }
   if (p.splitk > 1) {
     p.off_part = off;
     off = align256(off + int64_t(p.splitk) * p.M * p.N * (mode == RN_FP64 ? 16 : 8));

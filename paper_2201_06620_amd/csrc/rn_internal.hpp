@@ -77,9 +77,23 @@ struct TdPlan {
   double flops = 0;
 };
 
+// Network options of a handle (defaults when planning without one).
+struct NetOpts {
+  bool slice_sum = false;       // sum sliced bonds where they are contracted
+  int batch_bits = 64;          // sliced bonds batched per pass (the rest loop)
+  int64_t footprint = 0;        // workspace cap in bytes; 0: none
+};
+
+// Reduction-strategy options of a handle (defaults when planning without one).
+struct SplitPolicy {
+  int64_t pair_threshold = 0;                 // 0: heuristic
+  int64_t footprint = int64_t(1) << 30;       // bytes of partial sums
+};
+
 rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
                          const int32_t* axesA, const int32_t* axesB, rn_mode mode,
-                         TdPlan* P, bool allow_splitk = true);
+                         TdPlan* P, bool allow_splitk = true,
+                         const SplitPolicy* policy = nullptr);
 rn_status check_c(const TdPlan& P, const rn_tensor* C);
 
 // Optional per-launch event timing (rn_profile_enable).
@@ -161,12 +175,18 @@ struct DirectStep {
   int blocks_per_batch = 1;
   int8_t am[40] = {0}, ak[40] = {0}, bn[40] = {0}, bk[40] = {0};
   int64_t a_bs[RN_MAX_SLICED] = {0}, b_bs[RN_MAX_SLICED] = {0};
+  // Projection per pass: 1 + stored bit of the sliced bond the pass fixes
+  // (slice index i of the fixed ones), 0 when the operand does not carry it.
+  int8_t a_pp[RN_MAX_SLICED] = {0}, b_pp[RN_MAX_SLICED] = {0};
 };
 constexpr int64_t kDirectMaxK = 4096;
 size_t grouped_direct_bound(int n);
 size_t grouped_direct_build(const std::vector<DirectStep>& steps, rn_mode mode,
                             std::vector<char>& table, GroupedLaunch& G);
-hipError_t launch_direct_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s);
+// pass / nout: the pass index and the number of sliced bonds a pass fixes
+// (bit nout-1-i of pass is the value of fixed bond i).
+hipError_t launch_direct_grouped(const GroupedLaunch& G, const void* table_dev, int64_t pass,
+                                 int nout, hipStream_t s);
 size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
                           std::vector<char>& table, GroupedLaunch& G);
 hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s);
@@ -208,6 +228,8 @@ struct rn_ctx {
   size_t pinned_bytes = 0;
   hipEvent_t pinned_done = nullptr;
   bool graphs_enabled = true;
+  rn::SplitPolicy split;
+  rn::NetOpts net;
   std::vector<GraphEntry> graphs;
   std::vector<uint64_t> seen;  // keys run once directly; a repeat is captured
   uint64_t use_clock = 0;
@@ -225,6 +247,16 @@ uint64_t hash_tensor(uint64_t x, const rn_tensor& t);
 // launches it.  use_graphs: graphs are enabled, the stream is not the null
 // stream, not already capturing, and kernel timing is off.
 bool use_graphs(const rn_ctx* h, hipStream_t s);
+// Network plan and run under explicit options (the C entry points pass the
+// handle's).  *batch_bits receives the batched-slice count the plan chose.
+rn_status network_plan(int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                       int32_t nsteps, const int32_t* path, int32_t nsliced,
+                       const int32_t* sliced, rn_mode mode, const NetOpts& o, size_t* ws_bytes,
+                       double* flops, int32_t* max_rank, int* batch_bits);
+rn_status network_run(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                      int32_t nsteps, const int32_t* path, int32_t nsliced,
+                      const int32_t* sliced, rn_mode mode, const NetOpts& o, void* ws,
+                      size_t ws_bytes, hipStream_t s, double* amp_dev, double* slices_dev);
 rn_status replay_graph(rn_ctx* h, uint64_t key, hipStream_t s, bool* done);
 // True when `key` was run before (directly); otherwise remembers it.
 bool seen_before(rn_ctx* h, uint64_t key);

@@ -71,6 +71,7 @@ struct Request {
   std::vector<std::vector<int32_t>> labels;
   std::vector<int32_t> path, sliced;
   size_t ws_bytes = 0, tensor_bytes = 0, footprint = 0;
+  NetOpts opts;  // batched-slice count fitted to the budget at submission
   Clock::time_point t_submit, t_start, t_done;
   size_t arena_off = 0;
   int slot = -1;
@@ -143,9 +144,9 @@ int32_t start(rn_server* S, Request* r, int slot) {
   void* ws = base + off;
   std::vector<const int32_t*> lab(r->nt);
   for (int i = 0; i < r->nt; ++i) lab[i] = r->labels[i].data();
-  rn_status st = rn_contract_network(S->h, r->nt, dev.data(), lab.data(), r->nsteps,
-                                     r->path.data(), r->nsliced, r->sliced.data(), r->mode, ws,
-                                     r->ws_bytes, s, amp_dev, nullptr);
+  rn_status st = network_run(S->h, r->nt, dev.data(), lab.data(), r->nsteps, r->path.data(),
+                             r->nsliced, r->sliced.data(), r->mode, r->opts, ws, r->ws_bytes, s,
+                             amp_dev, nullptr);
   if (st != RN_OK) return st;
   if (hipMemcpyAsync(S->amp_host + 2 * slot, amp_dev, 2 * sizeof(double), hipMemcpyDeviceToHost,
                      s) != hipSuccess)
@@ -279,19 +280,41 @@ rn_status rn_server_submit(rn_server_t S, int32_t nt, const rn_tensor* T,
                            uint64_t* ticket) {
   if (!S || !ticket) return fail(RN_ERR_INVALID, "null argument");
   auto t0 = Clock::now();
+  if (nt < 1 || !T || !labels) return fail(RN_ERR_INVALID, "empty network");
+  const size_t es = mode == RN_FP64 ? 16 : 8;
+  size_t tensor_bytes = 0;
+  for (int i = 0; i < nt; ++i) {
+    if (T[i].rank < 0 || T[i].rank > 40) return fail(RN_ERR_INVALID, "tensor rank out of range");
+    tensor_bytes += al256(es << T[i].rank);
+  }
+  // Admission granularity: a request whose workspace would not fit the
+  // budget beside its tensors runs with fewer sliced bonds batched per pass
+  // (more passes, less memory); only one that does not fit even with a
+  // single slice per pass is refused at admission.
+  NetOpts o;
+  const size_t fixed = tensor_bytes + 256;
+  o.footprint = S->budget > fixed ? (int64_t)(S->budget - fixed) : 1;
   size_t ws = 0;
   double flops = 0;
   int32_t mr = 0;
-  rn_status st = rn_contract_network_plan(nullptr, nt, T, labels, nsteps, path, nsliced, sliced,
-                                          mode, &ws, &flops, &mr);
+  int bb = 0;
+  rn_status st = network_plan(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &ws, &flops,
+                              &mr, &bb);
+  if (st == RN_ERR_OOM) {
+    o = NetOpts{};
+    st = network_plan(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &ws, &flops, &mr,
+                      &bb);
+  }
   if (st != RN_OK) return st;
+  o.batch_bits = bb;
+  o.footprint = 0;
   Request* r = new Request();
+  r->opts = o;
   r->mode = mode;
   r->nt = nt;
   r->nsteps = nsteps;
   r->nsliced = nsliced;
   r->desc.assign(T, T + nt);
-  const size_t es = mode == RN_FP64 ? 16 : 8;
   for (int i = 0; i < nt; ++i) {
     size_t n = es << T[i].rank;
     r->data.emplace_back(static_cast<const char*>(T[i].data),

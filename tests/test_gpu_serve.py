@@ -126,3 +126,24 @@ def test_admission_respects_budget(requests_):
         assert srv.wait(t)["status"] == 0
     assert peak <= 64 << 20
     srv.close()
+
+
+def test_sliced_request_fitted_to_budget():
+    # A sliced request whose all-batched footprint exceeds the budget runs
+    # with fewer slices batched per pass instead of being refused.
+    import paper_2201_06620_amd as rn
+    w = configs.circuit_workload(3, 4, 10, 4242, n_slices=5, restarts=2)
+    ref, _ = oracle.contract_network(w.network.tensors, w.network.labels, w.path, w.sliced)
+    ref = complex(ref)
+    big = rn.Server(0, hbm_budget=1 << 30, max_active=1)
+    full = big.wait(submit(big, w, "fp64"))
+    big.close()
+    assert full["status"] == 0
+    budget = int(full["footprint"]) * 3 // 4
+    srv = rn.Server(0, hbm_budget=budget, max_active=2)
+    res = srv.wait(submit(srv, w, "fp64"))
+    srv.close()
+    log(f"  footprint all-batched={full['footprint']:.0f} fitted={res['footprint']:.0f}")
+    assert res["status"] == 0
+    assert res["footprint"] <= budget
+    assert abs(res["amp"] - ref) / max(abs(ref), 2.0 ** (-w.circuit.n / 2)) < 1e-12

@@ -162,6 +162,31 @@ def test_workspace_error_leaves_output(ctx):
     assert e.value.status == 4
 
 
+def test_shape_and_workspace_checks(ctx):
+    import ctypes
+    import paper_2201_06620_amd as rn
+    lib = rn.lib()
+    A = rn.descriptor([2] * 4, None, rn.C128, 0x1000)
+    B = rn.descriptor([2] * 4, None, rn.C128, 0x2000)
+    axa = np.array([3, 1], dtype=np.int32)
+    axb = np.array([0, 2], dtype=np.int32)
+    C = rn.RnTensor()
+    ws = ctypes.c_size_t()
+    assert lib.rn_block_tensordot_plan(ctx.h, ctypes.byref(A), ctypes.byref(B), 2,
+                                       axa.ctypes.data, axb.ctypes.data, 0, ctypes.byref(C),
+                                       ctypes.byref(ws), None) == 0
+    C.data = 0x3000
+    # Both checks fail before any pointer is used.
+    st = lib.rn_block_tensordot(ctx.h, ctypes.byref(A), ctypes.byref(B), 2, axa.ctypes.data,
+                                axb.ctypes.data, ctypes.byref(C), 0, None, 0, None)
+    assert st == 4  # RN_ERR_WORKSPACE
+    C.dims[0] = 4
+    st = lib.rn_block_tensordot(ctx.h, ctypes.byref(A), ctypes.byref(B), 2, axa.ctypes.data,
+                                axb.ctypes.data, ctypes.byref(C), 0, None, 1 << 30, None)
+    assert st == 2  # RN_ERR_SHAPE
+    assert b"dims" in lib.rn_last_error()
+
+
 def test_norm2_and_sum(ctx):
     import torch
     x = rng.complex_normal(44, 2 ** 18)

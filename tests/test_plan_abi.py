@@ -126,8 +126,8 @@ def test_plan_error_codes(kw, status):
     assert e.value.status == status
 
 
-def test_workspace_and_c_checks_before_device():
-    # rn_block_tensordot reports argument errors without touching the GPU.
+def test_block_tensordot_rejects_null_handle():
+    # Argument errors come back as status codes without touching a device.
     lib = rn.lib()
     A = rn.descriptor([2] * 4, None, rn.C128, 0x1000)
     B = rn.descriptor([2] * 4, None, rn.C128, 0x2000)
@@ -140,15 +140,13 @@ def test_workspace_and_c_checks_before_device():
                                        ctypes.byref(ws), None) == 0
     assert ws.value > 0
     C.data = 0x3000
-    fake = ctypes.c_void_p(0x10)   # never dereferenced: checks fail first
-    st = lib.rn_block_tensordot(fake, ctypes.byref(A), ctypes.byref(B), 2, axa.ctypes.data,
+    st = lib.rn_block_tensordot(None, ctypes.byref(A), ctypes.byref(B), 2, axa.ctypes.data,
                                 axb.ctypes.data, ctypes.byref(C), 0, None, 0, None)
-    assert st == 4  # RN_ERR_WORKSPACE
-    C.dims[0] = 4
-    st = lib.rn_block_tensordot(fake, ctypes.byref(A), ctypes.byref(B), 2, axa.ctypes.data,
-                                axb.ctypes.data, ctypes.byref(C), 0, None, 1 << 30, None)
-    assert st == 2  # RN_ERR_SHAPE
-    assert b"dims" in lib.rn_last_error()
+    assert st == 1  # RN_ERR_INVALID
+    assert b"handle" in lib.rn_last_error()
+    assert lib.rn_set_option(None, 1, 4) == 1
+    v = ctypes.c_int64()
+    assert lib.rn_get_option(None, 1, ctypes.byref(v)) == 1
 
 
 def test_network_plan_config2_host():
