@@ -108,6 +108,32 @@ rn_status rn_block_tensordot(rn_handle h, const rn_tensor* A, const rn_tensor* B
                              const int32_t* axesA, const int32_t* axesB, rn_tensor* C,
                              rn_mode mode, void* ws, size_t ws_bytes, void* stream);
 
+/* Streamed block tensordot, for operands larger than device memory: the
+ * commutative reduction of Section IV.A (pairs loaded as needed, each
+ * product added into its output block), with A->data and B->data in HOST
+ * memory (block-major, as for rn_block_tensordot; allocate with
+ * hipHostMalloc so the copies overlap compute) and C->data in device memory.
+ * Output block rows run outermost, then the coupled pairs in ascending
+ * order, then the output block columns: each A block is copied once, each
+ * B block once per output row.  Copies run on a copy stream the handle
+ * owns, compute on `stream`; the call returns once everything is queued,
+ * and the caller must keep A and B alive and unchanged until `stream` has
+ * reached that point.  Device memory: C plus the planned workspace (two
+ * staging slots per operand block, the permuted blocks and one partial
+ * output block).  Paired axes must have equal grids on A and B
+ * (RN_ERR_UNSUPPORTED otherwise).  The plan reports the workspace, useful
+ * flops and the host-to-device bytes the call will copy.  Calls on one
+ * handle share its copy stream and must not be issued from several threads
+ * at once. */
+rn_status rn_block_tensordot_streamed_plan(rn_handle h, const rn_tensor* A, const rn_tensor* B,
+                                           int32_t k, const int32_t* axesA,
+                                           const int32_t* axesB, rn_mode mode, rn_tensor* C,
+                                           size_t* ws_bytes, double* flops, double* h2d_bytes);
+rn_status rn_block_tensordot_streamed(rn_handle h, const rn_tensor* A, const rn_tensor* B,
+                                      int32_t k, const int32_t* axesA, const int32_t* axesB,
+                                      rn_tensor* C, rn_mode mode, void* ws, size_t ws_bytes,
+                                      void* stream);
+
 /* Pair list of one output block (step 2 of Section II.C): for C block
  * `cblock` (row-major linear block index) writes up to `cap` pairs
  * (A block index, B block index), each a row-major linear index into the

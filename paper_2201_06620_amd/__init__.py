@@ -32,7 +32,8 @@ EXPORTS = ["rn_create", "rn_destroy", "rn_status_str", "rn_last_error",
            "rn_profile_enable", "rn_profile_read", "rn_autotune_batch", "rn_tune_save",
            "rn_tune_load", "rn_tune_clear", "rn_tile_count", "rn_set_graphs", "rn_server_create",
            "rn_server_submit", "rn_server_poll", "rn_server_wait", "rn_server_stats",
-           "rn_server_destroy", "rn_set_option", "rn_get_option"]
+           "rn_server_destroy", "rn_set_option", "rn_get_option",
+           "rn_block_tensordot_streamed_plan", "rn_block_tensordot_streamed"]
 
 # Handle options (rn_option).
 OPTIONS = {"graphs": 0, "pair_split_threshold": 1, "split_footprint": 2, "slice_sum": 3,
@@ -105,6 +106,11 @@ def lib():
         L.rn_tile_count.argtypes = [ctypes.c_int]
         L.rn_set_graphs.argtypes = [p, ctypes.c_int]
         L.rn_set_option.argtypes = [p, ctypes.c_int, i64]
+        L.rn_block_tensordot_streamed_plan.argtypes = [p, T, T, i32, p, p, ctypes.c_int, T,
+                                                       ctypes.POINTER(sz),
+                                                       ctypes.POINTER(ctypes.c_double),
+                                                       ctypes.POINTER(ctypes.c_double)]
+        L.rn_block_tensordot_streamed.argtypes = [p, T, T, i32, p, p, T, ctypes.c_int, p, sz, p]
         L.rn_get_option.argtypes = [p, ctypes.c_int, ctypes.POINTER(i64)]
         L.rn_server_create.argtypes = [ctypes.c_int, sz, i32, ctypes.POINTER(p)]
         L.rn_server_submit.argtypes = [p, i32, T, pp, i32, p, i32, p, ctypes.c_int,
@@ -313,6 +319,49 @@ class Context:
                                        ctypes.byref(C), mode_id(mode), wp, wn, self._stream()),
               "block_tensordot")
         return out, cdims, cgrid
+
+    def plan_streamed(self, dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, mode="fp64"):
+        """(C dims, C grid, workspace bytes, useful flops, host-to-device bytes)."""
+        dt = dtype_of_mode(mode)
+        A, B, C = descriptor(dims_a, grid_a, dt), descriptor(dims_b, grid_b, dt), RnTensor()
+        aa, pa = _arr32(axes_a)
+        bb, pb = _arr32(axes_b)
+        ws, fl, hd = ctypes.c_size_t(), ctypes.c_double(), ctypes.c_double()
+        check(lib().rn_block_tensordot_streamed_plan(
+            self.h, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb, mode_id(mode),
+            ctypes.byref(C), ctypes.byref(ws), ctypes.byref(fl), ctypes.byref(hd)),
+            "streamed plan")
+        return ([C.dims[j] for j in range(C.rank)], [C.grid[j] for j in range(C.rank)],
+                ws.value, fl.value, hd.value)
+
+    def block_tensordot_streamed(self, a_host, dims_a, grid_a, b_host, dims_b, grid_b, axes_a,
+                                 axes_b, mode="fp64", out=None, workspace=None):
+        """Operands in (pinned) host memory, C on the device; returns C, dims, grid.
+
+        Queued on the current stream; a_host and b_host must stay alive and
+        unchanged until that stream has passed this call.
+        """
+        import torch
+        dt = dtype_of_mode(mode)
+        want = torch.complex128 if dt == C128 else torch.complex64
+        for t in (a_host, b_host):
+            if t.is_cuda or t.dtype != want or not t.is_contiguous():
+                raise ValueError("streamed operands: contiguous host tensors of the mode's dtype")
+        cd, cg, ws_n, _, _ = self.plan_streamed(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b,
+                                                 mode)
+        n = int(np.prod(cd, dtype=np.int64)) if cd else 1
+        if out is None:
+            out = torch.empty(n, dtype=want, device=torch.device("cuda", self.device))
+        A = descriptor(dims_a, grid_a, dt, a_host.data_ptr())
+        B = descriptor(dims_b, grid_b, dt, b_host.data_ptr())
+        C = descriptor(cd, cg, dt, out.data_ptr())
+        aa, pa = _arr32(axes_a)
+        bb, pb = _arr32(axes_b)
+        wp, wn = self._workspace(ws_n, workspace)
+        check(lib().rn_block_tensordot_streamed(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
+                                                pa, pb, ctypes.byref(C), mode_id(mode), wp, wn,
+                                                self._stream()), "streamed tensordot")
+        return out, cd, cg
 
     def block_tensordot_batch(self, problems, mode="fp32_4m", outs=None, workspace=None,
                               autotune=False):

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librosnet.so")
-SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "network.cpp", "batch.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "plan.cpp", "network.cpp", "batch.cpp", "serve.cpp",
+           "stream.cpp"]
 ARCH = os.environ.get("RN_OFFLOAD_ARCH", "gfx950")
 
 

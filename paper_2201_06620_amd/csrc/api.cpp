@@ -171,6 +171,12 @@ rn_status rn_destroy(rn_handle h) {
     hipEventDestroy(h->pinned_done);
   }
   if (h->pinned) hipHostFree(h->pinned);
+  if (h->copy_stream) {
+    hipStreamSynchronize(h->copy_stream);
+    hipStreamDestroy(h->copy_stream);
+  }
+  for (hipEvent_t e : h->copy_ev)
+    if (e) hipEventDestroy(e);
   delete h;
   return RN_OK;
 }

@@ -2217,6 +2217,33 @@ hipError_t launch_direct_grouped(const GroupedLaunch& G, const void* table_dev, 
 }
 
 // ===========================================================================
+// C += P over n complex elements (streamed contraction: the partial of one
+// block pair added to its output block).
+// ===========================================================================
+template <typename T>
+__global__ __launch_bounds__(256) void add_into(T* __restrict__ c, const T* __restrict__ p,
+                                                int64_t n) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    T a = c[i], b = p[i];
+    a.x += b.x;
+    a.y += b.y;
+    c[i] = a;
+  }
+}
+
+hipError_t launch_add_into(void* c, const void* p, int64_t n, int es, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 256 * 32);
+  if (es == 16)
+    add_into<double2><<<grid, 256, 0, s>>>(static_cast<double2*>(c),
+                                           static_cast<const double2*>(p), n);
+  else
+    add_into<float2><<<grid, 256, 0, s>>>(static_cast<float2*>(c), static_cast<const float2*>(p),
+                                          n);
+  return hipGetLastError();
+}
+
+// ===========================================================================
 // FP64 reductions.  Deterministic: every element goes to a fixed lane, lanes
 // combine in a fixed butterfly order (cross-lane shuffles), waves in a fixed
 // order through LDS, blocks in ascending order in a second pass.

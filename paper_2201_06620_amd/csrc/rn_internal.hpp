@@ -199,6 +199,7 @@ rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor
 hipError_t launch_norm2(const void* x, int64_t n, int dtype, double* out, double* scratch,
                         hipStream_t s);
 hipError_t launch_sum_c128(const double* vals, int64_t n, double* out, hipStream_t s);
+hipError_t launch_add_into(void* c, const void* p, int64_t n, int es, hipStream_t s);
 hipError_t launch_sum_slices(const void* vals, int es, int64_t n, double* out_sum,
                              double* out_each, hipStream_t s);
 
@@ -230,6 +231,9 @@ struct rn_ctx {
   bool graphs_enabled = true;
   rn::SplitPolicy split;
   rn::NetOpts net;
+  // Streamed contraction: host-to-device copy stream and its events.
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t copy_ev[9] = {nullptr};
   std::vector<GraphEntry> graphs;
   std::vector<uint64_t> seen;  // keys run once directly; a repeat is captured
   uint64_t use_clock = 0;
