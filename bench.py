@@ -137,6 +137,177 @@ def run_serving(args, torch, rn, log):
     return out
 
 
+def run_weak_share(args, torch, rn, log):
+    """Weak-scaling workload of the paper's evaluation (Section V.C), one
+    device's share at the real block shape: U (m x k) . V (n x k)^T with
+    blocks m_b = n_b = 2^14, k_b = 2^13, complex64, B_m x B_n = 8 x 6 output
+    blocks (Table I, one node) and B_k coupled pairs.  B_n = 6 is not a power
+    of two, so the share runs as two contractions sharing U: 4 and 2 output
+    block columns.
+
+    placement "hbm": both operands resident in HBM and the pairs fused into
+    one K loop (every pair's blocks in memory at once, the Eq. 1 regime).
+    placement "streamed": operands in pinned host memory, pairs copied in as
+    needed and added into the HBM output blocks (the commutative reduction,
+    Eq. 2 per block in flight).  Prints one JSON line per run.
+    """
+    ctx = rn.Context(0)
+    dev = "cuda:0"
+    mb_bits, nb_inner, kb_inner = args.weak_block_bits
+
+    def gen_device(n, seed):
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed)
+        return torch.randn(n, dtype=torch.complex64, device=dev, generator=g)
+
+    def gen_pinned(n, seed):
+        host = torch.empty(n, dtype=torch.complex64, pin_memory=True)
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed)
+        chunk = 1 << 27
+        for o in range(0, n, chunk):
+            m = min(chunk, n - o)
+            host[o:o + m].copy_(torch.randn(m, dtype=torch.complex64, device=dev, generator=g))
+        torch.cuda.synchronize()
+        return host
+
+    def shapes(bm_bits, bn_bits, bk_bits, blocked):
+        # Axes: U = [m block bits | m inner | k block bits | k inner]; for a
+        # blocked (block-major) store the block bits carry grid 2.
+        ua = bm_bits + mb_bits + bk_bits + kb_inner
+        va = bn_bits + nb_inner + bk_bits + kb_inner
+        g = 2 if blocked else 1
+        gu = [g] * bm_bits + [1] * mb_bits + [g] * bk_bits + [1] * kb_inner
+        gv = [g] * bn_bits + [1] * nb_inner + [g] * bk_bits + [1] * kb_inner
+        ax_u = list(range(bm_bits + mb_bits, ua))
+        ax_v = list(range(bn_bits + nb_inner, va))
+        return [2] * ua, gu, [2] * va, gv, ax_u, ax_v
+
+    def sample_check(c_flat, u_rows, v_rows, m_total, n_total, k_total, blocked, bn_bits):
+        # A few outputs recomputed in float64 with numpy from the operand rows.
+        rs = np.random.default_rng(13)
+        worst = 0.0
+        for _ in range(4):
+            i = int(rs.integers(0, m_total))
+            j = int(rs.integers(0, n_total))
+            ur = u_rows(i).astype(np.complex128)
+            vr = v_rows(j).astype(np.complex128)
+            ref = np.dot(ur, vr)
+            if blocked:
+                bi, ii = i >> mb_bits, i & ((1 << mb_bits) - 1)
+                bj, jj = j >> nb_inner, j & ((1 << nb_inner) - 1)
+                off = ((bi << bn_bits) + bj) * (1 << (mb_bits + nb_inner)) + (ii << nb_inner) + jj
+            else:
+                off = i * n_total + j
+            got = complex(c_flat[off].item())
+            worst = max(worst, abs(got - ref) / (np.linalg.norm(ur) * np.linalg.norm(vr)))
+        return worst
+
+    bm_bits = 3
+    results = []
+    for placement, bk_list, sub in (("hbm", args.weak_bk, None),
+                                    ("streamed", args.stream_bk, None),
+                                    ("streamed", args.stream_sub_bk, (0, 1)),
+                                    ("hbm", args.stream_sub_bk, (0, 1))):
+        for bk in bk_list:
+            bk_bits = int(bk).bit_length() - 1
+            rows_bits = bm_bits if sub is None else sub[0]
+            col_splits = [2, 1] if sub is None else [sub[1]]  # 4 + 2 columns, or a sub-grid
+            blocked = placement == "streamed"
+            m_total = 1 << (rows_bits + mb_bits)
+            k_total = 1 << (bk_bits + kb_inner)
+            log(f"weak share: placement={placement} B_k={bk} rows={1 << rows_bits} "
+                f"cols={sum(1 << c for c in col_splits)}")
+            u_n = m_total * k_total
+            seed = 5000 + bk
+            u = gen_pinned(u_n, seed) if blocked else gen_device(u_n, seed)
+            total_fl = 0.0
+            total_s = 0.0
+            dev_bytes = u_n * 8 if not blocked else 0
+            h2d = 0.0
+            ws_max = 0
+            worst = 0.0
+            for ci, bn_bits in enumerate(col_splits):
+                du, gu, dv, gv, ax_u, ax_v = shapes(rows_bits, bn_bits, bk_bits, blocked)
+                n_total = 1 << (bn_bits + nb_inner)
+                v_n = n_total * k_total
+                v = gen_pinned(v_n, seed * 10 + ci) if blocked else gen_device(v_n, seed * 10 + ci)
+                c = torch.empty(m_total * n_total, dtype=torch.complex64, device=dev)
+                if blocked:
+                    _, _, ws, fl, hb = ctx.plan_streamed(du, gu, dv, gv, ax_u, ax_v, "fp32_4m")
+                    h2d += hb
+                else:
+                    _, _, ws, fl = ctx.plan_block_tensordot(du, gu, dv, gv, ax_u, ax_v, "fp32_4m")
+                    dev_bytes += v_n * 8
+                wsb = torch.empty(max(ws, 1), dtype=torch.uint8, device=dev)
+                ws_max = max(ws_max, ws)
+                dev_bytes += m_total * n_total * 8
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                if blocked:
+                    ctx.block_tensordot_streamed(u, du, gu, v, dv, gv, ax_u, ax_v, "fp32_4m",
+                                                 out=c, workspace=wsb)
+                else:
+                    ctx.block_tensordot(u, du, gu, v, dv, gv, ax_u, ax_v, "fp32_4m", out=c,
+                                        workspace=wsb)
+                e1.record()
+                torch.cuda.synchronize()
+                sec = e0.elapsed_time(e1) / 1e3
+                total_s += sec
+                total_fl += fl
+                log(f"  columns 2^{bn_bits}: {sec:.2f} s, {fl / sec / 1e12:.1f} TFLOP/s")
+
+                def u_row(i, u=u, blocked=blocked, k_total=k_total):
+                    if not blocked:
+                        return u[i * k_total:(i + 1) * k_total].cpu().numpy()
+                    # Block-major: row i of block row bi spans B_k blocks.
+                    bi, ii = i >> mb_bits, i & ((1 << mb_bits) - 1)
+                    kb = 1 << kb_inner
+                    blk = (1 << mb_bits) * kb
+                    parts = [u[((bi << bk_bits) + q) * blk + ii * kb:
+                               ((bi << bk_bits) + q) * blk + (ii + 1) * kb]
+                             for q in range(1 << bk_bits)]
+                    return torch.cat(parts).cpu().numpy()
+
+                def v_row(j, v=v, blocked=blocked, k_total=k_total):
+                    if not blocked:
+                        return v[j * k_total:(j + 1) * k_total].cpu().numpy()
+                    bj, jj = j >> nb_inner, j & ((1 << nb_inner) - 1)
+                    kb = 1 << kb_inner
+                    blk = (1 << nb_inner) * kb
+                    parts = [v[((bj << bk_bits) + q) * blk + jj * kb:
+                               ((bj << bk_bits) + q) * blk + (jj + 1) * kb]
+                             for q in range(1 << bk_bits)]
+                    return torch.cat(parts).cpu().numpy()
+
+                worst = max(worst, sample_check(c, u_row, v_row, m_total, n_total, k_total,
+                                                blocked, bn_bits))
+                del v, c, wsb
+                torch.cuda.empty_cache()
+            del u
+            torch.cuda.empty_cache()
+            if blocked and hasattr(torch._C, "_host_emptyCache"):
+                torch._C._host_emptyCache()  # return the pinned staging to the system
+            kb_ = 1 << kb_inner
+            m_b = n_b = 1 << mb_bits
+            line = {"mode": "weak_share", "placement": placement, "B_k": bk,
+                    "B_m": 1 << rows_bits, "B_n": sum(1 << c for c in col_splits),
+                    "block": [m_b, n_b, kb_], "dtype": "c64 (fp32_4m)",
+                    "seconds": round(total_s, 3), "tflops": round(total_fl / total_s / 1e12, 2),
+                    "useful_flops": total_fl,
+                    "device_bytes": dev_bytes + ws_max,
+                    "eq1_task_elems": bk * kb_ * (m_b + n_b) + m_b * n_b,
+                    "eq2_task_elems": kb_ * (m_b + n_b) + m_b * n_b,
+                    "h2d_bytes": h2d, "h2d_GBps": round(h2d / total_s / 1e9, 2) if h2d else None,
+                    "max_rel_err_sampled": worst}
+            print(json.dumps(line), flush=True)
+            results.append(line)
+    ctx.close()
+    return results
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +326,18 @@ def main() -> int:
                     help="Poisson arrival rate as a fraction of the saturated throughput")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 1 GiB copy kernel first (HBM counter calibration)")
+    ap.add_argument("--weak", action="store_true",
+                    help="run only the weak-scaling share (one JSON line per run) and exit")
+    ap.add_argument("--weak-bk", type=lambda x: [int(v) for v in x.split(",") if v],
+                    default=[2, 4, 8], help="B_k values run with both operands in HBM")
+    ap.add_argument("--stream-bk", type=lambda x: [int(v) for v in x.split(",") if v],
+                    default=[2], help="B_k values streamed from host memory (8 x 6 blocks)")
+    ap.add_argument("--stream-sub-bk", type=lambda x: [int(v) for v in x.split(",") if v],
+                    default=[16], help="B_k values run on a 1 x 2 block sub-grid, streamed "
+                                       "and in HBM")
+    ap.add_argument("--weak-block-bits", type=lambda x: [int(v) for v in x.split(",")],
+                    default=[14, 14, 13], help="log2 of m_b, n_b, k_b (a smaller block for "
+                                               "quick checks)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -171,6 +354,9 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 1
+    if args.weak:
+        run_weak_share(args, torch, rn, log)
+        return 0
     ctx = rn.Context(0)
     dev = "cuda:0"
 
@@ -279,7 +465,8 @@ def main() -> int:
     if args.amp_requests > 0:
         w = configs.config2()
         lat = {}
-        for mode in ("fp64", "fp32_4m"):
+        for mode, slice_sum in (("fp64", 0), ("fp32_4m", 0), ("fp64", 1), ("fp32_4m", 1)):
+            ctx.set_option("slice_sum", slice_sum)
             dt = torch.complex128 if mode == "fp64" else torch.complex64
             ts = [torch.from_numpy(np.ascontiguousarray(t.reshape(-1))).to(dt).to(dev)
                   for t in w.network.tensors]
@@ -304,14 +491,62 @@ def main() -> int:
                 side_stream.synchronize()
                 xs.append(1e3 * (time.perf_counter() - t))
             a_ = ampt.cpu().numpy()
-            lat[mode] = {"p50_ms": percentile(xs, 50), "p99_ms": percentile(xs, 99),
-                         "amplitudes_per_s": 1e3 / float(np.mean(xs)),
-                         "amplitude": [float(a_[0]), float(a_[1])],
-                         "flops_per_amplitude": fl}
+            key = mode if not slice_sum else mode + "_slice_sum"
+            lat[key] = {"p50_ms": percentile(xs, 50), "p99_ms": percentile(xs, 99),
+                        "amplitudes_per_s": 1e3 / float(np.mean(xs)),
+                        "amplitude": [float(a_[0]), float(a_[1])],
+                        "flops_per_amplitude": fl}
+        ctx.set_option("slice_sum", 0)
+        from workloads import paths as _paths
+        _, unsliced, _ = _paths.path_stats(w.network.labels, w.path)
         amp = {"workload": "one amplitude of a 20-qubit random circuit (4x5 grid, 12 cycles), "
                            "greedy path, 4 sliced bonds = 16 slices batched, FP64 slice sum; "
-                           "one request at a time", **lat}
+                           "one request at a time.  *_slice_sum: each sliced bond summed in "
+                           "the step that contracts it (slices as blocks)", **lat,
+               "flops": {"independent_slices": w.meta["flops_per_slice"] * (1 << len(w.sliced)),
+                         "batched_broadcast": lat["fp64"]["flops_per_amplitude"],
+                         "slice_sum": lat["fp64_slice_sum"]["flops_per_amplitude"],
+                         "unsliced_same_path": unsliced}}
         log(f"amplitude latency: {amp}")
+
+        # Slices viewed as blocks on a circuit where slicing matters more:
+        # 6x6 grid, 10 cycles, sliced until the largest intermediate has rank
+        # <= 20 (6 bonds).  Independent slices redo every step per slice;
+        # batching broadcasts what does not depend on a slice; slice-sum also
+        # sums each sliced bond where it is contracted.
+        w6 = configs.circuit_workload(6, 6, 10, 777, max_rank=20, restarts=2)
+        ts = [torch.from_numpy(np.ascontiguousarray(t.reshape(-1))).to(torch.complex64).to(dev)
+              for t in w6.network.tensors]
+        sab = {"workload": "one amplitude, 36-qubit random circuit (6x6 grid, 10 cycles), "
+                           f"{len(w6.sliced)} sliced bonds, FP32-4M",
+               "flops": {"independent_slices": w6.meta["flops_per_slice"] << len(w6.sliced)}}
+        vals = {}
+        for name, ss in (("batched_broadcast", 0), ("slice_sum", 1)):
+            ctx.set_option("slice_sum", ss)
+            ws_n, fl, _ = ctx.contract_network_plan(ts, w6.network.labels, w6.path, w6.sliced,
+                                                    "fp32_4m")
+            wsb = torch.empty(max(ws_n, 1), dtype=torch.uint8, device=dev)
+            ampt = torch.zeros(2, dtype=torch.float64, device=dev)
+            xs = []
+            for it in range(3 + 10):
+                t = time.perf_counter()
+                with torch.cuda.stream(side_stream):
+                    ctx.contract_network(ts, w6.network.labels, w6.path, w6.sliced, "fp32_4m",
+                                         amp=ampt, workspace=wsb)
+                side_stream.synchronize()
+                if it >= 3:
+                    xs.append(1e3 * (time.perf_counter() - t))
+            a_ = ampt.cpu().numpy()
+            vals[name] = complex(a_[0], a_[1])
+            sab["flops"][name] = fl
+            sab[name] = {"p50_ms": percentile(xs, 50), "workspace_bytes": ws_n}
+            del wsb
+        ctx.set_option("slice_sum", 0)
+        ref6 = vals["batched_broadcast"]
+        sab["rel_diff_slice_sum_vs_batched"] = abs(vals["slice_sum"] - ref6) / max(
+            abs(ref6), 2.0 ** (-w6.circuit.n / 2))
+        amp["slices_as_blocks"] = sab
+        log(f"slices as blocks: {sab}")
 
     # ------------------------------- uneven batch: 256 problems, one call
     batch = None
