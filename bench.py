@@ -641,7 +641,7 @@ def main() -> int:
                    "M": M, "N": N, "K": K, "useful_flops_per_step": flops},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
-                     "kernel": "FP32-4M complex GEMM (cgemm_f32_rp, default large tile)",
+                     "kernel": "FP32-4M complex GEMM (cgemm_f32_big<1,4,4,1,16>, default large tile)",
                      "kernel_ms": gemm_ms},
         "cpu_baseline": cpu,
         "modes": modes,

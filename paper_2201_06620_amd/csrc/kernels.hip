@@ -334,6 +334,11 @@ __device__ __forceinline__ int64_t map2(int64_t x, int sh, int64_t hi, int64_t l
   return (x >> sh) * hi + (x & ((int64_t(1) << sh) - 1)) * lo;
 }
 
+template <bool B>
+struct BoolTag {
+  static constexpr bool value = B;
+};
+
 // Output element (row, col, part) of tile results: either straight into C
 // through the two-level maps, or into the split-K partial buffer.
 template <typename R>
@@ -1491,6 +1496,221 @@ __device__ __forceinline__ void cgemm_f32_rp_body(const GemmParams& p, int tm, i
       }
 }
 
+// Large-tile FP32-4M: each wave owns TM x TN Re/Im tile pairs (up to 16
+// accumulators), LDS rows padded to a multiple of 16 bytes so a lane reads
+// four consecutive k of its row in one 128-bit LDS read, and staging writes
+// are 64-bit.  Rows [a_r | a_i] and [b_r | -b_i] as in the planar tile; the
+// padding of 4 floats puts 16 consecutive rows on distinct 16-byte bank
+// groups.
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f32_big_body(const GemmParams& p, int tm, int tn,
+                                                   int split, int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK % 4 == 0, "k in groups of four");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 32;  // complex columns
+  constexpr int LDR = 2 * BK + 4;   // floats per LDS row, 16-byte multiple
+  constexpr int AV = BM * BK / 2;   // float4 loads (two complex) per stage
+  constexpr int BV = BN * BK / 2;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  extern __shared__ float4 big_lds[];
+  float* As0 = reinterpret_cast<float*>(big_lds);
+  float* Bs0 = As0 + 2 * BM * LDR;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const float2* __restrict__ Ag =
+      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const float2* __restrict__ Bg =
+      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+
+  // Interior tiles (whole tile inside M x N, K chunk a multiple of BK) load
+  // without guards, so no load sits behind a divergent branch and the loads
+  // of the next stage stay in flight across the MFMA phase.
+  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
+  float4 ra[NA], rb[NB];
+  auto gload_fast = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+      ra[j] = *reinterpret_cast<const float4*>(Ag + (row0 + r) * p.lda + k0 + c);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+      rb[j] = *reinterpret_cast<const float4*>(Bg + (col0 + r) * p.ldb + k0 + c);
+    }
+  };
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = row0 + r, gk = k0 + c;
+        if (gr < p.M) {
+          const float2* src = Ag + gr * p.lda + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = col0 + r, gk = k0 + c;
+        if (gr < p.N) {
+          const float2* src = Bg + gr * p.ldb + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      rb[j] = v;
+    }
+  };
+  auto sstore = [&](int buf) {
+    float* As = As0 + buf * BM * LDR;
+    float* Bs = Bs0 + buf * BN * LDR;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (AV % 256 == 0 || idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        float* row = As + r * LDR;
+        row[c] = ra[j].x;
+        row[c + 1] = ra[j].z;
+        row[BK + c] = ra[j].y;
+        row[BK + c + 1] = ra[j].w;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (BV % 256 == 0 || idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        float* row = Bs + r * LDR;
+        row[c] = rb[j].x;
+        row[c + 1] = rb[j].z;
+        row[BK + c] = -rb[j].y;
+        row[BK + c + 1] = -rb[j].w;
+      }
+    }
+  };
+
+  v16f cr[TM][TN], ci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
+
+  const int kh = lane >> 5;
+  const int aoff = (wm * TM * 32 + (lane & 31)) * LDR + kh * BK;
+  const int boff_r = (wn * TN * 32 + (lane & 31)) * LDR + kh * BK;
+  const int boff_i = (wn * TN * 32 + (lane & 31)) * LDR + (1 - kh) * BK;
+  const uint32_t flip = kh ? 0u : 0x80000000u;  // Im row: (-(-b_i), b_r)
+
+  auto mainloop = [&](auto tag) {
+  constexpr bool FAST = decltype(tag)::value;
+  if (nk > 0) {
+    if constexpr (FAST) gload_fast(kbeg); else gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int buf = it & 1;
+    const float* As = As0 + buf * BM * LDR;
+    const float* Bs = Bs0 + buf * BN * LDR;
+    // Fast path: always prefetch (the last stage re-reads itself), so the
+    // loop body has no branch and the loads stay in flight over the MFMAs.
+    if constexpr (FAST) {
+      gload_fast(kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
+      // Keep the loads at the top of the stage: the scheduler would
+      // otherwise sink them next to their LDS stores, exposing their latency.
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (it + 1 < nk) {
+      gload(kbeg + int64_t(it + 1) * BK);
+    }
+#pragma unroll
+    for (int kq = 0; kq < BK; kq += 4) {
+      float4 a4[TM], r4[TN], i4[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        a4[i] = *reinterpret_cast<const float4*>(As + aoff + i * 32 * LDR + kq);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        r4[j] = *reinterpret_cast<const float4*>(Bs + boff_r + j * 32 * LDR + kq);
+        float4 t = *reinterpret_cast<const float4*>(Bs + boff_i + j * 32 * LDR + kq);
+        t.x = __uint_as_float(__float_as_uint(t.x) ^ flip);
+        t.y = __uint_as_float(__float_as_uint(t.y) ^ flip);
+        t.z = __uint_as_float(__float_as_uint(t.z) ^ flip);
+        t.w = __uint_as_float(__float_as_uint(t.w) ^ flip);
+        i4[j] = t;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            const float av = q == 0 ? a4[i].x : q == 1 ? a4[i].y : q == 2 ? a4[i].z : a4[i].w;
+            const float bv = q == 0 ? r4[j].x : q == 1 ? r4[j].y : q == 2 ? r4[j].z : r4[j].w;
+            const float cv = q == 0 ? i4[j].x : q == 1 ? i4[j].y : q == 2 ? i4[j].z : i4[j].w;
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, cv, ci[i][j], 0, 0, 0);
+          }
+    }
+    if (FAST || it + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  };
+  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
+        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
+        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
+        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
+      }
+}
+
+// Dynamic LDS bytes of the large FP32 tile.
+template <int WM, int WN, int TM, int TN, int BK>
+constexpr size_t big_lds_bytes() {
+  return size_t(2) * (WM * TM * 32 + WN * TN * 32) * (2 * BK + 4) * sizeof(float);
+}
+
 // FP64 counterpart: v_mfma_f64_16x16x4_f64, 16 complex columns per tile
 // pair, 2 complex k per instruction (real k = lane / 16: complex k lane / 32,
 // half (lane / 16) & 1).
@@ -1753,6 +1973,28 @@ RN_GEMM_ENTRY(cgemm_f32_ri)
 RN_GEMM_ENTRY(cgemm_bf16x3_ri)
 RN_GEMM_ENTRY(cgemm_f32_rp)
 RN_GEMM_ENTRY(cgemm_f64_rp)
+RN_GEMM_ENTRY(cgemm_f32_big)
+
+// The large FP32 tiles take more than 64 KiB of dynamic LDS; raise each
+// kernel's limit once per process.
+static void big_tiles_setup() {
+  static const bool once = [] {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&cgemm_f32_big<2, 2, 2, 2, 16>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)big_lds_bytes<2, 2, 2, 2, 16>());
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&cgemm_f32_big_grouped<2, 2, 2, 2, 16>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)big_lds_bytes<2, 2, 2, 2, 16>());
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&cgemm_f32_big<1, 4, 4, 1, 16>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)big_lds_bytes<1, 4, 4, 1, 16>());
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&cgemm_f32_big_grouped<1, 4, 4, 1, 16>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)big_lds_bytes<1, 4, 4, 1, 16>());
+    return true;
+  }();
+  (void)once;
+}
 
 template <int MODE>
 __global__ __launch_bounds__(256) void cgemm_small(GemmParams p) {
@@ -1801,7 +2043,9 @@ struct TileCfg {
 // Index 0 = small-problem kernel; the rest are MFMA tile shapes per mode.
 static const TileCfg kF32Tiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 32, 16},
                                     {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
-                                    {128, 128, 8}, {128, 64, 16}, {128, 128, 8}};
+                                    {128, 128, 8}, {128, 64, 16}, {128, 128, 8},
+                                    {128, 128, 16}, {128, 128, 16}, {128, 64, 16},
+                                    {128, 64, 8},   {128, 128, 8},  {128, 128, 16}};
 static const TileCfg kF64Tiles[] = {{1, 1, 1}, {128, 64, 8}, {64, 32, 8}, {128, 64, 8},
                                     {64, 64, 8}};
 static const TileCfg kBF16Tiles[] = {{1, 1, 1},     {128, 64, 16}, {64, 32, 16},
@@ -1818,12 +2062,12 @@ static const TileCfg& tile_of(rn_mode mode, int t) {
 
 // Default tile shape when the autotuner has no entry: the one-thread kernel
 // for tiny problems, otherwise the largest tile the output fills (the
-// Re/Im-split tiles -- planar LDS rows for FP32-4M and FP64 -- measured
-// fastest on large pairs).
+// Re/Im-split tiles -- planar LDS rows; for FP32-4M the 128-bit-read large
+// tiles -- measured fastest on large pairs).
 static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
   if (M * N * K <= (int64_t(1) << 15) || M < 16 || N < 8) return 0;
   if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) {
-    if (mode == RN_FP32_4M) return 7;
+    if (mode == RN_FP32_4M) return N >= 128 ? 14 : 11;
     if (mode == RN_BF16X3) return N >= 128 ? 6 : 5;
     if (mode == RN_FP64) return 3;
     return 1;
@@ -1947,8 +2191,23 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f32_ri<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
       else if (tile == 7)
         cgemm_f32_rp<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 8)
         cgemm_f32_rp<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
+      else if (tile == 9)
+        cgemm_f32_rp<1, 4, 4, 1, 16><<<grid, 256, 0, s>>>(p);
+      else if (tile == 10) {
+        big_tiles_setup();
+        cgemm_f32_big<2, 2, 2, 2, 16><<<grid, 256, big_lds_bytes<2, 2, 2, 2, 16>(), s>>>(p);
+      } else if (tile == 11) {
+        cgemm_f32_big<2, 2, 2, 1, 16><<<grid, 256, big_lds_bytes<2, 2, 2, 1, 16>(), s>>>(p);
+      } else if (tile == 12) {
+        cgemm_f32_big<2, 2, 2, 1, 8><<<grid, 256, big_lds_bytes<2, 2, 2, 1, 8>(), s>>>(p);
+      } else if (tile == 13) {
+        cgemm_f32_big<2, 2, 2, 2, 8><<<grid, 256, big_lds_bytes<2, 2, 2, 2, 8>(), s>>>(p);
+      } else {
+        big_tiles_setup();
+        cgemm_f32_big<1, 4, 4, 1, 16><<<grid, 256, big_lds_bytes<1, 4, 4, 1, 16>(), s>>>(p);
+      }
     }
   }
   hipError_t e = hipGetLastError();
@@ -2050,7 +2309,26 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
       else if (tile == 5) cgemm_f32_ri_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
       else if (tile == 6) cgemm_f32_ri_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
       else if (tile == 7) cgemm_f32_rp_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      else cgemm_f32_rp_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 8) cgemm_f32_rp_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 9) cgemm_f32_rp_grouped<1, 4, 4, 1, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 10) {
+        big_tiles_setup();
+        cgemm_f32_big_grouped<2, 2, 2, 2, 16>
+            <<<grid, 256, big_lds_bytes<2, 2, 2, 2, 16>(), s>>>(t);
+      } else if (tile == 11) {
+        cgemm_f32_big_grouped<2, 2, 2, 1, 16>
+            <<<grid, 256, big_lds_bytes<2, 2, 2, 1, 16>(), s>>>(t);
+      } else if (tile == 12) {
+        cgemm_f32_big_grouped<2, 2, 2, 1, 8>
+            <<<grid, 256, big_lds_bytes<2, 2, 2, 1, 8>(), s>>>(t);
+      } else if (tile == 13) {
+        cgemm_f32_big_grouped<2, 2, 2, 2, 8>
+            <<<grid, 256, big_lds_bytes<2, 2, 2, 2, 8>(), s>>>(t);
+      } else {
+        big_tiles_setup();
+        cgemm_f32_big_grouped<1, 4, 4, 1, 16>
+            <<<grid, 256, big_lds_bytes<1, 4, 4, 1, 16>(), s>>>(t);
+      }
       break;
   }
   return hipGetLastError();
