@@ -1200,7 +1200,29 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
   const int64_t kend = min(p.K, kbeg + p.kchunk);
   const int nk = (int)((kend - kbeg + BK - 1) / BK);
 
+  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
   uint4 rah[NA], ral[NA], rbh[NB], rbl[NB];
+  // Interior tiles: unguarded loads (see the FP32 large tile).
+  auto gload_fast = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (AV % 256 == 0 || idx < AV) {  // threads past the tile load nothing
+        int64_t o = (row0 + idx / (BK / 4)) * p.lda + k0 + (idx % (BK / 4)) * 4;
+        rah[j] = *reinterpret_cast<const uint4*>(Agh + o);
+        ral[j] = *reinterpret_cast<const uint4*>(Agl + o);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (BV % 256 == 0 || idx < BV) {
+        int64_t o = (col0 + idx / (BK / 4)) * p.ldb + k0 + (idx % (BK / 4)) * 4;
+        rbh[j] = *reinterpret_cast<const uint4*>(Bgh + o);
+        rbl[j] = *reinterpret_cast<const uint4*>(Bgl + o);
+      }
+    }
+  };
   auto ld4 = [&](const uint32_t* src, int64_t gk) -> uint4 {
     if (gk + 3 < kend) return *reinterpret_cast<const uint4*>(src);
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
@@ -1245,7 +1267,7 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       int idx = tid + 256 * j;
-      if (idx < AV) {
+      if (AV % 256 == 0 || idx < AV) {
         int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
         *reinterpret_cast<uint4*>(&Ah[buf][r * LDK + c]) = rah[j];
         *reinterpret_cast<uint4*>(&Al[buf][r * LDK + c]) = ral[j];
@@ -1254,7 +1276,7 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       int idx = tid + 256 * j;
-      if (idx < BV) {
+      if (BV % 256 == 0 || idx < BV) {
         int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
         *reinterpret_cast<uint4*>(&Bh[buf][r * LDK + c]) = rbh[j];
         *reinterpret_cast<uint4*>(&Bl[buf][r * LDK + c]) = rbl[j];
@@ -1278,14 +1300,21 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
   const int arow = wm * TM * 32 + (lane & 31);
   const int bcol = wn * TN * 32 + (lane & 31);
 
+  auto mainloop = [&](auto tag) {
+  constexpr bool FAST = decltype(tag)::value;
   if (nk > 0) {
-    gload(kbeg);
+    if constexpr (FAST) gload_fast(kbeg); else gload(kbeg);
     sstore(0);
   }
   __syncthreads();
   for (int it = 0; it < nk; ++it) {
     const int buf = it & 1;
-    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
+    if constexpr (FAST) {
+      gload_fast(kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (it + 1 < nk) {
+      gload(kbeg + int64_t(it + 1) * BK);
+    }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 8) {
       v8bf ah[TM], al[TM];
@@ -1315,9 +1344,11 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
         }
       }
     }
-    if (it + 1 < nk) sstore(buf ^ 1);
+    if (FAST || it + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
+  };
+  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
 
   const int khalf = lane >> 5;
 #pragma unroll
@@ -1541,14 +1572,18 @@ __device__ __forceinline__ void cgemm_f32_big_body(const GemmParams& p, int tm, 
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       int idx = tid + 256 * j;
-      int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-      ra[j] = *reinterpret_cast<const float4*>(Ag + (row0 + r) * p.lda + k0 + c);
+      if (AV % 256 == 0 || idx < AV) {  // threads past the tile load nothing
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        ra[j] = *reinterpret_cast<const float4*>(Ag + (row0 + r) * p.lda + k0 + c);
+      }
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       int idx = tid + 256 * j;
-      int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-      rb[j] = *reinterpret_cast<const float4*>(Bg + (col0 + r) * p.ldb + k0 + c);
+      if (BV % 256 == 0 || idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        rb[j] = *reinterpret_cast<const float4*>(Bg + (col0 + r) * p.ldb + k0 + c);
+      }
     }
   };
   auto gload = [&](int64_t k0) {
@@ -1849,6 +1884,189 @@ __device__ __forceinline__ void cgemm_f64_rp_body(const GemmParams& p, int tm, i
       }
 }
 
+// Large-tile FP64: v_mfma_f64_16x16x4f64 (two complex k per instruction:
+// lane / 32 picks the complex k, (lane / 16) & 1 the real or imaginary
+// half).  LDS rows hold [re of even k | re of odd k | im of even k | im of
+// odd k], so the values one lane needs for two consecutive instructions are
+// adjacent and come in one 128-bit read; rows padded to 16-byte multiples.
+// Interior tiles load without guards and pin the next stage's loads to the
+// top of the stage, as in the FP32 large tile.
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f64_big_body(const GemmParams& p, int tm, int tn,
+                                                   int split, int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK % 4 == 0, "two instructions per 128-bit read");
+  constexpr int BM = WM * TM * 16;
+  constexpr int BN = WN * TN * 16;  // complex columns
+  constexpr int LDR = 2 * BK + 2;   // doubles per LDS row, 16-byte multiple
+  constexpr int HB = BK / 2;
+  constexpr int AV = BM * BK;       // complex loads per stage
+  constexpr int BV = BN * BK;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  extern __shared__ double2 big64_lds[];
+  double* As0 = reinterpret_cast<double*>(big64_lds);
+  double* Bs0 = As0 + 2 * BM * LDR;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const double2* __restrict__ Ag =
+      reinterpret_cast<const double2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const double2* __restrict__ Bg =
+      reinterpret_cast<const double2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
+
+  double2 ra[NA], rb[NB];
+  auto gload_fast = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (AV % 256 == 0 || idx < AV)  // threads past the tile load nothing
+        ra[j] = Ag[(row0 + idx / BK) * p.lda + k0 + idx % BK];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (BV % 256 == 0 || idx < BV) rb[j] = Bg[(col0 + idx / BK) * p.ldb + k0 + idx % BK];
+    }
+  };
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      double2 v = make_double2(0.0, 0.0);
+      if (idx < AV) {
+        int64_t gr = row0 + idx / BK, gk = k0 + idx % BK;
+        if (gr < p.M && gk < kend) v = Ag[gr * p.lda + gk];
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      double2 v = make_double2(0.0, 0.0);
+      if (idx < BV) {
+        int64_t gr = col0 + idx / BK, gk = k0 + idx % BK;
+        if (gr < p.N && gk < kend) v = Bg[gr * p.ldb + gk];
+      }
+      rb[j] = v;
+    }
+  };
+  // Complex k = c goes to position (c & 1) * HB + c / 2 of each half.
+  auto sstore = [&](int buf) {
+    double* As = As0 + buf * BM * LDR;
+    double* Bs = Bs0 + buf * BN * LDR;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (AV % 256 == 0 || idx < AV) {
+        int r = idx / BK, c = idx % BK;
+        double* row = As + r * LDR + (c & 1) * HB + (c >> 1);
+        row[0] = ra[j].x;
+        row[BK] = ra[j].y;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (BV % 256 == 0 || idx < BV) {
+        int r = idx / BK, c = idx % BK;
+        double* row = Bs + r * LDR + (c & 1) * HB + (c >> 1);
+        row[0] = rb[j].x;
+        row[BK] = -rb[j].y;
+      }
+    }
+  };
+
+  v4d cr[TM][TN], ci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cr[i][j][e] = ci[i][j][e] = 0.0;
+
+  const int kc = lane >> 5;
+  const int half = (lane >> 4) & 1;
+  const int aoff = (wm * TM * 16 + (lane & 15)) * LDR + half * BK + kc * HB;
+  const int boff_r = (wn * TN * 16 + (lane & 15)) * LDR + half * BK + kc * HB;
+  const int boff_i = (wn * TN * 16 + (lane & 15)) * LDR + (1 - half) * BK + kc * HB;
+  const bool negi = (half == 0);
+
+  auto mainloop = [&](auto tag) {
+    constexpr bool FAST = decltype(tag)::value;
+    if (nk > 0) {
+      if constexpr (FAST) gload_fast(kbeg); else gload(kbeg);
+      sstore(0);
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+      const int buf = it & 1;
+      const double* As = As0 + buf * BM * LDR;
+      const double* Bs = Bs0 + buf * BN * LDR;
+      if constexpr (FAST) {
+        gload_fast(kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
+        __builtin_amdgcn_sched_barrier(0);
+      } else if (it + 1 < nk) {
+        gload(kbeg + int64_t(it + 1) * BK);
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < HB; s2 += 2) {
+        double2 a2[TM], r2[TN], i2[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          a2[i] = *reinterpret_cast<const double2*>(As + aoff + i * 16 * LDR + s2);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          r2[j] = *reinterpret_cast<const double2*>(Bs + boff_r + j * 16 * LDR + s2);
+          double2 t = *reinterpret_cast<const double2*>(Bs + boff_i + j * 16 * LDR + s2);
+          i2[j] = negi ? make_double2(-t.x, -t.y) : t;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              const double av = q == 0 ? a2[i].x : a2[i].y;
+              const double bv = q == 0 ? r2[j].x : r2[j].y;
+              const double cv = q == 0 ? i2[j].x : i2[j].y;
+              cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, cr[i][j], 0, 0, 0);
+              ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cv, ci[i][j], 0, 0, 0);
+            }
+      }
+      if (FAST || it + 1 < nk) sstore(buf ^ 1);
+      __syncthreads();
+    }
+  };
+  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
+
+  // 16x16 f64 accumulator layout: column lane % 16, rows 4*e + lane/16.
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t row = row0 + wm * TM * 16 + i * 16 + 4 * e + (lane >> 4);
+        int64_t col = col0 + wn * TN * 16 + j * 16 + (lane & 15);
+        store_out<double>(p, b, split, row, col, 0, cr[i][j][e]);
+        store_out<double>(p, b, split, row, col, 1, ci[i][j][e]);
+      }
+}
+
+template <int WM, int WN, int TM, int TN, int BK>
+constexpr size_t big64_lds_bytes() {
+  return size_t(2) * (WM * TM * 16 + WN * TN * 16) * (2 * BK + 2) * sizeof(double);
+}
+
 // ---------------------------------------------------------------------------
 // Small problems: one thread per complex output, sequential K loop (FP64,
 // FP32 or split BF16 products).  Used when a tile would be mostly empty.
@@ -1965,6 +2183,22 @@ __device__ __forceinline__ int group_find(const GroupTable& g, int bid) {
     NAME##_body<WM, WN, TM, TN, BK>(p, local / p.tiles_n, local % p.tiles_n, 0, 0);     \
   }
 
+// Entry points whose register use is capped for WAVES waves per SIMD.
+#define RN_GEMM_ENTRY_OCC(NAME, WAVES)                                                              \
+  template <int WM, int WN, int TM, int TN, int BK>                                     \
+  __global__ __launch_bounds__(256, WAVES) void NAME(GemmParams p) {                           \
+    int tm, tn;                                                                         \
+    tile_coords(p.tiles_m, p.tiles_n, tm, tn);                                          \
+    NAME##_body<WM, WN, TM, TN, BK>(p, tm, tn, blockIdx.y, blockIdx.z);                 \
+  }                                                                                     \
+  template <int WM, int WN, int TM, int TN, int BK>                                     \
+  __global__ __launch_bounds__(256, WAVES) void NAME##_grouped(GroupTable g) {                 \
+    const int i = group_find(g, blockIdx.x);                                            \
+    const GemmParams& p = g.probs[i];                                                   \
+    const int local = blockIdx.x - g.prefix[i];                                         \
+    NAME##_body<WM, WN, TM, TN, BK>(p, local / p.tiles_n, local % p.tiles_n, 0, 0);     \
+  }
+
 RN_GEMM_ENTRY(cgemm_f32_4m)
 RN_GEMM_ENTRY(cgemm_f32_3m)
 RN_GEMM_ENTRY(cgemm_f64_4m)
@@ -1974,6 +2208,7 @@ RN_GEMM_ENTRY(cgemm_bf16x3_ri)
 RN_GEMM_ENTRY(cgemm_f32_rp)
 RN_GEMM_ENTRY(cgemm_f64_rp)
 RN_GEMM_ENTRY(cgemm_f32_big)
+RN_GEMM_ENTRY_OCC(cgemm_f64_big, 2)
 
 // The large FP32 tiles take more than 64 KiB of dynamic LDS; raise each
 // kernel's limit once per process.
@@ -2046,11 +2281,11 @@ static const TileCfg kF32Tiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 32, 16},
                                     {128, 128, 8}, {128, 64, 16}, {128, 128, 8},
                                     {128, 128, 16}, {128, 128, 16}, {128, 64, 16},
                                     {128, 64, 8},   {128, 128, 8},  {128, 128, 16}};
-static const TileCfg kF64Tiles[] = {{1, 1, 1}, {128, 64, 8}, {64, 32, 8}, {128, 64, 8},
-                                    {64, 64, 8}};
+static const TileCfg kF64Tiles[] = {{1, 1, 1},   {128, 64, 8}, {64, 32, 8}, {128, 64, 8},
+                                    {64, 64, 8},  {128, 64, 8}, {64, 128, 8}, {64, 64, 8}};
 static const TileCfg kBF16Tiles[] = {{1, 1, 1},     {128, 64, 16}, {64, 32, 16},
                                      {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
-                                     {128, 128, 8}, {256, 64, 8}};
+                                     {128, 128, 8}, {256, 64, 8},  {128, 128, 16}};
 static const TileCfg k3MTiles[] = {{1, 1, 1}, {128, 64, 16}, {64, 64, 16}};
 
 static const TileCfg& tile_of(rn_mode mode, int t) {
@@ -2068,7 +2303,7 @@ static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
   if (M * N * K <= (int64_t(1) << 15) || M < 16 || N < 8) return 0;
   if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) {
     if (mode == RN_FP32_4M) return N >= 128 ? 14 : 11;
-    if (mode == RN_BF16X3) return N >= 128 ? 6 : 5;
+    if (mode == RN_BF16X3) return N >= 128 ? 8 : 5;
     if (mode == RN_FP64) return 3;
     return 1;
   }
@@ -2154,8 +2389,14 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f64_4m<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
       else if (tile == 3)
         cgemm_f64_rp<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 4)
         cgemm_f64_rp<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
+      else if (tile == 5)
+        cgemm_f64_big<2, 2, 4, 2, 8><<<grid, 256, big64_lds_bytes<2, 2, 4, 2, 8>(), s>>>(p);
+      else if (tile == 6)
+        cgemm_f64_big<2, 2, 2, 4, 8><<<grid, 256, big64_lds_bytes<2, 2, 2, 4, 8>(), s>>>(p);
+      else
+        cgemm_f64_big<2, 2, 2, 2, 8><<<grid, 256, big64_lds_bytes<2, 2, 2, 2, 8>(), s>>>(p);
     } else if (g.mode == RN_FP32_3M) {
       if (tile == 1)
         cgemm_f32_3m<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
@@ -2174,8 +2415,10 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_bf16x3_ri<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
       else if (tile == 6)
         cgemm_bf16x3_ri<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 7)
         cgemm_bf16x3_ri<2, 2, 4, 1, 8><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_bf16x3_ri<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
     } else {
       if (tile == 1)
         cgemm_f32_4m<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
@@ -2283,7 +2526,16 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
       else if (tile == 1) cgemm_f64_4m_grouped<2, 2, 4, 4, 8><<<grid, 256, 0, s>>>(t);
       else if (tile == 2) cgemm_f64_4m_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
       else if (tile == 3) cgemm_f64_rp_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
-      else cgemm_f64_rp_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 4) cgemm_f64_rp_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 5)
+        cgemm_f64_big_grouped<2, 2, 4, 2, 8>
+            <<<grid, 256, big64_lds_bytes<2, 2, 4, 2, 8>(), s>>>(t);
+      else if (tile == 6)
+        cgemm_f64_big_grouped<2, 2, 2, 4, 8>
+            <<<grid, 256, big64_lds_bytes<2, 2, 2, 4, 8>(), s>>>(t);
+      else
+        cgemm_f64_big_grouped<2, 2, 2, 2, 8>
+            <<<grid, 256, big64_lds_bytes<2, 2, 2, 2, 8>(), s>>>(t);
       break;
     case RN_FP32_3M:
       if (tile == 0) cgemm_small_grouped<RN_FP32_3M><<<grid, 256, 0, s>>>(t);
@@ -2298,7 +2550,8 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
       else if (tile == 4) cgemm_bf16x3_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
       else if (tile == 5) cgemm_bf16x3_ri_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
       else if (tile == 6) cgemm_bf16x3_ri_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
-      else cgemm_bf16x3_ri_grouped<2, 2, 4, 1, 8><<<grid, 256, 0, s>>>(t);
+      else if (tile == 7) cgemm_bf16x3_ri_grouped<2, 2, 4, 1, 8><<<grid, 256, 0, s>>>(t);
+      else cgemm_bf16x3_ri_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
       break;
     default:
       if (tile == 0) cgemm_small_grouped<RN_FP32_4M><<<grid, 256, 0, s>>>(t);

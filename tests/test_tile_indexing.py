@@ -1,0 +1,110 @@
+"""Index bounds of the large GEMM tiles, checked on the CPU.
+
+For every tile shape instantiated in kernels.hip, the unguarded loads of
+interior tiles, the LDS staging stores and the per-lane LDS fragment reads
+are enumerated for all 256 threads (the same index arithmetic as the
+kernels) and must stay inside the tile, its K chunk and its LDS arrays.  A
+load by a thread past the tile would read rows beyond the matrix for the
+last tile row or column, so the fast-path loads carry the same
+`V % 256 == 0 || idx < V` guard that is modelled here.
+"""
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = open(os.path.join(ROOT, "paper_2201_06620_amd", "csrc", "kernels.hip")).read()
+
+
+def instances(name):
+    pat = name + r"(?:_grouped)?\s*<(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+)>"
+    return sorted(set(tuple(map(int, m)) for m in re.findall(pat, SRC)))
+
+
+def thread_loads(rows, bk, per_load):
+    """(row, first k) of each load a thread issues for one stage of a tile
+    with `rows` rows and `bk` complex k, `per_load` complex per load."""
+    v = rows * bk // per_load
+    for j in range((v + 255) // 256):
+        for tid in range(256):
+            idx = tid + 256 * j
+            if v % 256 == 0 or idx < v:
+                yield idx // (bk // per_load), (idx % (bk // per_load)) * per_load
+
+
+def test_fp32_large_tiles():
+    shapes = instances("cgemm_f32_big")
+    assert shapes
+    for wm_, wn_, tm, tn, bk in shapes:
+        bm, bn, ldr = wm_ * tm * 32, wn_ * tn * 32, 2 * bk + 4
+        for rows in (bm, bn):
+            for r, c in thread_loads(rows, bk, 2):
+                assert r < rows and c + 1 < bk
+                assert r * ldr + bk + c + 1 < rows * ldr  # planar staging store
+        for lane in range(64):
+            kh = lane >> 5
+            for w in range(4):
+                wm, wn = w // wn_, w % wn_
+                for kq in range(0, bk, 4):
+                    for i in range(tm):
+                        o = (wm * tm * 32 + lane % 32 + i * 32) * ldr + kh * bk + kq
+                        assert o % 4 == 0 and o + 3 < bm * ldr
+                    for j in range(tn):
+                        for half in (kh, 1 - kh):
+                            o = (wn * tn * 32 + lane % 32 + j * 32) * ldr + half * bk + kq
+                            assert o % 4 == 0 and o + 3 < bn * ldr
+
+
+def test_fp64_large_tiles():
+    shapes = instances("cgemm_f64_big")
+    assert shapes
+    for wm_, wn_, tm, tn, bk in shapes:
+        bm, bn, ldr, hb = wm_ * tm * 16, wn_ * tn * 16, 2 * bk + 2, bk // 2
+        for rows in (bm, bn):
+            for r, c in thread_loads(rows, bk, 1):
+                assert r < rows and c < bk
+                assert r * ldr + (c & 1) * hb + (c >> 1) + bk < rows * ldr
+        for lane in range(64):
+            kc, half = lane >> 5, (lane >> 4) & 1
+            for w in range(4):
+                wm, wn = w // wn_, w % wn_
+                for s2 in range(0, hb, 2):
+                    for i in range(tm):
+                        o = (wm * tm * 16 + lane % 16 + i * 16) * ldr + half * bk + kc * hb + s2
+                        assert o % 2 == 0 and o + 1 < bm * ldr
+                    for j in range(tn):
+                        for h in (half, 1 - half):
+                            o = (wn * tn * 16 + lane % 16 + j * 16) * ldr + h * bk + kc * hb + s2
+                            assert o % 2 == 0 and o + 1 < bn * ldr
+
+
+def test_bf16x3_tiles():
+    shapes = instances("cgemm_bf16x3_ri")
+    assert shapes
+    for wm_, wn_, tm, tn, bk in shapes:
+        bm, bn, ldk = wm_ * tm * 32, wn_ * tn * 32, bk + 4
+        for rows in (bm, bn):
+            for r, c in thread_loads(rows, bk, 4):
+                assert r < rows and c + 3 < bk
+                assert r * ldk + c + 3 < rows * ldk
+        for lane in range(64):
+            kq = (lane >> 5) * 4
+            for w in range(4):
+                wm, wn = w // wn_, w % wn_
+                for kk in range(0, bk, 8):
+                    for i in range(tm):
+                        o = (wm * tm * 32 + lane % 32 + i * 32) * ldk + kk + kq
+                        assert o % 4 == 0 and o + 3 < bm * ldk
+                    for j in range(tn):
+                        o = (wn * tn * 32 + lane % 32 + j * 32) * ldk + kk + kq
+                        assert o % 4 == 0 and o + 3 < bn * ldk
+
+
+def test_guard_matters():
+    # Without the guard, the 256 x 64 split-BF16 tile (B stage of 128 loads
+    # of four complex) would send threads 128..255 to B rows 64..127.
+    rows, bk, per = 64, 8, 4
+    v = rows * bk // per
+    assert v % 256 != 0
+    unguarded = [(tid // (bk // per)) for tid in range(256)]
+    assert max(unguarded) >= rows
+    assert max(r for r, _ in thread_loads(rows, bk, per)) < rows
