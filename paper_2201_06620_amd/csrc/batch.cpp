@@ -156,7 +156,7 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
     g.ccol = P.ccol;
     g.splitk = 1;
     int t = tuned_tile(h, P.mode, P.mbits, P.nbits, P.kbits);
-    g.tile = t >= 0 ? t : gemm_default_tile(P.mode, P.M, P.N, P.K);
+    g.tile = gemm_tile_valid(P.mode, t, P.M, P.N) ? t : gemm_default_tile(P.mode, P.M, P.N, P.K);
   }
   L->table.clear();
   std::vector<char> part;
@@ -438,7 +438,8 @@ rn_status rn_autotune_batch(rn_handle h, int32_t n, const rn_tensor* A, const rn
     std::vector<float> times;
     for (int t = 0; t < gemm_tile_count(P.mode) && st == RN_OK; ++t) {
       // The one-thread-per-output kernel only competes on small problems.
-      if (t == 0 && double(P.M) * double(P.N) * double(P.K) > double(int64_t(1) << 26)) {
+      if ((t == 0 && double(P.M) * double(P.N) * double(P.K) > double(int64_t(1) << 26)) ||
+          !gemm_tile_valid(P.mode, t, P.M, P.N)) {
         times.push_back(-1.f);
         continue;
       }

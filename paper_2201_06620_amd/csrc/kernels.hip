@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -148,16 +150,21 @@ __global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
 }
 
 // Many permutations in one launch: workgroup w moves one tile of job i,
-// prefix[i] <= w < prefix[i+1].
+// prefix[i] <= w < prefix[i+1].  The job's parameters are copied into LDS
+// first: the tile code reads them many times, and from the table in global
+// memory each read would be a dependent scalar load.
 struct PermTable {
   const PermParams* jobs;
   const int32_t* prefix;
   int n;
 };
+static_assert(sizeof(PermParams) % 4 == 0 && sizeof(PermParams) <= 4 * 256,
+              "parameters copied by one word per thread");
 
 template <typename T, int KIND, int E>
 __global__ __launch_bounds__(256) void permute_grouped(PermTable g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ PermParams sp;
   T* tile = reinterpret_cast<T*>(smem_raw);
   int lo = 0, hi = g.n - 1;
   const int bid = blockIdx.x;
@@ -166,11 +173,14 @@ __global__ __launch_bounds__(256) void permute_grouped(PermTable g) {
     if (g.prefix[mid] <= bid) lo = mid;
     else hi = mid - 1;
   }
-  const PermParams& p = g.jobs[lo];
+  if (threadIdx.x < sizeof(PermParams) / 4)
+    reinterpret_cast<uint32_t*>(&sp)[threadIdx.x] =
+        reinterpret_cast<const uint32_t*>(&g.jobs[lo])[threadIdx.x];
+  __syncthreads();
   int64_t in_lo, out_lo;
   int lds_lo;
-  perm_lo(p, threadIdx.x, in_lo, out_lo, lds_lo);
-  permute_tile<T, KIND, E, true>(p, bid - g.prefix[lo], tile, in_lo, out_lo, lds_lo);
+  perm_lo(sp, threadIdx.x, in_lo, out_lo, lds_lo);
+  permute_tile<T, KIND, E, true>(sp, bid - g.prefix[lo], tile, in_lo, out_lo, lds_lo);
 }
 
 template <typename T, int KIND>
@@ -293,12 +303,13 @@ hipError_t launch_permute_grouped(const GroupedLaunch& G, const void* table_dev,
   t.jobs = reinterpret_cast<const PermParams*>(static_cast<const char*>(table_dev) + G.params_off);
   t.prefix = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.prefix_off);
   t.n = G.n;
+  const unsigned grid = (unsigned)G.blocks;
   if (G.kind == 1)
-    permute_grouped<float2, 1, 16><<<G.blocks, 256, G.lds, s>>>(t);
+    permute_grouped<float2, 1, 16><<<grid, 256, G.lds, s>>>(t);
   else if (G.es == 16)
-    permute_grouped<double2, 0, 4><<<G.blocks, 256, G.lds, s>>>(t);
+    permute_grouped<double2, 0, 4><<<grid, 256, G.lds, s>>>(t);
   else
-    permute_grouped<float2, 0, 16><<<G.blocks, 256, G.lds, s>>>(t);
+    permute_grouped<float2, 0, 16><<<grid, 256, G.lds, s>>>(t);
   return hipGetLastError();
 }
 
@@ -2147,6 +2158,169 @@ __device__ __forceinline__ void cgemm_small_body(const GemmParams& p, int64_t bl
 }
 
 // ---------------------------------------------------------------------------
+// Skinny problems (at most 8 output rows after orienting, see
+// skinny_orient): memory-bound, so the GEMM streams each B row once.  A
+// workgroup owns 16 output columns (4 per wave); the A rows of the current
+// K chunk sit in LDS; each wave walks its columns with lanes striding over
+// k (coalesced B reads) and keeps per-(column, row) partial sums that are
+// combined across the wave by a fixed xor-shuffle tree at the end.
+// ---------------------------------------------------------------------------
+constexpr int kSkinnyRows = 8;
+constexpr int kSkinnyCols = 16;
+constexpr int kSkinnyKC = 256;
+
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int MODE>
+__device__ __forceinline__ void cgemm_skinny_body(const GemmParams& p, int tn, int split, int b) {
+  using R = typename std::conditional<MODE == RN_FP64, double, float>::type;
+  constexpr int CPW = kSkinnyCols / 4;
+  constexpr int NT = (MODE == RN_FP32_3M) ? 3 : 2;  // partial sums per (column, row)
+  // A chunk in LDS: complex elements (FP64/FP32) or hi and lo words (BF16x3).
+  constexpr int EB = (MODE == RN_FP64) ? 16 : 8;
+  __shared__ __align__(16) unsigned char a_lds[kSkinnyRows * kSkinnyKC * EB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int64_t ao = batch_off(p.a_bs, p.nbb, b), bo = batch_off(p.b_bs, p.nbb, b);
+  const int M = (int)p.M;
+  const int64_t n0 = int64_t(tn) * kSkinnyCols + wave * CPW;
+  R acc[CPW][kSkinnyRows][NT];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c)
+#pragma unroll
+    for (int m = 0; m < kSkinnyRows; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[c][m][t] = R(0);
+
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kSkinnyKC) {
+    const int kc = (int)min(int64_t(kSkinnyKC), kend - k0);
+    __syncthreads();
+    for (int idx = tid; idx < M * kSkinnyKC; idx += 256) {
+      const int m = idx / kSkinnyKC, kk = idx % kSkinnyKC;
+      if constexpr (MODE == RN_FP64) {
+        double2 v = make_double2(0.0, 0.0);
+        if (kk < kc) v = reinterpret_cast<const double2*>(p.A)[ao + m * p.lda + k0 + kk];
+        reinterpret_cast<double2*>(a_lds)[m * kSkinnyKC + kk] = v;
+      } else if constexpr (MODE == RN_BF16X3) {
+        uint2 v = make_uint2(0u, 0u);
+        if (kk < kc) {
+          const int64_t o = ao + m * p.lda + k0 + kk;
+          v.x = reinterpret_cast<const uint32_t*>(p.A)[o];
+          v.y = reinterpret_cast<const uint32_t*>(p.A2)[o];
+        }
+        reinterpret_cast<uint2*>(a_lds)[m * kSkinnyKC + kk] = v;
+      } else {
+        float2 v = make_float2(0.f, 0.f);
+        if (kk < kc) v = reinterpret_cast<const float2*>(p.A)[ao + m * p.lda + k0 + kk];
+        reinterpret_cast<float2*>(a_lds)[m * kSkinnyKC + kk] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int64_t n = n0 + c;
+      if (n >= p.N) continue;
+      for (int kk = lane; kk < kc; kk += 64) {
+        const int64_t bi = bo + n * p.ldb + k0 + kk;
+        if constexpr (MODE == RN_FP64) {
+          const double2 bb = reinterpret_cast<const double2*>(p.B)[bi];
+#pragma unroll
+          for (int m = 0; m < kSkinnyRows; ++m) {
+            if (m >= M) break;
+            const double2 a = reinterpret_cast<const double2*>(a_lds)[m * kSkinnyKC + kk];
+            acc[c][m][0] = fma(a.x, bb.x, acc[c][m][0]);
+            acc[c][m][0] = fma(-a.y, bb.y, acc[c][m][0]);
+            acc[c][m][1] = fma(a.x, bb.y, acc[c][m][1]);
+            acc[c][m][1] = fma(a.y, bb.x, acc[c][m][1]);
+          }
+        } else if constexpr (MODE == RN_BF16X3) {
+          const uint32_t bh = reinterpret_cast<const uint32_t*>(p.B)[bi];
+          const uint32_t bl = reinterpret_cast<const uint32_t*>(p.B2)[bi];
+          const float bhr = bf_lo(bh), bhi = bf_hi(bh), blr = bf_lo(bl), bli = bf_hi(bl);
+#pragma unroll
+          for (int m = 0; m < kSkinnyRows; ++m) {
+            if (m >= M) break;
+            const uint2 a = reinterpret_cast<const uint2*>(a_lds)[m * kSkinnyKC + kk];
+            const float ahr = bf_lo(a.x), ahi = bf_hi(a.x), alr = bf_lo(a.y), ali = bf_hi(a.y);
+            float re = acc[c][m][0], im = acc[c][m][1];
+            re = fmaf(alr, bhr, re); re = fmaf(-ali, bhi, re);
+            im = fmaf(alr, bhi, im); im = fmaf(ali, bhr, im);
+            re = fmaf(ahr, blr, re); re = fmaf(-ahi, bli, re);
+            im = fmaf(ahr, bli, im); im = fmaf(ahi, blr, im);
+            re = fmaf(ahr, bhr, re); re = fmaf(-ahi, bhi, re);
+            im = fmaf(ahr, bhi, im); im = fmaf(ahi, bhr, im);
+            acc[c][m][0] = re;
+            acc[c][m][1] = im;
+          }
+        } else {
+          const float2 bb = reinterpret_cast<const float2*>(p.B)[bi];
+#pragma unroll
+          for (int m = 0; m < kSkinnyRows; ++m) {
+            if (m >= M) break;
+            const float2 a = reinterpret_cast<const float2*>(a_lds)[m * kSkinnyKC + kk];
+            if constexpr (MODE == RN_FP32_3M) {
+              acc[c][m][0] = fmaf(a.x, bb.x, acc[c][m][0]);
+              acc[c][m][1] = fmaf(a.y, bb.y, acc[c][m][1]);
+              acc[c][m][2] = fmaf(a.x + a.y, bb.x + bb.y, acc[c][m][2]);
+            } else {
+              acc[c][m][0] = fmaf(a.x, bb.x, acc[c][m][0]);
+              acc[c][m][0] = fmaf(-a.y, bb.y, acc[c][m][0]);
+              acc[c][m][1] = fmaf(a.x, bb.y, acc[c][m][1]);
+              acc[c][m][1] = fmaf(a.y, bb.x, acc[c][m][1]);
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int64_t n = n0 + c;
+#pragma unroll
+    for (int m = 0; m < kSkinnyRows; ++m) {
+      if (m >= M) break;
+      R t[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) t[q] = wave_sum(acc[c][m][q]);
+      if (lane == 0 && n < p.N) {
+        R re = t[0], im = t[1];
+        if constexpr (MODE == RN_FP32_3M) {
+          re = t[0] - t[1];
+          im = (t[2] - t[0]) - t[1];
+        }
+        store_out<R>(p, b, split, m, n, 0, re);
+        store_out<R>(p, b, split, m, n, 1, im);
+      }
+    }
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void cgemm_skinny(GemmParams p) {
+  cgemm_skinny_body<MODE>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Orient a skinny problem so that its short side is M: C^T = B A^T runs
+// with the operands, strides and output maps exchanged.
+static void skinny_orient(GemmParams& p) {
+  if (p.M <= p.N) return;
+  std::swap(p.A, p.B);
+  std::swap(p.A2, p.B2);
+  std::swap(p.M, p.N);
+  std::swap(p.lda, p.ldb);
+  std::swap(p.crs, p.ccs);
+  std::swap(p.crh, p.cch);
+  std::swap(p.crl, p.ccl);
+  for (int i = 0; i < RN_MAX_SLICED; ++i) std::swap(p.a_bs[i], p.b_bs[i]);
+}
+
+// ---------------------------------------------------------------------------
 // Kernel entry points.  Single problem: the grid is (tiles, splits, slice
 // batch).  Grouped: many problems in one launch; workgroup w serves problem
 // i with prefix[i] <= w < prefix[i+1] (problems ordered by decreasing work,
@@ -2178,7 +2352,7 @@ __device__ __forceinline__ int group_find(const GroupTable& g, int bid) {
   template <int WM, int WN, int TM, int TN, int BK>                                     \
   __global__ __launch_bounds__(256) void NAME##_grouped(GroupTable g) {                 \
     const int i = group_find(g, blockIdx.x);                                            \
-    const GemmParams& p = g.probs[i];                                                   \
+    const GemmParams p = g.probs[i]; /* by value: uniform scalar loads, once */         \
     const int local = blockIdx.x - g.prefix[i];                                         \
     NAME##_body<WM, WN, TM, TN, BK>(p, local / p.tiles_n, local % p.tiles_n, 0, 0);     \
   }
@@ -2194,7 +2368,7 @@ __device__ __forceinline__ int group_find(const GroupTable& g, int bid) {
   template <int WM, int WN, int TM, int TN, int BK>                                     \
   __global__ __launch_bounds__(256, WAVES) void NAME##_grouped(GroupTable g) {                 \
     const int i = group_find(g, blockIdx.x);                                            \
-    const GemmParams& p = g.probs[i];                                                   \
+    const GemmParams p = g.probs[i]; /* by value: uniform scalar loads, once */         \
     const int local = blockIdx.x - g.prefix[i];                                         \
     NAME##_body<WM, WN, TM, TN, BK>(p, local / p.tiles_n, local % p.tiles_n, 0, 0);     \
   }
@@ -2239,7 +2413,15 @@ __global__ __launch_bounds__(256) void cgemm_small(GemmParams p) {
 template <int MODE>
 __global__ __launch_bounds__(256) void cgemm_small_grouped(GroupTable g) {
   const int i = group_find(g, blockIdx.x);
-  cgemm_small_body<MODE>(g.probs[i], blockIdx.x - g.prefix[i], 0, 0);
+  const GemmParams p = g.probs[i];
+  cgemm_small_body<MODE>(p, blockIdx.x - g.prefix[i], 0, 0);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void cgemm_skinny_grouped(GroupTable g) {
+  const int i = group_find(g, blockIdx.x);
+  const GemmParams p = g.probs[i];
+  cgemm_skinny_body<MODE>(p, blockIdx.x - g.prefix[i], 0, 0);
 }
 
 // Split-K reduction: C = sum over splits of the partials, in ascending split
@@ -2280,13 +2462,16 @@ static const TileCfg kF32Tiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 32, 16},
                                     {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
                                     {128, 128, 8}, {128, 64, 16}, {128, 128, 8},
                                     {128, 128, 16}, {128, 128, 16}, {128, 64, 16},
-                                    {128, 64, 8},   {128, 128, 8},  {128, 128, 16}};
+                                    {128, 64, 8},   {128, 128, 8},  {128, 128, 16},
+                                    {8, 16, 64}};
 static const TileCfg kF64Tiles[] = {{1, 1, 1},   {128, 64, 8}, {64, 32, 8}, {128, 64, 8},
-                                    {64, 64, 8},  {128, 64, 8}, {64, 128, 8}, {64, 64, 8}};
+                                    {64, 64, 8},  {128, 64, 8}, {64, 128, 8}, {64, 64, 8},
+                                    {8, 16, 64}};
 static const TileCfg kBF16Tiles[] = {{1, 1, 1},     {128, 64, 16}, {64, 32, 16},
                                      {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
-                                     {128, 128, 8}, {256, 64, 8},  {128, 128, 16}};
-static const TileCfg k3MTiles[] = {{1, 1, 1}, {128, 64, 16}, {64, 64, 16}};
+                                     {128, 128, 8}, {256, 64, 8},  {128, 128, 16},
+                                     {8, 16, 64}};
+static const TileCfg k3MTiles[] = {{1, 1, 1}, {128, 64, 16}, {64, 64, 16}, {8, 16, 64}};
 
 static const TileCfg& tile_of(rn_mode mode, int t) {
   if (mode == RN_FP64) return kF64Tiles[t];
@@ -2299,8 +2484,12 @@ static const TileCfg& tile_of(rn_mode mode, int t) {
 // for tiny problems, otherwise the largest tile the output fills (the
 // Re/Im-split tiles -- planar LDS rows; for FP32-4M the 128-bit-read large
 // tiles -- measured fastest on large pairs).
+static int tile_count_of(rn_mode mode);
+
 static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
-  if (M * N * K <= (int64_t(1) << 15) || M < 16 || N < 8) return 0;
+  if (M * N * K <= (int64_t(1) << 15)) return 0;
+  if (std::min(M, N) <= kSkinnyRows) return tile_count_of(mode) - 1;
+  if (M < 16 || N < 8) return 0;
   if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) {
     if (mode == RN_FP32_4M) return N >= 128 ? 14 : 11;
     if (mode == RN_BF16X3) return N >= 128 ? 8 : 5;
@@ -2314,6 +2503,8 @@ int choose_splitk(rn_mode mode, int64_t M, int64_t N, int64_t K, int64_t batch) 
   int t = choose_tile(mode, M, N, K);
   const TileCfg& c = tile_of(mode, t);
   int64_t tiles = ((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn) * batch;
+  if (t == tile_count_of(mode) - 1)  // skinny: one workgroup per 16 long-side entries
+    tiles = ((std::max(M, N) + kSkinnyCols - 1) / kSkinnyCols) * batch;
   int64_t minchunk = (t == 0) ? 64 : 4 * c.bk;
   int s = 1;
   while (s < 64 && tiles * s < 1024 && K / (2 * s) >= minchunk) s *= 2;
@@ -2349,11 +2540,21 @@ static void fill_params(const GemmLaunch& g, GemmParams& p) {
   p.kchunk = (g.K + g.splitk - 1) / g.splitk;
 }
 
-int gemm_tile_count(rn_mode mode) {
+static int tile_count_of(rn_mode mode) {
   if (mode == RN_FP64) return (int)(sizeof(kF64Tiles) / sizeof(kF64Tiles[0]));
   if (mode == RN_BF16X3) return (int)(sizeof(kBF16Tiles) / sizeof(kBF16Tiles[0]));
   if (mode == RN_FP32_3M) return (int)(sizeof(k3MTiles) / sizeof(k3MTiles[0]));
   return (int)(sizeof(kF32Tiles) / sizeof(kF32Tiles[0]));
+}
+
+int gemm_tile_count(rn_mode mode) { return tile_count_of(mode); }
+
+// The last tile of every mode is the skinny kernel, for problems whose
+// shorter output side has at most kSkinnyRows entries.
+bool gemm_tile_valid(rn_mode mode, int tile, int64_t M, int64_t N) {
+  if (tile < 0 || tile >= tile_count_of(mode)) return false;
+  if (tile == tile_count_of(mode) - 1) return std::min(M, N) <= kSkinnyRows;
+  return true;
 }
 
 int gemm_default_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
@@ -2364,11 +2565,26 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
   GemmParams p;
   fill_params(g, p);
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  const int tile = g.tile >= 0 ? g.tile : choose_tile(g.mode, g.M, g.N, g.K);
+  const int tile = gemm_tile_valid(g.mode, g.tile, g.M, g.N)
+                       ? g.tile
+                       : choose_tile(g.mode, g.M, g.N, g.K);
   const TileCfg& c = tile_of(g.mode, tile);
   const unsigned nbatch = 1u << g.nbb;
   const int ev = prof ? prof->begin(1, s) : -1;
-  if (tile == 0) {
+  if (tile == tile_count_of(g.mode) - 1) {
+    skinny_orient(p);
+    p.tiles_m = 1;
+    p.tiles_n = (int)((p.N + kSkinnyCols - 1) / kSkinnyCols);
+    dim3 grid((unsigned)p.tiles_n, (unsigned)g.splitk, nbatch);
+    if (g.mode == RN_FP64)
+      cgemm_skinny<RN_FP64><<<grid, 256, 0, s>>>(p);
+    else if (g.mode == RN_FP32_3M)
+      cgemm_skinny<RN_FP32_3M><<<grid, 256, 0, s>>>(p);
+    else if (g.mode == RN_BF16X3)
+      cgemm_skinny<RN_BF16X3><<<grid, 256, 0, s>>>(p);
+    else
+      cgemm_skinny<RN_FP32_4M><<<grid, 256, 0, s>>>(p);
+  } else if (tile == 0) {
     dim3 grid((unsigned)((g.M * g.N + 255) / 256), (unsigned)g.splitk, nbatch);
     if (g.mode == RN_FP64)
       cgemm_small<RN_FP64><<<grid, 256, 0, s>>>(p);
@@ -2493,7 +2709,12 @@ size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
     ps[i].splitk = 1;
     ps[i].kchunk = probs[i].K;
     int64_t blocks;
-    if (tile == 0) {
+    if (tile == tile_count_of(G.mode) - 1) {
+      skinny_orient(ps[i]);
+      ps[i].tiles_m = 1;
+      ps[i].tiles_n = (int)((ps[i].N + kSkinnyCols - 1) / kSkinnyCols);
+      blocks = ps[i].tiles_n;
+    } else if (tile == 0) {
       blocks = (probs[i].M * probs[i].N + 255) / 256;
     } else {
       ps[i].tiles_m = (int)((probs[i].M + c.bm - 1) / c.bm);
@@ -2520,6 +2741,15 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
   t.n = G.n;
   const dim3 grid((unsigned)G.blocks);
   const int tile = G.tile;
+  if (tile == tile_count_of(G.mode) - 1) {
+    switch (G.mode) {
+      case RN_FP64: cgemm_skinny_grouped<RN_FP64><<<grid, 256, 0, s>>>(t); break;
+      case RN_FP32_3M: cgemm_skinny_grouped<RN_FP32_3M><<<grid, 256, 0, s>>>(t); break;
+      case RN_BF16X3: cgemm_skinny_grouped<RN_BF16X3><<<grid, 256, 0, s>>>(t); break;
+      default: cgemm_skinny_grouped<RN_FP32_4M><<<grid, 256, 0, s>>>(t); break;
+    }
+    return hipGetLastError();
+  }
   switch (G.mode) {
     case RN_FP64:
       if (tile == 0) cgemm_small_grouped<RN_FP64><<<grid, 256, 0, s>>>(t);
@@ -2594,6 +2824,8 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
 // independent small steps of one dependency level of the path share one
 // launch.
 // ===========================================================================
+static_assert(sizeof(DirectStep) % 4 == 0 && sizeof(DirectStep) <= 4 * 256,
+              "step copied by one word per thread");
 struct DirectTable {
   const DirectStep* steps;
   const int32_t* prefix;
@@ -2613,7 +2845,12 @@ __global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
     if (g.prefix[mid] <= bid) lo = mid;
     else hi = mid - 1;
   }
-  const DirectStep& d = g.steps[lo];
+  // The step's bit maps are read per output; copy them into LDS once.
+  __shared__ __align__(16) uint32_t d_raw[sizeof(DirectStep) / 4];
+  if (threadIdx.x < sizeof(DirectStep) / 4)
+    d_raw[threadIdx.x] = reinterpret_cast<const uint32_t*>(&g.steps[lo])[threadIdx.x];
+  __syncthreads();
+  const DirectStep& d = *reinterpret_cast<const DirectStep*>(d_raw);
   const int local = bid - g.prefix[lo];
   const int b = local / d.blocks_per_batch;
   const int64_t e = int64_t(local % d.blocks_per_batch) * 256 + threadIdx.x;

@@ -144,6 +144,9 @@ struct GemmLaunch {
 };
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof = nullptr);
 int gemm_tile_count(rn_mode mode);
+// Whether tile index `tile` may run a problem with an M x N output (the
+// skinny kernel needs min(M, N) <= 8; launch_gemm falls back to the default).
+bool gemm_tile_valid(rn_mode mode, int tile, int64_t M, int64_t N);
 int gemm_default_tile(rn_mode mode, int64_t M, int64_t N, int64_t K);
 
 // Grouped launches: many problems (or permutations) in one kernel launch.

@@ -39,7 +39,8 @@ def all_tiles():
 
 
 @pytest.mark.parametrize("mode,tile", all_tiles())
-@pytest.mark.parametrize("shape", [(16, 15, 7), (11, 12, 5)])
+@pytest.mark.parametrize("shape", [(16, 15, 7), (11, 12, 5), (10, 14, 7), (14, 9, 7),
+                                   (8, 15, 8)])
 def test_forced_tile(ctx, tmp_path, mode, tile, shape):
     import torch
     ra, rb, k = shape
