@@ -45,8 +45,21 @@ def percentile(xs, q):
 
 
 def kernel_sha():
-    with open(os.path.join(ROOT, "paper_2201_06620_amd", "csrc", "kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the source the profiled GEMM is built from: the shared GEMM
+    parameter, output-map and tile-order code, the large FP32 tile body and
+    the entry-point macro.  A change there invalidates the stored counters."""
+    with open(os.path.join(ROOT, "paper_2201_06620_amd", "csrc", "kernels.hip")) as f:
+        src = f.read()
+    parts = []
+    for start, end in (("struct GemmParams {", "// FP32, 4M embedding"),
+                       ("void cgemm_f32_big_body(", "// Dynamic LDS bytes of the large FP32 tile."),
+                       ("#define RN_GEMM_ENTRY(NAME)", "// Entry points whose register use")):
+        i = src.find(start)
+        j = src.find(end, i + 1)
+        if i < 0 or j < 0:
+            return "missing"
+        parts.append(src[i:j])
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 
 def traffic_from_profiles(kernel, per_launch_units):
@@ -60,7 +73,7 @@ def traffic_from_profiles(kernel, per_launch_units):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernels_sha256_16") != kernel_sha():
+    if vals.get("kernel_source_sha256_16") != kernel_sha():
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
