@@ -475,6 +475,11 @@ class Context:
               "contract_network")
         return amp
 
+    def prepare_network(self, tensors, labels, path, sliced=(), mode="fp64"):
+        """A network call with its argument arrays built once (for repeated
+        amplitudes of one circuit: same tensors, new values written in place)."""
+        return PreparedNetwork(self, tensors, labels, path, sliced, mode)
+
     # -- kernel timing -------------------------------------------------------
     KERNEL_CLASSES = ("permute", "gemm", "splitk_reduce", "fp64_reduce")
 
@@ -574,3 +579,42 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class PreparedNetwork:
+    """Argument arrays of one network contraction, kept for repeated calls.
+
+    The tensors passed in must stay alive and keep their storage; their
+    contents may change between calls.
+    """
+
+    def __init__(self, ctx, tensors, labels, path, sliced, mode):
+        self.ctx = ctx
+        self.tensors = list(tensors)
+        self.mode = mode
+        self.Ts, self.lab_arr, self._keep = ctx._net_args(self.tensors, labels, mode)
+        self.pth, self.pp = _arr32([x for st in path for x in st])
+        self.sl, self.ps = _arr32(sliced)
+        self.nsteps = len(path)
+        ws_n, fl, mr = ctypes.c_size_t(), ctypes.c_double(), ctypes.c_int32()
+        check(lib().rn_contract_network_plan(ctx.h, len(self.tensors), self.Ts, self.lab_arr,
+                                             self.nsteps, self.pp, len(self.sl), self.ps,
+                                             mode_id(mode), ctypes.byref(ws_n), ctypes.byref(fl),
+                                             ctypes.byref(mr)), "network plan")
+        self.ws_bytes, self.flops, self.max_rank = ws_n.value, fl.value, mr.value
+        import torch
+        dev = self.tensors[0].device
+        self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+
+    def run(self, amp=None, slices=None):
+        """Amplitude (device tensor of 2 doubles) on the current stream."""
+        import torch
+        if amp is None:
+            amp = torch.zeros(2, dtype=torch.float64, device=self.tensors[0].device)
+        check(lib().rn_contract_network(self.ctx.h, len(self.tensors), self.Ts, self.lab_arr,
+                                        self.nsteps, self.pp, len(self.sl), self.ps,
+                                        mode_id(self.mode), self.workspace.data_ptr(),
+                                        self.ws_bytes, self.ctx._stream(), amp.data_ptr(),
+                                        slices.data_ptr() if slices is not None else None),
+              "contract_network")
+        return amp

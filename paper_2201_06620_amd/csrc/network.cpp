@@ -582,13 +582,89 @@ static rn_status plan_fitting(int32_t nt, const rn_tensor* T, const int32_t* con
   }
 }
 
+// Exact structural signature of a network call: everything the plan
+// depends on, nothing it does not (data pointers excluded).
+static bool net_signature(int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                          int32_t nsteps, const int32_t* path, int32_t nsliced,
+                          const int32_t* sliced, rn_mode mode, const NetOpts& o,
+                          std::vector<int64_t>& sig) {
+  if (nt < 1 || !T || !labels || nsteps < 0 || nsliced < 0 || (nsteps > 0 && !path) ||
+      (nsliced > 0 && !sliced))
+    return false;
+  sig.clear();
+  sig.push_back(mode);
+  sig.push_back(o.slice_sum);
+  sig.push_back(o.batch_bits);
+  sig.push_back(o.footprint);
+  sig.push_back(nt);
+  sig.push_back(nsteps);
+  sig.push_back(nsliced);
+  for (int i = 0; i < nt; ++i) {
+    const rn_tensor& t = T[i];
+    if (t.rank < 0 || t.rank > RN_MAX_RANK || (t.rank > 0 && !labels[i])) return false;
+    sig.push_back(t.rank);
+    sig.push_back(t.dtype);
+    for (int j = 0; j < t.rank; ++j) {
+      sig.push_back(t.dims[j]);
+      sig.push_back(t.grid[j]);
+      sig.push_back(labels[i][j]);
+    }
+  }
+  for (int i = 0; i < 2 * nsteps; ++i) sig.push_back(path[i]);
+  for (int i = 0; i < nsliced; ++i) sig.push_back(sliced[i]);
+  return true;
+}
+
+// Plan through the handle's cache (kept to 16 entries); with no handle, or
+// arguments too malformed to sign, plan directly.
+static rn_status cached_plan(rn_ctx* h, int32_t nt, const rn_tensor* T,
+                             const int32_t* const* labels, int32_t nsteps, const int32_t* path,
+                             int32_t nsliced, const int32_t* sliced, rn_mode mode,
+                             const NetOpts& o, std::shared_ptr<NetPlan>* out) {
+  std::vector<int64_t> sig;
+  const bool signable = h && net_signature(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, sig);
+  if (signable) {
+    auto& c = h->net_plans;
+    for (size_t i = 0; i < c.size(); ++i) {
+      if (c[i].first == sig) {
+        for (int j = 0; j < nt; ++j)
+          if (!T[j].data) return fail(RN_ERR_INVALID, "null tensor data");
+        auto hit = c[i];
+        c.erase(c.begin() + i);
+        c.push_back(hit);
+        *out = std::static_pointer_cast<NetPlan>(hit.second);
+        return RN_OK;
+      }
+    }
+  }
+  auto P = std::make_shared<NetPlan>();
+  rn_status st = plan_fitting(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, P.get());
+  if (st != RN_OK) return st;
+  if (signable) {
+    auto& c = h->net_plans;
+    if (c.size() >= 16) c.erase(c.begin());
+    c.push_back({std::move(sig), std::static_pointer_cast<void>(P)});
+  }
+  *out = P;
+  return RN_OK;
+}
+
 rn_status network_plan(int32_t nt, const rn_tensor* T, const int32_t* const* labels,
                        int32_t nsteps, const int32_t* path, int32_t nsliced,
                        const int32_t* sliced, rn_mode mode, const NetOpts& o, size_t* ws_bytes,
                        double* flops, int32_t* max_rank, int* batch_bits) {
-  NetPlan P;
-  rn_status st = plan_fitting(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &P);
+  return network_plan_h(nullptr, nt, T, labels, nsteps, path, nsliced, sliced, mode, o, ws_bytes,
+                        flops, max_rank, batch_bits);
+}
+
+rn_status network_plan_h(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                         int32_t nsteps, const int32_t* path, int32_t nsliced,
+                         const int32_t* sliced, rn_mode mode, const NetOpts& o,
+                         size_t* ws_bytes, double* flops, int32_t* max_rank, int* batch_bits) {
+  std::shared_ptr<NetPlan> PP;
+  rn_status st = cached_plan(h, nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &PP);
   if (st != RN_OK) return st;
+  const NetPlan& P = *PP;
   if (ws_bytes) *ws_bytes = (size_t)P.ws_bytes;
   if (flops) *flops = P.flops * double(int64_t(1) << P.nout);
   if (max_rank) *max_rank = P.max_rank;
@@ -601,9 +677,10 @@ rn_status network_run(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_t* 
                       const int32_t* sliced, rn_mode mode, const NetOpts& o, void* ws,
                       size_t ws_bytes, hipStream_t s, double* amp_dev, double* slices_dev) {
   if (!amp_dev) return fail(RN_ERR_INVALID, "null amplitude buffer");
-  NetPlan P;
-  rn_status st = plan_fitting(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &P);
+  std::shared_ptr<NetPlan> PP;
+  rn_status st = cached_plan(h, nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &PP);
   if (st != RN_OK) return st;
+  const NetPlan& P = *PP;
   if (P.slice_sum && slices_dev && nsliced > 0)
     return fail(RN_ERR_INVALID, "per-slice values do not exist in slice-sum mode");
   if ((int64_t)ws_bytes < P.ws_bytes || (P.ws_bytes > 0 && !ws))
@@ -660,8 +737,8 @@ rn_status rn_contract_network_plan(rn_handle h, int32_t nt, const rn_tensor* T,
                                    rn_mode mode, size_t* ws_bytes, double* flops,
                                    int32_t* max_rank) {
   const NetOpts o = h ? h->net : NetOpts{};
-  return network_plan(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, ws_bytes, flops,
-                      max_rank, nullptr);
+  return network_plan_h(h, nt, T, labels, nsteps, path, nsliced, sliced, mode, o, ws_bytes, flops,
+                        max_rank, nullptr);
 }
 
 rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,

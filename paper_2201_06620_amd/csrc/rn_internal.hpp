@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <functional>
 #include <map>
+#include <memory>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -239,6 +240,9 @@ struct rn_ctx {
   hipEvent_t copy_ev[9] = {nullptr};
   std::vector<GraphEntry> graphs;
   std::vector<uint64_t> seen;  // keys run once directly; a repeat is captured
+  // Network plans by exact structural signature (shapes, labels, path,
+  // sliced labels, mode, options); most recently used last.
+  std::vector<std::pair<std::vector<int64_t>, std::shared_ptr<void>>> net_plans;
   uint64_t use_clock = 0;
 };
 
@@ -260,6 +264,11 @@ rn_status network_plan(int32_t nt, const rn_tensor* T, const int32_t* const* lab
                        int32_t nsteps, const int32_t* path, int32_t nsliced,
                        const int32_t* sliced, rn_mode mode, const NetOpts& o, size_t* ws_bytes,
                        double* flops, int32_t* max_rank, int* batch_bits);
+// As network_plan, through the plan cache of handle h (may be null).
+rn_status network_plan_h(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                         int32_t nsteps, const int32_t* path, int32_t nsliced,
+                         const int32_t* sliced, rn_mode mode, const NetOpts& o,
+                         size_t* ws_bytes, double* flops, int32_t* max_rank, int* batch_bits);
 rn_status network_run(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_t* const* labels,
                       int32_t nsteps, const int32_t* path, int32_t nsliced,
                       const int32_t* sliced, rn_mode mode, const NetOpts& o, void* ws,

@@ -110,3 +110,34 @@ def test_ghz_network(ctx):
         path = paths.greedy_path(net.labels, 1, restarts=1)
         a = gpu_amp(ctx, net, path, [], "fp64")
         assert abs(a - expect) < 1e-15
+
+
+def test_prepared_network_repeats_and_new_values(ctx):
+    # A prepared call (plan cached on the handle, graph replayed on a side
+    # stream) gives the oracle's amplitude, and follows new tensor values
+    # written in place: another bitstring of the same circuit.
+    import torch
+    circ = circuits.random_circuit(3, 4, 8, seed=77)
+    psi = oracle.statevector(circ)
+    bits0 = circuits.random_bitstring(circ.n, seed=1)
+    net0 = circuits.circuit_network(circ, bits0)
+    path = paths.greedy_path(net0.labels, 9, restarts=2)
+    sliced = paths.greedy_slices(net0.labels, path, 3, n_slices=3)
+    ts = [torch.from_numpy(np.ascontiguousarray(t.reshape(-1))).cuda() for t in net0.tensors]
+    prep = ctx.prepare_network(ts, net0.labels, path, sliced, "fp64")
+    s = torch.cuda.Stream()
+    amp = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for trial in range(4):
+        bits = circuits.random_bitstring(circ.n, seed=1 + trial)
+        net = circuits.circuit_network(circ, bits)
+        assert net.labels == net0.labels
+        for t_dev, t_new in zip(ts, net.tensors):
+            t_dev.copy_(torch.from_numpy(np.ascontiguousarray(t_new.reshape(-1))))
+        torch.cuda.synchronize()
+        for _ in range(2):
+            with torch.cuda.stream(s):
+                prep.run(amp=amp)
+            s.synchronize()
+        a = amp.cpu().numpy()
+        x = int("".join(map(str, bits)), 2)
+        assert amp_err(complex(a[0], a[1]), psi[x], circ.n) < 1e-12
