@@ -672,6 +672,12 @@ rn_status network_plan_h(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_
   return RN_OK;
 }
 
+static rn_status run_planned(rn_ctx* h, const NetPlan& P, int32_t nt, const rn_tensor* T,
+                             const int32_t* const* labels, int32_t nsteps, const int32_t* path,
+                             int32_t nsliced, const int32_t* sliced, rn_mode mode, void* ws,
+                             size_t ws_bytes, hipStream_t s, double* amp_dev,
+                             double* slices_dev);
+
 rn_status network_run(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_t* const* labels,
                       int32_t nsteps, const int32_t* path, int32_t nsliced,
                       const int32_t* sliced, rn_mode mode, const NetOpts& o, void* ws,
@@ -680,7 +686,45 @@ rn_status network_run(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_t* 
   std::shared_ptr<NetPlan> PP;
   rn_status st = cached_plan(h, nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &PP);
   if (st != RN_OK) return st;
-  const NetPlan& P = *PP;
+  return run_planned(h, *PP, nt, T, labels, nsteps, path, nsliced, sliced, mode, ws, ws_bytes, s,
+                     amp_dev, slices_dev);
+}
+
+rn_status network_plan_keep(int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                            int32_t nsteps, const int32_t* path, int32_t nsliced,
+                            const int32_t* sliced, rn_mode mode, const NetOpts& o,
+                            std::shared_ptr<void>* plan, size_t* ws_bytes, double* flops,
+                            int* batch_bits) {
+  auto P = std::make_shared<NetPlan>();
+  rn_status st = plan_fitting(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, P.get());
+  if (st != RN_OK) return st;
+  if (ws_bytes) *ws_bytes = (size_t)P->ws_bytes;
+  if (flops) *flops = P->flops * double(int64_t(1) << P->nout);
+  if (batch_bits) *batch_bits = P->nsliced - P->nout;
+  *plan = std::static_pointer_cast<void>(P);
+  return RN_OK;
+}
+
+rn_status network_run_planned(rn_ctx* h, const std::shared_ptr<void>& plan, int32_t nt,
+                              const rn_tensor* T, const int32_t* const* labels, int32_t nsteps,
+                              const int32_t* path, int32_t nsliced, const int32_t* sliced,
+                              rn_mode mode, void* ws, size_t ws_bytes, hipStream_t s,
+                              double* amp_dev, double* slices_dev) {
+  if (!plan) return fail(RN_ERR_INVALID, "no plan");
+  if (!amp_dev) return fail(RN_ERR_INVALID, "null amplitude buffer");
+  for (int j = 0; j < nt; ++j)
+    if (!T[j].data) return fail(RN_ERR_INVALID, "null tensor data");
+  return run_planned(h, *std::static_pointer_cast<NetPlan>(plan), nt, T, labels, nsteps, path,
+                     nsliced, sliced, mode, ws, ws_bytes, s, amp_dev, slices_dev);
+}
+
+// Run a planned network (the plan matches these arguments).
+static rn_status run_planned(rn_ctx* h, const NetPlan& P, int32_t nt, const rn_tensor* T,
+                             const int32_t* const* labels, int32_t nsteps, const int32_t* path,
+                             int32_t nsliced, const int32_t* sliced, rn_mode mode, void* ws,
+                             size_t ws_bytes, hipStream_t s, double* amp_dev,
+                             double* slices_dev) {
+  rn_status st;
   if (P.slice_sum && slices_dev && nsliced > 0)
     return fail(RN_ERR_INVALID, "per-slice values do not exist in slice-sum mode");
   if ((int64_t)ws_bytes < P.ws_bytes || (P.ws_bytes > 0 && !ws))

@@ -264,6 +264,18 @@ rn_status network_plan(int32_t nt, const rn_tensor* T, const int32_t* const* lab
                        int32_t nsteps, const int32_t* path, int32_t nsliced,
                        const int32_t* sliced, rn_mode mode, const NetOpts& o, size_t* ws_bytes,
                        double* flops, int32_t* max_rank, int* batch_bits);
+// Plan once, run later (the server plans at submission and runs on its
+// worker thread): the plan is opaque to the caller.
+rn_status network_plan_keep(int32_t nt, const rn_tensor* T, const int32_t* const* labels,
+                            int32_t nsteps, const int32_t* path, int32_t nsliced,
+                            const int32_t* sliced, rn_mode mode, const NetOpts& o,
+                            std::shared_ptr<void>* plan, size_t* ws_bytes, double* flops,
+                            int* batch_bits);
+rn_status network_run_planned(rn_ctx* h, const std::shared_ptr<void>& plan, int32_t nt,
+                              const rn_tensor* T, const int32_t* const* labels, int32_t nsteps,
+                              const int32_t* path, int32_t nsliced, const int32_t* sliced,
+                              rn_mode mode, void* ws, size_t ws_bytes, hipStream_t s,
+                              double* amp_dev, double* slices_dev);
 // As network_plan, through the plan cache of handle h (may be null).
 rn_status network_plan_h(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_t* const* labels,
                          int32_t nsteps, const int32_t* path, int32_t nsliced,

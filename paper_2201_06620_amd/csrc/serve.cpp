@@ -72,6 +72,7 @@ struct Request {
   std::vector<int32_t> path, sliced;
   size_t ws_bytes = 0, tensor_bytes = 0, footprint = 0;
   NetOpts opts;  // batched-slice count fitted to the budget at submission
+  std::shared_ptr<void> plan;  // made at submission, run by the worker
   Clock::time_point t_submit, t_start, t_done;
   size_t arena_off = 0;
   int slot = -1;
@@ -144,9 +145,9 @@ int32_t start(rn_server* S, Request* r, int slot) {
   void* ws = base + off;
   std::vector<const int32_t*> lab(r->nt);
   for (int i = 0; i < r->nt; ++i) lab[i] = r->labels[i].data();
-  rn_status st = network_run(S->h, r->nt, dev.data(), lab.data(), r->nsteps, r->path.data(),
-                             r->nsliced, r->sliced.data(), r->mode, r->opts, ws, r->ws_bytes, s,
-                             amp_dev, nullptr);
+  rn_status st = network_run_planned(S->h, r->plan, r->nt, dev.data(), lab.data(), r->nsteps,
+                                     r->path.data(), r->nsliced, r->sliced.data(), r->mode, ws,
+                                     r->ws_bytes, s, amp_dev, nullptr);
   if (st != RN_OK) return st;
   if (hipMemcpyAsync(S->amp_host + 2 * slot, amp_dev, 2 * sizeof(double), hipMemcpyDeviceToHost,
                      s) != hipSuccess)
@@ -296,20 +297,21 @@ rn_status rn_server_submit(rn_server_t S, int32_t nt, const rn_tensor* T,
   o.footprint = S->budget > fixed ? (int64_t)(S->budget - fixed) : 1;
   size_t ws = 0;
   double flops = 0;
-  int32_t mr = 0;
   int bb = 0;
-  rn_status st = network_plan(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &ws, &flops,
-                              &mr, &bb);
+  std::shared_ptr<void> plan;
+  rn_status st = network_plan_keep(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &plan,
+                                   &ws, &flops, &bb);
   if (st == RN_ERR_OOM) {
     o = NetOpts{};
-    st = network_plan(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &ws, &flops, &mr,
-                      &bb);
+    st = network_plan_keep(nt, T, labels, nsteps, path, nsliced, sliced, mode, o, &plan, &ws,
+                           &flops, &bb);
   }
   if (st != RN_OK) return st;
   o.batch_bits = bb;
   o.footprint = 0;
   Request* r = new Request();
   r->opts = o;
+  r->plan = std::move(plan);
   r->mode = mode;
   r->nt = nt;
   r->nsteps = nsteps;
