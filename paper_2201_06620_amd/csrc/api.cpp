@@ -177,6 +177,14 @@ rn_status rn_destroy(rn_handle h) {
   }
   for (hipEvent_t e : h->copy_ev)
     if (e) hipEventDestroy(e);
+  for (int i = 0; i < 3; ++i) {
+    if (h->aux_streams[i]) {
+      hipStreamSynchronize(h->aux_streams[i]);
+      hipStreamDestroy(h->aux_streams[i]);
+    }
+    if (h->aux_join[i]) hipEventDestroy(h->aux_join[i]);
+  }
+  if (h->aux_fork) hipEventDestroy(h->aux_fork);
   delete h;
   return RN_OK;
 }

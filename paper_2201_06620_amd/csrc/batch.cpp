@@ -175,17 +175,57 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
   }
 }
 
+static rn_status aux_setup(rn_ctx* h) {
+  if (h->aux_fork) return RN_OK;
+  hipError_t e;
+  for (int i = 0; i < 3; ++i) {
+    if ((e = hipStreamCreateWithFlags(&h->aux_streams[i], hipStreamNonBlocking)) != hipSuccess)
+      return hipf(e, "batch stream");
+    if ((e = hipEventCreateWithFlags(&h->aux_join[i], hipEventDisableTiming)) != hipSuccess)
+      return hipf(e, "batch event");
+  }
+  if ((e = hipEventCreateWithFlags(&h->aux_fork, hipEventDisableTiming)) != hipSuccess)
+    return hipf(e, "batch event");
+  return RN_OK;
+}
+
+// One grouped permute, then the GEMM tile groups.  Without kernel timing the
+// groups run side by side on `s` and up to three more streams (fork after
+// the permute, join back onto `s`), so the tail of one group overlaps the
+// others instead of idling the GPU.
 rn_status launch_all(rn_ctx* h, const Launches& L, char* table_dev, hipStream_t s, bool prof) {
   hipError_t e;
   int ev = prof ? h->prof.begin(0, s) : -1;
   e = launch_permute_grouped(L.perm, table_dev, s);
   if (prof) h->prof.end(ev, s);
   if (e != hipSuccess) return hipf(e, "grouped permute");
-  for (const GroupedLaunch& G : L.gemms) {
-    ev = prof ? h->prof.begin(1, s) : -1;
-    e = launch_gemm_grouped(G, table_dev, s);
-    if (prof) h->prof.end(ev, s);
-    if (e != hipSuccess) return hipf(e, "grouped GEMM");
+  const int ng = (int)L.gemms.size();
+  if (prof || ng < 2) {
+    for (const GroupedLaunch& G : L.gemms) {
+      ev = prof ? h->prof.begin(1, s) : -1;
+      e = launch_gemm_grouped(G, table_dev, s);
+      if (prof) h->prof.end(ev, s);
+      if (e != hipSuccess) return hipf(e, "grouped GEMM");
+    }
+    return RN_OK;
+  }
+  if (!h->aux_fork) return fail(RN_ERR_INVALID, "batch streams not set up");
+  const int nstreams = std::min(ng, 4);
+  if ((e = hipEventRecord(h->aux_fork, s)) != hipSuccess) return hipf(e, "fork");
+  for (int j = 1; j < nstreams; ++j)
+    if ((e = hipStreamWaitEvent(h->aux_streams[j - 1], h->aux_fork, 0)) != hipSuccess)
+      return hipf(e, "fork wait");
+  for (int i = 0; i < ng; ++i) {
+    const int j = i % nstreams;
+    hipStream_t sj = j == 0 ? s : h->aux_streams[j - 1];
+    if ((e = launch_gemm_grouped(L.gemms[i], table_dev, sj)) != hipSuccess)
+      return hipf(e, "grouped GEMM");
+  }
+  for (int j = 1; j < nstreams; ++j) {
+    if ((e = hipEventRecord(h->aux_join[j - 1], h->aux_streams[j - 1])) != hipSuccess)
+      return hipf(e, "join");
+    if ((e = hipStreamWaitEvent(s, h->aux_join[j - 1], 0)) != hipSuccess)
+      return hipf(e, "join wait");
   }
   return RN_OK;
 }
@@ -351,6 +391,8 @@ rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
                                       " bytes needed)");
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hipf(e, "hipSetDevice");
+  // Side streams for the tile groups exist before any graph capture.
+  if ((st = aux_setup(h)) != RN_OK) return st;
   if (n == 0) return RN_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* table_dev = static_cast<char*>(ws) + bp.table_off;

@@ -235,6 +235,11 @@ struct rn_ctx {
   bool graphs_enabled = true;
   rn::SplitPolicy split;
   rn::NetOpts net;
+  // Batch: extra streams on which tile groups of one batch run side by side
+  // (fork/join by events; default priority), created on first use.
+  hipStream_t aux_streams[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t aux_fork = nullptr;
+  hipEvent_t aux_join[3] = {nullptr, nullptr, nullptr};
   // Streamed contraction: host-to-device copy stream and its events.
   hipStream_t copy_stream = nullptr;
   hipEvent_t copy_ev[9] = {nullptr};
