@@ -1186,7 +1186,19 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
   static_assert(BK % 8 == 0, "eight complex k per MFMA");
   constexpr int BM = WM * TM * 32;
   constexpr int BN = WN * TN * 32;  // complex columns
-  constexpr int LDK = BK + 4;
+  // LDS rows of BK words (BK / 4 chunks of 16 bytes), unpadded: chunk q of
+  // row r sits at chunk q ^ swz(r), which puts the rows one 128-bit read
+  // touches (consecutive rows, same chunk) and the chunks one staging store
+  // writes (whole consecutive rows) on distinct bank groups, for 32 or 64
+  // four-byte banks.
+  constexpr int LDK = BK;
+  static_assert(BK == 8 || BK == 16, "swizzle defined for 2 or 4 chunks per row");
+  auto swz = [](int r) -> int {
+    return BK == 16 ? (((r >> 1) ^ (r >> 3)) & 3) : (((r >> 2) ^ (r >> 3)) & 1);
+  };
+  auto chunk_at = [&](int r, int word) -> int {  // word: multiple of 4 within the row
+    return r * LDK + ((((word >> 2) ^ swz(r))) << 2);
+  };
   constexpr int AV = BM * BK / 4;
   constexpr int BV = BN * BK / 4;
   constexpr int NA = (AV + 255) / 256;
@@ -1280,8 +1292,8 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
       int idx = tid + 256 * j;
       if (AV % 256 == 0 || idx < AV) {
         int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-        *reinterpret_cast<uint4*>(&Ah[buf][r * LDK + c]) = rah[j];
-        *reinterpret_cast<uint4*>(&Al[buf][r * LDK + c]) = ral[j];
+        *reinterpret_cast<uint4*>(&Ah[buf][chunk_at(r, c)]) = rah[j];
+        *reinterpret_cast<uint4*>(&Al[buf][chunk_at(r, c)]) = ral[j];
       }
     }
 #pragma unroll
@@ -1289,8 +1301,8 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
       int idx = tid + 256 * j;
       if (BV % 256 == 0 || idx < BV) {
         int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-        *reinterpret_cast<uint4*>(&Bh[buf][r * LDK + c]) = rbh[j];
-        *reinterpret_cast<uint4*>(&Bl[buf][r * LDK + c]) = rbl[j];
+        *reinterpret_cast<uint4*>(&Bh[buf][chunk_at(r, c)]) = rbh[j];
+        *reinterpret_cast<uint4*>(&Bl[buf][chunk_at(r, c)]) = rbl[j];
       }
     }
   };
@@ -1331,13 +1343,13 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
       v8bf ah[TM], al[TM];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        int o = (arow + i * 32) * LDK + kk + kq;
+        int o = chunk_at(arow + i * 32, kk + kq);
         ah[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(&Ah[buf][o]));
         al[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(&Al[buf][o]));
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        int o = (bcol + j * 32) * LDK + kk + kq;
+        int o = chunk_at(bcol + j * 32, kk + kq);
         const v4u wh = *reinterpret_cast<const v4u*>(&Bh[buf][o]);
         const v4u wl = *reinterpret_cast<const v4u*>(&Bl[buf][o]);
         const v8bf bhr = __builtin_bit_cast(v8bf, wh ^ 0x80000000u);

@@ -77,26 +77,52 @@ def test_fp64_large_tiles():
                             assert o % 2 == 0 and o + 1 < bn * ldr
 
 
+def bf16_swz(bk, r):
+    return (((r >> 1) ^ (r >> 3)) & 3) if bk == 16 else (((r >> 2) ^ (r >> 3)) & 1)
+
+
+def bf16_chunk_at(bk, r, word):
+    return r * bk + (((word >> 2) ^ bf16_swz(bk, r)) << 2)
+
+
 def test_bf16x3_tiles():
     shapes = instances("cgemm_bf16x3_ri")
     assert shapes
     for wm_, wn_, tm, tn, bk in shapes:
-        bm, bn, ldk = wm_ * tm * 32, wn_ * tn * 32, bk + 4
+        bm, bn = wm_ * tm * 32, wn_ * tn * 32
         for rows in (bm, bn):
             for r, c in thread_loads(rows, bk, 4):
                 assert r < rows and c + 3 < bk
-                assert r * ldk + c + 3 < rows * ldk
+                o = bf16_chunk_at(bk, r, c)
+                assert o % 4 == 0 and r * bk <= o and o + 3 < (r + 1) * bk
         for lane in range(64):
             kq = (lane >> 5) * 4
             for w in range(4):
                 wm, wn = w // wn_, w % wn_
                 for kk in range(0, bk, 8):
                     for i in range(tm):
-                        o = (wm * tm * 32 + lane % 32 + i * 32) * ldk + kk + kq
-                        assert o % 4 == 0 and o + 3 < bm * ldk
+                        o = bf16_chunk_at(bk, wm * tm * 32 + lane % 32 + i * 32, kk + kq)
+                        assert o % 4 == 0 and o + 3 < bm * bk
                     for j in range(tn):
-                        o = (wn * tn * 32 + lane % 32 + j * 32) * ldk + kk + kq
-                        assert o % 4 == 0 and o + 3 < bn * ldk
+                        o = bf16_chunk_at(bk, wn * tn * 32 + lane % 32 + j * 32, kk + kq)
+                        assert o % 4 == 0 and o + 3 < bn * bk
+
+
+def test_bf16x3_swizzle_spreads_banks():
+    # For 32 banks (8 chunks per 128 bytes, 8 lanes of a 128-bit access per
+    # cycle) and 64 banks (16 chunks, 16 lanes): the rows of one fragment
+    # read, and the chunks of one staging store, fall on distinct chunks.
+    for bk in (8, 16):
+        cpr = bk // 4
+        for group, nchunk in ((8, 8), (16, 16)):
+            for r0 in range(0, 128, group):
+                for q in range(cpr):
+                    got = {(bf16_chunk_at(bk, r0 + l, 4 * q) // 4) % nchunk for l in range(group)}
+                    assert len(got) == group
+            for t0 in range(0, 256, group):
+                got = {(bf16_chunk_at(bk, t // cpr, 4 * (t % cpr)) // 4) % nchunk
+                       for t in range(t0, t0 + group)}
+                assert len(got) == group
 
 
 def test_guard_matters():
