@@ -2172,14 +2172,15 @@ __device__ __forceinline__ void cgemm_small_body(const GemmParams& p, int64_t bl
 // ---------------------------------------------------------------------------
 // Skinny problems (at most 8 output rows after orienting, see
 // skinny_orient): memory-bound, so the GEMM streams each B row once.  A
-// workgroup owns 16 output columns (4 per wave); the A rows of the current
-// K chunk sit in LDS; each wave walks its columns with lanes striding over
-// k (coalesced B reads) and keeps per-(column, row) partial sums that are
-// combined across the wave by a fixed xor-shuffle tree at the end.
+// workgroup owns 16 output columns (4 per wave).  Lane l of every wave
+// handles k = k0 + l + 64 u (u < U) of each K chunk, so it loads its A
+// values for the chunk once into registers and reuses them for all four
+// columns; the 4 x U loads of B per chunk are issued together.  Per-(column,
+// row) partial sums are combined across the wave by a fixed xor-shuffle
+// tree at the end.
 // ---------------------------------------------------------------------------
 constexpr int kSkinnyRows = 8;
 constexpr int kSkinnyCols = 16;
-constexpr int kSkinnyKC = 256;
 
 template <typename R>
 __device__ __forceinline__ R wave_sum(R v) {
@@ -2188,15 +2189,77 @@ __device__ __forceinline__ R wave_sum(R v) {
   return v;
 }
 
+// Operand element of each mode: complex128, complex64, or the bf16 hi/lo
+// words of one complex (re in the low half, im in the high half).
+template <int MODE>
+struct SkinnyElem {
+  using T = typename std::conditional<MODE == RN_FP64, double2,
+                                      typename std::conditional<MODE == RN_BF16X3, uint2,
+                                                                float2>::type>::type;
+};
+
+template <int MODE>
+__device__ __forceinline__ typename SkinnyElem<MODE>::T skinny_load(const void* X, const void* X2,
+                                                                   int64_t i) {
+  if constexpr (MODE == RN_FP64) {
+    return reinterpret_cast<const double2*>(X)[i];
+  } else if constexpr (MODE == RN_BF16X3) {
+    return make_uint2(reinterpret_cast<const uint32_t*>(X)[i],
+                      reinterpret_cast<const uint32_t*>(X2)[i]);
+  } else {
+    return reinterpret_cast<const float2*>(X)[i];
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ typename SkinnyElem<MODE>::T skinny_zero() {
+  if constexpr (MODE == RN_FP64) return make_double2(0.0, 0.0);
+  else if constexpr (MODE == RN_BF16X3) return make_uint2(0u, 0u);
+  else return make_float2(0.f, 0.f);
+}
+
+// acc[0..NT) += a * b in the mode's arithmetic (the same per-term formulas
+// as the one-thread kernel).
+template <int MODE, typename R, typename E>
+__device__ __forceinline__ void skinny_mac(R* acc, const E& a, const E& bb) {
+  if constexpr (MODE == RN_FP64) {
+    acc[0] = fma(a.x, bb.x, acc[0]);
+    acc[0] = fma(-a.y, bb.y, acc[0]);
+    acc[1] = fma(a.x, bb.y, acc[1]);
+    acc[1] = fma(a.y, bb.x, acc[1]);
+  } else if constexpr (MODE == RN_BF16X3) {
+    const float ahr = bf_lo(a.x), ahi = bf_hi(a.x), alr = bf_lo(a.y), ali = bf_hi(a.y);
+    const float bhr = bf_lo(bb.x), bhi = bf_hi(bb.x), blr = bf_lo(bb.y), bli = bf_hi(bb.y);
+    float re = acc[0], im = acc[1];
+    re = fmaf(alr, bhr, re); re = fmaf(-ali, bhi, re);
+    im = fmaf(alr, bhi, im); im = fmaf(ali, bhr, im);
+    re = fmaf(ahr, blr, re); re = fmaf(-ahi, bli, re);
+    im = fmaf(ahr, bli, im); im = fmaf(ahi, blr, im);
+    re = fmaf(ahr, bhr, re); re = fmaf(-ahi, bhi, re);
+    im = fmaf(ahr, bhi, im); im = fmaf(ahi, bhr, im);
+    acc[0] = re;
+    acc[1] = im;
+  } else if constexpr (MODE == RN_FP32_3M) {
+    acc[0] = fmaf(a.x, bb.x, acc[0]);
+    acc[1] = fmaf(a.y, bb.y, acc[1]);
+    acc[2] = fmaf(a.x + a.y, bb.x + bb.y, acc[2]);
+  } else {
+    acc[0] = fmaf(a.x, bb.x, acc[0]);
+    acc[0] = fmaf(-a.y, bb.y, acc[0]);
+    acc[1] = fmaf(a.x, bb.y, acc[1]);
+    acc[1] = fmaf(a.y, bb.x, acc[1]);
+  }
+}
+
 template <int MODE>
 __device__ __forceinline__ void cgemm_skinny_body(const GemmParams& p, int tn, int split, int b) {
   using R = typename std::conditional<MODE == RN_FP64, double, float>::type;
+  using E = typename SkinnyElem<MODE>::T;
   constexpr int CPW = kSkinnyCols / 4;
   constexpr int NT = (MODE == RN_FP32_3M) ? 3 : 2;  // partial sums per (column, row)
-  // A chunk in LDS: complex elements (FP64/FP32) or hi and lo words (BF16x3).
-  constexpr int EB = (MODE == RN_FP64) ? 16 : 8;
-  __shared__ __align__(16) unsigned char a_lds[kSkinnyRows * kSkinnyKC * EB];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int U = (MODE == RN_FP64) ? 2 : 4;      // k per lane per chunk
+  constexpr int KC = 64 * U;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t kbeg = int64_t(split) * p.kchunk;
   const int64_t kend = min(p.K, kbeg + p.kchunk);
   const int64_t ao = batch_off(p.a_bs, p.nbb, b), bo = batch_off(p.b_bs, p.nbb, b);
@@ -2210,86 +2273,32 @@ __device__ __forceinline__ void cgemm_skinny_body(const GemmParams& p, int tn, i
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[c][m][t] = R(0);
 
-  for (int64_t k0 = kbeg; k0 < kend; k0 += kSkinnyKC) {
-    const int kc = (int)min(int64_t(kSkinnyKC), kend - k0);
-    __syncthreads();
-    for (int idx = tid; idx < M * kSkinnyKC; idx += 256) {
-      const int m = idx / kSkinnyKC, kk = idx % kSkinnyKC;
-      if constexpr (MODE == RN_FP64) {
-        double2 v = make_double2(0.0, 0.0);
-        if (kk < kc) v = reinterpret_cast<const double2*>(p.A)[ao + m * p.lda + k0 + kk];
-        reinterpret_cast<double2*>(a_lds)[m * kSkinnyKC + kk] = v;
-      } else if constexpr (MODE == RN_BF16X3) {
-        uint2 v = make_uint2(0u, 0u);
-        if (kk < kc) {
-          const int64_t o = ao + m * p.lda + k0 + kk;
-          v.x = reinterpret_cast<const uint32_t*>(p.A)[o];
-          v.y = reinterpret_cast<const uint32_t*>(p.A2)[o];
-        }
-        reinterpret_cast<uint2*>(a_lds)[m * kSkinnyKC + kk] = v;
-      } else {
-        float2 v = make_float2(0.f, 0.f);
-        if (kk < kc) v = reinterpret_cast<const float2*>(p.A)[ao + m * p.lda + k0 + kk];
-        reinterpret_cast<float2*>(a_lds)[m * kSkinnyKC + kk] = v;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
+    E av[kSkinnyRows][U];
+#pragma unroll
+    for (int m = 0; m < kSkinnyRows; ++m)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = k0 + lane + 64 * u;
+        av[m][u] = (m < M && k < kend) ? skinny_load<MODE>(p.A, p.A2, ao + m * p.lda + k)
+                                       : skinny_zero<MODE>();
       }
-    }
-    __syncthreads();
+    E bv[CPW][U];
 #pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-      const int64_t n = n0 + c;
-      if (n >= p.N) continue;
-      for (int kk = lane; kk < kc; kk += 64) {
-        const int64_t bi = bo + n * p.ldb + k0 + kk;
-        if constexpr (MODE == RN_FP64) {
-          const double2 bb = reinterpret_cast<const double2*>(p.B)[bi];
+    for (int c = 0; c < CPW; ++c)
 #pragma unroll
-          for (int m = 0; m < kSkinnyRows; ++m) {
-            if (m >= M) break;
-            const double2 a = reinterpret_cast<const double2*>(a_lds)[m * kSkinnyKC + kk];
-            acc[c][m][0] = fma(a.x, bb.x, acc[c][m][0]);
-            acc[c][m][0] = fma(-a.y, bb.y, acc[c][m][0]);
-            acc[c][m][1] = fma(a.x, bb.y, acc[c][m][1]);
-            acc[c][m][1] = fma(a.y, bb.x, acc[c][m][1]);
-          }
-        } else if constexpr (MODE == RN_BF16X3) {
-          const uint32_t bh = reinterpret_cast<const uint32_t*>(p.B)[bi];
-          const uint32_t bl = reinterpret_cast<const uint32_t*>(p.B2)[bi];
-          const float bhr = bf_lo(bh), bhi = bf_hi(bh), blr = bf_lo(bl), bli = bf_hi(bl);
-#pragma unroll
-          for (int m = 0; m < kSkinnyRows; ++m) {
-            if (m >= M) break;
-            const uint2 a = reinterpret_cast<const uint2*>(a_lds)[m * kSkinnyKC + kk];
-            const float ahr = bf_lo(a.x), ahi = bf_hi(a.x), alr = bf_lo(a.y), ali = bf_hi(a.y);
-            float re = acc[c][m][0], im = acc[c][m][1];
-            re = fmaf(alr, bhr, re); re = fmaf(-ali, bhi, re);
-            im = fmaf(alr, bhi, im); im = fmaf(ali, bhr, im);
-            re = fmaf(ahr, blr, re); re = fmaf(-ahi, bli, re);
-            im = fmaf(ahr, bli, im); im = fmaf(ahi, blr, im);
-            re = fmaf(ahr, bhr, re); re = fmaf(-ahi, bhi, re);
-            im = fmaf(ahr, bhi, im); im = fmaf(ahi, bhr, im);
-            acc[c][m][0] = re;
-            acc[c][m][1] = im;
-          }
-        } else {
-          const float2 bb = reinterpret_cast<const float2*>(p.B)[bi];
-#pragma unroll
-          for (int m = 0; m < kSkinnyRows; ++m) {
-            if (m >= M) break;
-            const float2 a = reinterpret_cast<const float2*>(a_lds)[m * kSkinnyKC + kk];
-            if constexpr (MODE == RN_FP32_3M) {
-              acc[c][m][0] = fmaf(a.x, bb.x, acc[c][m][0]);
-              acc[c][m][1] = fmaf(a.y, bb.y, acc[c][m][1]);
-              acc[c][m][2] = fmaf(a.x + a.y, bb.x + bb.y, acc[c][m][2]);
-            } else {
-              acc[c][m][0] = fmaf(a.x, bb.x, acc[c][m][0]);
-              acc[c][m][0] = fmaf(-a.y, bb.y, acc[c][m][0]);
-              acc[c][m][1] = fmaf(a.x, bb.y, acc[c][m][1]);
-              acc[c][m][1] = fmaf(a.y, bb.x, acc[c][m][1]);
-            }
-          }
-        }
+      for (int u = 0; u < U; ++u) {
+        const int64_t k = k0 + lane + 64 * u;
+        const int64_t n = n0 + c;
+        bv[c][u] = (n < p.N && k < kend) ? skinny_load<MODE>(p.B, p.B2, bo + n * p.ldb + k)
+                                         : skinny_zero<MODE>();
       }
-    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int m = 0; m < kSkinnyRows; ++m) skinny_mac<MODE>(acc[c][m], av[m][u], bv[c][u]);
   }
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
