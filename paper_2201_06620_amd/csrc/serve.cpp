@@ -166,7 +166,9 @@ void worker_loop(rn_server* S) {
     // Retire finished requests.
     for (size_t i = 0; i < S->active.size();) {
       Request* r = S->active[i];
-      if (hipEventQuery(r->done_ev) == hipSuccess) {
+      const hipError_t q = hipEventQuery(r->done_ev);
+      if (q != hipErrorNotReady) {
+        // Done, or the stream failed: either way the request leaves.
         r->t_done = Clock::now();
         double amp[2] = {S->amp_host[2 * r->slot], S->amp_host[2 * r->slot + 1]};
         S->slot_busy[r->slot] = false;
@@ -174,7 +176,7 @@ void worker_loop(rn_server* S) {
         S->in_use -= r->footprint;
         S->active.erase(S->active.begin() + i);
         ++S->completed;
-        finish(S, r, RN_OK, amp);
+        finish(S, r, q == hipSuccess ? RN_OK : RN_ERR_HIP, q == hipSuccess ? amp : nullptr);
         progress = true;
       } else {
         ++i;

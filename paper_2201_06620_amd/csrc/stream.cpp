@@ -273,15 +273,21 @@ rn_status rn_block_tensordot_streamed(rn_handle h, const rn_tensor* A, const rn_
   auto hip_err = [](hipError_t err, const char* what) {
     return fail(RN_ERR_HIP, std::string(what) + ": " + hipGetErrorString(err));
   };
+  // Event record / wait, stopping at the first failure.
+  auto rec = [&](hipEvent_t ev, hipStream_t st) { if (e == hipSuccess) e = hipEventRecord(ev, st); };
+  auto wait = [&](hipStream_t st, hipEvent_t ev) {
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, ev, 0);
+  };
   // Copies start after whatever the caller queued before this call.
   if ((e = hipEventRecord(start, s)) != hipSuccess) return hip_err(e, "event record");
   if ((e = hipStreamWaitEvent(cs, start, 0)) != hipSuccess) return hip_err(e, "stream wait");
   // The first use of each slot must not wait on a stale record: mark all
   // free on the caller's stream now.
   for (int q = 0; q < 2; ++q) {
-    hipEventRecord(a_free[q], s);
-    hipEventRecord(b_free[q], s);
+    rec(a_free[q], s);
+    rec(b_free[q], s);
   }
+  if (e != hipSuccess) return hip_err(e, "event record");
   int64_t na = 0, nb = 0;  // A blocks and B blocks brought in so far
   for (int64_t r = 0; r < S.rows; ++r) {
     for (int64_t q = 0; q < S.pairs; ++q) {
@@ -293,8 +299,9 @@ rn_status rn_block_tensordot_streamed(rn_handle h, const rn_tensor* A, const rn_
       if ((e = hipMemcpyAsync(stA, ha + ai * S.blkA * S.es, S.blkA * S.es,
                               hipMemcpyHostToDevice, cs)) != hipSuccess)
         return hip_err(e, "copy A block");
-      hipEventRecord(a_ready[sa], cs);
-      hipStreamWaitEvent(s, a_ready[sa], 0);
+      rec(a_ready[sa], cs);
+      wait(s, a_ready[sa]);
+      if (e != hipSuccess) return hip_err(e, "copy event");
       const void* am = stA;
       const void* am2 = nullptr;
       if (S.permuteA) {
@@ -311,7 +318,7 @@ rn_status rn_block_tensordot_streamed(rn_handle h, const rn_tensor* A, const rn_
         if (e != hipSuccess) return hip_err(e, "permute A block");
         am = L.out;
         am2 = L.out2;
-        hipEventRecord(a_free[sa], s);
+        rec(a_free[sa], s);
       }
       for (int64_t c = 0; c < S.cols; ++c) {
         const int sb = (int)(nb & 1);
@@ -322,8 +329,9 @@ rn_status rn_block_tensordot_streamed(rn_handle h, const rn_tensor* A, const rn_
         if ((e = hipMemcpyAsync(stB, hb + bi * S.blkB * S.es, S.blkB * S.es,
                                 hipMemcpyHostToDevice, cs)) != hipSuccess)
           return hip_err(e, "copy B block");
-        hipEventRecord(b_ready[sb], cs);
-        hipStreamWaitEvent(s, b_ready[sb], 0);
+        rec(b_ready[sb], cs);
+        wait(s, b_ready[sb]);
+        if (e != hipSuccess) return hip_err(e, "copy event");
         const void* bm = stB;
         const void* bm2 = nullptr;
         if (S.permuteB) {
@@ -340,7 +348,7 @@ rn_status rn_block_tensordot_streamed(rn_handle h, const rn_tensor* A, const rn_
           if (e != hipSuccess) return hip_err(e, "permute B block");
           bm = L.out;
           bm2 = L.out2;
-          hipEventRecord(b_free[sb], s);
+          rec(b_free[sb], s);
         }
         // Output block (r, c): C's block index is row-major over
         // [A-free block coords | B-free block coords], i.e. r * cols + c.
@@ -361,7 +369,8 @@ rn_status rn_block_tensordot_streamed(rn_handle h, const rn_tensor* A, const rn_
         g.ccol.lo = 1;
         g.tile = tile;
         if ((e = launch_gemm(g, s, prof)) != hipSuccess) return hip_err(e, "complex GEMM");
-        if (!S.permuteB) hipEventRecord(b_free[sb], s);
+        if (!S.permuteB) rec(b_free[sb], s);
+        if (e != hipSuccess) return hip_err(e, "event record");
         if (q > 0) {
           int ev = prof->begin(2, s);
           e = launch_add_into(cblk, w + S.off_part, S.Mb * S.Nb, S.es, s);
@@ -369,7 +378,8 @@ rn_status rn_block_tensordot_streamed(rn_handle h, const rn_tensor* A, const rn_
           if (e != hipSuccess) return hip_err(e, "block add");
         }
       }
-      if (!S.permuteA) hipEventRecord(a_free[sa], s);
+      if (!S.permuteA) rec(a_free[sa], s);
+      if (e != hipSuccess) return hip_err(e, "event record");
     }
   }
   return RN_OK;
