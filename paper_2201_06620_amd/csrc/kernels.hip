@@ -149,6 +149,33 @@ __global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
     permute_tile<T, KIND, E, false>(p, t, tile, in_lo, out_lo, lds_lo);
 }
 
+// Job of global workgroup index w in a grouped launch: the largest i < n
+// with prefix[i] <= w (prefix is non-decreasing, prefix[0] = 0).  Every
+// wave searches on its own with two rounds of 64 parallel probes (n up to
+// 4096), so a workgroup pays two dependent loads instead of a
+// log2(n)-deep binary search through global memory.
+__device__ __forceinline__ int find_job(const int32_t* __restrict__ prefix, int n, int w) {
+  if (n <= 4096) {
+    const int lane = threadIdx.x & 63;
+    const int S = (n + 63) >> 6;
+    int idx = lane * S;
+    bool pred = idx < n && prefix[idx] <= w;
+    unsigned long long m = __ballot(pred);
+    const int base = (63 - __clzll(m)) * S;
+    idx = base + lane;
+    pred = lane < S && idx < n && prefix[idx] <= w;
+    m = __ballot(pred);
+    return base + (63 - __clzll(m));
+  }
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Many permutations in one launch: workgroup w moves one tile of job i,
 // prefix[i] <= w < prefix[i+1].  The job's parameters are copied into LDS
 // first: the tile code reads them many times, and from the table in global
@@ -166,13 +193,8 @@ __global__ __launch_bounds__(256) void permute_grouped(PermTable g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ PermParams sp;
   T* tile = reinterpret_cast<T*>(smem_raw);
-  int lo = 0, hi = g.n - 1;
   const int bid = blockIdx.x;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (g.prefix[mid] <= bid) lo = mid;
-    else hi = mid - 1;
-  }
+  const int lo = find_job(g.prefix, g.n, bid);
   if (threadIdx.x < sizeof(PermParams) / 4)
     reinterpret_cast<uint32_t*>(&sp)[threadIdx.x] =
         reinterpret_cast<const uint32_t*>(&g.jobs[lo])[threadIdx.x];
@@ -214,6 +236,16 @@ static void perm_setup(const PermLaunch& L, PermParams& p) {
     for (int o = 0; o < R; ++o) ord[o] = o;
     std::sort(ord, ord + R, [&](int a, int b) { return L.perm.src[a] < L.perm.src[b]; });
     for (int q = 0; q < tlow; ++q) inS[ord[q]] = true;
+    // Where the low input and output bits overlap, grow the tile with the
+    // next input bits up to 2 * tlow bits, so it is never a sliver (tiny
+    // tiles made a batch of many permutations dispatch-bound).
+    int nsel = 0;
+    for (int o = 0; o < R; ++o) nsel += inS[o] ? 1 : 0;
+    for (int q = tlow; q < R && nsel < 2 * tlow; ++q)
+      if (!inS[ord[q]]) {
+        inS[ord[q]] = true;
+        ++nsel;
+      }
   }
   int ls[16], ss[16], nS = 0, nO = 0;
   for (int o = 0; o < R; ++o) {
@@ -2354,13 +2386,7 @@ struct GroupTable {
 };
 
 __device__ __forceinline__ int group_find(const GroupTable& g, int bid) {
-  int lo = 0, hi = g.n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (g.prefix[mid] <= bid) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
+  return find_job(g.prefix, g.n, bid);
 }
 
 #define RN_GEMM_ENTRY(NAME)                                                              \
@@ -2859,13 +2885,8 @@ template <int MODE>
 __global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
   __shared__ int32_t koa[kDirectMaxK];
   __shared__ int32_t kob[kDirectMaxK];
-  int lo = 0, hi = g.n - 1;
   const int bid = blockIdx.x;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (g.prefix[mid] <= bid) lo = mid;
-    else hi = mid - 1;
-  }
+  const int lo = find_job(g.prefix, g.n, bid);
   // The step's bit maps are read per output; copy them into LDS once.
   __shared__ __align__(16) uint32_t d_raw[sizeof(DirectStep) / 4];
   if (threadIdx.x < sizeof(DirectStep) / 4)

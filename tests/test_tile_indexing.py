@@ -134,3 +134,38 @@ def test_guard_matters():
     unguarded = [(tid // (bk // per)) for tid in range(256)]
     assert max(unguarded) >= rows
     assert max(r for r, _ in thread_loads(rows, bk, per)) < rows
+
+
+def find_job_model(prefix, n, w):
+    """The grouped launches' two-round search (64 lanes per round)."""
+    if n <= 4096:
+        s = (n + 63) >> 6
+        lanes = [j for j in range(64) if j * s < n and prefix[j * s] <= w]
+        base = max(lanes) * s
+        lanes = [j for j in range(64) if j < s and base + j < n and prefix[base + j] <= w]
+        return base + max(lanes)
+    lo, hi = 0, n - 1
+    while lo < hi:
+        mid = (lo + hi + 1) >> 1
+        if prefix[mid] <= w:
+            lo = mid
+        else:
+            hi = mid - 1
+    return lo
+
+
+def test_find_job_matches_definition():
+    import random
+    rnd = random.Random(7)
+    for n in [1, 2, 3, 63, 64, 65, 127, 500, 4095, 4096, 4097, 6000]:
+        sizes = [rnd.choice([0, 0, 1, 2, 5, 40]) for _ in range(n)]
+        sizes[-1] = max(sizes[-1], 1)
+        prefix = [0]
+        for c in sizes:
+            prefix.append(prefix[-1] + c)
+        total = prefix[-1]
+        for w in sorted(set([0, total - 1] + [rnd.randrange(total) for _ in range(50)])):
+            want = max(i for i in range(n) if prefix[i] <= w)
+            got = find_job_model(prefix, n, w)
+            assert got == want
+            assert prefix[got] <= w < prefix[got + 1]
