@@ -2283,7 +2283,7 @@ __device__ __forceinline__ void skinny_mac(R* acc, const E& a, const E& bb) {
   }
 }
 
-template <int MODE>
+template <int MODE, int MR>
 __device__ __forceinline__ void cgemm_skinny_body(const GemmParams& p, int tn, int split, int b) {
   using R = typename std::conditional<MODE == RN_FP64, double, float>::type;
   using E = typename SkinnyElem<MODE>::T;
@@ -2297,18 +2297,18 @@ __device__ __forceinline__ void cgemm_skinny_body(const GemmParams& p, int tn, i
   const int64_t ao = batch_off(p.a_bs, p.nbb, b), bo = batch_off(p.b_bs, p.nbb, b);
   const int M = (int)p.M;
   const int64_t n0 = int64_t(tn) * kSkinnyCols + wave * CPW;
-  R acc[CPW][kSkinnyRows][NT];
+  R acc[CPW][MR][NT];
 #pragma unroll
   for (int c = 0; c < CPW; ++c)
 #pragma unroll
-    for (int m = 0; m < kSkinnyRows; ++m)
+    for (int m = 0; m < MR; ++m)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[c][m][t] = R(0);
 
   for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
-    E av[kSkinnyRows][U];
+    E av[MR][U];
 #pragma unroll
-    for (int m = 0; m < kSkinnyRows; ++m)
+    for (int m = 0; m < MR; ++m)
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t k = k0 + lane + 64 * u;
@@ -2330,13 +2330,13 @@ __device__ __forceinline__ void cgemm_skinny_body(const GemmParams& p, int tn, i
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int m = 0; m < kSkinnyRows; ++m) skinny_mac<MODE>(acc[c][m], av[m][u], bv[c][u]);
+        for (int m = 0; m < MR; ++m) skinny_mac<MODE>(acc[c][m], av[m][u], bv[c][u]);
   }
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
     const int64_t n = n0 + c;
 #pragma unroll
-    for (int m = 0; m < kSkinnyRows; ++m) {
+    for (int m = 0; m < MR; ++m) {
       if (m >= M) break;
       R t[NT];
 #pragma unroll
@@ -2354,9 +2354,27 @@ __device__ __forceinline__ void cgemm_skinny_body(const GemmParams& p, int tn, i
   }
 }
 
-template <int MODE>
+template <int MODE, int MR>
 __global__ __launch_bounds__(256) void cgemm_skinny(GemmParams p) {
-  cgemm_skinny_body<MODE>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+  cgemm_skinny_body<MODE, MR>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int MODE>
+static void launch_skinny_m(int mr, dim3 grid, const GemmParams& p, hipStream_t s) {
+  switch (mr) {
+    case 1: cgemm_skinny<MODE, 1><<<grid, 256, 0, s>>>(p); break;
+    case 2: cgemm_skinny<MODE, 2><<<grid, 256, 0, s>>>(p); break;
+    case 4: cgemm_skinny<MODE, 4><<<grid, 256, 0, s>>>(p); break;
+    default: cgemm_skinny<MODE, 8><<<grid, 256, 0, s>>>(p); break;
+  }
+}
+static void launch_skinny(rn_mode mode, int mr, dim3 grid, const GemmParams& p, hipStream_t s) {
+  switch (mode) {
+    case RN_FP64: launch_skinny_m<RN_FP64>(mr, grid, p, s); break;
+    case RN_FP32_3M: launch_skinny_m<RN_FP32_3M>(mr, grid, p, s); break;
+    case RN_BF16X3: launch_skinny_m<RN_BF16X3>(mr, grid, p, s); break;
+    default: launch_skinny_m<RN_FP32_4M>(mr, grid, p, s); break;
+  }
 }
 
 // Orient a skinny problem so that its short side is M: C^T = B A^T runs
@@ -2464,11 +2482,30 @@ __global__ __launch_bounds__(256) void cgemm_small_grouped(GroupTable g) {
   cgemm_small_body<MODE>(p, blockIdx.x - g.prefix[i], 0, 0);
 }
 
-template <int MODE>
+template <int MODE, int MR>
 __global__ __launch_bounds__(256) void cgemm_skinny_grouped(GroupTable g) {
   const int i = group_find(g, blockIdx.x);
   const GemmParams p = g.probs[i];
-  cgemm_skinny_body<MODE>(p, blockIdx.x - g.prefix[i], 0, 0);
+  cgemm_skinny_body<MODE, MR>(p, blockIdx.x - g.prefix[i], 0, 0);
+}
+
+template <int MODE>
+static void launch_skinny_grouped_m(int mr, dim3 grid, const GroupTable& t, hipStream_t s) {
+  switch (mr) {
+    case 1: cgemm_skinny_grouped<MODE, 1><<<grid, 256, 0, s>>>(t); break;
+    case 2: cgemm_skinny_grouped<MODE, 2><<<grid, 256, 0, s>>>(t); break;
+    case 4: cgemm_skinny_grouped<MODE, 4><<<grid, 256, 0, s>>>(t); break;
+    default: cgemm_skinny_grouped<MODE, 8><<<grid, 256, 0, s>>>(t); break;
+  }
+}
+static void launch_skinny_grouped(rn_mode mode, int mr, dim3 grid, const GroupTable& t,
+                                  hipStream_t s) {
+  switch (mode) {
+    case RN_FP64: launch_skinny_grouped_m<RN_FP64>(mr, grid, t, s); break;
+    case RN_FP32_3M: launch_skinny_grouped_m<RN_FP32_3M>(mr, grid, t, s); break;
+    case RN_BF16X3: launch_skinny_grouped_m<RN_BF16X3>(mr, grid, t, s); break;
+    default: launch_skinny_grouped_m<RN_FP32_4M>(mr, grid, t, s); break;
+  }
 }
 
 // Split-K reduction: C = sum over splits of the partials, in ascending split
@@ -2510,15 +2547,17 @@ static const TileCfg kF32Tiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 32, 16},
                                     {128, 128, 8}, {128, 64, 16}, {128, 128, 8},
                                     {128, 128, 16}, {128, 128, 16}, {128, 64, 16},
                                     {128, 64, 8},   {128, 128, 8},  {128, 128, 16},
+                                    {1, 16, 64},    {2, 16, 64},    {4, 16, 64},
                                     {8, 16, 64}};
 static const TileCfg kF64Tiles[] = {{1, 1, 1},   {128, 64, 8}, {64, 32, 8}, {128, 64, 8},
                                     {64, 64, 8},  {128, 64, 8}, {64, 128, 8}, {64, 64, 8},
-                                    {8, 16, 64}};
+                                    {1, 16, 64},  {2, 16, 64},  {4, 16, 64},  {8, 16, 64}};
 static const TileCfg kBF16Tiles[] = {{1, 1, 1},     {128, 64, 16}, {64, 32, 16},
                                      {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
                                      {128, 128, 8}, {256, 64, 8},  {128, 128, 16},
-                                     {8, 16, 64}};
-static const TileCfg k3MTiles[] = {{1, 1, 1}, {128, 64, 16}, {64, 64, 16}, {8, 16, 64}};
+                                     {1, 16, 64},   {2, 16, 64},   {4, 16, 64},   {8, 16, 64}};
+static const TileCfg k3MTiles[] = {{1, 1, 1},   {128, 64, 16}, {64, 64, 16},
+                                   {1, 16, 64}, {2, 16, 64},   {4, 16, 64},  {8, 16, 64}};
 
 static const TileCfg& tile_of(rn_mode mode, int t) {
   if (mode == RN_FP64) return kF64Tiles[t];
@@ -2533,9 +2572,21 @@ static const TileCfg& tile_of(rn_mode mode, int t) {
 // tiles -- measured fastest on large pairs).
 static int tile_count_of(rn_mode mode);
 
+// The last four tiles of every mode are the skinny kernel for at most 1, 2,
+// 4 and 8 rows on the short output side; 0 for any other tile.
+static int skinny_rows(rn_mode mode, int tile) {
+  const int first = tile_count_of(mode) - 4;
+  return (tile >= first && tile < first + 4) ? (1 << (tile - first)) : 0;
+}
+static int skinny_tile(rn_mode mode, int64_t rows) {
+  int t = tile_count_of(mode) - 4;
+  while (skinny_rows(mode, t) < rows) ++t;
+  return t;
+}
+
 static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
   if (M * N * K <= (int64_t(1) << 15)) return 0;
-  if (std::min(M, N) <= kSkinnyRows) return tile_count_of(mode) - 1;
+  if (std::min(M, N) <= kSkinnyRows) return skinny_tile(mode, std::min(M, N));
   if (M < 16 || N < 8) return 0;
   if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) {
     if (mode == RN_FP32_4M) return N >= 128 ? 14 : 11;
@@ -2550,7 +2601,7 @@ int choose_splitk(rn_mode mode, int64_t M, int64_t N, int64_t K, int64_t batch) 
   int t = choose_tile(mode, M, N, K);
   const TileCfg& c = tile_of(mode, t);
   int64_t tiles = ((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn) * batch;
-  if (t == tile_count_of(mode) - 1)  // skinny: one workgroup per 16 long-side entries
+  if (skinny_rows(mode, t))  // skinny: one workgroup per 16 long-side entries
     tiles = ((std::max(M, N) + kSkinnyCols - 1) / kSkinnyCols) * batch;
   int64_t minchunk = (t == 0) ? 64 : 4 * c.bk;
   int s = 1;
@@ -2596,11 +2647,11 @@ static int tile_count_of(rn_mode mode) {
 
 int gemm_tile_count(rn_mode mode) { return tile_count_of(mode); }
 
-// The last tile of every mode is the skinny kernel, for problems whose
-// shorter output side has at most kSkinnyRows entries.
+// The skinny tiles run problems whose shorter output side has at most their
+// row count.
 bool gemm_tile_valid(rn_mode mode, int tile, int64_t M, int64_t N) {
   if (tile < 0 || tile >= tile_count_of(mode)) return false;
-  if (tile == tile_count_of(mode) - 1) return std::min(M, N) <= kSkinnyRows;
+  if (const int mr = skinny_rows(mode, tile)) return std::min(M, N) <= mr;
   return true;
 }
 
@@ -2618,19 +2669,12 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
   const TileCfg& c = tile_of(g.mode, tile);
   const unsigned nbatch = 1u << g.nbb;
   const int ev = prof ? prof->begin(1, s) : -1;
-  if (tile == tile_count_of(g.mode) - 1) {
+  if (const int mr = skinny_rows(g.mode, tile)) {
     skinny_orient(p);
     p.tiles_m = 1;
     p.tiles_n = (int)((p.N + kSkinnyCols - 1) / kSkinnyCols);
     dim3 grid((unsigned)p.tiles_n, (unsigned)g.splitk, nbatch);
-    if (g.mode == RN_FP64)
-      cgemm_skinny<RN_FP64><<<grid, 256, 0, s>>>(p);
-    else if (g.mode == RN_FP32_3M)
-      cgemm_skinny<RN_FP32_3M><<<grid, 256, 0, s>>>(p);
-    else if (g.mode == RN_BF16X3)
-      cgemm_skinny<RN_BF16X3><<<grid, 256, 0, s>>>(p);
-    else
-      cgemm_skinny<RN_FP32_4M><<<grid, 256, 0, s>>>(p);
+    launch_skinny(g.mode, mr, grid, p, s);
   } else if (tile == 0) {
     dim3 grid((unsigned)((g.M * g.N + 255) / 256), (unsigned)g.splitk, nbatch);
     if (g.mode == RN_FP64)
@@ -2756,7 +2800,7 @@ size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
     ps[i].splitk = 1;
     ps[i].kchunk = probs[i].K;
     int64_t blocks;
-    if (tile == tile_count_of(G.mode) - 1) {
+    if (skinny_rows(G.mode, tile)) {
       skinny_orient(ps[i]);
       ps[i].tiles_m = 1;
       ps[i].tiles_n = (int)((ps[i].N + kSkinnyCols - 1) / kSkinnyCols);
@@ -2788,13 +2832,8 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
   t.n = G.n;
   const dim3 grid((unsigned)G.blocks);
   const int tile = G.tile;
-  if (tile == tile_count_of(G.mode) - 1) {
-    switch (G.mode) {
-      case RN_FP64: cgemm_skinny_grouped<RN_FP64><<<grid, 256, 0, s>>>(t); break;
-      case RN_FP32_3M: cgemm_skinny_grouped<RN_FP32_3M><<<grid, 256, 0, s>>>(t); break;
-      case RN_BF16X3: cgemm_skinny_grouped<RN_BF16X3><<<grid, 256, 0, s>>>(t); break;
-      default: cgemm_skinny_grouped<RN_FP32_4M><<<grid, 256, 0, s>>>(t); break;
-    }
+  if (const int mr = skinny_rows(G.mode, tile)) {
+    launch_skinny_grouped(G.mode, mr, grid, t, s);
     return hipGetLastError();
   }
   switch (G.mode) {
