@@ -1801,6 +1801,215 @@ constexpr size_t big_lds_bytes() {
   return size_t(2) * (WM * TM * 32 + WN * TN * 32) * (2 * BK + 4) * sizeof(float);
 }
 
+// Large-tile FP32-3M (Gauss): T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi)
+// as three real MFMA GEMMs whose K is the complex K (lane / 32 picks the
+// complex k of an instruction).  Each LDS row holds three planes (re, im,
+// re + im; the sums formed once while staging), each ordered [even k | odd
+// k], so the values one lane needs for four consecutive instructions are
+// adjacent and come in one 128-bit read; rows padded to an odd number of
+// 16-byte chunks.  Interior tiles use the pinned fast path of the FP32 large
+// tile.
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f32_3mbig_body(const GemmParams& p, int tm, int tn,
+                                                     int split, int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK % 8 == 0, "four instructions (eight complex k) per 128-bit read");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 32;
+  constexpr int HB = BK / 2;
+  constexpr int LDR = 3 * BK + 4;  // floats per row: 3 planes + pad (odd chunk count)
+  constexpr int AV = BM * BK / 2;  // float4 loads (two complex) per stage
+  constexpr int BV = BN * BK / 2;
+  constexpr int NA = (AV + 255) / 256;
+  constexpr int NB = (BV + 255) / 256;
+  __shared__ __align__(16) float As0[2 * BM * LDR];
+  __shared__ __align__(16) float Bs0[2 * BN * LDR];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const float2* __restrict__ Ag =
+      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const float2* __restrict__ Bg =
+      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
+
+  float4 ra[NA], rb[NB];
+  auto gload_fast = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (AV % 256 == 0 || idx < AV) {  // threads past the tile load nothing
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        ra[j] = *reinterpret_cast<const float4*>(Ag + (row0 + r) * p.lda + k0 + c);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (BV % 256 == 0 || idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        rb[j] = *reinterpret_cast<const float4*>(Bg + (col0 + r) * p.ldb + k0 + c);
+      }
+    }
+  };
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < AV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = row0 + r, gk = k0 + c;
+        if (gr < p.M) {
+          const float2* src = Ag + gr * p.lda + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (idx < BV) {
+        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
+        int64_t gr = col0 + r, gk = k0 + c;
+        if (gr < p.N) {
+          const float2* src = Bg + gr * p.ldb + gk;
+          if (gk + 1 < kend) {
+            v = *reinterpret_cast<const float4*>(src);
+          } else if (gk < kend) {
+            float2 t = src[0];
+            v.x = t.x;
+            v.y = t.y;
+          }
+        }
+      }
+      rb[j] = v;
+    }
+  };
+  // Complex k = c (even) and c + 1 go to index c / 2 of the even and odd
+  // halves of each plane.
+  auto put = [](float* row, int c, const float4& v) {
+    const int e = c >> 1;
+    row[e] = v.x;
+    row[HB + e] = v.z;
+    row[BK + e] = v.y;
+    row[BK + HB + e] = v.w;
+    row[2 * BK + e] = v.x + v.y;
+    row[2 * BK + HB + e] = v.z + v.w;
+  };
+  auto sstore = [&](int buf) {
+    float* As = As0 + buf * BM * LDR;
+    float* Bs = Bs0 + buf * BN * LDR;
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      int idx = tid + 256 * j;
+      if (AV % 256 == 0 || idx < AV) put(As + (idx / (BK / 2)) * LDR, (idx % (BK / 2)) * 2, ra[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      int idx = tid + 256 * j;
+      if (BV % 256 == 0 || idx < BV) put(Bs + (idx / (BK / 2)) * LDR, (idx % (BK / 2)) * 2, rb[j]);
+    }
+  };
+
+  v16f t1[TM][TN], t2[TM][TN], t3[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) t1[i][j][e] = t2[i][j][e] = t3[i][j][e] = 0.f;
+
+  const int kh = lane >> 5;
+  const int aoff = (wm * TM * 32 + (lane & 31)) * LDR + kh * HB;
+  const int boff = (wn * TN * 32 + (lane & 31)) * LDR + kh * HB;
+
+  auto mainloop = [&](auto tag) {
+    constexpr bool FAST = decltype(tag)::value;
+    if (nk > 0) {
+      if constexpr (FAST) gload_fast(kbeg); else gload(kbeg);
+      sstore(0);
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+      const int buf = it & 1;
+      const float* As = As0 + buf * BM * LDR;
+      const float* Bs = Bs0 + buf * BN * LDR;
+      if constexpr (FAST) {
+        gload_fast(kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
+        __builtin_amdgcn_sched_barrier(0);
+      } else if (it + 1 < nk) {
+        gload(kbeg + int64_t(it + 1) * BK);
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < HB; s4 += 4) {
+        float4 ar[TM], ai[TM], as[TM], br[TN], bi[TN], bs[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          const float* a = As + aoff + i * 32 * LDR + s4;
+          ar[i] = *reinterpret_cast<const float4*>(a);
+          ai[i] = *reinterpret_cast<const float4*>(a + BK);
+          as[i] = *reinterpret_cast<const float4*>(a + 2 * BK);
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const float* v = Bs + boff + j * 32 * LDR + s4;
+          br[j] = *reinterpret_cast<const float4*>(v);
+          bi[j] = *reinterpret_cast<const float4*>(v + BK);
+          bs[j] = *reinterpret_cast<const float4*>(v + 2 * BK);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              auto pick = [q](const float4& v) {
+                return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
+              };
+              t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pick(ar[i]), pick(br[j]), t1[i][j],
+                                                              0, 0, 0);
+              t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pick(ai[i]), pick(bi[j]), t2[i][j],
+                                                              0, 0, 0);
+              t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pick(as[i]), pick(bs[j]), t3[i][j],
+                                                              0, 0, 0);
+            }
+      }
+      if (FAST || it + 1 < nk) sstore(buf ^ 1);
+      __syncthreads();
+    }
+  };
+  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
+        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
+        const float a = t1[i][j][e], c = t2[i][j][e], d = t3[i][j][e];
+        store_out<float>(p, b, split, row, col, 0, a - c);
+        store_out<float>(p, b, split, row, col, 1, (d - a) - c);
+      }
+}
+
 // FP64 counterpart: v_mfma_f64_16x16x4_f64, 16 complex columns per tile
 // pair, 2 complex k per instruction (real k = lane / 16: complex k lane / 32,
 // half (lane / 16) & 1).
@@ -2447,6 +2656,7 @@ RN_GEMM_ENTRY(cgemm_bf16x3_ri)
 RN_GEMM_ENTRY(cgemm_f32_rp)
 RN_GEMM_ENTRY(cgemm_f64_rp)
 RN_GEMM_ENTRY(cgemm_f32_big)
+RN_GEMM_ENTRY(cgemm_f32_3mbig)
 RN_GEMM_ENTRY_OCC(cgemm_f64_big, 2)
 
 // The large FP32 tiles take more than 64 KiB of dynamic LDS; raise each
@@ -2556,8 +2766,9 @@ static const TileCfg kBF16Tiles[] = {{1, 1, 1},     {128, 64, 16}, {64, 32, 16},
                                      {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
                                      {128, 128, 8}, {256, 64, 8},  {128, 128, 16},
                                      {1, 16, 64},   {2, 16, 64},   {4, 16, 64},   {8, 16, 64}};
-static const TileCfg k3MTiles[] = {{1, 1, 1},   {128, 64, 16}, {64, 64, 16},
-                                   {1, 16, 64}, {2, 16, 64},   {4, 16, 64},  {8, 16, 64}};
+static const TileCfg k3MTiles[] = {{1, 1, 1},   {128, 64, 16}, {64, 64, 16},  {128, 64, 16},
+                                   {64, 128, 16}, {1, 16, 64}, {2, 16, 64},  {4, 16, 64},
+                                   {8, 16, 64}};
 
 static const TileCfg& tile_of(rn_mode mode, int t) {
   if (mode == RN_FP64) return kF64Tiles[t];
@@ -2591,8 +2802,7 @@ static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
   if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) {
     if (mode == RN_FP32_4M) return N >= 128 ? 14 : 11;
     if (mode == RN_BF16X3) return N >= 128 ? 8 : 5;
-    if (mode == RN_FP64) return 3;
-    return 1;
+    return 3;  // FP64 planar tile, FP32-3M large tile
   }
   return 2;
 }
@@ -2707,8 +2917,12 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
     } else if (g.mode == RN_FP32_3M) {
       if (tile == 1)
         cgemm_f32_3m<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 2)
         cgemm_f32_3m<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
+      else if (tile == 3)
+        cgemm_f32_3mbig<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_f32_3mbig<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(p);
     } else if (g.mode == RN_BF16X3) {
       if (tile == 1)
         cgemm_bf16x3<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
@@ -2856,7 +3070,9 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
     case RN_FP32_3M:
       if (tile == 0) cgemm_small_grouped<RN_FP32_3M><<<grid, 256, 0, s>>>(t);
       else if (tile == 1) cgemm_f32_3m_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      else cgemm_f32_3m_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 2) cgemm_f32_3m_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 3) cgemm_f32_3mbig_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
+      else cgemm_f32_3mbig_grouped<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(t);
       break;
     case RN_BF16X3:
       if (tile == 0) cgemm_small_grouped<RN_BF16X3><<<grid, 256, 0, s>>>(t);

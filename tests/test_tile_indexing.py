@@ -169,3 +169,31 @@ def test_find_job_matches_definition():
             got = find_job_model(prefix, n, w)
             assert got == want
             assert prefix[got] <= w < prefix[got + 1]
+
+
+def test_fp32_3m_large_tiles():
+    shapes = instances("cgemm_f32_3mbig")
+    assert shapes
+    for wm_, wn_, tm, tn, bk in shapes:
+        bm, bn, hb, ldr = wm_ * tm * 32, wn_ * tn * 32, bk // 2, 3 * bk + 4
+        assert ldr % 4 == 0 and (ldr // 4) % 2 == 1  # odd number of 16-byte chunks
+        for rows in (bm, bn):
+            for r, c in thread_loads(rows, bk, 2):
+                assert r < rows and c + 1 < bk and c % 2 == 0
+                e = c >> 1
+                for o in (e, hb + e, bk + e, bk + hb + e, 2 * bk + e, 2 * bk + hb + e):
+                    assert 0 <= o < 3 * bk
+        for lane in range(64):
+            kh = lane >> 5
+            for w in range(4):
+                wm, wn = w // wn_, w % wn_
+                for s4 in range(0, hb, 4):
+                    for plane in range(3):
+                        for i in range(tm):
+                            row = wm * tm * 32 + lane % 32 + i * 32
+                            o = row * ldr + kh * hb + s4 + plane * bk
+                            assert o % 4 == 0 and row * ldr <= o and o + 3 < (row + 1) * ldr
+                        for j in range(tn):
+                            row = wn * tn * 32 + lane % 32 + j * 32
+                            o = row * ldr + kh * hb + s4 + plane * bk
+                            assert o % 4 == 0 and row * ldr <= o and o + 3 < (row + 1) * ldr
