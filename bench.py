@@ -46,14 +46,14 @@ def percentile(xs, q):
 
 def kernel_sha():
     """Hash of the source the profiled GEMM is built from: the shared GEMM
-    parameter, output-map and tile-order code, the large FP32 tile body and
-    the entry-point macro.  A change there invalidates the stored counters."""
+    parameter, output-map and tile-order code, the direct-to-LDS FP32 tile
+    body and the entry-point macros.  A change there invalidates the stored counters."""
     with open(os.path.join(ROOT, "paper_2201_06620_amd", "csrc", "kernels.hip")) as f:
         src = f.read()
     parts = []
     for start, end in (("struct GemmParams {", "// FP32, 4M embedding"),
-                       ("void cgemm_f32_big_body(", "// Dynamic LDS bytes of the large FP32 tile."),
-                       ("#define RN_GEMM_ENTRY(NAME)", "// Entry points whose register use")):
+                       ("__device__ __forceinline__ int dl_swz(", "// Large-tile FP32-3M (Gauss)"),
+                       ("#define RN_GEMM_ENTRY(NAME)", "RN_GEMM_ENTRY(cgemm_f32_4m)")):
         i = src.find(start)
         j = src.find(end, i + 1)
         if i < 0 or j < 0:
@@ -649,7 +649,7 @@ def main() -> int:
                    "M": M, "N": N, "K": K, "useful_flops_per_step": flops},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
-                     "kernel": "FP32-4M complex GEMM (cgemm_f32_big<1,4,4,1,16>, default large tile)",
+                     "kernel": "FP32-4M complex GEMM (cgemm_f32_dl<1,4,4,1,16>, default large tile, direct-to-LDS staging)",
                      "kernel_ms": gemm_ms},
         "cpu_baseline": cpu,
         "modes": modes,

@@ -1801,6 +1801,223 @@ constexpr size_t big_lds_bytes() {
   return size_t(2) * (WM * TM * 32 + WN * TN * 32) * (2 * BK + 4) * sizeof(float);
 }
 
+// Large-tile FP32-4M with direct-to-LDS staging: interior tiles copy each
+// 16-byte chunk (two complex) of A and B from global memory straight into
+// LDS (global_load_lds_dwordx4: a wave writes 64 consecutive chunks), so no
+// VGPRs hold the next stage and no LDS stores are issued.  LDS rows keep the
+// interleaved (re, im) order of the operands, 8 chunks per row (16 complex
+// k), unpadded; logical chunk c of row r sits at chunk c ^ dl_swz(r), so the
+// 128-bit fragment reads of 8 (or 16) consecutive rows fall on distinct bank
+// groups.  A lane reads chunk 2g + kh of its row (kh = lane / 32) and feeds
+// its four floats to four MFMAs; the B lane that meets it in an instruction
+// reads the same logical chunk of its column and supplies b_r or -b_i (real
+// accumulator) and b_i or b_r (imaginary accumulator), i.e. the 4M
+// embedding with the real k of an instruction taken from consecutive floats.
+// Edge tiles stage through registers into the same layout, zero-filled.
+__device__ __forceinline__ int dl_swz(int r) { return (r ^ (r >> 3)) & 7; }
+
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f32_dl_body(const GemmParams& p, int tm, int tn,
+                                                  int split, int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK == 16, "eight 16-byte chunks per LDS row");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 32;  // complex columns
+  constexpr int CPR = BK / 2;       // chunks per row
+  constexpr int AV = BM * CPR;      // chunks per stage
+  constexpr int BV = BN * CPR;
+  static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
+  constexpr int NA = AV / 256;
+  constexpr int NB = BV / 256;
+  // One array per buffer: with the buffer known at compile time in every
+  // stage, the compiler can tell the copies into one buffer from the
+  // fragment reads of the other and does not wait for the copies first.
+  __shared__ __align__(16) float4 Ad0[AV], Ad1[AV];
+  __shared__ __align__(16) float4 Bd0[BV], Bd1[BV];
+  auto abuf = [&](auto t) -> float4* { if constexpr (decltype(t)::value) return Ad1; else return Ad0; };
+  auto bbuf = [&](auto t) -> float4* { if constexpr (decltype(t)::value) return Bd1; else return Bd0; };
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const float2* __restrict__ Ag =
+      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const float2* __restrict__ Bg =
+      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
+
+  // Slot s = 256 j + tid of a stage: row s / 8, stored chunk s % 8, which
+  // holds logical chunk (s % 8) ^ dl_swz(row).
+  auto dma = [&](auto buf, int64_t k0) {
+    float4* As = abuf(buf);
+    float4* Bs = bbuf(buf);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
+      __builtin_amdgcn_global_load_lds(
+          Ag + (row0 + r) * p.lda + k0 + 2 * c,
+          (__attribute__((address_space(3))) void*)(As + 256 * j + 64 * wave), 16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
+      __builtin_amdgcn_global_load_lds(
+          Bg + (col0 + r) * p.ldb + k0 + 2 * c,
+          (__attribute__((address_space(3))) void*)(Bs + 256 * j + 64 * wave), 16, 0, 0);
+    }
+  };
+  float4 ra[NA], rb[NB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = s & 7;
+      const int64_t gr = row0 + r, gk = k0 + 2 * c;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gr < p.M) {
+        const float2* src = Ag + gr * p.lda + gk;
+        if (gk + 1 < kend) {
+          v = *reinterpret_cast<const float4*>(src);
+        } else if (gk < kend) {
+          const float2 t = src[0];
+          v.x = t.x;
+          v.y = t.y;
+        }
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = s & 7;
+      const int64_t gr = col0 + r, gk = k0 + 2 * c;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gr < p.N) {
+        const float2* src = Bg + gr * p.ldb + gk;
+        if (gk + 1 < kend) {
+          v = *reinterpret_cast<const float4*>(src);
+        } else if (gk < kend) {
+          const float2 t = src[0];
+          v.x = t.x;
+          v.y = t.y;
+        }
+      }
+      rb[j] = v;
+    }
+  };
+  auto sstore = [&](auto buf) {
+    float4* As = abuf(buf);
+    float4* Bs = bbuf(buf);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s >> 3;
+      As[r * CPR + ((s & 7) ^ dl_swz(r))] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s >> 3;
+      Bs[r * CPR + ((s & 7) ^ dl_swz(r))] = rb[j];
+    }
+  };
+
+  v16f cr[TM][TN], ci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
+
+  const int kh = lane >> 5;
+  const int arow = wm * TM * 32 + (lane & 31);
+  const int brow = wn * TN * 32 + (lane & 31);
+
+  // One K stage computed from buffer CUR while the next stage fills the
+  // other buffer.
+  auto stage = [&](auto fast, auto cur, int it) {
+    constexpr bool FAST = decltype(fast)::value;
+    constexpr bool CUR = decltype(cur)::value;
+    const float4* As = abuf(cur);
+    const float4* Bs = bbuf(cur);
+    // Fast path: always fill the other buffer (the last stage copies itself
+    // again), so the stage has no branch.
+    if constexpr (FAST) {
+      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (it + 1 < nk) {
+      gload(kbeg + int64_t(it + 1) * BK);
+    }
+#pragma unroll
+    for (int g = 0; g < CPR / 2; ++g) {
+      float4 a4[TM], b4[TN], n4[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = arow + 32 * i;
+        a4[i] = As[r * CPR + ((2 * g + kh) ^ dl_swz(r))];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int r = brow + 32 * j;
+        b4[j] = Bs[r * CPR + ((2 * g + kh) ^ dl_swz(r))];
+        n4[j] = make_float4(b4[j].x, -b4[j].y, b4[j].z, -b4[j].w);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            const float av = q == 0 ? a4[i].x : q == 1 ? a4[i].y : q == 2 ? a4[i].z : a4[i].w;
+            const float bv = q == 0 ? n4[j].x : q == 1 ? n4[j].y : q == 2 ? n4[j].z : n4[j].w;
+            const float cv = q == 0 ? b4[j].y : q == 1 ? b4[j].x : q == 2 ? b4[j].w : b4[j].z;
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, cv, ci[i][j], 0, 0, 0);
+          }
+    }
+    if constexpr (FAST) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
+    } else if (it + 1 < nk) {
+      sstore(BoolTag<!CUR>{});
+    }
+    __syncthreads();
+  };
+
+  auto mainloop = [&](auto fast) {
+    constexpr bool FAST = decltype(fast)::value;
+    if (nk > 0) {
+      if constexpr (FAST) {
+        dma(BoolTag<false>{}, kbeg);
+        __builtin_amdgcn_s_waitcnt(0);
+      } else {
+        gload(kbeg);
+        sstore(BoolTag<false>{});
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; it += 2) {
+      stage(fast, BoolTag<false>{}, it);
+      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
+    }
+  };
+  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
+        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
+        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
+        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
+      }
+}
+
 // Large-tile FP32-3M (Gauss): T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi)
 // as three real MFMA GEMMs whose K is the complex K (lane / 32 picks the
 // complex k of an instruction).  Each LDS row holds three planes (re, im,
@@ -2331,6 +2548,186 @@ constexpr size_t big64_lds_bytes() {
   return size_t(2) * (WM * TM * 16 + WN * TN * 16) * (2 * BK + 2) * sizeof(double);
 }
 
+// Large-tile FP64 with direct-to-LDS staging, as the FP32 direct-LDS tile:
+// one 16-byte chunk is one complex (re, im), 8 chunks (BK = 8 complex k)
+// per LDS row, unpadded and XOR-swizzled by dl_swz.  In
+// v_mfma_f64_16x16x4f64 lane / 16 picks the real k; here it picks the
+// complex k (chunk 4g + lane / 16) and the two floats of the chunk feed two
+// instructions: a_r with b_r (real) and b_i (imaginary), then a_i with -b_i
+// and b_r.
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f64_dl_body(const GemmParams& p, int tm, int tn,
+                                                  int split, int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK == 8, "eight 16-byte chunks per LDS row");
+  constexpr int BM = WM * TM * 16;
+  constexpr int BN = WN * TN * 16;  // complex columns
+  constexpr int CPR = BK;           // chunks (complex) per row
+  constexpr int AV = BM * CPR;      // chunks per stage
+  constexpr int BV = BN * CPR;
+  static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
+  constexpr int NA = AV / 256;
+  constexpr int NB = BV / 256;
+  __shared__ __align__(16) double2 Ad0[AV], Ad1[AV];
+  __shared__ __align__(16) double2 Bd0[BV], Bd1[BV];
+  auto abuf = [&](auto t) -> double2* { if constexpr (decltype(t)::value) return Ad1; else return Ad0; };
+  auto bbuf = [&](auto t) -> double2* { if constexpr (decltype(t)::value) return Bd1; else return Bd0; };
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const double2* __restrict__ Ag =
+      reinterpret_cast<const double2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const double2* __restrict__ Bg =
+      reinterpret_cast<const double2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
+
+  auto dma = [&](auto buf, int64_t k0) {
+    double2* As = abuf(buf);
+    double2* Bs = bbuf(buf);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
+      __builtin_amdgcn_global_load_lds(
+          Ag + (row0 + r) * p.lda + k0 + c,
+          (__attribute__((address_space(3))) void*)(As + 256 * j + 64 * wave), 16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
+      __builtin_amdgcn_global_load_lds(
+          Bg + (col0 + r) * p.ldb + k0 + c,
+          (__attribute__((address_space(3))) void*)(Bs + 256 * j + 64 * wave), 16, 0, 0);
+    }
+  };
+  double2 ra[NA], rb[NB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j;
+      const int64_t gr = row0 + (s >> 3), gk = k0 + (s & 7);
+      ra[j] = (gr < p.M && gk < kend) ? Ag[gr * p.lda + gk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j;
+      const int64_t gr = col0 + (s >> 3), gk = k0 + (s & 7);
+      rb[j] = (gr < p.N && gk < kend) ? Bg[gr * p.ldb + gk] : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](auto buf) {
+    double2* As = abuf(buf);
+    double2* Bs = bbuf(buf);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s >> 3;
+      As[r * CPR + ((s & 7) ^ dl_swz(r))] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s >> 3;
+      Bs[r * CPR + ((s & 7) ^ dl_swz(r))] = rb[j];
+    }
+  };
+
+  v4d cr[TM][TN], ci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cr[i][j][e] = ci[i][j][e] = 0.0;
+
+  const int kq = lane >> 4;
+  const int arow = wm * TM * 16 + (lane & 15);
+  const int brow = wn * TN * 16 + (lane & 15);
+
+  auto stage = [&](auto fast, auto cur, int it) {
+    constexpr bool FAST = decltype(fast)::value;
+    constexpr bool CUR = decltype(cur)::value;
+    const double2* As = abuf(cur);
+    const double2* Bs = bbuf(cur);
+    if constexpr (FAST) {
+      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (it + 1 < nk) {
+      gload(kbeg + int64_t(it + 1) * BK);
+    }
+#pragma unroll
+    for (int g = 0; g < CPR / 4; ++g) {
+      double2 a2[TM], b2[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = arow + 16 * i;
+        a2[i] = As[r * CPR + ((4 * g + kq) ^ dl_swz(r))];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int r = brow + 16 * j;
+        b2[j] = Bs[r * CPR + ((4 * g + kq) ^ dl_swz(r))];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].x, b2[j].x, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].x, b2[j].y, ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].y, -b2[j].y, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].y, b2[j].x, ci[i][j], 0, 0, 0);
+        }
+    }
+    if constexpr (FAST) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
+    } else if (it + 1 < nk) {
+      sstore(BoolTag<!CUR>{});
+    }
+    __syncthreads();
+  };
+
+  auto mainloop = [&](auto fast) {
+    constexpr bool FAST = decltype(fast)::value;
+    if (nk > 0) {
+      if constexpr (FAST) {
+        dma(BoolTag<false>{}, kbeg);
+        __builtin_amdgcn_s_waitcnt(0);
+      } else {
+        gload(kbeg);
+        sstore(BoolTag<false>{});
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; it += 2) {
+      stage(fast, BoolTag<false>{}, it);
+      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
+    }
+  };
+  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
+
+  // 16x16 f64 accumulator layout: column lane % 16, rows 4*e + lane/16.
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t row = row0 + wm * TM * 16 + i * 16 + 4 * e + (lane >> 4);
+        int64_t col = col0 + wn * TN * 16 + j * 16 + (lane & 15);
+        store_out<double>(p, b, split, row, col, 0, cr[i][j][e]);
+        store_out<double>(p, b, split, row, col, 1, ci[i][j][e]);
+      }
+}
+
 // ---------------------------------------------------------------------------
 // Small problems: one thread per complex output, sequential K loop (FP64,
 // FP32 or split BF16 products).  Used when a tile would be mostly empty.
@@ -2657,6 +3054,8 @@ RN_GEMM_ENTRY(cgemm_f32_rp)
 RN_GEMM_ENTRY(cgemm_f64_rp)
 RN_GEMM_ENTRY(cgemm_f32_big)
 RN_GEMM_ENTRY(cgemm_f32_3mbig)
+RN_GEMM_ENTRY_OCC(cgemm_f32_dl, 2)
+RN_GEMM_ENTRY_OCC(cgemm_f64_dl, 2)
 RN_GEMM_ENTRY_OCC(cgemm_f64_big, 2)
 
 // The large FP32 tiles take more than 64 KiB of dynamic LDS; raise each
@@ -2757,11 +3156,13 @@ static const TileCfg kF32Tiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 32, 16},
                                     {128, 128, 8}, {128, 64, 16}, {128, 128, 8},
                                     {128, 128, 16}, {128, 128, 16}, {128, 64, 16},
                                     {128, 64, 8},   {128, 128, 8},  {128, 128, 16},
+                                    {128, 128, 16}, {128, 128, 16}, {128, 64, 16},
                                     {1, 16, 64},    {2, 16, 64},    {4, 16, 64},
                                     {8, 16, 64}};
-static const TileCfg kF64Tiles[] = {{1, 1, 1},   {128, 64, 8}, {64, 32, 8}, {128, 64, 8},
+static const TileCfg kF64Tiles[] = {{1, 1, 1},   {128, 64, 8}, {64, 32, 8},  {128, 64, 8},
                                     {64, 64, 8},  {128, 64, 8}, {64, 128, 8}, {64, 64, 8},
-                                    {1, 16, 64},  {2, 16, 64},  {4, 16, 64},  {8, 16, 64}};
+                                    {128, 64, 8}, {64, 128, 8}, {1, 16, 64},  {2, 16, 64},
+                                    {4, 16, 64},  {8, 16, 64}};
 static const TileCfg kBF16Tiles[] = {{1, 1, 1},     {128, 64, 16}, {64, 32, 16},
                                      {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
                                      {128, 128, 8}, {256, 64, 8},  {128, 128, 16},
@@ -2800,9 +3201,10 @@ static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
   if (std::min(M, N) <= kSkinnyRows) return skinny_tile(mode, std::min(M, N));
   if (M < 16 || N < 8) return 0;
   if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) {
-    if (mode == RN_FP32_4M) return N >= 128 ? 14 : 11;
+    if (mode == RN_FP32_4M) return N >= 128 ? 15 : 17;  // direct-to-LDS tiles
+    if (mode == RN_FP64) return N >= 128 ? 9 : 8;        // direct-to-LDS tiles
     if (mode == RN_BF16X3) return N >= 128 ? 8 : 5;
-    return 3;  // FP64 planar tile, FP32-3M large tile
+    return 3;  // FP32-3M large tile
   }
   return 2;
 }
@@ -2912,8 +3314,12 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f64_big<2, 2, 4, 2, 8><<<grid, 256, big64_lds_bytes<2, 2, 4, 2, 8>(), s>>>(p);
       else if (tile == 6)
         cgemm_f64_big<2, 2, 2, 4, 8><<<grid, 256, big64_lds_bytes<2, 2, 2, 4, 8>(), s>>>(p);
-      else
+      else if (tile == 7)
         cgemm_f64_big<2, 2, 2, 2, 8><<<grid, 256, big64_lds_bytes<2, 2, 2, 2, 8>(), s>>>(p);
+      else if (tile == 8)
+        cgemm_f64_dl<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_f64_dl<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(p);
     } else if (g.mode == RN_FP32_3M) {
       if (tile == 1)
         cgemm_f32_3m<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
@@ -2968,9 +3374,15 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f32_big<2, 2, 2, 1, 8><<<grid, 256, big_lds_bytes<2, 2, 2, 1, 8>(), s>>>(p);
       } else if (tile == 13) {
         cgemm_f32_big<2, 2, 2, 2, 8><<<grid, 256, big_lds_bytes<2, 2, 2, 2, 8>(), s>>>(p);
-      } else {
+      } else if (tile == 14) {
         big_tiles_setup();
         cgemm_f32_big<1, 4, 4, 1, 16><<<grid, 256, big_lds_bytes<1, 4, 4, 1, 16>(), s>>>(p);
+      } else if (tile == 15) {
+        cgemm_f32_dl<1, 4, 4, 1, 16><<<grid, 256, 0, s>>>(p);
+      } else if (tile == 16) {
+        cgemm_f32_dl<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
+      } else {
+        cgemm_f32_dl<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
       }
     }
   }
@@ -3063,9 +3475,13 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
       else if (tile == 6)
         cgemm_f64_big_grouped<2, 2, 2, 4, 8>
             <<<grid, 256, big64_lds_bytes<2, 2, 2, 4, 8>(), s>>>(t);
-      else
+      else if (tile == 7)
         cgemm_f64_big_grouped<2, 2, 2, 2, 8>
             <<<grid, 256, big64_lds_bytes<2, 2, 2, 2, 8>(), s>>>(t);
+      else if (tile == 8)
+        cgemm_f64_dl_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
+      else
+        cgemm_f64_dl_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
       break;
     case RN_FP32_3M:
       if (tile == 0) cgemm_small_grouped<RN_FP32_3M><<<grid, 256, 0, s>>>(t);
@@ -3109,10 +3525,16 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
       } else if (tile == 13) {
         cgemm_f32_big_grouped<2, 2, 2, 2, 8>
             <<<grid, 256, big_lds_bytes<2, 2, 2, 2, 8>(), s>>>(t);
-      } else {
+      } else if (tile == 14) {
         big_tiles_setup();
         cgemm_f32_big_grouped<1, 4, 4, 1, 16>
             <<<grid, 256, big_lds_bytes<1, 4, 4, 1, 16>(), s>>>(t);
+      } else if (tile == 15) {
+        cgemm_f32_dl_grouped<1, 4, 4, 1, 16><<<grid, 256, 0, s>>>(t);
+      } else if (tile == 16) {
+        cgemm_f32_dl_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
+      } else {
+        cgemm_f32_dl_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
       }
       break;
   }

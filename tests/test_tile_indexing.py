@@ -197,3 +197,89 @@ def test_fp32_3m_large_tiles():
                             row = wn * tn * 32 + lane % 32 + j * 32
                             o = row * ldr + kh * hb + s4 + plane * bk
                             assert o % 4 == 0 and row * ldr <= o and o + 3 < (row + 1) * ldr
+
+
+def dl_swz(r):
+    return (r ^ (r >> 3)) & 7
+
+
+def test_fp32_direct_lds_tiles():
+    # Direct-to-LDS tile: a wave's copy writes 64 consecutive 16-byte slots;
+    # slot s of a stage holds logical chunk (s % 8) ^ dl_swz(row) of row s / 8.
+    shapes = instances("cgemm_f32_dl")
+    assert shapes
+    for wm_, wn_, tm, tn, bk in shapes:
+        assert bk == 16
+        bm, bn = wm_ * tm * 32, wn_ * tn * 32
+        for rows in (bm, bn):
+            v = rows * 8
+            assert v % 256 == 0
+            seen = set()
+            for j in range(v // 256):
+                for tid in range(256):
+                    wave, lane = tid >> 6, tid & 63
+                    s = tid + 256 * j
+                    dst = 256 * j + 64 * wave + lane  # slot the copy writes
+                    assert dst == s and 0 <= dst < v
+                    r, c = s >> 3, (s & 7) ^ dl_swz(s >> 3)
+                    assert r < rows and 0 <= 2 * c and 2 * c + 1 < bk
+                    seen.add((r, c))
+                    # the edge path stores the same logical chunk at the same slot
+                    assert r * 8 + ((c ^ dl_swz(r)) & 7) == s
+            assert len(seen) == v  # every chunk of the stage exactly once
+        for lane in range(64):
+            kh = lane >> 5
+            for w in range(4):
+                wm, wn = w // wn_, w % wn_
+                for g in range(4):
+                    for base, t, n in ((wm * tm * 32, tm, bm), (wn * tn * 32, tn, bn)):
+                        for i in range(t):
+                            r = base + (lane & 31) + 32 * i
+                            slot = r * 8 + ((2 * g + kh) ^ dl_swz(r))
+                            assert r < n and r * 8 <= slot < r * 8 + 8
+                            # the slot holds logical chunk 2g + kh of row r
+                            assert ((slot & 7) ^ dl_swz(r)) == 2 * g + kh
+
+
+def test_fp32_direct_lds_reads_spread_banks():
+    # 128-bit fragment reads: 8 (32 banks) or 16 (64 banks) consecutive lanes
+    # read consecutive rows at one logical chunk; their slots must fall on
+    # distinct 16-byte bank groups.
+    for group, nchunk in ((8, 8), (16, 16)):
+        for r0 in range(0, 256, group):
+            for c in range(8):
+                got = {(r * 8 + (c ^ dl_swz(r))) % nchunk for r in range(r0, r0 + group)}
+                assert len(got) == group
+
+
+def test_fp64_direct_lds_tiles():
+    # FP64 direct-to-LDS tile: one chunk is one complex, 8 per row; lane / 16
+    # picks the chunk 4g + lane / 16 of a 16-row fragment.
+    shapes = instances("cgemm_f64_dl")
+    assert shapes
+    for wm_, wn_, tm, tn, bk in shapes:
+        assert bk == 8
+        bm, bn = wm_ * tm * 16, wn_ * tn * 16
+        for rows in (bm, bn):
+            v = rows * 8
+            assert v % 256 == 0
+            seen = set()
+            for j in range(v // 256):
+                for tid in range(256):
+                    s = tid + 256 * j
+                    assert 256 * j + 64 * (tid >> 6) + (tid & 63) == s < v
+                    r, c = s >> 3, (s & 7) ^ dl_swz(s >> 3)
+                    assert r < rows and 0 <= c < bk
+                    seen.add((r, c))
+            assert len(seen) == v
+        for lane in range(64):
+            kq = lane >> 4
+            for w in range(4):
+                wm, wn = w // wn_, w % wn_
+                for g in range(bk // 4):
+                    for base, t, n in ((wm * tm * 16, tm, bm), (wn * tn * 16, tn, bn)):
+                        for i in range(t):
+                            r = base + (lane & 15) + 16 * i
+                            slot = r * 8 + ((4 * g + kq) ^ dl_swz(r))
+                            assert r < n and r * 8 <= slot < r * 8 + 8
+                            assert ((slot & 7) ^ dl_swz(r)) == 4 * g + kq
