@@ -52,7 +52,7 @@ def kernel_sha():
         src = f.read()
     parts = []
     for start, end in (("struct GemmParams {", "// FP32, 4M embedding"),
-                       ("__device__ __forceinline__ int dl_swz(", "// Large-tile FP32-3M (Gauss)"),
+                       ("__device__ __forceinline__ int dl_swz(", "// FP32-3M (Gauss) with the direct-to-LDS staging"),
                        ("#define RN_GEMM_ENTRY(NAME)", "RN_GEMM_ENTRY(cgemm_f32_4m)")):
         i = src.find(start)
         j = src.find(end, i + 1)

@@ -1419,6 +1419,230 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
       }
 }
 
+// Split-BF16x3 with direct-to-LDS staging: the LDS layout of the Re/Im-split
+// BF16 tile (interleaved bf16 pairs, BK / 4 chunks of 16 bytes per row,
+// chunk q of row r at q ^ swz(r)) filled by global_load_lds_dwordx4 on
+// interior tiles (a wave writes 64 consecutive slots; slot s of a stage is
+// row s / (BK / 4), stored chunk s % (BK / 4)).  One array per buffer and the
+// stage loop unrolled by two, as in the FP32 direct-to-LDS tile.
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_bf16x3_dl_body(const GemmParams& p, int tm, int tn,
+                                                     int split, int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK == 16, "four 16-byte chunks per LDS row");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 32;  // complex columns
+  constexpr int CPR = BK / 4;       // chunks per row
+  constexpr int LDK = BK;           // words per row
+  auto swz = [](int r) -> int { return ((r >> 1) ^ (r >> 3)) & 3; };
+  auto chunk_at = [&](int r, int word) -> int {  // word: multiple of 4 within the row
+    return r * LDK + ((((word >> 2) ^ swz(r))) << 2);
+  };
+  constexpr int AV = BM * CPR;  // chunks per stage and part
+  constexpr int BV = BN * CPR;
+  static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
+  constexpr int NA = AV / 256;
+  constexpr int NB = BV / 256;
+  __shared__ __align__(16) uint32_t Ah0[BM * LDK], Ah1[BM * LDK], Al0[BM * LDK], Al1[BM * LDK];
+  __shared__ __align__(16) uint32_t Bh0[BN * LDK], Bh1[BN * LDK], Bl0[BN * LDK], Bl1[BN * LDK];
+  auto pick = [](auto t, uint32_t* x0, uint32_t* x1) -> uint32_t* {
+    if constexpr (decltype(t)::value) return x1; else return x0;
+  };
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const int64_t ao = batch_off(p.a_bs, p.nbb, b), bo = batch_off(p.b_bs, p.nbb, b);
+  const uint32_t* __restrict__ Agh = reinterpret_cast<const uint32_t*>(p.A) + ao;
+  const uint32_t* __restrict__ Agl = reinterpret_cast<const uint32_t*>(p.A2) + ao;
+  const uint32_t* __restrict__ Bgh = reinterpret_cast<const uint32_t*>(p.B) + bo;
+  const uint32_t* __restrict__ Bgl = reinterpret_cast<const uint32_t*>(p.B2) + bo;
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
+
+  auto dma = [&](auto buf, int64_t k0) {
+    uint32_t* ah = pick(buf, Ah0, Ah1);
+    uint32_t* al = pick(buf, Al0, Al1);
+    uint32_t* bh = pick(buf, Bh0, Bh1);
+    uint32_t* bl = pick(buf, Bl0, Bl1);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s / CPR, q = (s % CPR) ^ swz(r);
+      const int64_t o = (row0 + r) * p.lda + k0 + 4 * q;
+      const int d = 4 * (256 * j + 64 * wave);
+      __builtin_amdgcn_global_load_lds(Agh + o, (__attribute__((address_space(3))) void*)(ah + d),
+                                       16, 0, 0);
+      __builtin_amdgcn_global_load_lds(Agl + o, (__attribute__((address_space(3))) void*)(al + d),
+                                       16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s / CPR, q = (s % CPR) ^ swz(r);
+      const int64_t o = (col0 + r) * p.ldb + k0 + 4 * q;
+      const int d = 4 * (256 * j + 64 * wave);
+      __builtin_amdgcn_global_load_lds(Bgh + o, (__attribute__((address_space(3))) void*)(bh + d),
+                                       16, 0, 0);
+      __builtin_amdgcn_global_load_lds(Bgl + o, (__attribute__((address_space(3))) void*)(bl + d),
+                                       16, 0, 0);
+    }
+  };
+  uint4 rah[NA], ral[NA], rbh[NB], rbl[NB];
+  auto ld4 = [&](const uint32_t* src, int64_t gk) -> uint4 {
+    if (gk + 3 < kend) return *reinterpret_cast<const uint4*>(src);
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gk < kend) v.x = src[0];
+    if (gk + 1 < kend) v.y = src[1];
+    if (gk + 2 < kend) v.z = src[2];
+    return v;
+  };
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) * 4;
+      const int64_t gr = row0 + r, gk = k0 + c;
+      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
+      if (gr < p.M && gk < kend) {
+        h = ld4(Agh + gr * p.lda + gk, gk);
+        l = ld4(Agl + gr * p.lda + gk, gk);
+      }
+      rah[j] = h;
+      ral[j] = l;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) * 4;
+      const int64_t gr = col0 + r, gk = k0 + c;
+      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
+      if (gr < p.N && gk < kend) {
+        h = ld4(Bgh + gr * p.ldb + gk, gk);
+        l = ld4(Bgl + gr * p.ldb + gk, gk);
+      }
+      rbh[j] = h;
+      rbl[j] = l;
+    }
+  };
+  auto sstore = [&](auto buf) {
+    uint32_t* ah = pick(buf, Ah0, Ah1);
+    uint32_t* al = pick(buf, Al0, Al1);
+    uint32_t* bh = pick(buf, Bh0, Bh1);
+    uint32_t* bl = pick(buf, Bl0, Bl1);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) * 4;
+      *reinterpret_cast<uint4*>(ah + chunk_at(r, c)) = rah[j];
+      *reinterpret_cast<uint4*>(al + chunk_at(r, c)) = ral[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) * 4;
+      *reinterpret_cast<uint4*>(bh + chunk_at(r, c)) = rbh[j];
+      *reinterpret_cast<uint4*>(bl + chunk_at(r, c)) = rbl[j];
+    }
+  };
+
+  v16f cr[TM][TN], ci[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
+
+  // As in the Re/Im-split BF16 tile: A row lane % 32, complex k
+  // 4 * (lane / 32) + 0..3 of each group of eight; packed b becomes
+  // (b_r, -b_i) for the real tile and (b_i, b_r) for the imaginary tile.
+  const int kq = (lane >> 5) * 4;
+  const int arow = wm * TM * 32 + (lane & 31);
+  const int bcol = wn * TN * 32 + (lane & 31);
+
+  auto stage = [&](auto fast, auto cur, int it) {
+    constexpr bool FAST = decltype(fast)::value;
+    constexpr bool CUR = decltype(cur)::value;
+    const uint32_t* ahs = pick(cur, Ah0, Ah1);
+    const uint32_t* als = pick(cur, Al0, Al1);
+    const uint32_t* bhs = pick(cur, Bh0, Bh1);
+    const uint32_t* bls = pick(cur, Bl0, Bl1);
+    if constexpr (FAST) {
+      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (it + 1 < nk) {
+      gload(kbeg + int64_t(it + 1) * BK);
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 8) {
+      v8bf ah[TM], al[TM];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int o = chunk_at(arow + i * 32, kk + kq);
+        ah[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(ahs + o));
+        al[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(als + o));
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int o = chunk_at(bcol + j * 32, kk + kq);
+        const v4u wh = *reinterpret_cast<const v4u*>(bhs + o);
+        const v4u wl = *reinterpret_cast<const v4u*>(bls + o);
+        const v8bf bhr = __builtin_bit_cast(v8bf, wh ^ 0x80000000u);
+        const v8bf blr = __builtin_bit_cast(v8bf, wl ^ 0x80000000u);
+        const v8bf bhi = __builtin_bit_cast(v8bf, (wh >> 16) | (wh << 16));
+        const v8bf bli = __builtin_bit_cast(v8bf, (wl >> 16) | (wl << 16));
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhr, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhi, ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], blr, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bli, ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhr, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhi, ci[i][j], 0, 0, 0);
+        }
+      }
+    }
+    if constexpr (FAST) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
+    } else if (it + 1 < nk) {
+      sstore(BoolTag<!CUR>{});
+    }
+    __syncthreads();
+  };
+
+  auto mainloop = [&](auto fast) {
+    constexpr bool FAST = decltype(fast)::value;
+    if (nk > 0) {
+      if constexpr (FAST) {
+        dma(BoolTag<false>{}, kbeg);
+        __builtin_amdgcn_s_waitcnt(0);
+      } else {
+        gload(kbeg);
+        sstore(BoolTag<false>{});
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; it += 2) {
+      stage(fast, BoolTag<false>{}, it);
+      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
+    }
+  };
+  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
+
+  const int khalf = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * khalf + (e & 3);
+        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
+        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
+        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
+      }
+}
+
 // ---------------------------------------------------------------------------
 // Re/Im-split tiles with planar LDS rows.  While staging a chunk into LDS,
 // each row of A is stored as [a_r(0..BK-1) | a_i(0..BK-1)] and each row of B
@@ -2015,6 +2239,217 @@ __device__ __forceinline__ void cgemm_f32_dl_body(const GemmParams& p, int tm, i
         int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
         store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
         store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
+      }
+}
+
+// FP32-3M (Gauss) with the direct-to-LDS staging of the FP32-4M tile: the
+// same interleaved, swizzled LDS rows; a lane's chunk [a_r, a_i, a_r', a_i']
+// feeds T1 = Ar Br, T2 = Ai Bi and T3 = (Ar + Ai)(Br + Bi) for its two complex
+// k (the sums formed after the fragment read), six MFMAs per tile and chunk
+// where 4M takes eight.
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f32_3mdl_body(const GemmParams& p, int tm, int tn,
+                                                  int split, int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK == 16, "eight 16-byte chunks per LDS row");
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 32;  // complex columns
+  constexpr int CPR = BK / 2;       // chunks per row
+  constexpr int AV = BM * CPR;      // chunks per stage
+  constexpr int BV = BN * CPR;
+  static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
+  constexpr int NA = AV / 256;
+  constexpr int NB = BV / 256;
+  // One array per buffer: with the buffer known at compile time in every
+  // stage, the compiler can tell the copies into one buffer from the
+  // fragment reads of the other and does not wait for the copies first.
+  __shared__ __align__(16) float4 Ad0[AV], Ad1[AV];
+  __shared__ __align__(16) float4 Bd0[BV], Bd1[BV];
+  auto abuf = [&](auto t) -> float4* { if constexpr (decltype(t)::value) return Ad1; else return Ad0; };
+  auto bbuf = [&](auto t) -> float4* { if constexpr (decltype(t)::value) return Bd1; else return Bd0; };
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const float2* __restrict__ Ag =
+      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const float2* __restrict__ Bg =
+      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
+
+  // Slot s = 256 j + tid of a stage: row s / 8, stored chunk s % 8, which
+  // holds logical chunk (s % 8) ^ dl_swz(row).
+  auto dma = [&](auto buf, int64_t k0) {
+    float4* As = abuf(buf);
+    float4* Bs = bbuf(buf);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
+      __builtin_amdgcn_global_load_lds(
+          Ag + (row0 + r) * p.lda + k0 + 2 * c,
+          (__attribute__((address_space(3))) void*)(As + 256 * j + 64 * wave), 16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
+      __builtin_amdgcn_global_load_lds(
+          Bg + (col0 + r) * p.ldb + k0 + 2 * c,
+          (__attribute__((address_space(3))) void*)(Bs + 256 * j + 64 * wave), 16, 0, 0);
+    }
+  };
+  float4 ra[NA], rb[NB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = s & 7;
+      const int64_t gr = row0 + r, gk = k0 + 2 * c;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gr < p.M) {
+        const float2* src = Ag + gr * p.lda + gk;
+        if (gk + 1 < kend) {
+          v = *reinterpret_cast<const float4*>(src);
+        } else if (gk < kend) {
+          const float2 t = src[0];
+          v.x = t.x;
+          v.y = t.y;
+        }
+      }
+      ra[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = s & 7;
+      const int64_t gr = col0 + r, gk = k0 + 2 * c;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gr < p.N) {
+        const float2* src = Bg + gr * p.ldb + gk;
+        if (gk + 1 < kend) {
+          v = *reinterpret_cast<const float4*>(src);
+        } else if (gk < kend) {
+          const float2 t = src[0];
+          v.x = t.x;
+          v.y = t.y;
+        }
+      }
+      rb[j] = v;
+    }
+  };
+  auto sstore = [&](auto buf) {
+    float4* As = abuf(buf);
+    float4* Bs = bbuf(buf);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s >> 3;
+      As[r * CPR + ((s & 7) ^ dl_swz(r))] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s >> 3;
+      Bs[r * CPR + ((s & 7) ^ dl_swz(r))] = rb[j];
+    }
+  };
+
+  v16f t1[TM][TN], t2[TM][TN], t3[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) t1[i][j][e] = t2[i][j][e] = t3[i][j][e] = 0.f;
+
+  const int kh = lane >> 5;
+  const int arow = wm * TM * 32 + (lane & 31);
+  const int brow = wn * TN * 32 + (lane & 31);
+
+  // One K stage computed from buffer CUR while the next stage fills the
+  // other buffer.
+  auto stage = [&](auto fast, auto cur, int it) {
+    constexpr bool FAST = decltype(fast)::value;
+    constexpr bool CUR = decltype(cur)::value;
+    const float4* As = abuf(cur);
+    const float4* Bs = bbuf(cur);
+    // Fast path: always fill the other buffer (the last stage copies itself
+    // again), so the stage has no branch.
+    if constexpr (FAST) {
+      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (it + 1 < nk) {
+      gload(kbeg + int64_t(it + 1) * BK);
+    }
+#pragma unroll
+    for (int g = 0; g < CPR / 2; ++g) {
+      float4 a4[TM], b4[TN];
+      float2 as[TM], bs[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = arow + 32 * i;
+        a4[i] = As[r * CPR + ((2 * g + kh) ^ dl_swz(r))];
+        as[i] = make_float2(a4[i].x + a4[i].y, a4[i].z + a4[i].w);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int r = brow + 32 * j;
+        b4[j] = Bs[r * CPR + ((2 * g + kh) ^ dl_swz(r))];
+        bs[j] = make_float2(b4[j].x + b4[j].y, b4[j].z + b4[j].w);
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            const float ar = q ? a4[i].z : a4[i].x, ai = q ? a4[i].w : a4[i].y;
+            const float br = q ? b4[j].z : b4[j].x, bi = q ? b4[j].w : b4[j].y;
+            const float sa = q ? as[i].y : as[i].x, sb = q ? bs[j].y : bs[j].x;
+            t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, t1[i][j], 0, 0, 0);
+            t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, t2[i][j], 0, 0, 0);
+            t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa, sb, t3[i][j], 0, 0, 0);
+          }
+    }
+    if constexpr (FAST) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
+    } else if (it + 1 < nk) {
+      sstore(BoolTag<!CUR>{});
+    }
+    __syncthreads();
+  };
+
+  auto mainloop = [&](auto fast) {
+    constexpr bool FAST = decltype(fast)::value;
+    if (nk > 0) {
+      if constexpr (FAST) {
+        dma(BoolTag<false>{}, kbeg);
+        __builtin_amdgcn_s_waitcnt(0);
+      } else {
+        gload(kbeg);
+        sstore(BoolTag<false>{});
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; it += 2) {
+      stage(fast, BoolTag<false>{}, it);
+      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
+    }
+  };
+  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
+        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
+        const float a = t1[i][j][e], c = t2[i][j][e], d = t3[i][j][e];
+        store_out<float>(p, b, split, row, col, 0, a - c);
+        store_out<float>(p, b, split, row, col, 1, (d - a) - c);
       }
 }
 
@@ -3056,6 +3491,8 @@ RN_GEMM_ENTRY(cgemm_f32_big)
 RN_GEMM_ENTRY(cgemm_f32_3mbig)
 RN_GEMM_ENTRY_OCC(cgemm_f32_dl, 2)
 RN_GEMM_ENTRY_OCC(cgemm_f64_dl, 2)
+RN_GEMM_ENTRY_OCC(cgemm_f32_3mdl, 2)
+RN_GEMM_ENTRY_OCC(cgemm_bf16x3_dl, 2)
 RN_GEMM_ENTRY_OCC(cgemm_f64_big, 2)
 
 // The large FP32 tiles take more than 64 KiB of dynamic LDS; raise each
@@ -3163,13 +3600,14 @@ static const TileCfg kF64Tiles[] = {{1, 1, 1},   {128, 64, 8}, {64, 32, 8},  {12
                                     {64, 64, 8},  {128, 64, 8}, {64, 128, 8}, {64, 64, 8},
                                     {128, 64, 8}, {64, 128, 8}, {1, 16, 64},  {2, 16, 64},
                                     {4, 16, 64},  {8, 16, 64}};
-static const TileCfg kBF16Tiles[] = {{1, 1, 1},     {128, 64, 16}, {64, 32, 16},
-                                     {256, 64, 8},  {128, 128, 8}, {128, 64, 16},
-                                     {128, 128, 8}, {256, 64, 8},  {128, 128, 16},
-                                     {1, 16, 64},   {2, 16, 64},   {4, 16, 64},   {8, 16, 64}};
-static const TileCfg k3MTiles[] = {{1, 1, 1},   {128, 64, 16}, {64, 64, 16},  {128, 64, 16},
-                                   {64, 128, 16}, {1, 16, 64}, {2, 16, 64},  {4, 16, 64},
-                                   {8, 16, 64}};
+static const TileCfg kBF16Tiles[] = {{1, 1, 1},      {128, 64, 16},  {64, 32, 16},
+                                     {256, 64, 8},   {128, 128, 8},  {128, 64, 16},
+                                     {128, 128, 8},  {256, 64, 8},   {128, 128, 16},
+                                     {128, 128, 16}, {128, 64, 16},  {1, 16, 64},
+                                     {2, 16, 64},    {4, 16, 64},    {8, 16, 64}};
+static const TileCfg k3MTiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 64, 16}, {128, 64, 16},
+                                   {64, 128, 16}, {128, 64, 16}, {64, 128, 16}, {1, 16, 64},
+                                   {2, 16, 64},   {4, 16, 64},   {8, 16, 64}};
 
 static const TileCfg& tile_of(rn_mode mode, int t) {
   if (mode == RN_FP64) return kF64Tiles[t];
@@ -3179,9 +3617,9 @@ static const TileCfg& tile_of(rn_mode mode, int t) {
 }
 
 // Default tile shape when the autotuner has no entry: the one-thread kernel
-// for tiny problems, otherwise the largest tile the output fills (the
-// Re/Im-split tiles -- planar LDS rows; for FP32-4M the 128-bit-read large
-// tiles -- measured fastest on large pairs).
+// for tiny problems, the skinny kernel for outputs with at most 8 rows or
+// columns, otherwise the largest tile the output fills (the direct-to-LDS
+// tiles, measured fastest on large pairs).
 static int tile_count_of(rn_mode mode);
 
 // The last four tiles of every mode are the skinny kernel for at most 1, 2,
@@ -3201,10 +3639,11 @@ static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
   if (std::min(M, N) <= kSkinnyRows) return skinny_tile(mode, std::min(M, N));
   if (M < 16 || N < 8) return 0;
   if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) {
-    if (mode == RN_FP32_4M) return N >= 128 ? 15 : 17;  // direct-to-LDS tiles
-    if (mode == RN_FP64) return N >= 128 ? 9 : 8;        // direct-to-LDS tiles
-    if (mode == RN_BF16X3) return N >= 128 ? 8 : 5;
-    return 3;  // FP32-3M large tile
+    // Direct-to-LDS tiles, except the 128 x 64 split-BF16 Re/Im tile.
+    if (mode == RN_FP32_4M) return N >= 128 ? 15 : 17;
+    if (mode == RN_FP64) return N >= 128 ? 9 : 8;
+    if (mode == RN_BF16X3) return N >= 128 ? 9 : 5;
+    return N >= 128 ? 6 : 5;  // FP32-3M
   }
   return 2;
 }
@@ -3327,8 +3766,12 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f32_3m<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
       else if (tile == 3)
         cgemm_f32_3mbig<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 4)
         cgemm_f32_3mbig<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(p);
+      else if (tile == 5)
+        cgemm_f32_3mdl<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_f32_3mdl<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(p);
     } else if (g.mode == RN_BF16X3) {
       if (tile == 1)
         cgemm_bf16x3<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
@@ -3344,8 +3787,12 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_bf16x3_ri<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
       else if (tile == 7)
         cgemm_bf16x3_ri<2, 2, 4, 1, 8><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 8)
         cgemm_bf16x3_ri<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
+      else if (tile == 9)
+        cgemm_bf16x3_dl<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_bf16x3_dl<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
     } else {
       if (tile == 1)
         cgemm_f32_4m<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
@@ -3488,7 +3935,9 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
       else if (tile == 1) cgemm_f32_3m_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
       else if (tile == 2) cgemm_f32_3m_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
       else if (tile == 3) cgemm_f32_3mbig_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      else cgemm_f32_3mbig_grouped<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 4) cgemm_f32_3mbig_grouped<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 5) cgemm_f32_3mdl_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
+      else cgemm_f32_3mdl_grouped<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(t);
       break;
     case RN_BF16X3:
       if (tile == 0) cgemm_small_grouped<RN_BF16X3><<<grid, 256, 0, s>>>(t);
@@ -3499,7 +3948,9 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
       else if (tile == 5) cgemm_bf16x3_ri_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
       else if (tile == 6) cgemm_bf16x3_ri_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
       else if (tile == 7) cgemm_bf16x3_ri_grouped<2, 2, 4, 1, 8><<<grid, 256, 0, s>>>(t);
-      else cgemm_bf16x3_ri_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 8) cgemm_bf16x3_ri_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
+      else if (tile == 9) cgemm_bf16x3_dl_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
+      else cgemm_bf16x3_dl_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
       break;
     default:
       if (tile == 0) cgemm_small_grouped<RN_FP32_4M><<<grid, 256, 0, s>>>(t);

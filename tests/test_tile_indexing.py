@@ -283,3 +283,49 @@ def test_fp64_direct_lds_tiles():
                             slot = r * 8 + ((4 * g + kq) ^ dl_swz(r))
                             assert r < n and r * 8 <= slot < r * 8 + 8
                             assert ((slot & 7) ^ dl_swz(r)) == 4 * g + kq
+
+
+def test_fp32_3m_direct_lds_tiles():
+    # Same staging and fragment reads as the FP32-4M direct-to-LDS tile.
+    shapes = instances("cgemm_f32_3mdl")
+    assert shapes
+    for wm_, wn_, tm, tn, bk in shapes:
+        assert bk == 16
+        bm, bn = wm_ * tm * 32, wn_ * tn * 32
+        for rows in (bm, bn):
+            assert (rows * 8) % 256 == 0
+        for lane in range(64):
+            kh = lane >> 5
+            for w in range(4):
+                wm, wn = w // wn_, w % wn_
+                for g in range(4):
+                    for base, t, n in ((wm * tm * 32, tm, bm), (wn * tn * 32, tn, bn)):
+                        for i in range(t):
+                            r = base + (lane & 31) + 32 * i
+                            slot = r * 8 + ((2 * g + kh) ^ dl_swz(r))
+                            assert r < n and r * 8 <= slot < r * 8 + 8
+
+
+def test_bf16x3_direct_lds_tiles():
+    # Slot s of a stage (one part, hi or lo) is row s / 4, stored chunk s % 4,
+    # holding logical chunk (s % 4) ^ swz(row): the word offset 4 s equals
+    # the Re/Im-split tile's chunk_at(row, 4 * logical chunk).
+    shapes = instances("cgemm_bf16x3_dl")
+    assert shapes
+    for wm_, wn_, tm, tn, bk in shapes:
+        assert bk == 16
+        cpr = bk // 4
+        bm, bn = wm_ * tm * 32, wn_ * tn * 32
+        for rows in (bm, bn):
+            v = rows * cpr
+            assert v % 256 == 0
+            seen = set()
+            for j in range(v // 256):
+                for tid in range(256):
+                    s = tid + 256 * j
+                    assert 256 * j + 64 * (tid >> 6) + (tid & 63) == s < v
+                    r, q = s // cpr, (s % cpr) ^ bf16_swz(bk, s // cpr)
+                    assert r < rows and 0 <= q < cpr
+                    assert bf16_chunk_at(bk, r, 4 * q) == 4 * s
+                    seen.add((r, q))
+            assert len(seen) == v
