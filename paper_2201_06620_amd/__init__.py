@@ -368,45 +368,18 @@ class Context:
         """problems: list of (a, dims_a, grid_a, b, dims_b, grid_b, axes_a, axes_b).
 
         autotune=True first times the tile shapes of every untuned problem
-        shape (synchronously), then runs the batch with the chosen tiles."""
-        import torch
-        n = len(problems)
-        dt = dtype_of_mode(mode)
-        want = torch.complex128 if dt == C128 else torch.complex64
-        As, Bs, Cs = (RnTensor * n)(), (RnTensor * n)(), (RnTensor * n)()
-        ks = np.zeros(max(n, 1), dtype=np.int32)
-        keep = []
-        pa_arr = (ctypes.c_void_p * max(n, 1))()
-        pb_arr = (ctypes.c_void_p * max(n, 1))()
-        for i, (a, da, ga, b, db, gb, axa, axb) in enumerate(problems):
-            As[i] = descriptor(da, ga, dt, a.data_ptr())
-            Bs[i] = descriptor(db, gb, dt, b.data_ptr())
-            x, px = _arr32(axa)
-            y, py = _arr32(axb)
-            keep += [x, y]
-            ks[i] = len(x)
-            pa_arr[i] = px
-            pb_arr[i] = py
-        ws_n, fl = ctypes.c_size_t(), ctypes.c_double()
-        check(lib().rn_block_tensordot_batch_plan(self.h, n, As, Bs, ks.ctypes.data, pa_arr,
-                                                  pb_arr, mode_id(mode), Cs, ctypes.byref(ws_n),
-                                                  ctypes.byref(fl)), "batch plan")
-        results = []
-        for i in range(n):
-            cd = [Cs[i].dims[j] for j in range(Cs[i].rank)]
-            cg = [Cs[i].grid[j] for j in range(Cs[i].rank)]
-            o = outs[i] if outs is not None else torch.empty(
-                int(np.prod(cd, dtype=np.int64)) if cd else 1, dtype=want,
-                device=problems[i][0].device)
-            Cs[i].data = o.data_ptr()
-            results.append((o, cd, cg))
-        wp, wn = self._workspace(ws_n.value, workspace)
+        shape (synchronously), then runs the batch with the chosen tiles.
+        Returns ([(C, dims, grid)], useful flops)."""
+        pb = PreparedBatch(self, problems, mode, outs, workspace, own_workspace=False)
         if autotune:
-            check(lib().rn_autotune_batch(self.h, n, As, Bs, ks.ctypes.data, pa_arr, pb_arr, Cs,
-                                          mode_id(mode), wp, wn, self._stream()), "autotune")
-        check(lib().rn_block_tensordot_batch(self.h, n, As, Bs, ks.ctypes.data, pa_arr, pb_arr,
-                                             Cs, mode_id(mode), wp, wn, self._stream()), "batch")
-        return results, fl.value
+            pb.autotune()
+        pb.run()
+        return pb.results, pb.flops
+
+    def prepare_batch(self, problems, mode="fp32_4m", outs=None, workspace=None):
+        """A batch call with its descriptors, plan and outputs built once, for
+        repeated calls on the same tensors (values may change in place)."""
+        return PreparedBatch(self, problems, mode, outs, workspace)
 
     def set_graphs(self, on: bool) -> None:
         check(lib().rn_set_graphs(self.h, 1 if on else 0), "set_graphs")
@@ -579,6 +552,73 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class PreparedBatch:
+    """Argument arrays, plan and outputs of one batch of block tensordots,
+    kept for repeated calls.
+
+    The operand tensors (and `outs`, if given) must stay alive and keep
+    their storage; their contents may change between calls.  A repeated
+    call on the same stream replays the batch's HIP graph.
+    """
+
+    def __init__(self, ctx, problems, mode, outs=None, workspace=None, own_workspace=True):
+        import torch
+        self.ctx = ctx
+        self.mode = mode
+        self.problems = list(problems)
+        n = self.n = len(self.problems)
+        dt = dtype_of_mode(mode)
+        want = torch.complex128 if dt == C128 else torch.complex64
+        self.As, self.Bs, self.Cs = (RnTensor * n)(), (RnTensor * n)(), (RnTensor * n)()
+        self.ks = np.zeros(max(n, 1), dtype=np.int32)
+        self._keep = []
+        self.pa = (ctypes.c_void_p * max(n, 1))()
+        self.pb = (ctypes.c_void_p * max(n, 1))()
+        for i, (a, da, ga, b, db, gb, axa, axb) in enumerate(self.problems):
+            self.As[i] = descriptor(da, ga, dt, a.data_ptr())
+            self.Bs[i] = descriptor(db, gb, dt, b.data_ptr())
+            x, px = _arr32(axa)
+            y, py = _arr32(axb)
+            self._keep += [x, y]
+            self.ks[i] = len(x)
+            self.pa[i] = px
+            self.pb[i] = py
+        ws_n, fl = ctypes.c_size_t(), ctypes.c_double()
+        check(lib().rn_block_tensordot_batch_plan(ctx.h, n, self.As, self.Bs, self.ks.ctypes.data,
+                                                  self.pa, self.pb, mode_id(mode), self.Cs,
+                                                  ctypes.byref(ws_n), ctypes.byref(fl)),
+              "batch plan")
+        self.flops = fl.value
+        self.results = []
+        for i in range(n):
+            cd = [self.Cs[i].dims[j] for j in range(self.Cs[i].rank)]
+            cg = [self.Cs[i].grid[j] for j in range(self.Cs[i].rank)]
+            o = outs[i] if outs is not None else torch.empty(
+                int(np.prod(cd, dtype=np.int64)) if cd else 1, dtype=want,
+                device=self.problems[i][0].device)
+            self.Cs[i].data = o.data_ptr()
+            self.results.append((o, cd, cg))
+        self.outputs = [o for o, _, _ in self.results]
+        if own_workspace and ws_n.value > 0 and workspace is None:
+            workspace = torch.empty(ws_n.value, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        self.workspace = workspace  # kept alive with the plan (else the handle's last one)
+        self.wp, self.wn = ctx._workspace(ws_n.value, workspace)
+
+    def autotune(self):
+        """Time the tile shapes of every untuned problem shape (synchronous)."""
+        check(lib().rn_autotune_batch(self.ctx.h, self.n, self.As, self.Bs, self.ks.ctypes.data,
+                                      self.pa, self.pb, self.Cs, mode_id(self.mode), self.wp,
+                                      self.wn, self.ctx._stream()), "autotune")
+
+    def run(self):
+        """Enqueue the batch on the current stream; returns the outputs."""
+        check(lib().rn_block_tensordot_batch(self.ctx.h, self.n, self.As, self.Bs,
+                                             self.ks.ctypes.data, self.pa, self.pb, self.Cs,
+                                             mode_id(self.mode), self.wp, self.wn,
+                                             self.ctx._stream()), "batch")
+        return self.outputs
 
 
 class PreparedNetwork:

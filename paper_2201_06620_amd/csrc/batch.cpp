@@ -71,17 +71,42 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct BatchPlan {
   std::vector<TdPlan> plans;
   std::vector<size_t> region;   // workspace offset of each problem's temporaries
+  std::vector<int> split;       // K splits of each problem's GEMM (1 = none)
+  std::vector<size_t> partial;  // workspace offset of its split-K partials
   std::vector<int> order;       // problems by decreasing work
   size_t table_off = 0;
   size_t ws_bytes = 0;
   double flops = 0;
 };
 
+// One group per GEMM tile shape: the grouped permute of the operands its
+// problems need, then its grouped GEMM.  Groups are spread over up to four
+// streams, longest first onto the least loaded stream, so one group's
+// (HBM-bound) permute overlaps other groups' GEMMs.
 struct Launches {
   std::vector<char> table;
-  GroupedLaunch perm;
+  std::vector<GroupedLaunch> perms;  // perms[g].n == 0: no permute needed
   std::vector<GroupedLaunch> gemms;
+  std::vector<int> lane;             // stream slot of each group
+  int lanes = 1;
+  GroupedLaunch reduce;              // split-K partials of all groups
 };
+
+// K splits of one problem's GEMM inside a batch.  Problems with at most 128
+// output tiles and K >= 512 run their K loop in up to 16 independent chunks
+// of at least 128 (partials summed afterwards in a fixed order), so they do
+// not leave a handful of workgroups looping over K while the rest of the
+// batch has finished; at most 512 workgroups per problem.  Counted with the
+// smallest MFMA tile (64 x 32), so the choice, and the workspace, do not
+// depend on the tile the tuner picks.
+static int batch_split(int64_t M, int64_t N, int64_t K) {
+  if (std::min(M, N) <= 8 || K < 512) return 1;  // skinny kernel: no split
+  const int64_t tiles = ((M + 63) / 64) * ((N + 31) / 32);
+  if (tiles > 128) return 1;
+  int s = 1;
+  while (s < 16 && K / (2 * s) >= 128 && tiles * 2 * s <= 512) s *= 2;
+  return s;
+}
 
 rn_status plan_batch(int32_t n, const rn_tensor* A, const rn_tensor* B, const int32_t* k,
                      const int32_t* const* axesA, const int32_t* const* axesB, rn_mode mode,
@@ -90,14 +115,23 @@ rn_status plan_batch(int32_t n, const rn_tensor* A, const rn_tensor* B, const in
     return fail(RN_ERR_INVALID, "bad batch arguments");
   bp->plans.resize(n);
   bp->region.resize(n);
+  bp->split.assign(n, 1);
+  bp->partial.assign(n, 0);
   size_t off = 0;
   for (int i = 0; i < n; ++i) {
-    rn_status st = plan_tensordot(&A[i], &B[i], k[i], axesA[i], axesB[i], mode, &bp->plans[i],
+    TdPlan& P = bp->plans[i];
+    rn_status st = plan_tensordot(&A[i], &B[i], k[i], axesA[i], axesB[i], mode, &P,
                                   /*allow_splitk=*/false);
     if (st != RN_OK) return fail(st, "problem " + std::to_string(i) + ": " + last_error());
     bp->region[i] = off;
-    off += align256(bp->plans[i].ws_bytes);
-    bp->flops += bp->plans[i].flops;
+    off += align256(P.ws_bytes);
+    bp->split[i] = batch_split(P.M, P.N, P.K);
+    if (bp->split[i] > 1) {
+      bp->partial[i] = off;
+      const size_t es = mode == RN_FP64 ? 16 : 8;
+      off += align256(size_t(bp->split[i]) * size_t(P.M) * size_t(P.N) * es);
+    }
+    bp->flops += P.flops;
   }
   bp->order.resize(n);
   std::iota(bp->order.begin(), bp->order.end(), 0);
@@ -112,7 +146,7 @@ rn_status plan_batch(int32_t n, const rn_tensor* A, const rn_tensor* B, const in
 void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, const rn_tensor* B,
                     const rn_tensor* C, char* ws, Launches* L) {
   const int n = (int)bp.plans.size();
-  std::vector<PermLaunch> jobs;
+  std::vector<std::vector<PermLaunch>> jobs(n);
   std::vector<GemmLaunch> gl(n);
   for (int i : bp.order) {
     const TdPlan& P = bp.plans[i];
@@ -130,7 +164,7 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
       pl.perm = P.permA;
       pl.in_es = P.es;
       pl.kind = split_prec ? 1 : 0;
-      jobs.push_back(pl);
+      jobs[i].push_back(pl);
       g.A = pl.out;
       g.A2 = pl.out2;
     }
@@ -142,7 +176,7 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
       pl.perm = P.permB;
       pl.in_es = P.es;
       pl.kind = split_prec ? 1 : 0;
-      jobs.push_back(pl);
+      jobs[i].push_back(pl);
       g.B = pl.out;
       g.B2 = pl.out2;
     }
@@ -154,24 +188,76 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
     g.ldb = P.K;
     g.crow = P.crow;
     g.ccol = P.ccol;
-    g.splitk = 1;
     int t = tuned_tile(h, P.mode, P.mbits, P.nbits, P.kbits);
     g.tile = gemm_tile_valid(P.mode, t, P.M, P.N) ? t : gemm_default_tile(P.mode, P.M, P.N, P.K);
+    const bool split = base && bp.split[i] > 1 && gemm_tile_splits(P.mode, g.tile);
+    g.splitk = split ? bp.split[i] : 1;
+    g.partial = split ? ws + bp.partial[i] : nullptr;
   }
   L->table.clear();
-  std::vector<char> part;
-  if (grouped_perm_build(jobs, part, L->perm) > 0) L->table = part;
-  std::map<int, std::vector<GemmLaunch>> by_tile;
-  for (int i : bp.order) by_tile[gl[i].tile].push_back(gl[i]);
+  L->perms.clear();
   L->gemms.clear();
+  std::map<int, std::vector<int>> by_tile;
+  for (int i : bp.order) by_tile[gl[i].tile].push_back(i);
+  std::vector<char> part;
+  std::vector<GemmLaunch> split_probs;
+  std::vector<double> cost;
   for (auto& kv : by_tile) {
-    GroupedLaunch G;
+    std::vector<PermLaunch> pj;
+    std::vector<GemmLaunch> gg;
+    double c = 0;
+    for (int i : kv.second) {
+      pj.insert(pj.end(), jobs[i].begin(), jobs[i].end());
+      gg.push_back(gl[i]);
+      const TdPlan& P = bp.plans[i];
+      // Rough time: MFMA-bound flops or HBM-bound bytes, plus the permutes.
+      const double bytes = double(P.es) * double(P.M * P.K + P.N * P.K + P.M * P.N);
+      c += std::max(P.flops / 150e12, bytes / 6e12) +
+           (P.permuteA ? 2.0 * P.es * P.M * P.K / 6e12 : 0.0) +
+           (P.permuteB ? 2.0 * P.es * P.N * P.K / 6e12 : 0.0);
+    }
+    GroupedLaunch G, PG;
     size_t base = L->table.size();
-    if (grouped_gemm_build(kv.second, kv.first, part, G) == 0) continue;
+    if (grouped_gemm_build(gg, kv.first, part, G) == 0) continue;
     G.params_off += base;
     G.prefix_off += base;
     L->table.insert(L->table.end(), part.begin(), part.end());
+    base = L->table.size();
+    if (grouped_perm_build(pj, part, PG) > 0) {
+      PG.params_off += base;
+      PG.prefix_off += base;
+      L->table.insert(L->table.end(), part.begin(), part.end());
+    }
     L->gemms.push_back(G);
+    L->perms.push_back(PG);
+    cost.push_back(c);
+    for (const GemmLaunch& g : gg)
+      if (g.splitk > 1) split_probs.push_back(g);
+  }
+  // Longest group first, each onto the least loaded of up to four streams.
+  const int ng = (int)L->gemms.size();
+  std::vector<int> idx(ng);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  L->lanes = std::max(1, std::min(ng, 4));
+  std::vector<double> load(L->lanes, 0.0);
+  std::vector<GroupedLaunch> perms, gemms;
+  L->lane.clear();
+  for (int g : idx) {
+    const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[j] += cost[g];
+    perms.push_back(L->perms[g]);
+    gemms.push_back(L->gemms[g]);
+    L->lane.push_back(j);
+  }
+  L->perms.swap(perms);
+  L->gemms.swap(gemms);
+  L->reduce = GroupedLaunch{};
+  const size_t base = L->table.size();
+  if (grouped_reduce_build(split_probs, part, L->reduce) > 0) {
+    L->reduce.params_off += base;
+    L->reduce.prefix_off += base;
+    L->table.insert(L->table.end(), part.begin(), part.end());
   }
 }
 
@@ -195,39 +281,46 @@ static rn_status aux_setup(rn_ctx* h) {
 // others instead of idling the GPU.
 rn_status launch_all(rn_ctx* h, const Launches& L, char* table_dev, hipStream_t s, bool prof) {
   hipError_t e;
-  int ev = prof ? h->prof.begin(0, s) : -1;
-  e = launch_permute_grouped(L.perm, table_dev, s);
-  if (prof) h->prof.end(ev, s);
-  if (e != hipSuccess) return hipf(e, "grouped permute");
+  auto group = [&](int i, hipStream_t sj) -> rn_status {
+    int ev = prof ? h->prof.begin(0, sj) : -1;
+    e = launch_permute_grouped(L.perms[i], table_dev, sj);
+    if (prof) h->prof.end(ev, sj);
+    if (e != hipSuccess) return hipf(e, "grouped permute");
+    ev = prof ? h->prof.begin(1, sj) : -1;
+    e = launch_gemm_grouped(L.gemms[i], table_dev, sj);
+    if (prof) h->prof.end(ev, sj);
+    return e == hipSuccess ? RN_OK : hipf(e, "grouped GEMM");
+  };
+  auto reduce = [&]() -> rn_status {
+    if (L.reduce.n == 0) return RN_OK;
+    const int ev2 = prof ? h->prof.begin(2, s) : -1;
+    hipError_t er = launch_reduce_grouped(L.reduce, table_dev, s);
+    if (prof) h->prof.end(ev2, s);
+    return er == hipSuccess ? RN_OK : hipf(er, "grouped split-K reduce");
+  };
   const int ng = (int)L.gemms.size();
-  if (prof || ng < 2) {
-    for (const GroupedLaunch& G : L.gemms) {
-      ev = prof ? h->prof.begin(1, s) : -1;
-      e = launch_gemm_grouped(G, table_dev, s);
-      if (prof) h->prof.end(ev, s);
-      if (e != hipSuccess) return hipf(e, "grouped GEMM");
-    }
-    return RN_OK;
+  rn_status st;
+  if (prof || L.lanes < 2) {
+    for (int i = 0; i < ng; ++i)
+      if ((st = group(i, s)) != RN_OK) return st;
+    return reduce();
   }
   if (!h->aux_fork) return fail(RN_ERR_INVALID, "batch streams not set up");
-  const int nstreams = std::min(ng, 4);
   if ((e = hipEventRecord(h->aux_fork, s)) != hipSuccess) return hipf(e, "fork");
-  for (int j = 1; j < nstreams; ++j)
+  for (int j = 1; j < L.lanes; ++j)
     if ((e = hipStreamWaitEvent(h->aux_streams[j - 1], h->aux_fork, 0)) != hipSuccess)
       return hipf(e, "fork wait");
   for (int i = 0; i < ng; ++i) {
-    const int j = i % nstreams;
-    hipStream_t sj = j == 0 ? s : h->aux_streams[j - 1];
-    if ((e = launch_gemm_grouped(L.gemms[i], table_dev, sj)) != hipSuccess)
-      return hipf(e, "grouped GEMM");
+    const int j = L.lane[i];
+    if ((st = group(i, j == 0 ? s : h->aux_streams[j - 1])) != RN_OK) return st;
   }
-  for (int j = 1; j < nstreams; ++j) {
+  for (int j = 1; j < L.lanes; ++j) {
     if ((e = hipEventRecord(h->aux_join[j - 1], h->aux_streams[j - 1])) != hipSuccess)
       return hipf(e, "join");
     if ((e = hipStreamWaitEvent(s, h->aux_join[j - 1], 0)) != hipSuccess)
       return hipf(e, "join wait");
   }
-  return RN_OK;
+  return reduce();
 }
 
 bool graphs_wanted(const rn_ctx* h, hipStream_t s) {
@@ -374,7 +467,44 @@ rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
                                    rn_tensor* C, rn_mode mode, void* ws, size_t ws_bytes,
                                    void* stream) {
   if (!h) return fail(RN_ERR_INVALID, "null handle");
-  if (n > 0 && !C) return fail(RN_ERR_INVALID, "null C descriptors");
+  if (n < 0 || (n > 0 && (!A || !B || !C || !k || !axesA || !axesB)))
+    return fail(RN_ERR_INVALID, "bad batch arguments");
+  // Enough checking to read every descriptor and axis list safely.
+  for (int i = 0; i < n; ++i) {
+    const bool ranks_ok = A[i].rank >= 0 && A[i].rank <= RN_MAX_RANK && B[i].rank >= 0 &&
+                          B[i].rank <= RN_MAX_RANK && C[i].rank >= 0 && C[i].rank <= RN_MAX_RANK;
+    if (!ranks_ok || k[i] < 0 || k[i] > RN_MAX_RANK || (k[i] > 0 && (!axesA[i] || !axesB[i])))
+      return fail(RN_ERR_INVALID, "problem " + std::to_string(i) + ": bad rank or axes");
+  }
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hipf(e, "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // A call identical to an earlier captured one (same descriptors, data
+  // pointers, workspace, stream and tuning) replays its graph without
+  // planning again: that call was planned and checked in full.
+  uint64_t key = 0;
+  const bool graphs = n > 0 && use_graphs(h, s);
+  if (graphs) {
+    key = 1469598103934665603ull;
+    key = hash_bytes(key, "batch", 5);
+    key = hash_bytes(key, &mode, sizeof(mode));
+    key = hash_bytes(key, &n, sizeof(n));
+    for (int i = 0; i < n; ++i) {
+      key = hash_tensor(key, A[i]);
+      key = hash_tensor(key, B[i]);
+      key = hash_tensor(key, C[i]);
+      key = hash_bytes(key, &k[i], sizeof(int32_t));
+      key = hash_bytes(key, axesA[i], sizeof(int32_t) * (size_t)k[i]);
+      key = hash_bytes(key, axesB[i], sizeof(int32_t) * (size_t)k[i]);
+    }
+    key = hash_bytes(key, &ws, sizeof(ws));
+    key = hash_bytes(key, &ws_bytes, sizeof(ws_bytes));
+    key = hash_bytes(key, &s, sizeof(s));
+    key = hash_bytes(key, &g_tune_version, sizeof(g_tune_version));
+    bool done = false;
+    rn_status st = replay_graph(h, key, s, &done);
+    if (st != RN_OK || done) return st;
+  }
   BatchPlan bp;
   rn_status st = plan_batch(n, A, B, k, axesA, axesB, mode, &bp);
   if (st != RN_OK) return st;
@@ -389,36 +519,16 @@ rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
   if (ws_bytes < need || (need > 0 && !ws))
     return fail(RN_ERR_WORKSPACE, "workspace smaller than planned (" + std::to_string(need) +
                                       " bytes needed)");
-  hipError_t e = hipSetDevice(h->device);
-  if (e != hipSuccess) return hipf(e, "hipSetDevice");
+  if (L.table.size() > need - bp.table_off)
+    return fail(RN_ERR_INVALID, "internal: launch tables exceed their planned bound");
   // Side streams for the tile groups exist before any graph capture.
   if ((st = aux_setup(h)) != RN_OK) return st;
   if (n == 0) return RN_OK;
-  hipStream_t s = static_cast<hipStream_t>(stream);
   char* table_dev = static_cast<char*>(ws) + bp.table_off;
-  if (use_graphs(h, s)) {
-    uint64_t key = 1469598103934665603ull;
-    key = hash_bytes(key, "batch", 5);
-    key = hash_bytes(key, &mode, sizeof(mode));
-    key = hash_bytes(key, &n, sizeof(n));
-    for (int i = 0; i < n; ++i) {
-      key = hash_tensor(key, A[i]);
-      key = hash_tensor(key, B[i]);
-      key = hash_tensor(key, C[i]);
-      key = hash_bytes(key, &k[i], sizeof(int32_t));
-      key = hash_bytes(key, axesA[i], sizeof(int32_t) * (size_t)k[i]);
-      key = hash_bytes(key, axesB[i], sizeof(int32_t) * (size_t)k[i]);
-    }
-    key = hash_bytes(key, &ws, sizeof(ws));
-    key = hash_bytes(key, &s, sizeof(s));
-    key = hash_bytes(key, &g_tune_version, sizeof(g_tune_version));
-    bool done = false;
-    if ((st = replay_graph(h, key, s, &done)) != RN_OK || done) return st;
-    if (seen_before(h, key))
-      return capture_and_launch(h, key, L.table, table_dev, s, [&](hipStream_t cs) {
-        return launch_all(h, L, table_dev, cs, false);
-      });
-  }
+  if (graphs && seen_before(h, key))
+    return capture_and_launch(h, key, L.table, table_dev, s, [&](hipStream_t cs) {
+      return launch_all(h, L, table_dev, cs, false);
+    });
   if ((st = upload_table(h, L.table, table_dev, s)) != RN_OK) return st;
   return launch_all(h, L, table_dev, s, h->prof.on);
 }

@@ -3460,7 +3460,9 @@ __device__ __forceinline__ int group_find(const GroupTable& g, int bid) {
     const int i = group_find(g, blockIdx.x);                                            \
     const GemmParams p = g.probs[i]; /* by value: uniform scalar loads, once */         \
     const int local = blockIdx.x - g.prefix[i];                                         \
-    NAME##_body<WM, WN, TM, TN, BK>(p, local / p.tiles_n, local % p.tiles_n, 0, 0);     \
+    const int per = p.tiles_m * p.tiles_n; /* tiles per K split */                      \
+    NAME##_body<WM, WN, TM, TN, BK>(p, (local % per) / p.tiles_n, local % p.tiles_n,    \
+                                    local / per, 0);                                    \
   }
 
 // Entry points whose register use is capped for WAVES waves per SIMD.
@@ -3476,7 +3478,9 @@ __device__ __forceinline__ int group_find(const GroupTable& g, int bid) {
     const int i = group_find(g, blockIdx.x);                                            \
     const GemmParams p = g.probs[i]; /* by value: uniform scalar loads, once */         \
     const int local = blockIdx.x - g.prefix[i];                                         \
-    NAME##_body<WM, WN, TM, TN, BK>(p, local / p.tiles_n, local % p.tiles_n, 0, 0);     \
+    const int per = p.tiles_m * p.tiles_n; /* tiles per K split */                      \
+    NAME##_body<WM, WN, TM, TN, BK>(p, (local % per) / p.tiles_n, local % p.tiles_n,    \
+                                    local / per, 0);                                    \
   }
 
 RN_GEMM_ENTRY(cgemm_f32_4m)
@@ -3489,7 +3493,9 @@ RN_GEMM_ENTRY(cgemm_f32_rp)
 RN_GEMM_ENTRY(cgemm_f64_rp)
 RN_GEMM_ENTRY(cgemm_f32_big)
 RN_GEMM_ENTRY(cgemm_f32_3mbig)
-RN_GEMM_ENTRY_OCC(cgemm_f32_dl, 2)
+// Two waves per SIMD for the 128 x 128 tiles, three for 128 x 64 (48 KiB of
+// LDS: three workgroups per CU), four for the 64 x 64 and 128 x 32 tiles.
+RN_GEMM_ENTRY_OCC(cgemm_f32_dl, (TM * TN * WM * WN <= 4 ? 4 : TM * TN * WM * WN <= 8 ? 3 : 2))
 RN_GEMM_ENTRY_OCC(cgemm_f64_dl, 2)
 RN_GEMM_ENTRY_OCC(cgemm_f32_3mdl, 2)
 RN_GEMM_ENTRY_OCC(cgemm_bf16x3_dl, 2)
@@ -3579,6 +3585,33 @@ __global__ __launch_bounds__(256) void splitk_reduce(GemmParams p) {
   }
 }
 
+// Grouped form: workgroup w serves problem i with prefix[i] <= w <
+// prefix[i+1], 256 outputs each; partials summed in ascending split order.
+template <typename R>
+__global__ __launch_bounds__(256) void splitk_reduce_grouped(GroupTable g) {
+  const int i = group_find(g, blockIdx.x);
+  // By reference: a copy of the parameters (with their stride arrays) would
+  // live in scratch memory, per thread, for a few loads.
+  const GemmParams& p = g.probs[i];
+  const int64_t nb = int64_t(1) << p.nbb;
+  const int64_t e = int64_t(blockIdx.x - g.prefix[i]) * 256 + threadIdx.x;
+  if (e >= nb * p.M * p.N) return;
+  const int64_t b = e / (p.M * p.N);
+  const int64_t rc = e % (p.M * p.N);
+  const int64_t row = rc / p.N, col = rc % p.N;
+  const R* part = reinterpret_cast<const R*>(p.partial);
+  R re = 0, im = 0;
+  for (int s = 0; s < p.splitk; ++s) {
+    const int64_t idx = (int64_t(s) * nb + b) * p.M * p.N + rc;
+    re += part[2 * idx];
+    im += part[2 * idx + 1];
+  }
+  const int64_t off = batch_off(p.c_bs, p.nbb, (int)b) + map2(row, p.crs, p.crh, p.crl) +
+                      map2(col, p.ccs, p.cch, p.ccl);
+  reinterpret_cast<R*>(p.C)[2 * off] = re;
+  reinterpret_cast<R*>(p.C)[2 * off + 1] = im;
+}
+
 // ---------------------------------------------------------------------------
 // Tile configurations and dispatch.
 // ---------------------------------------------------------------------------
@@ -3594,8 +3627,8 @@ static const TileCfg kF32Tiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 32, 16},
                                     {128, 128, 16}, {128, 128, 16}, {128, 64, 16},
                                     {128, 64, 8},   {128, 128, 8},  {128, 128, 16},
                                     {128, 128, 16}, {128, 128, 16}, {128, 64, 16},
-                                    {1, 16, 64},    {2, 16, 64},    {4, 16, 64},
-                                    {8, 16, 64}};
+                                    {64, 64, 16},   {128, 32, 16},  {1, 16, 64},
+                                    {2, 16, 64},    {4, 16, 64},    {8, 16, 64}};
 static const TileCfg kF64Tiles[] = {{1, 1, 1},   {128, 64, 8}, {64, 32, 8},  {128, 64, 8},
                                     {64, 64, 8},  {128, 64, 8}, {64, 128, 8}, {64, 64, 8},
                                     {128, 64, 8}, {64, 128, 8}, {1, 16, 64},  {2, 16, 64},
@@ -3704,6 +3737,10 @@ bool gemm_tile_valid(rn_mode mode, int tile, int64_t M, int64_t N) {
   if (tile < 0 || tile >= tile_count_of(mode)) return false;
   if (const int mr = skinny_rows(mode, tile)) return std::min(M, N) <= mr;
   return true;
+}
+
+bool gemm_tile_splits(rn_mode mode, int tile) {
+  return tile > 0 && tile < tile_count_of(mode) && !skinny_rows(mode, tile);
 }
 
 int gemm_default_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
@@ -3828,8 +3865,12 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f32_dl<1, 4, 4, 1, 16><<<grid, 256, 0, s>>>(p);
       } else if (tile == 16) {
         cgemm_f32_dl<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
-      } else {
+      } else if (tile == 17) {
         cgemm_f32_dl<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
+      } else if (tile == 18) {
+        cgemm_f32_dl<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
+      } else {
+        cgemm_f32_dl<4, 1, 1, 1, 16><<<grid, 256, 0, s>>>(p);
       }
     }
   }
@@ -3852,8 +3893,13 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
 // whatever the tile choice (at most one GEMM group per tile shape).
 size_t grouped_table_bound(rn_mode mode, int n) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  size_t b = al(2 * size_t(n) * sizeof(PermParams)) + al((2 * size_t(n) + 1) * sizeof(int32_t));
-  b += size_t(gemm_tile_count(mode)) *
+  // Permutes: up to two per problem, split over one table per tile shape
+  // (each table padded to 256 bytes twice).
+  const size_t groups = size_t(gemm_tile_count(mode));
+  size_t b = 2 * size_t(n) * sizeof(PermParams) + (2 * size_t(n) + groups) * sizeof(int32_t) +
+             2 * 256 * groups;
+  // One GEMM group per tile shape, plus the split-K reduction's table.
+  b += size_t(gemm_tile_count(mode) + 1) *
        (al(size_t(n) * sizeof(GemmParams)) + al((size_t(n) + 1) * sizeof(int32_t)));
   return b;
 }
@@ -3868,10 +3914,16 @@ size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
   const TileCfg& c = tile_of(G.mode, tile);
   std::vector<GemmParams> ps(probs.size());
   std::vector<int32_t> prefix(probs.size() + 1, 0);
+  // The MFMA tiles also split K (splitk > 1: partials reduced afterwards by
+  // splitk_reduce_grouped); the skinny and one-thread kernels do not.
+  const bool can_split = tile != 0 && !skinny_rows(G.mode, tile);
   for (size_t i = 0; i < probs.size(); ++i) {
     fill_params(probs[i], ps[i]);
-    ps[i].splitk = 1;
-    ps[i].kchunk = probs[i].K;
+    if (!can_split || probs[i].splitk <= 1 || !probs[i].partial) {
+      ps[i].splitk = 1;
+      ps[i].partial = nullptr;
+    }
+    ps[i].kchunk = (probs[i].K + ps[i].splitk - 1) / ps[i].splitk;
     int64_t blocks;
     if (skinny_rows(G.mode, tile)) {
       skinny_orient(ps[i]);
@@ -3883,7 +3935,7 @@ size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
     } else {
       ps[i].tiles_m = (int)((probs[i].M + c.bm - 1) / c.bm);
       ps[i].tiles_n = (int)((probs[i].N + c.bn - 1) / c.bn);
-      blocks = int64_t(ps[i].tiles_m) * ps[i].tiles_n;
+      blocks = int64_t(ps[i].tiles_m) * ps[i].tiles_n * ps[i].splitk;
     }
     prefix[i + 1] = prefix[i] + (int32_t)blocks;
   }
@@ -3984,11 +4036,56 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
         cgemm_f32_dl_grouped<1, 4, 4, 1, 16><<<grid, 256, 0, s>>>(t);
       } else if (tile == 16) {
         cgemm_f32_dl_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
-      } else {
+      } else if (tile == 17) {
         cgemm_f32_dl_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
+      } else if (tile == 18) {
+        cgemm_f32_dl_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
+      } else {
+        cgemm_f32_dl_grouped<4, 1, 1, 1, 16><<<grid, 256, 0, s>>>(t);
       }
       break;
   }
+  return hipGetLastError();
+}
+
+// Reduction of the split-K partials of a grouped batch: one table entry per
+// problem that was split (the GEMM parameters, with its partial buffer).
+size_t grouped_reduce_build(const std::vector<GemmLaunch>& probs, std::vector<char>& table,
+                            GroupedLaunch& G) {
+  G = GroupedLaunch{};
+  std::vector<GemmParams> ps;
+  std::vector<int32_t> prefix(1, 0);
+  for (const GemmLaunch& g : probs) {
+    if (g.splitk <= 1 || !g.partial || g.M <= 0 || g.N <= 0) continue;
+    GemmParams p;
+    fill_params(g, p);
+    ps.push_back(p);
+    const int64_t total = (int64_t(1) << g.nbb) * g.M * g.N;
+    prefix.push_back(prefix.back() + (int32_t)((total + 255) / 256));
+  }
+  G.n = (int)ps.size();
+  if (ps.empty()) return 0;
+  G.mode = probs[0].mode;
+  G.blocks = prefix.back();
+  G.params_off = 0;
+  G.prefix_off = (ps.size() * sizeof(GemmParams) + 255) & ~size_t(255);
+  size_t bytes = (G.prefix_off + prefix.size() * sizeof(int32_t) + 255) & ~size_t(255);
+  table.assign(bytes, 0);
+  memcpy(table.data(), ps.data(), ps.size() * sizeof(GemmParams));
+  memcpy(table.data() + G.prefix_off, prefix.data(), prefix.size() * sizeof(int32_t));
+  return bytes;
+}
+
+hipError_t launch_reduce_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s) {
+  if (G.n == 0 || G.blocks == 0) return hipSuccess;
+  GroupTable t;
+  t.probs = reinterpret_cast<const GemmParams*>(static_cast<const char*>(table_dev) + G.params_off);
+  t.prefix = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.prefix_off);
+  t.n = G.n;
+  if (G.mode == RN_FP64)
+    splitk_reduce_grouped<double><<<dim3((unsigned)G.blocks), 256, 0, s>>>(t);
+  else
+    splitk_reduce_grouped<float><<<dim3((unsigned)G.blocks), 256, 0, s>>>(t);
   return hipGetLastError();
 }
 

@@ -149,6 +149,9 @@ int gemm_tile_count(rn_mode mode);
 // skinny kernel needs min(M, N) <= 8; launch_gemm falls back to the default).
 bool gemm_tile_valid(rn_mode mode, int tile, int64_t M, int64_t N);
 int gemm_default_tile(rn_mode mode, int64_t M, int64_t N, int64_t K);
+// Whether tile index `tile` can split K across workgroups (the MFMA tiles;
+// not the one-thread or skinny kernels).
+bool gemm_tile_splits(rn_mode mode, int tile);
 
 // Grouped launches: many problems (or permutations) in one kernel launch.
 // The host builds a parameter table plus a prefix sum of workgroups per
@@ -194,6 +197,9 @@ hipError_t launch_direct_grouped(const GroupedLaunch& G, const void* table_dev, 
 size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
                           std::vector<char>& table, GroupedLaunch& G);
 hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s);
+size_t grouped_reduce_build(const std::vector<GemmLaunch>& probs, std::vector<char>& table,
+                            GroupedLaunch& G);
+hipError_t launch_reduce_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s);
 int choose_splitk(rn_mode mode, int64_t M, int64_t N, int64_t K, int64_t batch);
 
 rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor* B,

@@ -175,3 +175,42 @@ def test_network_graph_replay_matches_eager(ctx):
         torch.randn(1 << 16, device="cuda").sum()
         torch.cuda.synchronize()
         assert torch.equal(amp, eager), rep
+
+
+def test_prepared_batch_replays_new_values(ctx):
+    # A prepared batch on a side stream runs directly, is captured, then
+    # replayed without planning; operands rewritten in place before every
+    # call must show up in every result (Gaussian integers: bit-exact).
+    import torch
+    import paper_2201_06620_amd as rn
+    probs = small_batch(12, seed=4242, integer=True)
+    items = [(to_dev(p.a.data, "fp32_4m"), p.a.dims, p.a.grid, to_dev(p.b.data, "fp32_4m"),
+              p.b.dims, p.b.grid, p.axes_a, p.axes_b) for p in probs]
+    side = torch.cuda.Stream()
+    ctx.set_graphs(True)
+    pb = ctx.prepare_batch(items, "fp32_4m")
+    for rep in range(4):
+        log(f"prepared batch call {rep}")
+        rs = np.random.default_rng(99 + rep)
+        news = []
+        for (a, _, _, b, _, _, _, _), p in zip(items, probs):
+            na = rs.integers(-8, 9, a.numel()) + 1j * rs.integers(-8, 9, a.numel())
+            nb = rs.integers(-8, 9, b.numel()) + 1j * rs.integers(-8, 9, b.numel())
+            a.copy_(torch.from_numpy(na).to(torch.complex64))
+            b.copy_(torch.from_numpy(nb).to(torch.complex64))
+            news.append((na, nb))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            outs = pb.run()
+        side.synchronize()
+        for p, (na, nb), o in zip(probs, news, outs):
+            ref, _, _ = oracle.block_tensordot(na, p.a.dims, p.a.grid, nb, p.b.dims, p.b.grid,
+                                               p.axes_a, p.axes_b)
+            assert np.array_equal(o.cpu().numpy().astype(np.complex128), ref), rep
+    # A call that differs only in a too small workspace size is planned
+    # again (no replay) and refused.
+    pb.wn = 256
+    with pytest.raises(rn.RnError):
+        with torch.cuda.stream(side):
+            pb.run()
+    side.synchronize()
