@@ -155,11 +155,18 @@ rn_status rn_block_footprint(const rn_tensor* A, const rn_tensor* B, int32_t k,
 
 /* Many independent block tensordots in one call (same mode).  Plans every
  * problem first (any invalid problem fails the whole call before anything is
- * enqueued).  Then one grouped launch relayouts every operand that needs it
- * and one grouped launch per GEMM tile shape contracts all problems, the
- * problems ordered by decreasing flops; no split-K.  Per-problem parameters
- * are copied into the end of the workspace first.  ws_bytes from
- * rn_block_tensordot_batch_plan. */
+ * enqueued).  The problems are grouped by GEMM tile shape; per group one
+ * grouped launch relayouts the operands that need it and one grouped launch
+ * contracts its problems (ordered by decreasing flops), the groups spread
+ * over up to four streams joined back into `stream`.  Problems with few
+ * output tiles and K >= 512 split K (partials in the workspace, summed in
+ * ascending order by one grouped launch at the end), so results do not
+ * depend on the other problems of the batch.  Per-problem parameters are
+ * copied into the end of the workspace first.  ws_bytes from
+ * rn_block_tensordot_batch_plan.  With graph replay on, a call identical to
+ * an earlier captured one (descriptors, data pointers, axes, workspace
+ * pointer and size, stream, tuning) replays its graph without planning
+ * again; the earlier call was checked in full. */
 rn_status rn_block_tensordot_batch_plan(rn_handle h, int32_t n, const rn_tensor* A,
                                         const rn_tensor* B, const int32_t* k,
                                         const int32_t* const* axesA,
