@@ -2039,15 +2039,19 @@ constexpr size_t big_lds_bytes() {
 // embedding with the real k of an instruction taken from consecutive floats.
 // Edge tiles stage through registers into the same layout, zero-filled.
 __device__ __forceinline__ int dl_swz(int r) { return (r ^ (r >> 3)) & 7; }
+// Rows of 16 chunks (BK = 32): 256-byte rows start on the same bank, so the
+// low four row bits alone spread 8 or 16 consecutive rows.
+__device__ __forceinline__ int dl_swz16(int r) { return r & 15; }
 
 template <int WM, int WN, int TM, int TN, int BK>
 __device__ __forceinline__ void cgemm_f32_dl_body(const GemmParams& p, int tm, int tn,
                                                   int split, int b) {
   static_assert(WM * WN == 4, "four waves");
-  static_assert(BK == 16, "eight 16-byte chunks per LDS row");
+  static_assert(BK == 16 || BK == 32, "eight or sixteen 16-byte chunks per LDS row");
   constexpr int BM = WM * TM * 32;
   constexpr int BN = WN * TN * 32;  // complex columns
   constexpr int CPR = BK / 2;       // chunks per row
+  auto swz = [](int r) -> int { return CPR == 8 ? dl_swz(r) : dl_swz16(r); };
   constexpr int AV = BM * CPR;      // chunks per stage
   constexpr int BV = BN * CPR;
   static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
@@ -2076,21 +2080,21 @@ __device__ __forceinline__ void cgemm_f32_dl_body(const GemmParams& p, int tm, i
   const int nk = (int)((kend - kbeg + BK - 1) / BK);
   const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
 
-  // Slot s = 256 j + tid of a stage: row s / 8, stored chunk s % 8, which
-  // holds logical chunk (s % 8) ^ dl_swz(row).
+  // Slot s = 256 j + tid of a stage: row s / CPR, stored chunk s % CPR,
+  // which holds logical chunk (s % CPR) ^ swz(row).
   auto dma = [&](auto buf, int64_t k0) {
     float4* As = abuf(buf);
     float4* Bs = bbuf(buf);
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
+      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) ^ swz(r);
       __builtin_amdgcn_global_load_lds(
           Ag + (row0 + r) * p.lda + k0 + 2 * c,
           (__attribute__((address_space(3))) void*)(As + 256 * j + 64 * wave), 16, 0, 0);
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
+      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) ^ swz(r);
       __builtin_amdgcn_global_load_lds(
           Bg + (col0 + r) * p.ldb + k0 + 2 * c,
           (__attribute__((address_space(3))) void*)(Bs + 256 * j + 64 * wave), 16, 0, 0);
@@ -2100,7 +2104,7 @@ __device__ __forceinline__ void cgemm_f32_dl_body(const GemmParams& p, int tm, i
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = s & 7;
+      const int s = tid + 256 * j, r = s / CPR, c = s % CPR;
       const int64_t gr = row0 + r, gk = k0 + 2 * c;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (gr < p.M) {
@@ -2117,7 +2121,7 @@ __device__ __forceinline__ void cgemm_f32_dl_body(const GemmParams& p, int tm, i
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = s & 7;
+      const int s = tid + 256 * j, r = s / CPR, c = s % CPR;
       const int64_t gr = col0 + r, gk = k0 + 2 * c;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (gr < p.N) {
@@ -2138,13 +2142,13 @@ __device__ __forceinline__ void cgemm_f32_dl_body(const GemmParams& p, int tm, i
     float4* Bs = bbuf(buf);
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s >> 3;
-      As[r * CPR + ((s & 7) ^ dl_swz(r))] = ra[j];
+      const int s = tid + 256 * j, r = s / CPR;
+      As[r * CPR + ((s % CPR) ^ swz(r))] = ra[j];
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s >> 3;
-      Bs[r * CPR + ((s & 7) ^ dl_swz(r))] = rb[j];
+      const int s = tid + 256 * j, r = s / CPR;
+      Bs[r * CPR + ((s % CPR) ^ swz(r))] = rb[j];
     }
   };
 
@@ -2181,12 +2185,12 @@ __device__ __forceinline__ void cgemm_f32_dl_body(const GemmParams& p, int tm, i
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int r = arow + 32 * i;
-        a4[i] = As[r * CPR + ((2 * g + kh) ^ dl_swz(r))];
+        a4[i] = As[r * CPR + ((2 * g + kh) ^ swz(r))];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int r = brow + 32 * j;
-        b4[j] = Bs[r * CPR + ((2 * g + kh) ^ dl_swz(r))];
+        b4[j] = Bs[r * CPR + ((2 * g + kh) ^ swz(r))];
         n4[j] = make_float4(b4[j].x, -b4[j].y, b4[j].z, -b4[j].w);
       }
 #pragma unroll
@@ -3627,8 +3631,9 @@ static const TileCfg kF32Tiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 32, 16},
                                     {128, 128, 16}, {128, 128, 16}, {128, 64, 16},
                                     {128, 64, 8},   {128, 128, 8},  {128, 128, 16},
                                     {128, 128, 16}, {128, 128, 16}, {128, 64, 16},
-                                    {64, 64, 16},   {128, 32, 16},  {1, 16, 64},
-                                    {2, 16, 64},    {4, 16, 64},    {8, 16, 64}};
+                                    {64, 64, 16},   {128, 32, 16},  {64, 64, 32},
+                                    {128, 32, 32},  {1, 16, 64},    {2, 16, 64},
+                                    {4, 16, 64},    {8, 16, 64}};
 static const TileCfg kF64Tiles[] = {{1, 1, 1},   {128, 64, 8}, {64, 32, 8},  {128, 64, 8},
                                     {64, 64, 8},  {128, 64, 8}, {64, 128, 8}, {64, 64, 8},
                                     {128, 64, 8}, {64, 128, 8}, {1, 16, 64},  {2, 16, 64},
@@ -3869,8 +3874,12 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f32_dl<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
       } else if (tile == 18) {
         cgemm_f32_dl<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
-      } else {
+      } else if (tile == 19) {
         cgemm_f32_dl<4, 1, 1, 1, 16><<<grid, 256, 0, s>>>(p);
+      } else if (tile == 20) {
+        cgemm_f32_dl<2, 2, 1, 1, 32><<<grid, 256, 0, s>>>(p);
+      } else {
+        cgemm_f32_dl<4, 1, 1, 1, 32><<<grid, 256, 0, s>>>(p);
       }
     }
   }
@@ -4040,8 +4049,12 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
         cgemm_f32_dl_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
       } else if (tile == 18) {
         cgemm_f32_dl_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
-      } else {
+      } else if (tile == 19) {
         cgemm_f32_dl_grouped<4, 1, 1, 1, 16><<<grid, 256, 0, s>>>(t);
+      } else if (tile == 20) {
+        cgemm_f32_dl_grouped<2, 2, 1, 1, 32><<<grid, 256, 0, s>>>(t);
+      } else {
+        cgemm_f32_dl_grouped<4, 1, 1, 1, 32><<<grid, 256, 0, s>>>(t);
       }
       break;
   }

@@ -203,16 +203,23 @@ def dl_swz(r):
     return (r ^ (r >> 3)) & 7
 
 
+def dl_swz16(r):
+    return r & 15
+
+
 def test_fp32_direct_lds_tiles():
     # Direct-to-LDS tile: a wave's copy writes 64 consecutive 16-byte slots;
-    # slot s of a stage holds logical chunk (s % 8) ^ dl_swz(row) of row s / 8.
+    # slot s of a stage holds logical chunk (s % cpr) ^ swz(row) of row
+    # s / cpr, with cpr = BK / 2 chunks per row (8 or 16).
     shapes = instances("cgemm_f32_dl")
     assert shapes
     for wm_, wn_, tm, tn, bk in shapes:
-        assert bk == 16
+        assert bk in (16, 32)
+        cpr = bk // 2
+        swz = dl_swz if cpr == 8 else dl_swz16
         bm, bn = wm_ * tm * 32, wn_ * tn * 32
         for rows in (bm, bn):
-            v = rows * 8
+            v = rows * cpr
             assert v % 256 == 0
             seen = set()
             for j in range(v // 256):
@@ -221,35 +228,36 @@ def test_fp32_direct_lds_tiles():
                     s = tid + 256 * j
                     dst = 256 * j + 64 * wave + lane  # slot the copy writes
                     assert dst == s and 0 <= dst < v
-                    r, c = s >> 3, (s & 7) ^ dl_swz(s >> 3)
+                    r, c = s // cpr, (s % cpr) ^ swz(s // cpr)
                     assert r < rows and 0 <= 2 * c and 2 * c + 1 < bk
                     seen.add((r, c))
                     # the edge path stores the same logical chunk at the same slot
-                    assert r * 8 + ((c ^ dl_swz(r)) & 7) == s
+                    assert r * cpr + ((c ^ swz(r)) % cpr) == s
             assert len(seen) == v  # every chunk of the stage exactly once
         for lane in range(64):
             kh = lane >> 5
             for w in range(4):
                 wm, wn = w // wn_, w % wn_
-                for g in range(4):
+                for g in range(cpr // 2):
                     for base, t, n in ((wm * tm * 32, tm, bm), (wn * tn * 32, tn, bn)):
                         for i in range(t):
                             r = base + (lane & 31) + 32 * i
-                            slot = r * 8 + ((2 * g + kh) ^ dl_swz(r))
-                            assert r < n and r * 8 <= slot < r * 8 + 8
+                            slot = r * cpr + ((2 * g + kh) ^ swz(r))
+                            assert r < n and r * cpr <= slot < r * cpr + cpr
                             # the slot holds logical chunk 2g + kh of row r
-                            assert ((slot & 7) ^ dl_swz(r)) == 2 * g + kh
+                            assert ((slot % cpr) ^ swz(r)) == 2 * g + kh
 
 
 def test_fp32_direct_lds_reads_spread_banks():
     # 128-bit fragment reads: 8 (32 banks) or 16 (64 banks) consecutive lanes
     # read consecutive rows at one logical chunk; their slots must fall on
-    # distinct 16-byte bank groups.
-    for group, nchunk in ((8, 8), (16, 16)):
-        for r0 in range(0, 256, group):
-            for c in range(8):
-                got = {(r * 8 + (c ^ dl_swz(r))) % nchunk for r in range(r0, r0 + group)}
-                assert len(got) == group
+    # distinct 16-byte bank groups, for rows of 8 and of 16 chunks.
+    for cpr, swz in ((8, dl_swz), (16, dl_swz16)):
+        for group, nchunk in ((8, 8), (16, 16)):
+            for r0 in range(0, 256, group):
+                for c in range(cpr):
+                    got = {(r * cpr + (c ^ swz(r))) % nchunk for r in range(r0, r0 + group)}
+                    assert len(got) == group
 
 
 def test_fp64_direct_lds_tiles():
