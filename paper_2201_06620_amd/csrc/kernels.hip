@@ -3673,8 +3673,11 @@ static int skinny_tile(rn_mode mode, int64_t rows) {
 }
 
 static int choose_tile(rn_mode mode, int64_t M, int64_t N, int64_t K) {
-  if (M * N * K <= (int64_t(1) << 15)) return 0;
+  // The one-thread kernel loops over K alone: only for short K.  Long K with
+  // a narrow output goes to the skinny kernel, whose lanes stride over K.
+  if (M * N * K <= (int64_t(1) << 15) && K <= 256) return 0;
   if (std::min(M, N) <= kSkinnyRows) return skinny_tile(mode, std::min(M, N));
+  if (M * N * K <= (int64_t(1) << 15)) return 0;
   if (M < 16 || N < 8) return 0;
   if (M >= 128 && N >= 64 && M * N >= (int64_t(1) << 18)) {
     // Direct-to-LDS tiles, except the 128 x 64 split-BF16 Re/Im tile.
