@@ -86,3 +86,66 @@ def test_rank28_sampled_integers_bitwise():
         assert np.array_equal(got, ref), mode
 
     run_modes(p, idx, check)
+
+
+def unitary_rank28(seed):
+    """A 2^14 x 2^14 unitary as a rank-28 tensor (row bits, then column
+    bits): the Kronecker product of seven 4 x 4 unitaries Q_i, each the Q
+    factor of a seeded complex normal matrix.  Also returns
+    || |U|^T |U| ||_F = prod_i || |Q_i|^T |Q_i| ||_F (|U| is the Kronecker
+    product of the |Q_i|), the scale of the terms the contraction sums."""
+    rs = np.random.default_rng(seed)
+    u = np.ones((1, 1), dtype=np.complex128)
+    scale = 1.0
+    for _ in range(7):
+        q, _ = np.linalg.qr(rs.normal(size=(4, 4)) + 1j * rs.normal(size=(4, 4)))
+        u = np.kron(u, q)
+        scale *= np.linalg.norm(np.abs(q).T @ np.abs(q))
+    return u.reshape([2] * RANK), scale, rs
+
+
+def test_rank28_unitary_full_output():
+    # Closed form at full size, every output checked: contracting a unitary
+    # U with conj(U) over its row axes gives the identity over the column
+    # axes, whatever order the axes are stored and paired in.  U's axes are
+    # stored in a seeded random order and the 14 row axes paired in another,
+    # so both operands take real permutes.  The exact result is the sum of
+    # 2^14 terms that cancel to 0 or 1, so the error is measured against the
+    # scale of those terms, || |U|^T |U| ||_F (normwise, as rounding error
+    # bounds are stated), with the mode's tolerance; the error relative to
+    # ||I||_F is logged too.
+    import torch
+    import paper_2201_06620_amd as rn
+    log("generating a rank-28 unitary")
+    u, scale, rs = unitary_rank28(2814)
+    perm = rs.permutation(RANK)            # stored axis j holds original axis perm[j]
+    pos = np.argsort(perm)                 # original axis -> stored position
+    rows = rs.permutation(K)               # pairing order of the row axes
+    axes = [int(pos[a]) for a in rows]
+    t = np.ascontiguousarray(u.transpose(perm)).reshape(-1)
+    tc = np.conj(t)
+    del u
+    ctx = rn.Context(0)
+    dims = [2] * RANK
+    n = 2 ** (RANK - K)
+    log(f"scale || |U|^T |U| ||_F = {scale:.4g}, ||I||_F = {np.sqrt(n):.4g}")
+    errs = {}
+    for dt, modes in ((torch.complex64, ("fp32_4m", "fp32_3m", "bf16x3")),
+                      (torch.complex128, ("fp64",))):
+        a = torch.from_numpy(t).to(dt).cuda()
+        b = torch.from_numpy(tc).to(dt).cuda()
+        for mode in modes:
+            log(f"mode {mode}: U . conj(U) over 14 row axes, full 2^28 output")
+            c, cd, _ = ctx.block_tensordot(a, dims, None, b, dims, None, axes, axes, mode)
+            assert cd == [2] * (2 * (RANK - K))
+            m = c.view(n, n).to(torch.complex128)
+            d = m.diagonal()
+            err2 = (m.abs() ** 2).sum() - (d.abs() ** 2).sum() + ((d - 1).abs() ** 2).sum()
+            err = float(err2.clamp(min=0).sqrt())
+            errs[mode] = err / scale
+            log(f"  ||C - I||_F / scale = {err / scale:.3e}   / ||I||_F = {err / np.sqrt(n):.3e}")
+            del c, m, d
+        del a, b
+        torch.cuda.empty_cache()
+    for mode, e in errs.items():
+        assert e < TOL[mode], (mode, e)
