@@ -4224,6 +4224,11 @@ __global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
   }
 }
 
+size_t grouped_perm_bound(int n) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  return al(size_t(n) * sizeof(PermParams)) + al((size_t(n) + 1) * sizeof(int32_t));
+}
+
 size_t grouped_direct_bound(int n) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   return al(size_t(n) * sizeof(DirectStep)) + al((size_t(n) + 1) * sizeof(int32_t));

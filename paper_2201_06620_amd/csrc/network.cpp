@@ -344,8 +344,10 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
   if (!eff(fin).empty()) return fail(RN_ERR_INVALID, "network does not close to a scalar");
   // Workspace in execution order: level by level; the small steps of a
   // level run together in one launch, so their results are all live at once
-  // and their operands are released only after that launch; the large steps
-  // of the level then run one after another.
+  // and their operands are released only after that launch; then one grouped
+  // launch permutes the operands of all large steps of the level (their
+  // permuted copies stay live until the level ends), and the large steps'
+  // GEMMs run one after another.
   auto release_operand = [&](int id) {
     if (!P.T[id].input) arena.release(P.T[id].off, P.T[id].bytes);
   };
@@ -368,8 +370,19 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
         st.offB = arena.alloc(st.bbytes);
         if (split_prec) st.offB2 = arena.alloc(st.bbytes);
       }
+    }
+    for (int si : lv) {
+      NStep& st = P.steps[si];
+      if (st.direct) continue;
       if (st.splitk > 1) st.offPart = arena.alloc(st.pbytes);
       P.T[nt + si].off = arena.alloc(P.T[nt + si].bytes);
+      if (st.splitk > 1) arena.release(st.offPart, st.pbytes);
+      release_operand(st.a);
+      release_operand(st.b);
+    }
+    for (int si : lv) {
+      NStep& st = P.steps[si];
+      if (st.direct) continue;
       if (st.permuteA) {
         arena.release(st.offA, st.abytes);
         if (split_prec) arena.release(st.offA2, st.abytes);
@@ -378,9 +391,6 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
         arena.release(st.offB, st.bbytes);
         if (split_prec) arena.release(st.offB2, st.bbytes);
       }
-      if (st.splitk > 1) arena.release(st.offPart, st.pbytes);
-      release_operand(st.a);
-      release_operand(st.b);
     }
   }
   P.sums_off = (arena.peak + 255) & ~int64_t(255);
@@ -388,9 +398,14 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
   P.table_off = P.sums_off + (npass > 1 ? ((16 * npass + 255) & ~int64_t(255)) : 0);
   int64_t tbytes = 0;
   for (auto& lv : P.levels) {
-    int nd = 0;
-    for (int si : lv) nd += P.steps[si].direct ? 1 : 0;
+    int nd = 0, np = 0;
+    for (int si : lv) {
+      const NStep& st = P.steps[si];
+      nd += st.direct ? 1 : 0;
+      np += st.direct ? 0 : (st.permuteA ? 1 : 0) + (st.permuteB ? 1 : 0);
+    }
     if (nd) tbytes += (int64_t)grouped_direct_bound(nd);
+    if (np && P.nout == 0) tbytes += (int64_t)grouped_perm_bound(np);
   }
   P.ws_bytes = P.table_off + tbytes;
   *NP = std::move(P);
@@ -410,56 +425,95 @@ static const void* tensor_ptr(const NetPlan& P, const rn_tensor* T, char* w, int
   return static_cast<const char*>(T[t.input_idx].data) + off * P.es;
 }
 
-// Parameter tables of the grouped small-step launches, one per level, with
-// operand pointers resolved for this call (pass 0; the kernel adds the
-// projection offsets of later passes).
-using LevelLaunches = std::vector<GroupedLaunch>;
+// Parameter tables of the grouped launches of each level, with operand
+// pointers resolved for this call: the small steps (pass 0; the kernel adds
+// the projection offsets of later passes) and, when the network runs in one
+// pass, the permutes of the large steps' operands.
+struct LevelLaunches {
+  std::vector<GroupedLaunch> direct, perm;
+};
 static void build_net_tables(const NetPlan& P, const rn_tensor* T, void* ws,
                              std::vector<char>& blob, LevelLaunches& per_level) {
   char* w = static_cast<char*>(ws);
   const int nt = (int)P.T.size() - (int)P.steps.size();
+  const bool split_prec = (P.mode == RN_BF16X3);
   blob.clear();
-  per_level.assign(P.levels.size(), GroupedLaunch{});
+  per_level.direct.assign(P.levels.size(), GroupedLaunch{});
+  per_level.perm.assign(P.levels.size(), GroupedLaunch{});
   std::vector<char> part;
   auto ptr = [&](int id) { return tensor_ptr(P, T, w, id, 0); };
   for (size_t L = 0; L < P.levels.size(); ++L) {
     std::vector<DirectStep> ds;
+    std::vector<PermLaunch> pj;
     for (int si : P.levels[L]) {
       const NStep& st = P.steps[si];
-      if (!st.direct) continue;
+      if (!st.direct) {
+        if (P.nout != 0) continue;
+        for (int side = 0; side < 2; ++side) {
+          if (!(side ? st.permuteB : st.permuteA)) continue;
+          PermLaunch pl;
+          pl.in = ptr(side ? st.b : st.a);
+          pl.out = w + (side ? st.offB : st.offA);
+          pl.out2 = split_prec ? w + (side ? st.offB2 : st.offA2) : nullptr;
+          pl.perm = side ? st.permB : st.permA;
+          pl.in_es = P.es;
+          pl.kind = split_prec ? 1 : 0;
+          pj.push_back(pl);
+        }
+        continue;
+      }
       DirectStep d = st.dstep;
       d.A = ptr(st.a);
       d.B = ptr(st.b);
       d.C = w + P.T[nt + si].off;
       ds.push_back(d);
     }
-    if (ds.empty()) continue;
-    GroupedLaunch G;
-    size_t base = blob.size();
-    grouped_direct_build(ds, P.mode, part, G);
-    G.params_off += base;
-    G.prefix_off += base;
-    blob.insert(blob.end(), part.begin(), part.end());
-    per_level[L] = G;
+    if (!ds.empty()) {
+      GroupedLaunch G;
+      size_t base = blob.size();
+      grouped_direct_build(ds, P.mode, part, G);
+      G.params_off += base;
+      G.prefix_off += base;
+      blob.insert(blob.end(), part.begin(), part.end());
+      per_level.direct[L] = G;
+    }
+    if (!pj.empty()) {
+      GroupedLaunch G;
+      size_t base = blob.size();
+      grouped_perm_build(pj, part, G);
+      G.params_off += base;
+      G.prefix_off += base;
+      blob.insert(blob.end(), part.begin(), part.end());
+      per_level.perm[L] = G;
+    }
   }
 }
 
 static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hipStream_t s,
                               int64_t pass, double* sum_dev, double* slices_dev, Profiler* prof,
-                              const std::vector<GroupedLaunch>& per_level) {
+                              const LevelLaunches& per_level) {
   char* w = static_cast<char*>(ws);
   const bool split_prec = (P.mode == RN_BF16X3);
   auto ptr = [&](int id) { return tensor_ptr(P, T, w, id, pass); };
   hipError_t e;
   const int nt = (int)P.T.size() - (int)P.steps.size();
   for (size_t L = 0; L < P.levels.size(); ++L) {
-    // All small steps of this level in one launch, then the large ones.
-    if (per_level[L].n > 0) {
+    // All small steps of this level in one launch, then the permutes of the
+    // large steps in one launch, then the large steps' GEMMs.
+    if (per_level.direct[L].n > 0) {
       int ev = prof->begin(1, s);
-      e = launch_direct_grouped(per_level[L], w + P.table_off, pass, P.nout, s);
+      e = launch_direct_grouped(per_level.direct[L], w + P.table_off, pass, P.nout, s);
       prof->end(ev, s);
       if (e != hipSuccess)
         return fail(RN_ERR_HIP, std::string("network small steps: ") + hipGetErrorString(e));
+    }
+    const bool grouped_perm = per_level.perm[L].n > 0;
+    if (grouped_perm) {
+      int ev = prof->begin(0, s);
+      e = launch_permute_grouped(per_level.perm[L], w + P.table_off, s);
+      prof->end(ev, s);
+      if (e != hipSuccess)
+        return fail(RN_ERR_HIP, std::string("network permutes: ") + hipGetErrorString(e));
     }
     for (int si : P.levels[L]) {
       const NStep& st = P.steps[si];
@@ -468,7 +522,16 @@ static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hi
       const void* bm = ptr(st.b);
       const void* am2 = nullptr;
       const void* bm2 = nullptr;
-      if (st.permuteA) {
+      if (grouped_perm) {
+        if (st.permuteA) {
+          am = w + st.offA;
+          am2 = split_prec ? w + st.offA2 : nullptr;
+        }
+        if (st.permuteB) {
+          bm = w + st.offB;
+          bm2 = split_prec ? w + st.offB2 : nullptr;
+        }
+      } else if (st.permuteA) {
         PermLaunch pl;
         pl.in = am;
         pl.out = w + st.offA;
@@ -484,7 +547,7 @@ static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hi
         am = pl.out;
         am2 = pl.out2;
       }
-      if (st.permuteB) {
+      if (!grouped_perm && st.permuteB) {
         PermLaunch pl;
         pl.in = bm;
         pl.out = w + st.offB;

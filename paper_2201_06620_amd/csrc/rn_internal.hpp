@@ -188,6 +188,8 @@ struct DirectStep {
 };
 constexpr int64_t kDirectMaxK = 4096;
 size_t grouped_direct_bound(int n);
+// Bytes of the table of one grouped permute of n jobs.
+size_t grouped_perm_bound(int n);
 size_t grouped_direct_build(const std::vector<DirectStep>& steps, rn_mode mode,
                             std::vector<char>& table, GroupedLaunch& G);
 // pass / nout: the pass index and the number of sliced bonds a pass fixes
