@@ -2,12 +2,14 @@
 // tile autotuner.
 //
 // A batch of independent contractions (the uneven-problem workload) is run
-// as one grouped permute launch over every operand that needs a relayout
-// and one grouped GEMM launch per tile shape, with problems ordered by
-// decreasing work so the largest start first.  The per-problem parameters
-// travel in a small table copied into the workspace.  When the same call is
-// repeated on a non-default stream, the recorded sequence (table copy plus
-// launches) is replayed as a HIP graph.
+// as one group per GEMM tile shape: a grouped permute of the operands its
+// problems need, then one grouped GEMM launch, problems ordered by
+// decreasing work so the largest start first; the groups are spread over up
+// to four streams, and problems with few tiles and a long K split K with one
+// grouped reduction at the end.  The per-problem parameters travel in a
+// small table copied into the workspace.  When the same call is repeated on
+// a non-default stream, the recorded sequence (table copy plus launches) is
+// replayed as a HIP graph, found before any planning.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -7,7 +7,8 @@
 // real 2k x 2n matrix whose 2x2 cell for b is [[b_r, b_i], [-b_i, b_r]].  One
 // real GEMM then yields C already interleaved, with 8*M*N*K real flops.  The
 // embedding of B is never stored: each lane builds its B operand from the
-// complex value in LDS (select re or im, flip a sign).
+// complex value in LDS (select re or im, flip a sign), or, in the
+// direct-to-LDS tiles, the pairing of MFMA operands does it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
