@@ -214,3 +214,28 @@ def test_prepared_batch_replays_new_values(ctx):
         with torch.cuda.stream(side):
             pb.run()
     side.synchronize()
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "fp32_3m", "bf16x3"])
+def test_batch_split_k_every_mode(ctx, mode):
+    # Problems with few output tiles and a long K split K inside a batch
+    # (partials reduced in ascending order afterwards): 16 x 16 and 32 x 64
+    # outputs with K = 1024 and 512, beside one that does not split.
+    tol = {"fp64": 1e-12, "fp32_4m": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3}[mode]
+    r = rng.SplitMix64(9090)
+    shapes = [(14, 14, 10), (14, 15, 9), (10, 9, 3)]
+    for integer in (False, True):
+        probs = [configs.make_problem(ra, rb, r.sample(ra, k), r.sample(rb, k),
+                                      configs.split_first(ra), configs.split_first(rb),
+                                      9100 + 7 * i, integer)
+                 for i, (ra, rb, k) in enumerate(shapes)]
+        _, res = run_batch(ctx, probs, mode)
+        for p, (c, cd, cg) in zip(probs, res):
+            ref, rd, rg = oracle.block_tensordot(p.a.data, p.a.dims, p.a.grid, p.b.data,
+                                                 p.b.dims, p.b.grid, p.axes_a, p.axes_b)
+            got = c.cpu().numpy().astype(np.complex128)
+            if integer:
+                assert np.array_equal(got, ref), mode
+            else:
+                err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+                assert err < tol, (mode, err)
