@@ -355,7 +355,7 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the contraction is not "
+        print(json.dumps({"error": "the library runs on one GPU; the contraction is not "
                                    "sharded across GPUs (run with --gpus 1)"}))
         return 2
 
