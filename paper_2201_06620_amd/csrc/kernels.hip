@@ -3168,6 +3168,181 @@ __device__ __forceinline__ void cgemm_f64_dl_body(const GemmParams& p, int tm, i
       }
 }
 
+// FP64 Gauss (3M) with the direct-to-LDS staging of the FP64 tile: the chunk
+// (a_r, a_i) a lane reads feeds T1 = Ar Br, T2 = Ai Bi and
+// T3 = (Ar + Ai)(Br + Bi), three instructions per tile and complex k where
+// the 4M tile takes four; Re = T1 - T2, Im = T3 - T1 - T2.  Three
+// accumulators per 16 x 16 tile: 64 x 64 is the largest tile without spills.
+// An alternative FP64 tile (the FP64 default stays the 4M one).
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_f64_3mdl_body(const GemmParams& p, int tm, int tn,
+                                                  int split, int b) {
+  static_assert(WM * WN == 4, "four waves");
+  static_assert(BK == 8, "eight 16-byte chunks per LDS row");
+  constexpr int BM = WM * TM * 16;
+  constexpr int BN = WN * TN * 16;  // complex columns
+  constexpr int CPR = BK;           // chunks (complex) per row
+  constexpr int AV = BM * CPR;      // chunks per stage
+  constexpr int BV = BN * CPR;
+  static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
+  constexpr int NA = AV / 256;
+  constexpr int NB = BV / 256;
+  __shared__ __align__(16) double2 Ad0[AV], Ad1[AV];
+  __shared__ __align__(16) double2 Bd0[BV], Bd1[BV];
+  auto abuf = [&](auto t) -> double2* { if constexpr (decltype(t)::value) return Ad1; else return Ad0; };
+  auto bbuf = [&](auto t) -> double2* { if constexpr (decltype(t)::value) return Bd1; else return Bd0; };
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const double2* __restrict__ Ag =
+      reinterpret_cast<const double2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
+  const double2* __restrict__ Bg =
+      reinterpret_cast<const double2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
+
+  auto dma = [&](auto buf, int64_t k0) {
+    double2* As = abuf(buf);
+    double2* Bs = bbuf(buf);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
+      __builtin_amdgcn_global_load_lds(
+          Ag + (row0 + r) * p.lda + k0 + c,
+          (__attribute__((address_space(3))) void*)(As + 256 * j + 64 * wave), 16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
+      __builtin_amdgcn_global_load_lds(
+          Bg + (col0 + r) * p.ldb + k0 + c,
+          (__attribute__((address_space(3))) void*)(Bs + 256 * j + 64 * wave), 16, 0, 0);
+    }
+  };
+  double2 ra[NA], rb[NB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j;
+      const int64_t gr = row0 + (s >> 3), gk = k0 + (s & 7);
+      ra[j] = (gr < p.M && gk < kend) ? Ag[gr * p.lda + gk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j;
+      const int64_t gr = col0 + (s >> 3), gk = k0 + (s & 7);
+      rb[j] = (gr < p.N && gk < kend) ? Bg[gr * p.ldb + gk] : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&](auto buf) {
+    double2* As = abuf(buf);
+    double2* Bs = bbuf(buf);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + 256 * j, r = s >> 3;
+      As[r * CPR + ((s & 7) ^ dl_swz(r))] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + 256 * j, r = s >> 3;
+      Bs[r * CPR + ((s & 7) ^ dl_swz(r))] = rb[j];
+    }
+  };
+
+  v4d t1[TM][TN], t2[TM][TN], t3[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) t1[i][j][e] = t2[i][j][e] = t3[i][j][e] = 0.0;
+
+  const int kq = lane >> 4;
+  const int arow = wm * TM * 16 + (lane & 15);
+  const int brow = wn * TN * 16 + (lane & 15);
+
+  auto stage = [&](auto fast, auto cur, int it) {
+    constexpr bool FAST = decltype(fast)::value;
+    constexpr bool CUR = decltype(cur)::value;
+    const double2* As = abuf(cur);
+    const double2* Bs = bbuf(cur);
+    if constexpr (FAST) {
+      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (it + 1 < nk) {
+      gload(kbeg + int64_t(it + 1) * BK);
+    }
+#pragma unroll
+    for (int g = 0; g < CPR / 4; ++g) {
+      double2 a2[TM], b2[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = arow + 16 * i;
+        a2[i] = As[r * CPR + ((4 * g + kq) ^ dl_swz(r))];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int r = brow + 16 * j;
+        b2[j] = Bs[r * CPR + ((4 * g + kq) ^ dl_swz(r))];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          t1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].x, b2[j].x, t1[i][j], 0, 0, 0);
+          t2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].y, b2[j].y, t2[i][j], 0, 0, 0);
+          t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].x + a2[i].y, b2[j].x + b2[j].y,
+                                                          t3[i][j], 0, 0, 0);
+        }
+    }
+    if constexpr (FAST) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
+    } else if (it + 1 < nk) {
+      sstore(BoolTag<!CUR>{});
+    }
+    __syncthreads();
+  };
+
+  auto mainloop = [&](auto fast) {
+    constexpr bool FAST = decltype(fast)::value;
+    if (nk > 0) {
+      if constexpr (FAST) {
+        dma(BoolTag<false>{}, kbeg);
+        __builtin_amdgcn_s_waitcnt(0);
+      } else {
+        gload(kbeg);
+        sstore(BoolTag<false>{});
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; it += 2) {
+      stage(fast, BoolTag<false>{}, it);
+      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
+    }
+  };
+  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
+
+  // 16x16 f64 accumulator layout: column lane % 16, rows 4*e + lane/16.
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t row = row0 + wm * TM * 16 + i * 16 + 4 * e + (lane >> 4);
+        int64_t col = col0 + wn * TN * 16 + j * 16 + (lane & 15);
+        const double a = t1[i][j][e], c = t2[i][j][e], d = t3[i][j][e];
+        store_out<double>(p, b, split, row, col, 0, a - c);
+        store_out<double>(p, b, split, row, col, 1, (d - a) - c);
+      }
+}
+
 // ---------------------------------------------------------------------------
 // Small problems: one thread per complex output, sequential K loop (FP64,
 // FP32 or split BF16 products).  Used when a tile would be mostly empty.
@@ -3502,6 +3677,7 @@ RN_GEMM_ENTRY(cgemm_f32_3mbig)
 // LDS: three workgroups per CU), four for the 64 x 64 and 128 x 32 tiles.
 RN_GEMM_ENTRY_OCC(cgemm_f32_dl, (TM * TN * WM * WN <= 4 ? 4 : TM * TN * WM * WN <= 8 ? 3 : 2))
 RN_GEMM_ENTRY_OCC(cgemm_f64_dl, 2)
+RN_GEMM_ENTRY_OCC(cgemm_f64_3mdl, 2)
 RN_GEMM_ENTRY_OCC(cgemm_f32_3mdl, 2)
 RN_GEMM_ENTRY_OCC(cgemm_bf16x3_dl, 2)
 RN_GEMM_ENTRY_OCC(cgemm_f64_big, 2)
@@ -3637,8 +3813,8 @@ static const TileCfg kF32Tiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 32, 16},
                                     {4, 16, 64},    {8, 16, 64}};
 static const TileCfg kF64Tiles[] = {{1, 1, 1},   {128, 64, 8}, {64, 32, 8},  {128, 64, 8},
                                     {64, 64, 8},  {128, 64, 8}, {64, 128, 8}, {64, 64, 8},
-                                    {128, 64, 8}, {64, 128, 8}, {1, 16, 64},  {2, 16, 64},
-                                    {4, 16, 64},  {8, 16, 64}};
+                                    {128, 64, 8}, {64, 128, 8}, {64, 64, 8},  {1, 16, 64},
+                                    {2, 16, 64},  {4, 16, 64},  {8, 16, 64}};
 static const TileCfg kBF16Tiles[] = {{1, 1, 1},      {128, 64, 16},  {64, 32, 16},
                                      {256, 64, 8},   {128, 128, 8},  {128, 64, 16},
                                      {128, 128, 8},  {256, 64, 8},   {128, 128, 16},
@@ -3803,8 +3979,10 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
         cgemm_f64_big<2, 2, 2, 2, 8><<<grid, 256, big64_lds_bytes<2, 2, 2, 2, 8>(), s>>>(p);
       else if (tile == 8)
         cgemm_f64_dl<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
-      else
+      else if (tile == 9)
         cgemm_f64_dl<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(p);
+      else
+        cgemm_f64_3mdl<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
     } else if (g.mode == RN_FP32_3M) {
       if (tile == 1)
         cgemm_f32_3m<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
@@ -3992,8 +4170,10 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
             <<<grid, 256, big64_lds_bytes<2, 2, 2, 2, 8>(), s>>>(t);
       else if (tile == 8)
         cgemm_f64_dl_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
-      else
+      else if (tile == 9)
         cgemm_f64_dl_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
+      else
+        cgemm_f64_3mdl_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
       break;
     case RN_FP32_3M:
       if (tile == 0) cgemm_small_grouped<RN_FP32_3M><<<grid, 256, 0, s>>>(t);

@@ -337,3 +337,41 @@ def test_bf16x3_direct_lds_tiles():
                     assert bf16_chunk_at(bk, r, 4 * q) == 4 * s
                     seen.add((r, q))
             assert len(seen) == v
+
+
+def test_fp64_3m_direct_lds_tiles():
+    # Same staging and fragment reads as the FP64 4M direct-to-LDS tile.
+    shapes = instances("cgemm_f64_3mdl")
+    assert shapes
+    for wm_, wn_, tm, tn, bk in shapes:
+        assert bk == 8
+        bm, bn = wm_ * tm * 16, wn_ * tn * 16
+        for rows in (bm, bn):
+            assert (rows * 8) % 256 == 0
+        for lane in range(64):
+            kq = lane >> 4
+            for w in range(4):
+                wm, wn = w // wn_, w % wn_
+                for g in range(bk // 4):
+                    for base, t, n in ((wm * tm * 16, tm, bm), (wn * tn * 16, tn, bn)):
+                        for i in range(t):
+                            r = base + (lane & 15) + 16 * i
+                            slot = r * 8 + ((4 * g + kq) ^ dl_swz(r))
+                            assert r < n and r * 8 <= slot < r * 8 + 8
+
+
+def test_fp64_gauss_tile_index():
+    # bench.py selects the FP64 Gauss tile by index through a tune file: it
+    # is the last FP64 tile before the four skinny ones.
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    table = SRC[SRC.index("kF64Tiles[] = {"):]
+    table = table[:table.index("};")]
+    entries = re.findall(r"\{\d+, \d+, \d+\}", table)
+    assert bench.FP64_GAUSS_TILE == len(entries) - 5
+    launch = SRC[SRC.index("hipError_t launch_gemm(const GemmLaunch& g"):]
+    launch = launch[:launch.index("} else if (g.mode == RN_FP32_3M)")]
+    assert re.search(r"else\s+cgemm_f64_3mdl<2, 2, 2, 2, 8>", launch)
+    assert "tile == %d" % (bench.FP64_GAUSS_TILE - 1) in launch
