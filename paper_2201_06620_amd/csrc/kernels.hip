@@ -3172,7 +3172,8 @@ __device__ __forceinline__ void cgemm_f64_dl_body(const GemmParams& p, int tm, i
 // (a_r, a_i) a lane reads feeds T1 = Ar Br, T2 = Ai Bi and
 // T3 = (Ar + Ai)(Br + Bi), three instructions per tile and complex k where
 // the 4M tile takes four; Re = T1 - T2, Im = T3 - T1 - T2.  Three
-// accumulators per 16 x 16 tile: 64 x 64 is the largest tile without spills.
+// accumulators per 16 x 16 tile: 64 x 64 is the largest tile without spills
+// in the loop; it runs three waves per SIMD (32 KiB of LDS per workgroup).
 // An alternative FP64 tile (the FP64 default stays the 4M one).
 template <int WM, int WN, int TM, int TN, int BK>
 __device__ __forceinline__ void cgemm_f64_3mdl_body(const GemmParams& p, int tm, int tn,
@@ -3677,7 +3678,7 @@ RN_GEMM_ENTRY(cgemm_f32_3mbig)
 // LDS: three workgroups per CU), four for the 64 x 64 and 128 x 32 tiles.
 RN_GEMM_ENTRY_OCC(cgemm_f32_dl, (TM * TN * WM * WN <= 4 ? 4 : TM * TN * WM * WN <= 8 ? 3 : 2))
 RN_GEMM_ENTRY_OCC(cgemm_f64_dl, 2)
-RN_GEMM_ENTRY_OCC(cgemm_f64_3mdl, 2)
+RN_GEMM_ENTRY_OCC(cgemm_f64_3mdl, 3)
 RN_GEMM_ENTRY_OCC(cgemm_f32_3mdl, 2)
 RN_GEMM_ENTRY_OCC(cgemm_bf16x3_dl, 2)
 RN_GEMM_ENTRY_OCC(cgemm_f64_big, 2)
