@@ -63,7 +63,9 @@ typedef enum {
 typedef enum { RN_C64 = 1, RN_C128 = 2 } rn_dtype;
 
 /* Arithmetic of the per-pair complex GEMM:
- *   RN_FP64    complex128, 4 real products per complex product, FP64 MFMA;
+ *   RN_FP64    complex128, 4 real products per complex product, FP64 MFMA
+ *              (a tune entry, from rn_autotune_batch or a tune file, may select
+ *              the FP64 Gauss tile instead: 3 real products, same tolerance);
  *   RN_FP32_4M complex64, 4 real products, FP32 MFMA, FP32 accumulation;
  *   RN_FP32_3M complex64, 3 real products (Gauss), FP32 MFMA;
  *   RN_BF16X3  complex64 operands split as x = hi + lo (both bfloat16),
