@@ -138,7 +138,8 @@ rn_status rn_block_tensordot_streamed(rn_handle h, const rn_tensor* A, const rn_
 
 /* Pair list of one output block (step 2 of Section II.C): for C block
  * `cblock` (row-major linear block index) writes up to `cap` pairs
- * (A block index, B block index), each a row-major linear index into the
+ * (A block index, B block index) into `pairs`, a host array of 2*cap
+ * int64 values (NULL: count only), each a row-major linear index into the
  * operand's own stored grid, in the order the GEMM K loop visits them
  * (ascending contracted block coordinates on the refined grid).  When a
  * stored block is finer-split by the refinement, the same stored block index

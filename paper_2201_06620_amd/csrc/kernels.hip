@@ -28,6 +28,16 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
+// Largest grid of one launch: HIP counts the work-items of a grid dimension
+// in 32 bits, and every kernel here runs 256 per workgroup.
+constexpr int64_t kMaxGrid = ((int64_t(1) << 32) - 1) / 256;
+
+// Block count of a grouped launch, or -1 when the groups add up to more than
+// one launch can hold (the launch then reports hipErrorInvalidConfiguration
+// instead of wrapping its 32-bit prefix sums).
+static int grouped_blocks(int64_t total) { return total <= kMaxGrid ? (int)total : -1; }
+static int32_t prefix_entry(int64_t total) { return (int32_t)std::min(total, kMaxGrid); }
+
 // ===========================================================================
 // Index permutation (TTGT relayout).  Output bit o of the linear element
 // index reads input bit src[o]; input bits outside src are fixed by in_base
@@ -314,12 +324,14 @@ size_t grouped_perm_build(const std::vector<PermLaunch>& jobs, std::vector<char>
   std::vector<PermParams> ps(jobs.size());
   std::vector<int32_t> prefix(jobs.size() + 1, 0);
   int max_tsize = 1;
+  int64_t total = 0;
   for (size_t i = 0; i < jobs.size(); ++i) {
     perm_setup(jobs[i], ps[i]);
     max_tsize = std::max(max_tsize, 1 << ps[i].nS);
-    prefix[i + 1] = prefix[i] + (int32_t)ps[i].ntiles;
+    total += ps[i].ntiles;
+    prefix[i + 1] = prefix_entry(total);
   }
-  G.blocks = prefix.back();
+  G.blocks = grouped_blocks(total);
   G.lds = size_t(max_tsize + (max_tsize >> 5) + 1) * G.es;
   G.params_off = 0;
   G.prefix_off = (jobs.size() * sizeof(PermParams) + 255) & ~size_t(255);
@@ -332,6 +344,7 @@ size_t grouped_perm_build(const std::vector<PermLaunch>& jobs, std::vector<char>
 
 hipError_t launch_permute_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s) {
   if (G.n == 0 || G.blocks == 0) return hipSuccess;
+  if (G.blocks < 0) return hipErrorInvalidConfiguration;
   PermTable t;
   t.jobs = reinterpret_cast<const PermParams*>(static_cast<const char*>(table_dev) + G.params_off);
   t.prefix = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.prefix_off);
@@ -3506,7 +3519,8 @@ __device__ __forceinline__ void skinny_mac(R* acc, const E& a, const E& bb) {
 }
 
 template <int MODE, int MR>
-__device__ __forceinline__ void cgemm_skinny_body(const GemmParams& p, int tn, int split, int b) {
+__device__ __forceinline__ void cgemm_skinny_body(const GemmParams& p, int64_t tn, int split,
+                                                  int b) {
   using R = typename std::conditional<MODE == RN_FP64, double, float>::type;
   using E = typename SkinnyElem<MODE>::T;
   constexpr int CPW = kSkinnyCols / 4;
@@ -3576,9 +3590,12 @@ __device__ __forceinline__ void cgemm_skinny_body(const GemmParams& p, int tn, i
   }
 }
 
+// Column tiles run grid-stride, so an outer product (K = 1) with billions of
+// columns still fits one launch.
 template <int MODE, int MR>
 __global__ __launch_bounds__(256) void cgemm_skinny(GemmParams p) {
-  cgemm_skinny_body<MODE, MR>(p, blockIdx.x, blockIdx.y, blockIdx.z);
+  for (int64_t tn = blockIdx.x; tn < p.tiles_n; tn += gridDim.x)
+    cgemm_skinny_body<MODE, MR>(p, tn, blockIdx.y, blockIdx.z);
 }
 
 template <int MODE>
@@ -3945,11 +3962,14 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
   const int ev = prof ? prof->begin(1, s) : -1;
   if (const int mr = skinny_rows(g.mode, tile)) {
     skinny_orient(p);
+    const int64_t tiles = (p.N + kSkinnyCols - 1) / kSkinnyCols;
+    if (tiles > INT32_MAX) return hipErrorInvalidConfiguration;
     p.tiles_m = 1;
-    p.tiles_n = (int)((p.N + kSkinnyCols - 1) / kSkinnyCols);
-    dim3 grid((unsigned)p.tiles_n, (unsigned)g.splitk, nbatch);
+    p.tiles_n = (int)tiles;
+    dim3 grid((unsigned)std::min<int64_t>(tiles, int64_t(1) << 20), (unsigned)g.splitk, nbatch);
     launch_skinny(g.mode, mr, grid, p, s);
   } else if (tile == 0) {
+    if ((g.M * g.N + 255) / 256 > kMaxGrid) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)((g.M * g.N + 255) / 256), (unsigned)g.splitk, nbatch);
     if (g.mode == RN_FP64)
       cgemm_small<RN_FP64><<<grid, 256, 0, s>>>(p);
@@ -3960,9 +3980,11 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
     else
       cgemm_small<RN_FP32_4M><<<grid, 256, 0, s>>>(p);
   } else {
-    p.tiles_m = (int)((g.M + c.bm - 1) / c.bm);
-    p.tiles_n = (int)((g.N + c.bn - 1) / c.bn);
-    dim3 grid((unsigned)(p.tiles_m * p.tiles_n), (unsigned)g.splitk, nbatch);
+    const int64_t tm = (g.M + c.bm - 1) / c.bm, tn = (g.N + c.bn - 1) / c.bn;
+    if (tm * tn > kMaxGrid) return hipErrorInvalidConfiguration;
+    p.tiles_m = (int)tm;
+    p.tiles_n = (int)tn;
+    dim3 grid((unsigned)(tm * tn), (unsigned)g.splitk, nbatch);
     if (g.mode == RN_FP64) {
       if (tile == 1)
         cgemm_f64_4m<2, 2, 4, 4, 8><<<grid, 256, 0, s>>>(p);
@@ -4106,6 +4128,7 @@ size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
   const TileCfg& c = tile_of(G.mode, tile);
   std::vector<GemmParams> ps(probs.size());
   std::vector<int32_t> prefix(probs.size() + 1, 0);
+  int64_t total = 0;
   // The MFMA tiles also split K (splitk > 1: partials reduced afterwards by
   // splitk_reduce_grouped); the skinny and one-thread kernels do not.
   const bool can_split = tile != 0 && !skinny_rows(G.mode, tile);
@@ -4119,19 +4142,21 @@ size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
     int64_t blocks;
     if (skinny_rows(G.mode, tile)) {
       skinny_orient(ps[i]);
+      blocks = (ps[i].N + kSkinnyCols - 1) / kSkinnyCols;
       ps[i].tiles_m = 1;
-      ps[i].tiles_n = (int)((ps[i].N + kSkinnyCols - 1) / kSkinnyCols);
-      blocks = ps[i].tiles_n;
+      ps[i].tiles_n = (int)std::min<int64_t>(blocks, INT32_MAX);
     } else if (tile == 0) {
       blocks = (probs[i].M * probs[i].N + 255) / 256;
     } else {
-      ps[i].tiles_m = (int)((probs[i].M + c.bm - 1) / c.bm);
-      ps[i].tiles_n = (int)((probs[i].N + c.bn - 1) / c.bn);
-      blocks = int64_t(ps[i].tiles_m) * ps[i].tiles_n * ps[i].splitk;
+      const int64_t tm = (probs[i].M + c.bm - 1) / c.bm, tn = (probs[i].N + c.bn - 1) / c.bn;
+      ps[i].tiles_m = (int)std::min<int64_t>(tm, INT32_MAX);
+      ps[i].tiles_n = (int)std::min<int64_t>(tn, INT32_MAX);
+      blocks = tm * tn * ps[i].splitk;
     }
-    prefix[i + 1] = prefix[i] + (int32_t)blocks;
+    total += blocks;
+    prefix[i + 1] = prefix_entry(total);
   }
-  G.blocks = prefix.back();
+  G.blocks = grouped_blocks(total);
   G.params_off = 0;
   G.prefix_off = (probs.size() * sizeof(GemmParams) + 255) & ~size_t(255);
   size_t bytes = (G.prefix_off + prefix.size() * sizeof(int32_t) + 255) & ~size_t(255);
@@ -4143,6 +4168,7 @@ size_t grouped_gemm_build(const std::vector<GemmLaunch>& probs, int tile,
 
 hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s) {
   if (G.n == 0 || G.blocks == 0) return hipSuccess;
+  if (G.blocks < 0) return hipErrorInvalidConfiguration;
   GroupTable t;
   t.probs = reinterpret_cast<const GemmParams*>(static_cast<const char*>(table_dev) + G.params_off);
   t.prefix = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.prefix_off);
@@ -4253,18 +4279,19 @@ size_t grouped_reduce_build(const std::vector<GemmLaunch>& probs, std::vector<ch
   G = GroupedLaunch{};
   std::vector<GemmParams> ps;
   std::vector<int32_t> prefix(1, 0);
+  int64_t total = 0;
   for (const GemmLaunch& g : probs) {
     if (g.splitk <= 1 || !g.partial || g.M <= 0 || g.N <= 0) continue;
     GemmParams p;
     fill_params(g, p);
     ps.push_back(p);
-    const int64_t total = (int64_t(1) << g.nbb) * g.M * g.N;
-    prefix.push_back(prefix.back() + (int32_t)((total + 255) / 256));
+    total += ((int64_t(1) << g.nbb) * g.M * g.N + 255) / 256;
+    prefix.push_back(prefix_entry(total));
   }
   G.n = (int)ps.size();
   if (ps.empty()) return 0;
   G.mode = probs[0].mode;
-  G.blocks = prefix.back();
+  G.blocks = grouped_blocks(total);
   G.params_off = 0;
   G.prefix_off = (ps.size() * sizeof(GemmParams) + 255) & ~size_t(255);
   size_t bytes = (G.prefix_off + prefix.size() * sizeof(int32_t) + 255) & ~size_t(255);
@@ -4276,6 +4303,7 @@ size_t grouped_reduce_build(const std::vector<GemmLaunch>& probs, std::vector<ch
 
 hipError_t launch_reduce_grouped(const GroupedLaunch& G, const void* table_dev, hipStream_t s) {
   if (G.n == 0 || G.blocks == 0) return hipSuccess;
+  if (G.blocks < 0) return hipErrorInvalidConfiguration;
   GroupTable t;
   t.probs = reinterpret_cast<const GemmParams*>(static_cast<const char*>(table_dev) + G.params_off);
   t.prefix = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.prefix_off);
@@ -4423,9 +4451,12 @@ size_t grouped_direct_build(const std::vector<DirectStep>& steps, rn_mode mode,
   G.mode = mode;
   if (steps.empty()) return 0;
   std::vector<int32_t> prefix(steps.size() + 1, 0);
-  for (size_t i = 0; i < steps.size(); ++i)
-    prefix[i + 1] = prefix[i] + steps[i].blocks_per_batch * (1 << steps[i].nbb);
-  G.blocks = prefix.back();
+  int64_t total = 0;
+  for (size_t i = 0; i < steps.size(); ++i) {
+    total += int64_t(steps[i].blocks_per_batch) << steps[i].nbb;
+    prefix[i + 1] = prefix_entry(total);
+  }
+  G.blocks = grouped_blocks(total);
   G.params_off = 0;
   G.prefix_off = (steps.size() * sizeof(DirectStep) + 255) & ~size_t(255);
   size_t bytes = (G.prefix_off + prefix.size() * sizeof(int32_t) + 255) & ~size_t(255);
@@ -4438,6 +4469,7 @@ size_t grouped_direct_build(const std::vector<DirectStep>& steps, rn_mode mode,
 hipError_t launch_direct_grouped(const GroupedLaunch& G, const void* table_dev, int64_t pass,
                                  int nout, hipStream_t s) {
   if (G.n == 0 || G.blocks == 0) return hipSuccess;
+  if (G.blocks < 0) return hipErrorInvalidConfiguration;
   if (nout < 0 || nout > RN_MAX_SLICED) return hipErrorInvalidValue;
   DirectTable t;
   t.pass = pass;

@@ -149,3 +149,39 @@ def test_rank28_unitary_full_output():
         torch.cuda.empty_cache()
     for mode, e in errs.items():
         assert e < TOL[mode], (mode, e)
+
+
+def test_outer_product_more_column_tiles_than_workgroups():
+    # An outer product (no contracted axis, K = 1) of a 2-vector with a
+    # rank-25 tensor runs on the skinny kernel with 2^21 column tiles of 16,
+    # more than the 2^20 workgroups it launches, so every workgroup loops over
+    # two tiles.  Gaussian-integer inputs make every product exact: sampled
+    # outputs (the first and last tiles of both passes, plus random ones)
+    # must be bit-identical to the oracle in every mode.
+    import torch
+    import paper_2201_06620_amd as rn
+    rb = 25
+    n = 2 ** rb
+    rs = np.random.default_rng(2525)
+    a = (rs.integers(-8, 9, 2) + 1j * rs.integers(-8, 9, 2)).astype(np.complex128)
+    b = (rs.integers(-8, 9, n) + 1j * rs.integers(-8, 9, n)).astype(np.complex128)
+    cols = np.concatenate([np.arange(64), np.arange(2 ** 24 - 64, 2 ** 24 + 64),
+                           np.arange(n - 64, n), rs.integers(0, n, 256)])
+    idx = np.unique(np.concatenate([cols, n + cols]).astype(np.int64))
+    log(f"oracle on {idx.size} sampled outputs of a 2 x 2^{rb} outer product")
+    ref = oracle.tensordot_entries(a, b.reshape([2] * rb), [], [], idx)
+    ctx = rn.Context(0)
+    for dt, modes in ((torch.complex64, ("fp32_4m", "fp32_3m", "bf16x3")),
+                      (torch.complex128, ("fp64",))):
+        ta = torch.from_numpy(a).to(dt).cuda()
+        tb = torch.from_numpy(b).to(dt).cuda()
+        for mode in modes:
+            log(f"mode {mode}: outer product, 2^{rb + 1} outputs")
+            c, cd, _ = ctx.block_tensordot(ta, [2], None, tb, [2] * rb, None, [], [], mode)
+            torch.cuda.synchronize()
+            assert cd == [2] * (rb + 1)
+            got = c[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.complex128)
+            assert np.array_equal(got, ref), mode
+            del c
+        del ta, tb
+        torch.cuda.empty_cache()
