@@ -103,6 +103,10 @@ def test_footprint_equations_weak_scaling_shapes():
     (dict(grid_a=[4, 1, 1]), 3),                             # grid above dim
     (dict(dims_a=[3, 2, 2], dims_b=[3, 2, 2]), 7),           # not a power of two
     (dict(grid_a=[1, 1, 1], dims_a=[2, 2, 2], mode="fp32_4m", dtype=2), 1),  # dtype/mode
+    (dict(grid_a=[1, 1, 3], dims_a=[2, 2, 4], dims_b=[2, 2, 4]), 7),  # grid not a power of 2
+    (dict(dims_a=[0, 2, 2]), 2),                             # empty axis
+    (dict(dims_a=[2] * 21, grid_a=[1] * 21, dims_b=[2] * 21, grid_b=[1] * 21,
+          axes_a=[], axes_b=[]), 7),                         # output above 2^40 entries
 ])
 def test_plan_error_codes(kw, status):
     args = dict(dims_a=[2, 2, 2], grid_a=[1, 1, 1], dims_b=[2, 2, 2], grid_b=[1, 1, 1],
