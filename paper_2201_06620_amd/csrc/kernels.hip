@@ -3761,6 +3761,35 @@ static void launch_skinny_grouped(rn_mode mode, int mr, dim3 grid, const GroupTa
 
 // Split-K reduction: C = sum over splits of the partials, in ascending split
 // order, written through the two-level maps.
+// Sum of output e's partials (split s at complex index s * total + e) in
+// ascending split order, which fixes the rounding.  Eight splits are loaded
+// before any is added, so a long split list costs an eighth of the chain of
+// dependent loads.
+template <typename R>
+__device__ __forceinline__ void splitk_sum(const void* partial, int splitk, int64_t total,
+                                           int64_t e, R& re, R& im) {
+  using V = typename std::conditional<std::is_same<R, double>::value, double2, float2>::type;
+  const V* __restrict__ pv = reinterpret_cast<const V*>(partial);
+  re = R(0);
+  im = R(0);
+  int s = 0;
+  for (; s + 8 <= splitk; s += 8) {
+    V v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = pv[int64_t(s + u) * total + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      re += v[u].x;
+      im += v[u].y;
+    }
+  }
+  for (; s < splitk; ++s) {
+    const V v = pv[int64_t(s) * total + e];
+    re += v.x;
+    im += v.y;
+  }
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void splitk_reduce(GemmParams p) {
   const int64_t nb = int64_t(1) << p.nbb;
@@ -3770,13 +3799,8 @@ __global__ __launch_bounds__(256) void splitk_reduce(GemmParams p) {
     const int64_t b = e / (p.M * p.N);
     const int64_t rc = e % (p.M * p.N);
     const int64_t row = rc / p.N, col = rc % p.N;
-    const R* part = reinterpret_cast<const R*>(p.partial);
-    R re = 0, im = 0;
-    for (int s = 0; s < p.splitk; ++s) {
-      int64_t idx = (int64_t(s) * nb + b) * p.M * p.N + rc;
-      re += part[2 * idx];
-      im += part[2 * idx + 1];
-    }
+    R re, im;
+    splitk_sum<R>(p.partial, p.splitk, total, e, re, im);
     int64_t off = batch_off(p.c_bs, p.nbb, (int)b) + map2(row, p.crs, p.crh, p.crl) +
                   map2(col, p.ccs, p.cch, p.ccl);
     reinterpret_cast<R*>(p.C)[2 * off] = re;
@@ -3793,18 +3817,14 @@ __global__ __launch_bounds__(256) void splitk_reduce_grouped(GroupTable g) {
   // live in scratch memory, per thread, for a few loads.
   const GemmParams& p = g.probs[i];
   const int64_t nb = int64_t(1) << p.nbb;
+  const int64_t total = nb * p.M * p.N;
   const int64_t e = int64_t(blockIdx.x - g.prefix[i]) * 256 + threadIdx.x;
-  if (e >= nb * p.M * p.N) return;
+  if (e >= total) return;
   const int64_t b = e / (p.M * p.N);
   const int64_t rc = e % (p.M * p.N);
   const int64_t row = rc / p.N, col = rc % p.N;
-  const R* part = reinterpret_cast<const R*>(p.partial);
-  R re = 0, im = 0;
-  for (int s = 0; s < p.splitk; ++s) {
-    const int64_t idx = (int64_t(s) * nb + b) * p.M * p.N + rc;
-    re += part[2 * idx];
-    im += part[2 * idx + 1];
-  }
+  R re, im;
+  splitk_sum<R>(p.partial, p.splitk, total, e, re, im);
   const int64_t off = batch_off(p.c_bs, p.nbb, (int)b) + map2(row, p.crs, p.crh, p.crl) +
                       map2(col, p.ccs, p.cch, p.ccl);
   reinterpret_cast<R*>(p.C)[2 * off] = re;
