@@ -29,9 +29,13 @@
  *     finished the enqueued work.  The library never frees caller memory.
  *   - Asynchrony: compute calls enqueue kernels on `stream` (a hipStream_t,
  *     NULL for the default stream) and return; they do not synchronise.
- *   - Errors: every call returns rn_status and never throws.  On failure
- *     nothing has been enqueued (argument checks run before any launch) and
- *     rn_last_error() gives a message for the calling thread.
+ *   - Errors: every call returns rn_status and never throws, and
+ *     rn_last_error() gives a message for the calling thread.  Argument
+ *     errors are found before any launch, so nothing has been enqueued.
+ *     RN_ERR_HIP reports a HIP call that failed, e.g. a launch whose grid
+ *     exceeds HIP's 2^32 work-items per dimension (the library refuses such
+ *     a launch instead of wrapping its size); kernels of the same call
+ *     enqueued before it may have run, and the output is then undefined.
  *   - Modes and dtypes: RN_FP64 computes in double with RN_C128 tensors;
  *     RN_FP32_4M, RN_FP32_3M and RN_BF16X3 take RN_C64 tensors and
  *     accumulate in float.
