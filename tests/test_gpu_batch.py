@@ -239,3 +239,28 @@ def test_batch_split_k_every_mode(ctx, mode):
             else:
                 err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
                 assert err < tol, (mode, err)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m"])
+def test_batch_more_problems_than_one_search_round(ctx, mode):
+    # 4500 tiny problems (operand ranks 2-7, 0-3 contracted axes): the grouped
+    # permute and GEMM launches hold more than 4096 jobs, so every workgroup
+    # finds its job by the binary search over the prefix sums instead of the
+    # two 64-wide probe rounds.  Gaussian integers: every output bit-exact.
+    r = rng.SplitMix64(4500)
+    probs = []
+    while len(probs) < 4500:
+        ra, rb, k = r.randint(2, 7), r.randint(2, 7), r.randint(0, 3)
+        if k > min(ra, rb) or ra + rb - 2 * k > 8:
+            continue
+        axa, axb = r.sample(ra, k), r.sample(rb, k)
+        probs.append(configs.make_problem(ra, rb, axa, axb, configs.split_first(ra, 1),
+                                          configs.split_first(rb, 1), 90000 + len(probs),
+                                          integer=True))
+    log(f"{mode}: batch of {len(probs)} problems")
+    _, res = run_batch(ctx, probs, mode)
+    for i, (p, (c, cd, cg)) in enumerate(zip(probs, res)):
+        ref, rd, rg = oracle.block_tensordot(p.a.data, p.a.dims, p.a.grid, p.b.data, p.b.dims,
+                                             p.b.grid, p.axes_a, p.axes_b)
+        assert cd == rd and cg == rg, i
+        assert np.array_equal(c.cpu().numpy().astype(np.complex128), ref), (mode, i)
