@@ -199,3 +199,42 @@ def test_norm2_and_sum(ctx):
     s = ctx.sum_c128(dev(v, "fp64")).cpu().numpy()
     ref = np.sum(v)
     assert abs(complex(s[0], s[1]) - ref) < 1e-12 * abs(ref) + 1e-13
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "fp32_3m", "bf16x3"])
+def test_rank_above_32_mixed_dims(ctx, mode):
+    # Ranks past numpy's old 32-axis limit (Section V): A rank 40, B rank 34,
+    # C rank 50, with dims 1, 2 and 4 in seeded orders, 12 contracted pairs
+    # (nine of dim 1), and grids that split a dim-4 free axis and a dim-2
+    # contracted axis of A only (common refinement on that pair).  The same
+    # flat Gaussian-integer buffers are the block-major operands of both
+    # sides, so every output is exact.
+    rs = np.random.default_rng(4034)
+    kd = [2, 2, 4] + [1] * 9
+    fa = [2, 2, 2, 4] + [1] * 24
+    fb = [2, 2, 4, 2] + [1] * 18
+    pa = rs.permutation(len(kd) + len(fa))      # stored position of each logical axis
+    pb = rs.permutation(len(kd) + len(fb))
+    dims_a = [0] * len(pa)
+    dims_b = [0] * len(pb)
+    for i, d in enumerate(kd + fa):
+        dims_a[pa[i]] = d
+    for i, d in enumerate(kd + fb):
+        dims_b[pb[i]] = d
+    axes_a = [int(pa[i]) for i in range(len(kd))]
+    axes_b = [int(pb[i]) for i in range(len(kd))]
+    grid_a = [1] * len(dims_a)
+    grid_b = [1] * len(dims_b)
+    grid_a[pa[len(kd) + 3]] = 2                  # A's dim-4 free axis in two blocks
+    grid_a[pa[0]] = 2                            # first contracted pair, A side only
+    grid_b[pb[len(kd) + 2]] = 4                  # B's dim-4 free axis in four blocks
+    na, nb = int(np.prod(dims_a)), int(np.prod(dims_b))
+    a = (rs.integers(-8, 9, na) + 1j * rs.integers(-8, 9, na)).astype(np.complex128)
+    b = (rs.integers(-8, 9, nb) + 1j * rs.integers(-8, 9, nb)).astype(np.complex128)
+    import torch
+    c, cd, cg = ctx.block_tensordot(dev(a, mode), dims_a, grid_a, dev(b, mode), dims_b, grid_b,
+                                    axes_a, axes_b, mode)
+    torch.cuda.synchronize()
+    ref, rd, rg = oracle.block_tensordot(a, dims_a, grid_a, b, dims_b, grid_b, axes_a, axes_b)
+    assert len(cd) == 50 and cd == rd and cg == rg
+    assert np.array_equal(host(c), ref), mode

@@ -270,6 +270,26 @@ def test_block_tensordot_outer_and_scalar():
     assert abs(C - ref) < 1e-14 * abs(ref)
 
 
+def test_tensordot_rank_above_32_matches_numpy():
+    # Rank 40 x rank 34 -> rank 50 with dims 1, 2 and 4 in a seeded order
+    # (Section V: tensors past 32 axes); numpy 2 handles 64 axes.
+    rs = np.random.default_rng(4034)
+    kd = [2, 2, 4] + [1] * 9
+    pa, pb = rs.permutation(40), rs.permutation(34)
+    da, db = [0] * 40, [0] * 34
+    for i, d in enumerate(kd + [2, 2, 2, 4] + [1] * 24):
+        da[pa[i]] = d
+    for i, d in enumerate(kd + [2, 2, 4, 2] + [1] * 18):
+        db[pb[i]] = d
+    axa, axb = [int(x) for x in pa[:12]], [int(x) for x in pb[:12]]
+    a = rs.normal(size=da) + 1j * rs.normal(size=da)
+    b = rs.normal(size=db) + 1j * rs.normal(size=db)
+    got = oracle.tensordot(a, b, axa, axb)
+    ref = np.tensordot(a, b, (axa, axb))
+    assert got.shape == ref.shape and got.ndim == 50
+    assert rel_err(got, ref) < 1e-14
+
+
 # -------------------------------------------------------------- statevector
 
 def dense_unitary(circ):
