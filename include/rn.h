@@ -170,7 +170,8 @@ rn_status rn_block_footprint(const rn_tensor* A, const rn_tensor* B, int32_t k,
  * ascending order by one grouped launch at the end), so results do not
  * depend on the other problems of the batch.  Per-problem parameters are
  * copied into the end of the workspace first.  ws_bytes from
- * rn_block_tensordot_batch_plan.  With graph replay on, a call identical to
+ * rn_block_tensordot_batch_plan.  An empty batch (n = 0) is valid: it plans
+ * to 0 bytes and 0 flops and enqueues nothing.  With graph replay on, a call identical to
  * an earlier captured one (descriptors, data pointers, axes, workspace
  * pointer and size, stream, tuning) replays its graph without planning
  * again; the earlier call was checked in full. */

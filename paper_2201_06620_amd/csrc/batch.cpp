@@ -458,7 +458,8 @@ rn_status rn_block_tensordot_batch_plan(rn_handle h, int32_t n, const rn_tensor*
       }
     }
   }
-  if (ws_bytes) *ws_bytes = bp.table_off + grouped_table_bound(mode, n);
+  // An empty batch launches nothing and needs no workspace.
+  if (ws_bytes) *ws_bytes = n == 0 ? 0 : bp.table_off + grouped_table_bound(mode, n);
   if (flops) *flops = bp.flops;
   return RN_OK;
 }
@@ -477,6 +478,10 @@ rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
                           B[i].rank <= RN_MAX_RANK && C[i].rank >= 0 && C[i].rank <= RN_MAX_RANK;
     if (!ranks_ok || k[i] < 0 || k[i] > RN_MAX_RANK || (k[i] > 0 && (!axesA[i] || !axesB[i])))
       return fail(RN_ERR_INVALID, "problem " + std::to_string(i) + ": bad rank or axes");
+  }
+  if (n == 0) {
+    if (mode < RN_FP64 || mode > RN_BF16X3) return fail(RN_ERR_INVALID, "unknown mode");
+    return RN_OK;  // nothing to launch
   }
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return hipf(e, "hipSetDevice");

@@ -264,3 +264,13 @@ def test_batch_more_problems_than_one_search_round(ctx, mode):
                                              p.b.grid, p.axes_a, p.axes_b)
         assert cd == rd and cg == rg, i
         assert np.array_equal(c.cpu().numpy().astype(np.complex128), ref), (mode, i)
+
+
+def test_empty_batch_enqueues_nothing(ctx):
+    # n = 0 through the C ABI: OK, nothing launched, no workspace needed.
+    import torch
+    import paper_2201_06620_amd as rn
+    s = torch.cuda.current_stream().cuda_stream
+    assert rn.lib().rn_block_tensordot_batch(ctx.h, 0, None, None, None, None, None, None, 1,
+                                             None, 0, s) == 0
+    torch.cuda.synchronize()

@@ -181,3 +181,17 @@ def test_network_plan_config2_host():
                                       sl.ctypes.data, 0, ctypes.byref(ws), ctypes.byref(fl),
                                       ctypes.byref(mr))
     assert st == 1
+
+
+def test_batch_plan_empty_and_invalid_counts():
+    # An empty batch plans to nothing (no flops, no workspace);
+    # a negative count, or a positive one without descriptors, is refused.
+    L = rn.lib()
+    ws, fl = ctypes.c_size_t(), ctypes.c_double(-1.0)
+    assert L.rn_block_tensordot_batch_plan(None, 0, None, None, None, None, None, 1, None,
+                                           ctypes.byref(ws), ctypes.byref(fl)) == 0
+    assert fl.value == 0.0 and ws.value == 0
+    for n in (-1, 2):
+        assert L.rn_block_tensordot_batch_plan(None, n, None, None, None, None, None, 1, None,
+                                               ctypes.byref(ws), ctypes.byref(fl)) == 1
+        assert b"batch" in L.rn_last_error()
