@@ -141,3 +141,23 @@ def test_prepared_network_repeats_and_new_values(ctx):
         a = amp.cpu().numpy()
         x = int("".join(map(str, bits)), 2)
         assert amp_err(complex(a[0], a[1]), psi[x], circ.n) < 1e-12
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m"])
+def test_degenerate_networks(ctx, mode):
+    # A network that is one scalar (no step) returns that scalar; two vectors
+    # sharing one bond (one step) return their dot product, with the bond
+    # also sliced (two slices summed in FP64).
+    import torch
+    dt = torch.complex128 if mode == "fp64" else torch.complex64
+    s = torch.tensor([1.25 - 0.5j], dtype=dt, device="cuda")
+    amp = ctx.contract_network([s], [[]], [], [], mode)
+    torch.cuda.synchronize()
+    assert complex(*amp.cpu().numpy()) == 1.25 - 0.5j
+    a = np.array([1.5 + 2j, -0.5 + 1j])
+    b = np.array([2 - 1j, 4 + 0.25j])
+    ta, tb = (torch.from_numpy(x).to(dt).cuda() for x in (a, b))
+    for sliced in ([], [7]):
+        amp = ctx.contract_network([ta, tb], [[7], [7]], [(0, 1)], sliced, mode)
+        torch.cuda.synchronize()
+        assert complex(*amp.cpu().numpy()) == complex(np.dot(a, b)), sliced
