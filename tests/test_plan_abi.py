@@ -195,3 +195,21 @@ def test_batch_plan_empty_and_invalid_counts():
         assert L.rn_block_tensordot_batch_plan(None, n, None, None, None, None, None, 1, None,
                                                ctypes.byref(ws), ctypes.byref(fl)) == 1
         assert b"batch" in L.rn_last_error()
+
+
+def test_missing_library_fails_loudly():
+    # No CPU fallback: without the built HIP library every entry point of the
+    # binding raises instead of computing anything.
+    import subprocess
+    import sys
+    code = ("import paper_2201_06620_amd as rn\n"
+            "rn.LIB_PATH = '/nonexistent/librosnet.so'\n"
+            "try:\n"
+            "    rn.plan_block_tensordot([2, 2], None, [2, 2], None, [1], [0], 'fp64')\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n")
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       timeout=300, cwd=root)
+    assert r.returncode == 0 and "raised:" in r.stdout and "no CPU fallback" in r.stdout
