@@ -4557,29 +4557,32 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 constexpr int kRedBlocks = 2048;  // partials; the handle's reduction scratch holds 4096
 
-// Each thread keeps four independent loads in flight per round (four
-// partial sums, added in a fixed order), enough bytes in flight per CU for
-// the read to run near HBM speed.
+// Each thread keeps four independent loads in flight per round: a block
+// reads four consecutive 256-element pieces of one 1024-element chunk (the
+// chunks dealt round robin over the blocks), so the loads stay close in
+// memory; four partial sums, added in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void norm2_partial(const T* x, int64_t n, double* part) {
   __shared__ double sh[4];
-  const int64_t stride = int64_t(kRedBlocks) * 256;
+  const int64_t stride = int64_t(kRedBlocks) * 1024;
   double s4[4] = {0.0, 0.0, 0.0, 0.0};
-  int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
+  int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  for (; i + 768 < n; i += stride) {
     T v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = x[i + u * stride];
+    for (int u = 0; u < 4; ++u) v[u] = x[i + 256 * u];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const double re = (double)v[u].x, im = (double)v[u].y;
       s4[u] += re * re + im * im;
     }
   }
-  for (; i < n; i += stride) {
-    const double re = (double)x[i].x, im = (double)x[i].y;
-    s4[0] += re * re + im * im;
-  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (i + 256 * u < n) {
+      const double re = (double)x[i + 256 * u].x, im = (double)x[i + 256 * u].y;
+      s4[u] += re * re + im * im;
+    }
   double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
