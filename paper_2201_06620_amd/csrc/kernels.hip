@@ -304,7 +304,10 @@ hipError_t launch_permute(const PermLaunch& L, hipStream_t s) {
   const int tsize = 1 << p.nS;
   const int E = tsize >= 256 ? tsize / 256 : 1;
   size_t lds = size_t(tsize + (tsize >> 5) + 1) * L.in_es;
-  unsigned grid = (unsigned)std::min<int64_t>(p.ntiles, 256 * 16);
+  // Up to 64 workgroups per CU, each looping over a few tiles: a 2^28-element
+  // complex64 relayout measured 0.84 ms here against 0.86-0.89 ms with 2, 4 or
+  // 16 per CU and 0.89 ms with one tile per workgroup.
+  unsigned grid = (unsigned)std::min<int64_t>(p.ntiles, 256 * 64);
   if (L.kind == 1)
     launch_perm_e<float2, 1>(p, E, grid, lds, s);
   else if (L.in_es == 16)
