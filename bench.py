@@ -105,7 +105,7 @@ def run_serving(args, torch, rn, log):
         f"{[w.meta['sites'] for w in reqs]}")
     free, total = torch.cuda.mem_get_info()
     budget = int(0.9 * free)
-    srv = rn.Server(0, hbm_budget=budget, max_active=4)
+    srv = rn.Server(0, hbm_budget=budget, max_active=args.serve_slots)
     tensors = [[t.astype(np.complex64) for t in w.network.tensors] for w in reqs]
 
     def submit(i):
@@ -139,8 +139,8 @@ def run_serving(args, torch, rn, log):
     same = sum(1 for a, b in zip(sat, res) if a["amp"] == b["amp"] and a["status"] == 0)
     out = {"workload": "amplitude requests for seeded random circuits on 30-53-site grids, 8-14 "
                        "cycles, sliced to largest intermediate rank <= 30 (<= 6 sliced bonds), "
-                       "complex64 FP32-4M with FP64 slice sums; HBM-footprint admission, 4 "
-                       "concurrent slots",
+                       "complex64 FP32-4M with FP64 slice sums; HBM-footprint admission, "
+                       f"{args.serve_slots} concurrent slots",
            "requests": len(reqs), "saturated_amplitudes_per_s": thr,
            "arrival_rate_per_s": lam, "load": args.serve_load,
            "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
@@ -338,6 +338,8 @@ def main() -> int:
     ap.add_argument("--no-side", action="store_true")
     ap.add_argument("--no-batch", dest="batch", action="store_false")
     ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-slots", type=int, default=4,
+                    help="requests the server runs concurrently (1-16)")
     ap.add_argument("--serve-load", type=float, default=0.75,
                     help="Poisson arrival rate as a fraction of the saturated throughput")
     ap.add_argument("--copy-calib", action="store_true",
