@@ -48,20 +48,20 @@ def percentile(xs, q):
 
 
 def kernel_sha():
-    """Hash of the source the profiled GEMM is built from: the shared GEMM
-    parameter, output-map and tile-order code, the direct-to-LDS FP32 tile
-    body and the entry-point macros.  A change there invalidates the stored counters."""
-    with open(os.path.join(ROOT, "paper_2201_06620_amd", "csrc", "kernels.hip")) as f:
+    """Hash of the source the profiled GEMM is built from: the shared device
+    header (GEMM parameters, output maps, tile order, entry-point macros) and
+    the direct-to-LDS FP32 tile with its entry points.  A change there
+    invalidates the stored counters."""
+    csrc = os.path.join(ROOT, "paper_2201_06620_amd", "csrc")
+    with open(os.path.join(csrc, "kcommon.hpp")) as f:
+        parts = [f.read()]
+    with open(os.path.join(csrc, "gemm_f32_4m.hip")) as f:
         src = f.read()
-    parts = []
-    for start, end in (("struct GemmParams {", "// FP32, 4M embedding"),
-                       ("__device__ __forceinline__ int dl_swz(", "// FP32-3M (Gauss) with the direct-to-LDS staging"),
-                       ("#define RN_GEMM_ENTRY(NAME)", "RN_GEMM_ENTRY(cgemm_f32_4m)")):
-        i = src.find(start)
-        j = src.find(end, i + 1)
-        if i < 0 or j < 0:
-            return "missing"
-        parts.append(src[i:j])
+    i = src.find("// Large-tile FP32-4M with direct-to-LDS staging")
+    j = src.find("void launch_tiles_f32_4m(", i) if i >= 0 else -1
+    if i < 0 or j < 0:
+        return "missing"
+    parts.append(src[i:j])
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 

@@ -1,5 +1,7 @@
-// HIP kernels for gfx950 (MI355X): index permutation, complex GEMM on MFMA,
-// split-K reduction and FP64 reductions.
+// HIP kernels for gfx950 (MI355X): index permutation, GEMM dispatch (the
+// MFMA tiles live in one file per mode, gemm_*.hip), the one-thread and
+// skinny GEMM kernels, split-K reduction, small network steps and FP64
+// reductions.
 //
 // Terminology: a "complex column" is one complex output element per row; in
 // the 4M real embedding a complex m x k matrix A is the real m x 2k matrix of
@@ -18,19 +20,9 @@
 #include <cstring>
 #include <vector>
 
-#include "rn_internal.hpp"
+#include "kcommon.hpp"
 
 namespace rn {
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef float v16f __attribute__((ext_vector_type(16)));
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-
-// Largest grid of one launch: HIP counts the work-items of a grid dimension
-// in 32 bits, and every kernel here runs 256 per workgroup.
-constexpr int64_t kMaxGrid = ((int64_t(1) << 32) - 1) / 256;
 
 // Block count of a grouped launch, or -1 when the groups add up to more than
 // one launch can hold (the launch then reports hipErrorInvalidConfiguration
@@ -65,24 +57,6 @@ struct PermParams {
   int64_t hi_out[16];
   int32_t hi_lds[16];
 };
-
-__device__ __forceinline__ int lds_pad(int x) { return x + (x >> 5); }
-
-__device__ __forceinline__ uint32_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
-
-// hi = nearest bfloat16 of x; lo = nearest bfloat16 of the exact residual
-// x - hi (Henry, Tang and Heinecke, "Leveraging the bfloat16 artificial
-// intelligence datatype for higher-precision computations", ARITH 2019).
-__device__ __forceinline__ void bf16_split(float x, uint32_t& hi, uint32_t& lo) {
-  hi = bf16_rne(x);
-  float r = x - __uint_as_float(hi << 16);
-  lo = bf16_rne(r);
-}
 
 // Thread-fixed low parts of the tile-local index u = tid + 256 * j.
 __device__ __forceinline__ void perm_lo(const PermParams& p, int tid, int64_t& in_lo,
@@ -160,32 +134,6 @@ __global__ __launch_bounds__(256) void permute_kernel(PermParams p) {
     permute_tile<T, KIND, E, false>(p, t, tile, in_lo, out_lo, lds_lo);
 }
 
-// Job of global workgroup index w in a grouped launch: the largest i < n
-// with prefix[i] <= w (prefix is non-decreasing, prefix[0] = 0).  Every
-// wave searches on its own with two rounds of 64 parallel probes (n up to
-// 4096), so a workgroup pays two dependent loads instead of a
-// log2(n)-deep binary search through global memory.
-__device__ __forceinline__ int find_job(const int32_t* __restrict__ prefix, int n, int w) {
-  if (n <= 4096) {
-    const int lane = threadIdx.x & 63;
-    const int S = (n + 63) >> 6;
-    int idx = lane * S;
-    bool pred = idx < n && prefix[idx] <= w;
-    unsigned long long m = __ballot(pred);
-    const int base = (63 - __clzll(m)) * S;
-    idx = base + lane;
-    pred = lane < S && idx < n && prefix[idx] <= w;
-    m = __ballot(pred);
-    return base + (63 - __clzll(m));
-  }
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= w) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 // Many permutations in one launch: workgroup w moves one tile of job i,
 // prefix[i] <= w < prefix[i+1].  The job's parameters are copied into LDS
@@ -362,3003 +310,7 @@ hipError_t launch_permute_grouped(const GroupedLaunch& G, const void* table_dev,
   return hipGetLastError();
 }
 
-// ===========================================================================
-// Complex GEMM: C[M x N] = A[M x K] * B[N x K]^T (both operands K-contiguous),
-// batched over slices, optionally split along K into partial sums.
-// ===========================================================================
-struct GemmParams {
-  const void* A;
-  const void* B;
-  const void* A2;
-  const void* B2;
-  void* C;
-  void* partial;
-  int64_t M, N, K, lda, ldb;
-  int64_t crh, crl, cch, ccl;
-  int crs, ccs;
-  int nbb;
-  int splitk;
-  int64_t kchunk;
-  int tiles_m, tiles_n;
-  int64_t a_bs[RN_MAX_SLICED], b_bs[RN_MAX_SLICED], c_bs[RN_MAX_SLICED];
-};
 
-__device__ __forceinline__ int64_t batch_off(const int64_t* st, int nbb, int b) {
-  int64_t o = 0;
-  for (int i = 0; i < nbb; ++i)
-    if ((b >> i) & 1) o += st[i];
-  return o;
-}
-
-__device__ __forceinline__ int64_t map2(int64_t x, int sh, int64_t hi, int64_t lo) {
-  return (x >> sh) * hi + (x & ((int64_t(1) << sh) - 1)) * lo;
-}
-
-template <bool B>
-struct BoolTag {
-  static constexpr bool value = B;
-};
-
-// Output element (row, col, part) of tile results: either straight into C
-// through the two-level maps, or into the split-K partial buffer.
-template <typename R>
-__device__ __forceinline__ void store_out(const GemmParams& p, int b, int split, int64_t row,
-                                          int64_t col, int part, R v) {
-  if (row >= p.M || col >= p.N) return;
-  if (p.splitk > 1) {
-    int64_t nb = int64_t(1) << p.nbb;
-    int64_t idx = ((int64_t(split) * nb + b) * p.M + row) * p.N + col;
-    reinterpret_cast<R*>(p.partial)[2 * idx + part] = v;
-  } else {
-    int64_t off = batch_off(p.c_bs, p.nbb, b) + map2(row, p.crs, p.crh, p.crl) +
-                  map2(col, p.ccs, p.cch, p.ccl);
-    reinterpret_cast<R*>(p.C)[2 * off + part] = v;
-  }
-}
-
-// Workgroup -> output tile.  Hardware hands consecutive workgroups to the 8
-// XCDs round-robin; renumbering them so each XCD receives one contiguous run
-// of logical tiles, and walking tiles in column groups of GROUP_M row tiles,
-// keeps the A row panels and B column panels a group shares inside one L2.
-__device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
-  int nwg = gridDim.x;
-  int bid = blockIdx.x;
-  if ((nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
-  const int GROUP_M = 8;
-  int group_size = GROUP_M * tiles_n;
-  int g = bid / group_size;
-  int first_m = g * GROUP_M;
-  int gm = min(tiles_m - first_m, GROUP_M);
-  int r = bid % group_size;
-  tm = first_m + r % gm;
-  tn = r / gm;
-}
-
-// ---------------------------------------------------------------------------
-// FP32, 4M embedding, v_mfma_f32_32x32x2_f32.
-// WM x WN waves; each wave owns TM x TN MFMA tiles of 32 x 32 real outputs.
-// ---------------------------------------------------------------------------
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f32_4m_body(const GemmParams& p, int tm, int tn, int split,
-                                                int b) {
-  static_assert(WM * WN == 4, "four waves");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 16;  // complex columns
-  constexpr int LDK = BK + 1;       // padded LDS row, complex elements
-  constexpr int AV = BM * BK / 2;   // float4 (two complex) loads per A chunk
-  constexpr int BV = BN * BK / 2;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  __shared__ float2 As[2][BM * LDK];
-  __shared__ float2 Bs[2][BN * LDK];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const float2* __restrict__ Ag =
-      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const float2* __restrict__ Bg =
-      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-
-  float4 ra[NA], rb[NB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = row0 + r, gk = k0 + c;
-        if (gr < p.M) {
-          const float2* src = Ag + gr * p.lda + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = col0 + r, gk = k0 + c;
-        if (gr < p.N) {
-          const float2* src = Bg + gr * p.ldb + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      rb[j] = v;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        As[buf][r * LDK + c] = make_float2(ra[j].x, ra[j].y);
-        As[buf][r * LDK + c + 1] = make_float2(ra[j].z, ra[j].w);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        Bs[buf][r * LDK + c] = make_float2(rb[j].x, rb[j].y);
-        Bs[buf][r * LDK + c + 1] = make_float2(rb[j].z, rb[j].w);
-      }
-    }
-  };
-
-  v16f acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-
-  // Lane roles in the 32x32x2 MFMA: A operand row = lane % 32, k = lane / 32
-  // (k 0 = real part, k 1 = imaginary part of the complex a); B operand real
-  // column n = lane % 32 (complex column n / 2, part n & 1), same k.
-  const int khalf = lane >> 5;
-  const int par = lane & 1;
-  const bool b_take_re = (khalf == par);
-  const uint32_t b_sign = (khalf == 1 && par == 0) ? 0x80000000u : 0u;
-  const int arow = wm * TM * 32 + (lane & 31);
-  const int bcol = wn * TN * 16 + ((lane & 31) >> 1);
-
-  if (nk > 0) {
-    gload(kbeg);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      float af[TM], bf[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        float2 a = As[buf][(arow + i * 32) * LDK + kk];
-        af[i] = khalf ? a.y : a.x;
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        float2 bv = Bs[buf][(bcol + j * 16) * LDK + kk];
-        float v = b_take_re ? bv.x : bv.y;
-        bf[j] = __uint_as_float(__float_as_uint(v) ^ b_sign);
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-    if (it + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
-  // 32x32 accumulator layout: lane holds real column lane % 32 and rows
-  // 8*(e/4) + 4*(lane/32) + e%4 for e = 0..15.
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * khalf + (e & 3);
-        int n = wn * TN * 32 + j * 32 + (lane & 31);
-        store_out<float>(p, b, split, row, col0 + (n >> 1), n & 1, acc[i][j][e]);
-      }
-}
-
-// ---------------------------------------------------------------------------
-// FP32, 3M (Gauss): T1 = Ar.Br, T2 = Ai.Bi, T3 = (Ar + Ai).(Br + Bi);
-// Re C = T1 - T2, Im C = (T3 - T1) - T2.  v_mfma_f32_32x32x2_f32 with the
-// two k of one instruction = two consecutive complex k: lane halves read
-// different complex elements and use both parts, so the operands stay
-// interleaved in memory and LDS (no planar copy) and each 32x32 tile is 32
-// complex columns.  6 real flops per complex multiply-add are executed.
-// ---------------------------------------------------------------------------
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f32_3m_body(const GemmParams& p, int tm, int tn, int split,
-                                                int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK % 2 == 0, "two complex k per MFMA");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 32;  // complex columns
-  constexpr int LDK = BK + 1;
-  constexpr int AV = BM * BK / 2;
-  constexpr int BV = BN * BK / 2;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  __shared__ float2 As[2][BM * LDK];
-  __shared__ float2 Bs[2][BN * LDK];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const float2* __restrict__ Ag =
-      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const float2* __restrict__ Bg =
-      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-
-  float4 ra[NA], rb[NB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = row0 + r, gk = k0 + c;
-        if (gr < p.M) {
-          const float2* src = Ag + gr * p.lda + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = col0 + r, gk = k0 + c;
-        if (gr < p.N) {
-          const float2* src = Bg + gr * p.ldb + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      rb[j] = v;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        As[buf][r * LDK + c] = make_float2(ra[j].x, ra[j].y);
-        As[buf][r * LDK + c + 1] = make_float2(ra[j].z, ra[j].w);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        Bs[buf][r * LDK + c] = make_float2(rb[j].x, rb[j].y);
-        Bs[buf][r * LDK + c + 1] = make_float2(rb[j].z, rb[j].w);
-      }
-    }
-  };
-
-  v16f t1[TM][TN], t2[TM][TN], t3[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) t1[i][j][e] = t2[i][j][e] = t3[i][j][e] = 0.f;
-
-  const int kh = lane >> 5;
-  const int arow = wm * TM * 32 + (lane & 31);
-  const int bcol = wn * TN * 32 + (lane & 31);
-
-  if (nk > 0) {
-    gload(kbeg);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 2) {
-      float ar[TM], ai[TM], as[TM], br[TN], bi[TN], bs[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        float2 a = As[buf][(arow + i * 32) * LDK + kk + kh];
-        ar[i] = a.x;
-        ai[i] = a.y;
-        as[i] = a.x + a.y;
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        float2 v = Bs[buf][(bcol + j * 32) * LDK + kk + kh];
-        br[j] = v.x;
-        bi[j] = v.y;
-        bs[j] = v.x + v.y;
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], t1[i][j], 0, 0, 0);
-          t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], bi[j], t2[i][j], 0, 0, 0);
-          t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(as[i], bs[j], t3[i][j], 0, 0, 0);
-        }
-    }
-    if (it + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
-        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
-        float a = t1[i][j][e], c = t2[i][j][e];
-        store_out<float>(p, b, split, row, col, 0, a - c);
-        store_out<float>(p, b, split, row, col, 1, (t3[i][j][e] - a) - c);
-      }
-}
-
-// ---------------------------------------------------------------------------
-// FP64, 4M embedding, v_mfma_f64_16x16x4_f64 (4 real k = 2 complex k).
-// ---------------------------------------------------------------------------
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f64_4m_body(const GemmParams& p, int tm, int tn, int split,
-                                                int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK % 2 == 0, "two complex k per MFMA");
-  constexpr int BM = WM * TM * 16;
-  constexpr int BN = WN * TN * 8;  // complex columns
-  constexpr int LDK = BK + 1;
-  constexpr int AV = BM * BK;  // double2 loads
-  constexpr int BV = BN * BK;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  __shared__ double2 As[2][BM * LDK];
-  __shared__ double2 Bs[2][BN * LDK];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const double2* __restrict__ Ag =
-      reinterpret_cast<const double2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const double2* __restrict__ Bg =
-      reinterpret_cast<const double2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-
-  double2 ra[NA], rb[NB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      double2 v = make_double2(0.0, 0.0);
-      if (idx < AV) {
-        int r = idx / BK, c = idx % BK;
-        int64_t gr = row0 + r, gk = k0 + c;
-        if (gr < p.M && gk < kend) v = Ag[gr * p.lda + gk];
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      double2 v = make_double2(0.0, 0.0);
-      if (idx < BV) {
-        int r = idx / BK, c = idx % BK;
-        int64_t gr = col0 + r, gk = k0 + c;
-        if (gr < p.N && gk < kend) v = Bg[gr * p.ldb + gk];
-      }
-      rb[j] = v;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < AV) As[buf][(idx / BK) * LDK + idx % BK] = ra[j];
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < BV) Bs[buf][(idx / BK) * LDK + idx % BK] = rb[j];
-    }
-  };
-
-  v4d acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.0;
-
-  // 16x16x4 f64 roles: A row = lane % 16, real k = lane / 16, i.e. complex k
-  // lane / 32 and part (lane / 16) & 1; B real column n = lane % 16 (complex
-  // column n / 2, part n & 1), same real k.
-  const int kc = lane >> 5;
-  const int kpart = (lane >> 4) & 1;
-  const int par = lane & 1;
-  const bool b_take_re = (kpart == par);
-  const bool b_neg = (kpart == 1 && par == 0);
-  const int arow = wm * TM * 16 + (lane & 15);
-  const int bcol = wn * TN * 8 + ((lane & 15) >> 1);
-
-  if (nk > 0) {
-    gload(kbeg);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 2) {
-      double af[TM], bf[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        double2 a = As[buf][(arow + i * 16) * LDK + kk + kc];
-        af[i] = kpart ? a.y : a.x;
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        double2 bv = Bs[buf][(bcol + j * 8) * LDK + kk + kc];
-        double v = b_take_re ? bv.x : bv.y;
-        bf[j] = b_neg ? -v : v;
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-    if (it + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
-  // 16x16 f64 accumulator layout (unlike the f32 16x16 one): lane holds
-  // real column lane % 16 and rows 4*e + lane/16 for e = 0..3.
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int64_t row = row0 + wm * TM * 16 + i * 16 + 4 * e + (lane >> 4);
-        int n = wn * TN * 16 + j * 16 + (lane & 15);
-        store_out<double>(p, b, split, row, col0 + (n >> 1), n & 1, acc[i][j][e]);
-      }
-}
-
-// ---------------------------------------------------------------------------
-// Split BF16 x3, 4M embedding, v_mfma_f32_32x32x16_bf16.
-// Operands are bf16 complex pairs packed as uint32 (re low, im high), hi and
-// lo parts in separate arrays.  Per 16 real k: lo*hi + hi*lo + hi*hi into
-// one FP32 accumulator.
-// ---------------------------------------------------------------------------
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_bf16x3_body(const GemmParams& p, int tm, int tn, int split,
-                                                int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK % 8 == 0, "eight complex k per MFMA");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 16;
-  constexpr int LDK = BK + 4;       // uint32 per padded row
-  constexpr int AV = BM * BK / 4;   // uint4 loads (4 complex) per array
-  constexpr int BV = BN * BK / 4;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  __shared__ __align__(16) uint32_t Ah[2][BM * LDK];
-  __shared__ __align__(16) uint32_t Al[2][BM * LDK];
-  __shared__ __align__(16) uint32_t Bh[2][BN * LDK];
-  __shared__ __align__(16) uint32_t Bl[2][BN * LDK];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const int64_t ao = batch_off(p.a_bs, p.nbb, b), bo = batch_off(p.b_bs, p.nbb, b);
-  const uint32_t* __restrict__ Agh = reinterpret_cast<const uint32_t*>(p.A) + ao;
-  const uint32_t* __restrict__ Agl = reinterpret_cast<const uint32_t*>(p.A2) + ao;
-  const uint32_t* __restrict__ Bgh = reinterpret_cast<const uint32_t*>(p.B) + bo;
-  const uint32_t* __restrict__ Bgl = reinterpret_cast<const uint32_t*>(p.B2) + bo;
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-
-  uint4 rah[NA], ral[NA], rbh[NB], rbl[NB];
-  auto ld4 = [&](const uint32_t* src, int64_t gk) -> uint4 {
-    if (gk + 3 < kend) return *reinterpret_cast<const uint4*>(src);
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gk < kend) v.x = src[0];
-    if (gk + 1 < kend) v.y = src[1];
-    if (gk + 2 < kend) v.z = src[2];
-    return v;
-  };
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
-      if (idx < AV) {
-        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-        int64_t gr = row0 + r, gk = k0 + c;
-        if (gr < p.M && gk < kend) {
-          h = ld4(Agh + gr * p.lda + gk, gk);
-          l = ld4(Agl + gr * p.lda + gk, gk);
-        }
-      }
-      rah[j] = h;
-      ral[j] = l;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
-      if (idx < BV) {
-        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-        int64_t gr = col0 + r, gk = k0 + c;
-        if (gr < p.N && gk < kend) {
-          h = ld4(Bgh + gr * p.ldb + gk, gk);
-          l = ld4(Bgl + gr * p.ldb + gk, gk);
-        }
-      }
-      rbh[j] = h;
-      rbl[j] = l;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < AV) {
-        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-        *reinterpret_cast<uint4*>(&Ah[buf][r * LDK + c]) = rah[j];
-        *reinterpret_cast<uint4*>(&Al[buf][r * LDK + c]) = ral[j];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < BV) {
-        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-        *reinterpret_cast<uint4*>(&Bh[buf][r * LDK + c]) = rbh[j];
-        *reinterpret_cast<uint4*>(&Bl[buf][r * LDK + c]) = rbl[j];
-      }
-    }
-  };
-
-  v16f acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-
-  // 32x32x16 bf16 roles: A row = lane % 32, real k = 8*(lane/32) + 0..7,
-  // i.e. complex k 4*(lane/32) + 0..3 in interleaved (re, im) order; B real
-  // column n = lane % 32 reads the same four complex b's of complex column
-  // n / 2 and turns each packed (b_r, b_i) into (b_r, -b_i) for n even or
-  // (b_i, b_r) for n odd.
-  const int kq = (lane >> 5) * 4;
-  const bool odd = lane & 1;
-  const int arow = wm * TM * 32 + (lane & 31);
-  const int bcol = wn * TN * 16 + ((lane & 31) >> 1);
-  auto bfix = [&](v4u w) -> v4u {
-    if (odd) return (w >> 16) | (w << 16);
-    return w ^ 0x80000000u;
-  };
-
-  if (nk > 0) {
-    gload(kbeg);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 8) {
-      v8bf ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        int o = (arow + i * 32) * LDK + kk + kq;
-        ah[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(&Ah[buf][o]));
-        al[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(&Al[buf][o]));
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        int o = (bcol + j * 16) * LDK + kk + kq;
-        bh[j] = __builtin_bit_cast(v8bf, bfix(*reinterpret_cast<const v4u*>(&Bh[buf][o])));
-        bl[j] = __builtin_bit_cast(v8bf, bfix(*reinterpret_cast<const v4u*>(&Bl[buf][o])));
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
-    }
-    if (it + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
-  const int khalf = lane >> 5;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * khalf + (e & 3);
-        int n = wn * TN * 32 + j * 32 + (lane & 31);
-        store_out<float>(p, b, split, row, col0 + (n >> 1), n & 1, acc[i][j][e]);
-      }
-}
-
-// ---------------------------------------------------------------------------
-// Re/Im-split variants of the 4M kernels.  Each 32x32 MFMA tile covers 32
-// complex columns and comes in a pair: one accumulates the real parts and
-// one the imaginary parts of C.  For the real part, B's embedded rows are
-// (b_r, -b_i) per complex k; for the imaginary part (b_i, b_r).  All lanes
-// of one MFMA then apply the same transform to the same complex B values,
-// so a B fragment is read from LDS once for both tiles and no lane diverges.
-// ---------------------------------------------------------------------------
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f32_ri_body(const GemmParams& p, int tm, int tn, int split,
-                                                  int b) {
-  static_assert(WM * WN == 4, "four waves");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 32;  // complex columns
-  constexpr int LDK = BK + 1;
-  constexpr int AV = BM * BK / 2;
-  constexpr int BV = BN * BK / 2;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  __shared__ float2 As[2][BM * LDK];
-  __shared__ float2 Bs[2][BN * LDK];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const float2* __restrict__ Ag =
-      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const float2* __restrict__ Bg =
-      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-
-  float4 ra[NA], rb[NB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = row0 + r, gk = k0 + c;
-        if (gr < p.M) {
-          const float2* src = Ag + gr * p.lda + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = col0 + r, gk = k0 + c;
-        if (gr < p.N) {
-          const float2* src = Bg + gr * p.ldb + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      rb[j] = v;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        As[buf][r * LDK + c] = make_float2(ra[j].x, ra[j].y);
-        As[buf][r * LDK + c + 1] = make_float2(ra[j].z, ra[j].w);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        Bs[buf][r * LDK + c] = make_float2(rb[j].x, rb[j].y);
-        Bs[buf][r * LDK + c + 1] = make_float2(rb[j].z, rb[j].w);
-      }
-    }
-  };
-
-  v16f cr[TM][TN], ci[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
-
-  // Lane roles: A row = lane % 32, real k = lane / 32 (0: re, 1: im part of
-  // complex a); B complex column = lane % 32, same real k.
-  const int kh = lane >> 5;
-  const uint32_t neg = kh ? 0x80000000u : 0u;
-  const int arow = wm * TM * 32 + (lane & 31);
-  const int bcol = wn * TN * 32 + (lane & 31);
-
-  if (nk > 0) {
-    gload(kbeg);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      float af[TM], br[TN], bi[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        float2 a = As[buf][(arow + i * 32) * LDK + kk];
-        af[i] = kh ? a.y : a.x;
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        float2 v = Bs[buf][(bcol + j * 32) * LDK + kk];
-        // Real-part row: (b_r, -b_i); imaginary-part row: (b_i, b_r).
-        br[j] = __uint_as_float(__float_as_uint(kh ? v.y : v.x) ^ neg);
-        bi[j] = kh ? v.x : v.y;
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], br[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bi[j], ci[i][j], 0, 0, 0);
-        }
-    }
-    if (it + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
-        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
-        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
-        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
-      }
-}
-
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm, int tn,
-                                                     int split, int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK % 8 == 0, "eight complex k per MFMA");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 32;  // complex columns
-  // LDS rows of BK words (BK / 4 chunks of 16 bytes), unpadded: chunk q of
-  // row r sits at chunk q ^ swz(r), which puts the rows one 128-bit read
-  // touches (consecutive rows, same chunk) and the chunks one staging store
-  // writes (whole consecutive rows) on distinct bank groups, for 32 or 64
-  // four-byte banks.
-  constexpr int LDK = BK;
-  static_assert(BK == 8 || BK == 16, "swizzle defined for 2 or 4 chunks per row");
-  auto swz = [](int r) -> int {
-    return BK == 16 ? (((r >> 1) ^ (r >> 3)) & 3) : (((r >> 2) ^ (r >> 3)) & 1);
-  };
-  auto chunk_at = [&](int r, int word) -> int {  // word: multiple of 4 within the row
-    return r * LDK + ((((word >> 2) ^ swz(r))) << 2);
-  };
-  constexpr int AV = BM * BK / 4;
-  constexpr int BV = BN * BK / 4;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  __shared__ __align__(16) uint32_t Ah[2][BM * LDK];
-  __shared__ __align__(16) uint32_t Al[2][BM * LDK];
-  __shared__ __align__(16) uint32_t Bh[2][BN * LDK];
-  __shared__ __align__(16) uint32_t Bl[2][BN * LDK];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const int64_t ao = batch_off(p.a_bs, p.nbb, b), bo = batch_off(p.b_bs, p.nbb, b);
-  const uint32_t* __restrict__ Agh = reinterpret_cast<const uint32_t*>(p.A) + ao;
-  const uint32_t* __restrict__ Agl = reinterpret_cast<const uint32_t*>(p.A2) + ao;
-  const uint32_t* __restrict__ Bgh = reinterpret_cast<const uint32_t*>(p.B) + bo;
-  const uint32_t* __restrict__ Bgl = reinterpret_cast<const uint32_t*>(p.B2) + bo;
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-
-  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
-  uint4 rah[NA], ral[NA], rbh[NB], rbl[NB];
-  // Interior tiles: unguarded loads (see the FP32 large tile).
-  auto gload_fast = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (AV % 256 == 0 || idx < AV) {  // threads past the tile load nothing
-        int64_t o = (row0 + idx / (BK / 4)) * p.lda + k0 + (idx % (BK / 4)) * 4;
-        rah[j] = *reinterpret_cast<const uint4*>(Agh + o);
-        ral[j] = *reinterpret_cast<const uint4*>(Agl + o);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (BV % 256 == 0 || idx < BV) {
-        int64_t o = (col0 + idx / (BK / 4)) * p.ldb + k0 + (idx % (BK / 4)) * 4;
-        rbh[j] = *reinterpret_cast<const uint4*>(Bgh + o);
-        rbl[j] = *reinterpret_cast<const uint4*>(Bgl + o);
-      }
-    }
-  };
-  auto ld4 = [&](const uint32_t* src, int64_t gk) -> uint4 {
-    if (gk + 3 < kend) return *reinterpret_cast<const uint4*>(src);
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gk < kend) v.x = src[0];
-    if (gk + 1 < kend) v.y = src[1];
-    if (gk + 2 < kend) v.z = src[2];
-    return v;
-  };
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
-      if (idx < AV) {
-        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-        int64_t gr = row0 + r, gk = k0 + c;
-        if (gr < p.M && gk < kend) {
-          h = ld4(Agh + gr * p.lda + gk, gk);
-          l = ld4(Agl + gr * p.lda + gk, gk);
-        }
-      }
-      rah[j] = h;
-      ral[j] = l;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
-      if (idx < BV) {
-        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-        int64_t gr = col0 + r, gk = k0 + c;
-        if (gr < p.N && gk < kend) {
-          h = ld4(Bgh + gr * p.ldb + gk, gk);
-          l = ld4(Bgl + gr * p.ldb + gk, gk);
-        }
-      }
-      rbh[j] = h;
-      rbl[j] = l;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (AV % 256 == 0 || idx < AV) {
-        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-        *reinterpret_cast<uint4*>(&Ah[buf][chunk_at(r, c)]) = rah[j];
-        *reinterpret_cast<uint4*>(&Al[buf][chunk_at(r, c)]) = ral[j];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (BV % 256 == 0 || idx < BV) {
-        int r = idx / (BK / 4), c = (idx % (BK / 4)) * 4;
-        *reinterpret_cast<uint4*>(&Bh[buf][chunk_at(r, c)]) = rbh[j];
-        *reinterpret_cast<uint4*>(&Bl[buf][chunk_at(r, c)]) = rbl[j];
-      }
-    }
-  };
-
-  v16f cr[TM][TN], ci[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
-
-  // A row = lane % 32 and complex k 4*(lane/32) + 0..3 (interleaved re, im
-  // = 8 real k); B complex column = lane % 32, same complex k.  Packed b
-  // (b_r | b_i << 16) becomes (b_r, -b_i) for the real-part tile and
-  // (b_i, b_r) for the imaginary-part tile.
-  const int kq = (lane >> 5) * 4;
-  const int arow = wm * TM * 32 + (lane & 31);
-  const int bcol = wn * TN * 32 + (lane & 31);
-
-  auto mainloop = [&](auto tag) {
-  constexpr bool FAST = decltype(tag)::value;
-  if (nk > 0) {
-    if constexpr (FAST) gload_fast(kbeg); else gload(kbeg);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    if constexpr (FAST) {
-      gload_fast(kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
-      __builtin_amdgcn_sched_barrier(0);
-    } else if (it + 1 < nk) {
-      gload(kbeg + int64_t(it + 1) * BK);
-    }
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 8) {
-      v8bf ah[TM], al[TM];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        int o = chunk_at(arow + i * 32, kk + kq);
-        ah[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(&Ah[buf][o]));
-        al[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(&Al[buf][o]));
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        int o = chunk_at(bcol + j * 32, kk + kq);
-        const v4u wh = *reinterpret_cast<const v4u*>(&Bh[buf][o]);
-        const v4u wl = *reinterpret_cast<const v4u*>(&Bl[buf][o]);
-        const v8bf bhr = __builtin_bit_cast(v8bf, wh ^ 0x80000000u);
-        const v8bf blr = __builtin_bit_cast(v8bf, wl ^ 0x80000000u);
-        const v8bf bhi = __builtin_bit_cast(v8bf, (wh >> 16) | (wh << 16));
-        const v8bf bli = __builtin_bit_cast(v8bf, (wl >> 16) | (wl << 16));
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhr, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhi, ci[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], blr, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bli, ci[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhr, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhi, ci[i][j], 0, 0, 0);
-        }
-      }
-    }
-    if (FAST || it + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-  }
-  };
-  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
-
-  const int khalf = lane >> 5;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * khalf + (e & 3);
-        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
-        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
-        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
-      }
-}
-
-// Split-BF16x3 with direct-to-LDS staging: the LDS layout of the Re/Im-split
-// BF16 tile (interleaved bf16 pairs, BK / 4 chunks of 16 bytes per row,
-// chunk q of row r at q ^ swz(r)) filled by global_load_lds_dwordx4 on
-// interior tiles (a wave writes 64 consecutive slots; slot s of a stage is
-// row s / (BK / 4), stored chunk s % (BK / 4)).  One array per buffer and the
-// stage loop unrolled by two, as in the FP32 direct-to-LDS tile.
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_bf16x3_dl_body(const GemmParams& p, int tm, int tn,
-                                                     int split, int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK == 16, "four 16-byte chunks per LDS row");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 32;  // complex columns
-  constexpr int CPR = BK / 4;       // chunks per row
-  constexpr int LDK = BK;           // words per row
-  auto swz = [](int r) -> int { return ((r >> 1) ^ (r >> 3)) & 3; };
-  auto chunk_at = [&](int r, int word) -> int {  // word: multiple of 4 within the row
-    return r * LDK + ((((word >> 2) ^ swz(r))) << 2);
-  };
-  constexpr int AV = BM * CPR;  // chunks per stage and part
-  constexpr int BV = BN * CPR;
-  static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
-  constexpr int NA = AV / 256;
-  constexpr int NB = BV / 256;
-  __shared__ __align__(16) uint32_t Ah0[BM * LDK], Ah1[BM * LDK], Al0[BM * LDK], Al1[BM * LDK];
-  __shared__ __align__(16) uint32_t Bh0[BN * LDK], Bh1[BN * LDK], Bl0[BN * LDK], Bl1[BN * LDK];
-  auto pick = [](auto t, uint32_t* x0, uint32_t* x1) -> uint32_t* {
-    if constexpr (decltype(t)::value) return x1; else return x0;
-  };
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const int64_t ao = batch_off(p.a_bs, p.nbb, b), bo = batch_off(p.b_bs, p.nbb, b);
-  const uint32_t* __restrict__ Agh = reinterpret_cast<const uint32_t*>(p.A) + ao;
-  const uint32_t* __restrict__ Agl = reinterpret_cast<const uint32_t*>(p.A2) + ao;
-  const uint32_t* __restrict__ Bgh = reinterpret_cast<const uint32_t*>(p.B) + bo;
-  const uint32_t* __restrict__ Bgl = reinterpret_cast<const uint32_t*>(p.B2) + bo;
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
-
-  auto dma = [&](auto buf, int64_t k0) {
-    uint32_t* ah = pick(buf, Ah0, Ah1);
-    uint32_t* al = pick(buf, Al0, Al1);
-    uint32_t* bh = pick(buf, Bh0, Bh1);
-    uint32_t* bl = pick(buf, Bl0, Bl1);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s / CPR, q = (s % CPR) ^ swz(r);
-      const int64_t o = (row0 + r) * p.lda + k0 + 4 * q;
-      const int d = 4 * (256 * j + 64 * wave);
-      __builtin_amdgcn_global_load_lds(Agh + o, (__attribute__((address_space(3))) void*)(ah + d),
-                                       16, 0, 0);
-      __builtin_amdgcn_global_load_lds(Agl + o, (__attribute__((address_space(3))) void*)(al + d),
-                                       16, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s / CPR, q = (s % CPR) ^ swz(r);
-      const int64_t o = (col0 + r) * p.ldb + k0 + 4 * q;
-      const int d = 4 * (256 * j + 64 * wave);
-      __builtin_amdgcn_global_load_lds(Bgh + o, (__attribute__((address_space(3))) void*)(bh + d),
-                                       16, 0, 0);
-      __builtin_amdgcn_global_load_lds(Bgl + o, (__attribute__((address_space(3))) void*)(bl + d),
-                                       16, 0, 0);
-    }
-  };
-  uint4 rah[NA], ral[NA], rbh[NB], rbl[NB];
-  auto ld4 = [&](const uint32_t* src, int64_t gk) -> uint4 {
-    if (gk + 3 < kend) return *reinterpret_cast<const uint4*>(src);
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gk < kend) v.x = src[0];
-    if (gk + 1 < kend) v.y = src[1];
-    if (gk + 2 < kend) v.z = src[2];
-    return v;
-  };
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) * 4;
-      const int64_t gr = row0 + r, gk = k0 + c;
-      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
-      if (gr < p.M && gk < kend) {
-        h = ld4(Agh + gr * p.lda + gk, gk);
-        l = ld4(Agl + gr * p.lda + gk, gk);
-      }
-      rah[j] = h;
-      ral[j] = l;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) * 4;
-      const int64_t gr = col0 + r, gk = k0 + c;
-      uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
-      if (gr < p.N && gk < kend) {
-        h = ld4(Bgh + gr * p.ldb + gk, gk);
-        l = ld4(Bgl + gr * p.ldb + gk, gk);
-      }
-      rbh[j] = h;
-      rbl[j] = l;
-    }
-  };
-  auto sstore = [&](auto buf) {
-    uint32_t* ah = pick(buf, Ah0, Ah1);
-    uint32_t* al = pick(buf, Al0, Al1);
-    uint32_t* bh = pick(buf, Bh0, Bh1);
-    uint32_t* bl = pick(buf, Bl0, Bl1);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) * 4;
-      *reinterpret_cast<uint4*>(ah + chunk_at(r, c)) = rah[j];
-      *reinterpret_cast<uint4*>(al + chunk_at(r, c)) = ral[j];
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) * 4;
-      *reinterpret_cast<uint4*>(bh + chunk_at(r, c)) = rbh[j];
-      *reinterpret_cast<uint4*>(bl + chunk_at(r, c)) = rbl[j];
-    }
-  };
-
-  v16f cr[TM][TN], ci[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
-
-  // As in the Re/Im-split BF16 tile: A row lane % 32, complex k
-  // 4 * (lane / 32) + 0..3 of each group of eight; packed b becomes
-  // (b_r, -b_i) for the real tile and (b_i, b_r) for the imaginary tile.
-  const int kq = (lane >> 5) * 4;
-  const int arow = wm * TM * 32 + (lane & 31);
-  const int bcol = wn * TN * 32 + (lane & 31);
-
-  auto stage = [&](auto fast, auto cur, int it) {
-    constexpr bool FAST = decltype(fast)::value;
-    constexpr bool CUR = decltype(cur)::value;
-    const uint32_t* ahs = pick(cur, Ah0, Ah1);
-    const uint32_t* als = pick(cur, Al0, Al1);
-    const uint32_t* bhs = pick(cur, Bh0, Bh1);
-    const uint32_t* bls = pick(cur, Bl0, Bl1);
-    if constexpr (FAST) {
-      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
-      __builtin_amdgcn_sched_barrier(0);
-    } else if (it + 1 < nk) {
-      gload(kbeg + int64_t(it + 1) * BK);
-    }
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 8) {
-      v8bf ah[TM], al[TM];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int o = chunk_at(arow + i * 32, kk + kq);
-        ah[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(ahs + o));
-        al[i] = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4u*>(als + o));
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int o = chunk_at(bcol + j * 32, kk + kq);
-        const v4u wh = *reinterpret_cast<const v4u*>(bhs + o);
-        const v4u wl = *reinterpret_cast<const v4u*>(bls + o);
-        const v8bf bhr = __builtin_bit_cast(v8bf, wh ^ 0x80000000u);
-        const v8bf blr = __builtin_bit_cast(v8bf, wl ^ 0x80000000u);
-        const v8bf bhi = __builtin_bit_cast(v8bf, (wh >> 16) | (wh << 16));
-        const v8bf bli = __builtin_bit_cast(v8bf, (wl >> 16) | (wl << 16));
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhr, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bhi, ci[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], blr, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bli, ci[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhr, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bhi, ci[i][j], 0, 0, 0);
-        }
-      }
-    }
-    if constexpr (FAST) {
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
-    } else if (it + 1 < nk) {
-      sstore(BoolTag<!CUR>{});
-    }
-    __syncthreads();
-  };
-
-  auto mainloop = [&](auto fast) {
-    constexpr bool FAST = decltype(fast)::value;
-    if (nk > 0) {
-      if constexpr (FAST) {
-        dma(BoolTag<false>{}, kbeg);
-        __builtin_amdgcn_s_waitcnt(0);
-      } else {
-        gload(kbeg);
-        sstore(BoolTag<false>{});
-      }
-    }
-    __syncthreads();
-    for (int it = 0; it < nk; it += 2) {
-      stage(fast, BoolTag<false>{}, it);
-      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
-    }
-  };
-  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
-
-  const int khalf = lane >> 5;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * khalf + (e & 3);
-        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
-        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
-        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
-      }
-}
-
-// ---------------------------------------------------------------------------
-// Re/Im-split tiles with planar LDS rows.  While staging a chunk into LDS,
-// each row of A is stored as [a_r(0..BK-1) | a_i(0..BK-1)] and each row of B
-// as [b_r(0..BK-1) | -b_i(0..BK-1)], so the MFMA lane whose real k is the
-// imaginary half reads the second half directly: no per-fragment select.
-// The real-part tile uses B rows as stored; the imaginary-part tile needs
-// (b_i, b_r), read from the other half with one sign flip on the first.
-// ---------------------------------------------------------------------------
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f32_rp_body(const GemmParams& p, int tm, int tn, int split,
-                                                  int b) {
-  static_assert(WM * WN == 4, "four waves");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 32;  // complex columns
-  constexpr int LDR = 2 * BK + 1;   // floats per padded LDS row
-  constexpr int AV = BM * BK / 2;
-  constexpr int BV = BN * BK / 2;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  __shared__ float As[2][BM * LDR];
-  __shared__ float Bs[2][BN * LDR];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const float2* __restrict__ Ag =
-      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const float2* __restrict__ Bg =
-      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-
-  float4 ra[NA], rb[NB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = row0 + r, gk = k0 + c;
-        if (gr < p.M) {
-          const float2* src = Ag + gr * p.lda + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = col0 + r, gk = k0 + c;
-        if (gr < p.N) {
-          const float2* src = Bg + gr * p.ldb + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      rb[j] = v;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        float* row = &As[buf][r * LDR];
-        row[c] = ra[j].x;
-        row[c + 1] = ra[j].z;
-        row[BK + c] = ra[j].y;
-        row[BK + c + 1] = ra[j].w;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        float* row = &Bs[buf][r * LDR];
-        row[c] = rb[j].x;
-        row[c + 1] = rb[j].z;
-        row[BK + c] = -rb[j].y;
-        row[BK + c + 1] = -rb[j].w;
-      }
-    }
-  };
-
-  v16f cr[TM][TN], ci[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
-
-  const int kh = lane >> 5;
-  const int aoff = (wm * TM * 32 + (lane & 31)) * LDR + kh * BK;
-  const int boff_r = (wn * TN * 32 + (lane & 31)) * LDR + kh * BK;
-  const int boff_i = (wn * TN * 32 + (lane & 31)) * LDR + (1 - kh) * BK;
-  const uint32_t flip = kh ? 0u : 0x80000000u;  // Im row: (-(-b_i), b_r)
-
-  if (nk > 0) {
-    gload(kbeg);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      float af[TM], br[TN], bi[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) af[i] = As[buf][aoff + i * 32 * LDR + kk];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        br[j] = Bs[buf][boff_r + j * 32 * LDR + kk];
-        bi[j] = __uint_as_float(__float_as_uint(Bs[buf][boff_i + j * 32 * LDR + kk]) ^ flip);
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], br[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bi[j], ci[i][j], 0, 0, 0);
-        }
-    }
-    if (it + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
-        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
-        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
-        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
-      }
-}
-
-// Large-tile FP32-4M: each wave owns TM x TN Re/Im tile pairs (up to 16
-// accumulators), LDS rows padded to a multiple of 16 bytes so a lane reads
-// four consecutive k of its row in one 128-bit LDS read, and staging writes
-// are 64-bit.  Rows [a_r | a_i] and [b_r | -b_i] as in the planar tile; the
-// padding of 4 floats puts 16 consecutive rows on distinct 16-byte bank
-// groups.
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f32_big_body(const GemmParams& p, int tm, int tn,
-                                                   int split, int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK % 4 == 0, "k in groups of four");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 32;  // complex columns
-  constexpr int LDR = 2 * BK + 4;   // floats per LDS row, 16-byte multiple
-  constexpr int AV = BM * BK / 2;   // float4 loads (two complex) per stage
-  constexpr int BV = BN * BK / 2;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  extern __shared__ float4 big_lds[];
-  float* As0 = reinterpret_cast<float*>(big_lds);
-  float* Bs0 = As0 + 2 * BM * LDR;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const float2* __restrict__ Ag =
-      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const float2* __restrict__ Bg =
-      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-
-  // Interior tiles (whole tile inside M x N, K chunk a multiple of BK) load
-  // without guards, so no load sits behind a divergent branch and the loads
-  // of the next stage stay in flight across the MFMA phase.
-  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
-  float4 ra[NA], rb[NB];
-  auto gload_fast = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (AV % 256 == 0 || idx < AV) {  // threads past the tile load nothing
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        ra[j] = *reinterpret_cast<const float4*>(Ag + (row0 + r) * p.lda + k0 + c);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (BV % 256 == 0 || idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        rb[j] = *reinterpret_cast<const float4*>(Bg + (col0 + r) * p.ldb + k0 + c);
-      }
-    }
-  };
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = row0 + r, gk = k0 + c;
-        if (gr < p.M) {
-          const float2* src = Ag + gr * p.lda + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = col0 + r, gk = k0 + c;
-        if (gr < p.N) {
-          const float2* src = Bg + gr * p.ldb + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      rb[j] = v;
-    }
-  };
-  auto sstore = [&](int buf) {
-    float* As = As0 + buf * BM * LDR;
-    float* Bs = Bs0 + buf * BN * LDR;
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (AV % 256 == 0 || idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        float* row = As + r * LDR;
-        row[c] = ra[j].x;
-        row[c + 1] = ra[j].z;
-        row[BK + c] = ra[j].y;
-        row[BK + c + 1] = ra[j].w;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (BV % 256 == 0 || idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        float* row = Bs + r * LDR;
-        row[c] = rb[j].x;
-        row[c + 1] = rb[j].z;
-        row[BK + c] = -rb[j].y;
-        row[BK + c + 1] = -rb[j].w;
-      }
-    }
-  };
-
-  v16f cr[TM][TN], ci[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
-
-  const int kh = lane >> 5;
-  const int aoff = (wm * TM * 32 + (lane & 31)) * LDR + kh * BK;
-  const int boff_r = (wn * TN * 32 + (lane & 31)) * LDR + kh * BK;
-  const int boff_i = (wn * TN * 32 + (lane & 31)) * LDR + (1 - kh) * BK;
-  const uint32_t flip = kh ? 0u : 0x80000000u;  // Im row: (-(-b_i), b_r)
-
-  auto mainloop = [&](auto tag) {
-  constexpr bool FAST = decltype(tag)::value;
-  if (nk > 0) {
-    if constexpr (FAST) gload_fast(kbeg); else gload(kbeg);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    const float* As = As0 + buf * BM * LDR;
-    const float* Bs = Bs0 + buf * BN * LDR;
-    // Fast path: always prefetch (the last stage re-reads itself), so the
-    // loop body has no branch and the loads stay in flight over the MFMAs.
-    if constexpr (FAST) {
-      gload_fast(kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
-      // Keep the loads at the top of the stage: the scheduler would
-      // otherwise sink them next to their LDS stores, exposing their latency.
-      __builtin_amdgcn_sched_barrier(0);
-    } else if (it + 1 < nk) {
-      gload(kbeg + int64_t(it + 1) * BK);
-    }
-#pragma unroll
-    for (int kq = 0; kq < BK; kq += 4) {
-      float4 a4[TM], r4[TN], i4[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-        a4[i] = *reinterpret_cast<const float4*>(As + aoff + i * 32 * LDR + kq);
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        r4[j] = *reinterpret_cast<const float4*>(Bs + boff_r + j * 32 * LDR + kq);
-        float4 t = *reinterpret_cast<const float4*>(Bs + boff_i + j * 32 * LDR + kq);
-        t.x = __uint_as_float(__float_as_uint(t.x) ^ flip);
-        t.y = __uint_as_float(__float_as_uint(t.y) ^ flip);
-        t.z = __uint_as_float(__float_as_uint(t.z) ^ flip);
-        t.w = __uint_as_float(__float_as_uint(t.w) ^ flip);
-        i4[j] = t;
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            const float av = q == 0 ? a4[i].x : q == 1 ? a4[i].y : q == 2 ? a4[i].z : a4[i].w;
-            const float bv = q == 0 ? r4[j].x : q == 1 ? r4[j].y : q == 2 ? r4[j].z : r4[j].w;
-            const float cv = q == 0 ? i4[j].x : q == 1 ? i4[j].y : q == 2 ? i4[j].z : i4[j].w;
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, cv, ci[i][j], 0, 0, 0);
-          }
-    }
-    if (FAST || it + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-  }
-  };
-  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
-
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
-        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
-        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
-        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
-      }
-}
-
-// Dynamic LDS bytes of the large FP32 tile.
-template <int WM, int WN, int TM, int TN, int BK>
-constexpr size_t big_lds_bytes() {
-  return size_t(2) * (WM * TM * 32 + WN * TN * 32) * (2 * BK + 4) * sizeof(float);
-}
-
-// Large-tile FP32-4M with direct-to-LDS staging: interior tiles copy each
-// 16-byte chunk (two complex) of A and B from global memory straight into
-// LDS (global_load_lds_dwordx4: a wave writes 64 consecutive chunks), so no
-// VGPRs hold the next stage and no LDS stores are issued.  LDS rows keep the
-// interleaved (re, im) order of the operands, 8 chunks per row (16 complex
-// k), unpadded; logical chunk c of row r sits at chunk c ^ dl_swz(r), so the
-// 128-bit fragment reads of 8 (or 16) consecutive rows fall on distinct bank
-// groups.  A lane reads chunk 2g + kh of its row (kh = lane / 32) and feeds
-// its four floats to four MFMAs; the B lane that meets it in an instruction
-// reads the same logical chunk of its column and supplies b_r or -b_i (real
-// accumulator) and b_i or b_r (imaginary accumulator), i.e. the 4M
-// embedding with the real k of an instruction taken from consecutive floats.
-// Edge tiles stage through registers into the same layout, zero-filled.
-__device__ __forceinline__ int dl_swz(int r) { return (r ^ (r >> 3)) & 7; }
-// Rows of 16 chunks (BK = 32): 256-byte rows start on the same bank, so the
-// low four row bits alone spread 8 or 16 consecutive rows.
-__device__ __forceinline__ int dl_swz16(int r) { return r & 15; }
-
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f32_dl_body(const GemmParams& p, int tm, int tn,
-                                                  int split, int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK == 16 || BK == 32, "eight or sixteen 16-byte chunks per LDS row");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 32;  // complex columns
-  constexpr int CPR = BK / 2;       // chunks per row
-  auto swz = [](int r) -> int { return CPR == 8 ? dl_swz(r) : dl_swz16(r); };
-  constexpr int AV = BM * CPR;      // chunks per stage
-  constexpr int BV = BN * CPR;
-  static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
-  constexpr int NA = AV / 256;
-  constexpr int NB = BV / 256;
-  // One array per buffer: with the buffer known at compile time in every
-  // stage, the compiler can tell the copies into one buffer from the
-  // fragment reads of the other and does not wait for the copies first.
-  __shared__ __align__(16) float4 Ad0[AV], Ad1[AV];
-  __shared__ __align__(16) float4 Bd0[BV], Bd1[BV];
-  auto abuf = [&](auto t) -> float4* { if constexpr (decltype(t)::value) return Ad1; else return Ad0; };
-  auto bbuf = [&](auto t) -> float4* { if constexpr (decltype(t)::value) return Bd1; else return Bd0; };
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const float2* __restrict__ Ag =
-      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const float2* __restrict__ Bg =
-      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
-
-  // Slot s = 256 j + tid of a stage: row s / CPR, stored chunk s % CPR,
-  // which holds logical chunk (s % CPR) ^ swz(row).
-  auto dma = [&](auto buf, int64_t k0) {
-    float4* As = abuf(buf);
-    float4* Bs = bbuf(buf);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) ^ swz(r);
-      __builtin_amdgcn_global_load_lds(
-          Ag + (row0 + r) * p.lda + k0 + 2 * c,
-          (__attribute__((address_space(3))) void*)(As + 256 * j + 64 * wave), 16, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) ^ swz(r);
-      __builtin_amdgcn_global_load_lds(
-          Bg + (col0 + r) * p.ldb + k0 + 2 * c,
-          (__attribute__((address_space(3))) void*)(Bs + 256 * j + 64 * wave), 16, 0, 0);
-    }
-  };
-  float4 ra[NA], rb[NB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s / CPR, c = s % CPR;
-      const int64_t gr = row0 + r, gk = k0 + 2 * c;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gr < p.M) {
-        const float2* src = Ag + gr * p.lda + gk;
-        if (gk + 1 < kend) {
-          v = *reinterpret_cast<const float4*>(src);
-        } else if (gk < kend) {
-          const float2 t = src[0];
-          v.x = t.x;
-          v.y = t.y;
-        }
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s / CPR, c = s % CPR;
-      const int64_t gr = col0 + r, gk = k0 + 2 * c;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gr < p.N) {
-        const float2* src = Bg + gr * p.ldb + gk;
-        if (gk + 1 < kend) {
-          v = *reinterpret_cast<const float4*>(src);
-        } else if (gk < kend) {
-          const float2 t = src[0];
-          v.x = t.x;
-          v.y = t.y;
-        }
-      }
-      rb[j] = v;
-    }
-  };
-  auto sstore = [&](auto buf) {
-    float4* As = abuf(buf);
-    float4* Bs = bbuf(buf);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s / CPR;
-      As[r * CPR + ((s % CPR) ^ swz(r))] = ra[j];
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s / CPR;
-      Bs[r * CPR + ((s % CPR) ^ swz(r))] = rb[j];
-    }
-  };
-
-  v16f cr[TM][TN], ci[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) cr[i][j][e] = ci[i][j][e] = 0.f;
-
-  const int kh = lane >> 5;
-  const int arow = wm * TM * 32 + (lane & 31);
-  const int brow = wn * TN * 32 + (lane & 31);
-
-  // One K stage computed from buffer CUR while the next stage fills the
-  // other buffer.
-  auto stage = [&](auto fast, auto cur, int it) {
-    constexpr bool FAST = decltype(fast)::value;
-    constexpr bool CUR = decltype(cur)::value;
-    const float4* As = abuf(cur);
-    const float4* Bs = bbuf(cur);
-    // Fast path: always fill the other buffer (the last stage copies itself
-    // again), so the stage has no branch.
-    if constexpr (FAST) {
-      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
-      __builtin_amdgcn_sched_barrier(0);
-    } else if (it + 1 < nk) {
-      gload(kbeg + int64_t(it + 1) * BK);
-    }
-#pragma unroll
-    for (int g = 0; g < CPR / 2; ++g) {
-      float4 a4[TM], b4[TN], n4[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int r = arow + 32 * i;
-        a4[i] = As[r * CPR + ((2 * g + kh) ^ swz(r))];
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int r = brow + 32 * j;
-        b4[j] = Bs[r * CPR + ((2 * g + kh) ^ swz(r))];
-        n4[j] = make_float4(b4[j].x, -b4[j].y, b4[j].z, -b4[j].w);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            const float av = q == 0 ? a4[i].x : q == 1 ? a4[i].y : q == 2 ? a4[i].z : a4[i].w;
-            const float bv = q == 0 ? n4[j].x : q == 1 ? n4[j].y : q == 2 ? n4[j].z : n4[j].w;
-            const float cv = q == 0 ? b4[j].y : q == 1 ? b4[j].x : q == 2 ? b4[j].w : b4[j].z;
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, cv, ci[i][j], 0, 0, 0);
-          }
-    }
-    if constexpr (FAST) {
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
-    } else if (it + 1 < nk) {
-      sstore(BoolTag<!CUR>{});
-    }
-    __syncthreads();
-  };
-
-  auto mainloop = [&](auto fast) {
-    constexpr bool FAST = decltype(fast)::value;
-    if (nk > 0) {
-      if constexpr (FAST) {
-        dma(BoolTag<false>{}, kbeg);
-        __builtin_amdgcn_s_waitcnt(0);
-      } else {
-        gload(kbeg);
-        sstore(BoolTag<false>{});
-      }
-    }
-    __syncthreads();
-    for (int it = 0; it < nk; it += 2) {
-      stage(fast, BoolTag<false>{}, it);
-      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
-    }
-  };
-  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
-
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
-        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
-        store_out<float>(p, b, split, row, col, 0, cr[i][j][e]);
-        store_out<float>(p, b, split, row, col, 1, ci[i][j][e]);
-      }
-}
-
-// FP32-3M (Gauss) with the direct-to-LDS staging of the FP32-4M tile: the
-// same interleaved, swizzled LDS rows; a lane's chunk [a_r, a_i, a_r', a_i']
-// feeds T1 = Ar Br, T2 = Ai Bi and T3 = (Ar + Ai)(Br + Bi) for its two complex
-// k (the sums formed after the fragment read), six MFMAs per tile and chunk
-// where 4M takes eight.
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f32_3mdl_body(const GemmParams& p, int tm, int tn,
-                                                  int split, int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK == 16, "eight 16-byte chunks per LDS row");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 32;  // complex columns
-  constexpr int CPR = BK / 2;       // chunks per row
-  constexpr int AV = BM * CPR;      // chunks per stage
-  constexpr int BV = BN * CPR;
-  static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
-  constexpr int NA = AV / 256;
-  constexpr int NB = BV / 256;
-  // One array per buffer: with the buffer known at compile time in every
-  // stage, the compiler can tell the copies into one buffer from the
-  // fragment reads of the other and does not wait for the copies first.
-  __shared__ __align__(16) float4 Ad0[AV], Ad1[AV];
-  __shared__ __align__(16) float4 Bd0[BV], Bd1[BV];
-  auto abuf = [&](auto t) -> float4* { if constexpr (decltype(t)::value) return Ad1; else return Ad0; };
-  auto bbuf = [&](auto t) -> float4* { if constexpr (decltype(t)::value) return Bd1; else return Bd0; };
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const float2* __restrict__ Ag =
-      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const float2* __restrict__ Bg =
-      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
-
-  // Slot s = 256 j + tid of a stage: row s / 8, stored chunk s % 8, which
-  // holds logical chunk (s % 8) ^ dl_swz(row).
-  auto dma = [&](auto buf, int64_t k0) {
-    float4* As = abuf(buf);
-    float4* Bs = bbuf(buf);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
-      __builtin_amdgcn_global_load_lds(
-          Ag + (row0 + r) * p.lda + k0 + 2 * c,
-          (__attribute__((address_space(3))) void*)(As + 256 * j + 64 * wave), 16, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
-      __builtin_amdgcn_global_load_lds(
-          Bg + (col0 + r) * p.ldb + k0 + 2 * c,
-          (__attribute__((address_space(3))) void*)(Bs + 256 * j + 64 * wave), 16, 0, 0);
-    }
-  };
-  float4 ra[NA], rb[NB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = s & 7;
-      const int64_t gr = row0 + r, gk = k0 + 2 * c;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gr < p.M) {
-        const float2* src = Ag + gr * p.lda + gk;
-        if (gk + 1 < kend) {
-          v = *reinterpret_cast<const float4*>(src);
-        } else if (gk < kend) {
-          const float2 t = src[0];
-          v.x = t.x;
-          v.y = t.y;
-        }
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = s & 7;
-      const int64_t gr = col0 + r, gk = k0 + 2 * c;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gr < p.N) {
-        const float2* src = Bg + gr * p.ldb + gk;
-        if (gk + 1 < kend) {
-          v = *reinterpret_cast<const float4*>(src);
-        } else if (gk < kend) {
-          const float2 t = src[0];
-          v.x = t.x;
-          v.y = t.y;
-        }
-      }
-      rb[j] = v;
-    }
-  };
-  auto sstore = [&](auto buf) {
-    float4* As = abuf(buf);
-    float4* Bs = bbuf(buf);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s >> 3;
-      As[r * CPR + ((s & 7) ^ dl_swz(r))] = ra[j];
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s >> 3;
-      Bs[r * CPR + ((s & 7) ^ dl_swz(r))] = rb[j];
-    }
-  };
-
-  v16f t1[TM][TN], t2[TM][TN], t3[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) t1[i][j][e] = t2[i][j][e] = t3[i][j][e] = 0.f;
-
-  const int kh = lane >> 5;
-  const int arow = wm * TM * 32 + (lane & 31);
-  const int brow = wn * TN * 32 + (lane & 31);
-
-  // One K stage computed from buffer CUR while the next stage fills the
-  // other buffer.
-  auto stage = [&](auto fast, auto cur, int it) {
-    constexpr bool FAST = decltype(fast)::value;
-    constexpr bool CUR = decltype(cur)::value;
-    const float4* As = abuf(cur);
-    const float4* Bs = bbuf(cur);
-    // Fast path: always fill the other buffer (the last stage copies itself
-    // again), so the stage has no branch.
-    if constexpr (FAST) {
-      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
-      __builtin_amdgcn_sched_barrier(0);
-    } else if (it + 1 < nk) {
-      gload(kbeg + int64_t(it + 1) * BK);
-    }
-#pragma unroll
-    for (int g = 0; g < CPR / 2; ++g) {
-      float4 a4[TM], b4[TN];
-      float2 as[TM], bs[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int r = arow + 32 * i;
-        a4[i] = As[r * CPR + ((2 * g + kh) ^ dl_swz(r))];
-        as[i] = make_float2(a4[i].x + a4[i].y, a4[i].z + a4[i].w);
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int r = brow + 32 * j;
-        b4[j] = Bs[r * CPR + ((2 * g + kh) ^ dl_swz(r))];
-        bs[j] = make_float2(b4[j].x + b4[j].y, b4[j].z + b4[j].w);
-      }
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            const float ar = q ? a4[i].z : a4[i].x, ai = q ? a4[i].w : a4[i].y;
-            const float br = q ? b4[j].z : b4[j].x, bi = q ? b4[j].w : b4[j].y;
-            const float sa = q ? as[i].y : as[i].x, sb = q ? bs[j].y : bs[j].x;
-            t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, t1[i][j], 0, 0, 0);
-            t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, t2[i][j], 0, 0, 0);
-            t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa, sb, t3[i][j], 0, 0, 0);
-          }
-    }
-    if constexpr (FAST) {
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
-    } else if (it + 1 < nk) {
-      sstore(BoolTag<!CUR>{});
-    }
-    __syncthreads();
-  };
-
-  auto mainloop = [&](auto fast) {
-    constexpr bool FAST = decltype(fast)::value;
-    if (nk > 0) {
-      if constexpr (FAST) {
-        dma(BoolTag<false>{}, kbeg);
-        __builtin_amdgcn_s_waitcnt(0);
-      } else {
-        gload(kbeg);
-        sstore(BoolTag<false>{});
-      }
-    }
-    __syncthreads();
-    for (int it = 0; it < nk; it += 2) {
-      stage(fast, BoolTag<false>{}, it);
-      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
-    }
-  };
-  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
-
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
-        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
-        const float a = t1[i][j][e], c = t2[i][j][e], d = t3[i][j][e];
-        store_out<float>(p, b, split, row, col, 0, a - c);
-        store_out<float>(p, b, split, row, col, 1, (d - a) - c);
-      }
-}
-
-// Large-tile FP32-3M (Gauss): T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi)
-// as three real MFMA GEMMs whose K is the complex K (lane / 32 picks the
-// complex k of an instruction).  Each LDS row holds three planes (re, im,
-// re + im; the sums formed once while staging), each ordered [even k | odd
-// k], so the values one lane needs for four consecutive instructions are
-// adjacent and come in one 128-bit read; rows padded to an odd number of
-// 16-byte chunks.  Interior tiles use the pinned fast path of the FP32 large
-// tile.
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f32_3mbig_body(const GemmParams& p, int tm, int tn,
-                                                     int split, int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK % 8 == 0, "four instructions (eight complex k) per 128-bit read");
-  constexpr int BM = WM * TM * 32;
-  constexpr int BN = WN * TN * 32;
-  constexpr int HB = BK / 2;
-  constexpr int LDR = 3 * BK + 4;  // floats per row: 3 planes + pad (odd chunk count)
-  constexpr int AV = BM * BK / 2;  // float4 loads (two complex) per stage
-  constexpr int BV = BN * BK / 2;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  __shared__ __align__(16) float As0[2 * BM * LDR];
-  __shared__ __align__(16) float Bs0[2 * BN * LDR];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const float2* __restrict__ Ag =
-      reinterpret_cast<const float2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const float2* __restrict__ Bg =
-      reinterpret_cast<const float2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
-
-  float4 ra[NA], rb[NB];
-  auto gload_fast = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (AV % 256 == 0 || idx < AV) {  // threads past the tile load nothing
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        ra[j] = *reinterpret_cast<const float4*>(Ag + (row0 + r) * p.lda + k0 + c);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (BV % 256 == 0 || idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        rb[j] = *reinterpret_cast<const float4*>(Bg + (col0 + r) * p.ldb + k0 + c);
-      }
-    }
-  };
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < AV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = row0 + r, gk = k0 + c;
-        if (gr < p.M) {
-          const float2* src = Ag + gr * p.lda + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < BV) {
-        int r = idx / (BK / 2), c = (idx % (BK / 2)) * 2;
-        int64_t gr = col0 + r, gk = k0 + c;
-        if (gr < p.N) {
-          const float2* src = Bg + gr * p.ldb + gk;
-          if (gk + 1 < kend) {
-            v = *reinterpret_cast<const float4*>(src);
-          } else if (gk < kend) {
-            float2 t = src[0];
-            v.x = t.x;
-            v.y = t.y;
-          }
-        }
-      }
-      rb[j] = v;
-    }
-  };
-  // Complex k = c (even) and c + 1 go to index c / 2 of the even and odd
-  // halves of each plane.
-  auto put = [](float* row, int c, const float4& v) {
-    const int e = c >> 1;
-    row[e] = v.x;
-    row[HB + e] = v.z;
-    row[BK + e] = v.y;
-    row[BK + HB + e] = v.w;
-    row[2 * BK + e] = v.x + v.y;
-    row[2 * BK + HB + e] = v.z + v.w;
-  };
-  auto sstore = [&](int buf) {
-    float* As = As0 + buf * BM * LDR;
-    float* Bs = Bs0 + buf * BN * LDR;
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (AV % 256 == 0 || idx < AV) put(As + (idx / (BK / 2)) * LDR, (idx % (BK / 2)) * 2, ra[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (BV % 256 == 0 || idx < BV) put(Bs + (idx / (BK / 2)) * LDR, (idx % (BK / 2)) * 2, rb[j]);
-    }
-  };
-
-  v16f t1[TM][TN], t2[TM][TN], t3[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) t1[i][j][e] = t2[i][j][e] = t3[i][j][e] = 0.f;
-
-  const int kh = lane >> 5;
-  const int aoff = (wm * TM * 32 + (lane & 31)) * LDR + kh * HB;
-  const int boff = (wn * TN * 32 + (lane & 31)) * LDR + kh * HB;
-
-  auto mainloop = [&](auto tag) {
-    constexpr bool FAST = decltype(tag)::value;
-    if (nk > 0) {
-      if constexpr (FAST) gload_fast(kbeg); else gload(kbeg);
-      sstore(0);
-    }
-    __syncthreads();
-    for (int it = 0; it < nk; ++it) {
-      const int buf = it & 1;
-      const float* As = As0 + buf * BM * LDR;
-      const float* Bs = Bs0 + buf * BN * LDR;
-      if constexpr (FAST) {
-        gload_fast(kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
-        __builtin_amdgcn_sched_barrier(0);
-      } else if (it + 1 < nk) {
-        gload(kbeg + int64_t(it + 1) * BK);
-      }
-#pragma unroll
-      for (int s4 = 0; s4 < HB; s4 += 4) {
-        float4 ar[TM], ai[TM], as[TM], br[TN], bi[TN], bs[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          const float* a = As + aoff + i * 32 * LDR + s4;
-          ar[i] = *reinterpret_cast<const float4*>(a);
-          ai[i] = *reinterpret_cast<const float4*>(a + BK);
-          as[i] = *reinterpret_cast<const float4*>(a + 2 * BK);
-        }
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          const float* v = Bs + boff + j * 32 * LDR + s4;
-          br[j] = *reinterpret_cast<const float4*>(v);
-          bi[j] = *reinterpret_cast<const float4*>(v + BK);
-          bs[j] = *reinterpret_cast<const float4*>(v + 2 * BK);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-              auto pick = [q](const float4& v) {
-                return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
-              };
-              t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pick(ar[i]), pick(br[j]), t1[i][j],
-                                                              0, 0, 0);
-              t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pick(ai[i]), pick(bi[j]), t2[i][j],
-                                                              0, 0, 0);
-              t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(pick(as[i]), pick(bs[j]), t3[i][j],
-                                                              0, 0, 0);
-            }
-      }
-      if (FAST || it + 1 < nk) sstore(buf ^ 1);
-      __syncthreads();
-    }
-  };
-  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
-
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * kh + (e & 3);
-        int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
-        const float a = t1[i][j][e], c = t2[i][j][e], d = t3[i][j][e];
-        store_out<float>(p, b, split, row, col, 0, a - c);
-        store_out<float>(p, b, split, row, col, 1, (d - a) - c);
-      }
-}
-
-// FP64 counterpart: v_mfma_f64_16x16x4_f64, 16 complex columns per tile
-// pair, 2 complex k per instruction (real k = lane / 16: complex k lane / 32,
-// half (lane / 16) & 1).
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f64_rp_body(const GemmParams& p, int tm, int tn, int split,
-                                                  int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK % 2 == 0, "two complex k per MFMA");
-  constexpr int BM = WM * TM * 16;
-  constexpr int BN = WN * TN * 16;  // complex columns
-  constexpr int LDR = 2 * BK + 1;   // doubles per padded LDS row
-  constexpr int AV = BM * BK;
-  constexpr int BV = BN * BK;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  __shared__ double As[2][BM * LDR];
-  __shared__ double Bs[2][BN * LDR];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const double2* __restrict__ Ag =
-      reinterpret_cast<const double2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const double2* __restrict__ Bg =
-      reinterpret_cast<const double2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-
-  double2 ra[NA], rb[NB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      double2 v = make_double2(0.0, 0.0);
-      if (idx < AV) {
-        int r = idx / BK, c = idx % BK;
-        int64_t gr = row0 + r, gk = k0 + c;
-        if (gr < p.M && gk < kend) v = Ag[gr * p.lda + gk];
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      double2 v = make_double2(0.0, 0.0);
-      if (idx < BV) {
-        int r = idx / BK, c = idx % BK;
-        int64_t gr = col0 + r, gk = k0 + c;
-        if (gr < p.N && gk < kend) v = Bg[gr * p.ldb + gk];
-      }
-      rb[j] = v;
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < AV) {
-        int r = idx / BK, c = idx % BK;
-        As[buf][r * LDR + c] = ra[j].x;
-        As[buf][r * LDR + BK + c] = ra[j].y;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (idx < BV) {
-        int r = idx / BK, c = idx % BK;
-        Bs[buf][r * LDR + c] = rb[j].x;
-        Bs[buf][r * LDR + BK + c] = -rb[j].y;
-      }
-    }
-  };
-
-  v4d cr[TM][TN], ci[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) cr[i][j][e] = ci[i][j][e] = 0.0;
-
-  const int kc = lane >> 5;
-  const int half = (lane >> 4) & 1;
-  const int aoff = (wm * TM * 16 + (lane & 15)) * LDR + half * BK + kc;
-  const int boff_r = (wn * TN * 16 + (lane & 15)) * LDR + half * BK + kc;
-  const int boff_i = (wn * TN * 16 + (lane & 15)) * LDR + (1 - half) * BK + kc;
-  const bool negi = (half == 0);
-
-  if (nk > 0) {
-    gload(kbeg);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < nk) gload(kbeg + int64_t(it + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 2) {
-      double af[TM], br[TN], bi[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) af[i] = As[buf][aoff + i * 16 * LDR + kk];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        br[j] = Bs[buf][boff_r + j * 16 * LDR + kk];
-        double v = Bs[buf][boff_i + j * 16 * LDR + kk];
-        bi[j] = negi ? -v : v;
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], br[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bi[j], ci[i][j], 0, 0, 0);
-        }
-    }
-    if (it + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-  }
-
-  // 16x16 f64 accumulator layout: column lane % 16, rows 4*e + lane/16.
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int64_t row = row0 + wm * TM * 16 + i * 16 + 4 * e + (lane >> 4);
-        int64_t col = col0 + wn * TN * 16 + j * 16 + (lane & 15);
-        store_out<double>(p, b, split, row, col, 0, cr[i][j][e]);
-        store_out<double>(p, b, split, row, col, 1, ci[i][j][e]);
-      }
-}
-
-// Large-tile FP64: v_mfma_f64_16x16x4f64 (two complex k per instruction:
-// lane / 32 picks the complex k, (lane / 16) & 1 the real or imaginary
-// half).  LDS rows hold [re of even k | re of odd k | im of even k | im of
-// odd k], so the values one lane needs for two consecutive instructions are
-// adjacent and come in one 128-bit read; rows padded to 16-byte multiples.
-// Interior tiles load without guards and pin the next stage's loads to the
-// top of the stage, as in the FP32 large tile.
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f64_big_body(const GemmParams& p, int tm, int tn,
-                                                   int split, int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK % 4 == 0, "two instructions per 128-bit read");
-  constexpr int BM = WM * TM * 16;
-  constexpr int BN = WN * TN * 16;  // complex columns
-  constexpr int LDR = 2 * BK + 2;   // doubles per LDS row, 16-byte multiple
-  constexpr int HB = BK / 2;
-  constexpr int AV = BM * BK;       // complex loads per stage
-  constexpr int BV = BN * BK;
-  constexpr int NA = (AV + 255) / 256;
-  constexpr int NB = (BV + 255) / 256;
-  extern __shared__ double2 big64_lds[];
-  double* As0 = reinterpret_cast<double*>(big64_lds);
-  double* Bs0 = As0 + 2 * BM * LDR;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const double2* __restrict__ Ag =
-      reinterpret_cast<const double2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const double2* __restrict__ Bg =
-      reinterpret_cast<const double2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
-
-  double2 ra[NA], rb[NB];
-  auto gload_fast = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (AV % 256 == 0 || idx < AV)  // threads past the tile load nothing
-        ra[j] = Ag[(row0 + idx / BK) * p.lda + k0 + idx % BK];
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (BV % 256 == 0 || idx < BV) rb[j] = Bg[(col0 + idx / BK) * p.ldb + k0 + idx % BK];
-    }
-  };
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      double2 v = make_double2(0.0, 0.0);
-      if (idx < AV) {
-        int64_t gr = row0 + idx / BK, gk = k0 + idx % BK;
-        if (gr < p.M && gk < kend) v = Ag[gr * p.lda + gk];
-      }
-      ra[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      double2 v = make_double2(0.0, 0.0);
-      if (idx < BV) {
-        int64_t gr = col0 + idx / BK, gk = k0 + idx % BK;
-        if (gr < p.N && gk < kend) v = Bg[gr * p.ldb + gk];
-      }
-      rb[j] = v;
-    }
-  };
-  // Complex k = c goes to position (c & 1) * HB + c / 2 of each half.
-  auto sstore = [&](int buf) {
-    double* As = As0 + buf * BM * LDR;
-    double* Bs = Bs0 + buf * BN * LDR;
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      int idx = tid + 256 * j;
-      if (AV % 256 == 0 || idx < AV) {
-        int r = idx / BK, c = idx % BK;
-        double* row = As + r * LDR + (c & 1) * HB + (c >> 1);
-        row[0] = ra[j].x;
-        row[BK] = ra[j].y;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      int idx = tid + 256 * j;
-      if (BV % 256 == 0 || idx < BV) {
-        int r = idx / BK, c = idx % BK;
-        double* row = Bs + r * LDR + (c & 1) * HB + (c >> 1);
-        row[0] = rb[j].x;
-        row[BK] = -rb[j].y;
-      }
-    }
-  };
-
-  v4d cr[TM][TN], ci[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) cr[i][j][e] = ci[i][j][e] = 0.0;
-
-  const int kc = lane >> 5;
-  const int half = (lane >> 4) & 1;
-  const int aoff = (wm * TM * 16 + (lane & 15)) * LDR + half * BK + kc * HB;
-  const int boff_r = (wn * TN * 16 + (lane & 15)) * LDR + half * BK + kc * HB;
-  const int boff_i = (wn * TN * 16 + (lane & 15)) * LDR + (1 - half) * BK + kc * HB;
-  const bool negi = (half == 0);
-
-  auto mainloop = [&](auto tag) {
-    constexpr bool FAST = decltype(tag)::value;
-    if (nk > 0) {
-      if constexpr (FAST) gload_fast(kbeg); else gload(kbeg);
-      sstore(0);
-    }
-    __syncthreads();
-    for (int it = 0; it < nk; ++it) {
-      const int buf = it & 1;
-      const double* As = As0 + buf * BM * LDR;
-      const double* Bs = Bs0 + buf * BN * LDR;
-      if constexpr (FAST) {
-        gload_fast(kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
-        __builtin_amdgcn_sched_barrier(0);
-      } else if (it + 1 < nk) {
-        gload(kbeg + int64_t(it + 1) * BK);
-      }
-#pragma unroll
-      for (int s2 = 0; s2 < HB; s2 += 2) {
-        double2 a2[TM], r2[TN], i2[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-          a2[i] = *reinterpret_cast<const double2*>(As + aoff + i * 16 * LDR + s2);
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          r2[j] = *reinterpret_cast<const double2*>(Bs + boff_r + j * 16 * LDR + s2);
-          double2 t = *reinterpret_cast<const double2*>(Bs + boff_i + j * 16 * LDR + s2);
-          i2[j] = negi ? make_double2(-t.x, -t.y) : t;
-        }
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-          for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-              const double av = q == 0 ? a2[i].x : a2[i].y;
-              const double bv = q == 0 ? r2[j].x : r2[j].y;
-              const double cv = q == 0 ? i2[j].x : i2[j].y;
-              cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, cr[i][j], 0, 0, 0);
-              ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cv, ci[i][j], 0, 0, 0);
-            }
-      }
-      if (FAST || it + 1 < nk) sstore(buf ^ 1);
-      __syncthreads();
-    }
-  };
-  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
-
-  // 16x16 f64 accumulator layout: column lane % 16, rows 4*e + lane/16.
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int64_t row = row0 + wm * TM * 16 + i * 16 + 4 * e + (lane >> 4);
-        int64_t col = col0 + wn * TN * 16 + j * 16 + (lane & 15);
-        store_out<double>(p, b, split, row, col, 0, cr[i][j][e]);
-        store_out<double>(p, b, split, row, col, 1, ci[i][j][e]);
-      }
-}
-
-template <int WM, int WN, int TM, int TN, int BK>
-constexpr size_t big64_lds_bytes() {
-  return size_t(2) * (WM * TM * 16 + WN * TN * 16) * (2 * BK + 2) * sizeof(double);
-}
-
-// Large-tile FP64 with direct-to-LDS staging, as the FP32 direct-LDS tile:
-// one 16-byte chunk is one complex (re, im), 8 chunks (BK = 8 complex k)
-// per LDS row, unpadded and XOR-swizzled by dl_swz.  In
-// v_mfma_f64_16x16x4f64 lane / 16 picks the real k; here it picks the
-// complex k (chunk 4g + lane / 16) and the two floats of the chunk feed two
-// instructions: a_r with b_r (real) and b_i (imaginary), then a_i with -b_i
-// and b_r.
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f64_dl_body(const GemmParams& p, int tm, int tn,
-                                                  int split, int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK == 8, "eight 16-byte chunks per LDS row");
-  constexpr int BM = WM * TM * 16;
-  constexpr int BN = WN * TN * 16;  // complex columns
-  constexpr int CPR = BK;           // chunks (complex) per row
-  constexpr int AV = BM * CPR;      // chunks per stage
-  constexpr int BV = BN * CPR;
-  static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
-  constexpr int NA = AV / 256;
-  constexpr int NB = BV / 256;
-  __shared__ __align__(16) double2 Ad0[AV], Ad1[AV];
-  __shared__ __align__(16) double2 Bd0[BV], Bd1[BV];
-  auto abuf = [&](auto t) -> double2* { if constexpr (decltype(t)::value) return Ad1; else return Ad0; };
-  auto bbuf = [&](auto t) -> double2* { if constexpr (decltype(t)::value) return Bd1; else return Bd0; };
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const double2* __restrict__ Ag =
-      reinterpret_cast<const double2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const double2* __restrict__ Bg =
-      reinterpret_cast<const double2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
-
-  auto dma = [&](auto buf, int64_t k0) {
-    double2* As = abuf(buf);
-    double2* Bs = bbuf(buf);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
-      __builtin_amdgcn_global_load_lds(
-          Ag + (row0 + r) * p.lda + k0 + c,
-          (__attribute__((address_space(3))) void*)(As + 256 * j + 64 * wave), 16, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
-      __builtin_amdgcn_global_load_lds(
-          Bg + (col0 + r) * p.ldb + k0 + c,
-          (__attribute__((address_space(3))) void*)(Bs + 256 * j + 64 * wave), 16, 0, 0);
-    }
-  };
-  double2 ra[NA], rb[NB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j;
-      const int64_t gr = row0 + (s >> 3), gk = k0 + (s & 7);
-      ra[j] = (gr < p.M && gk < kend) ? Ag[gr * p.lda + gk] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j;
-      const int64_t gr = col0 + (s >> 3), gk = k0 + (s & 7);
-      rb[j] = (gr < p.N && gk < kend) ? Bg[gr * p.ldb + gk] : make_double2(0.0, 0.0);
-    }
-  };
-  auto sstore = [&](auto buf) {
-    double2* As = abuf(buf);
-    double2* Bs = bbuf(buf);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s >> 3;
-      As[r * CPR + ((s & 7) ^ dl_swz(r))] = ra[j];
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s >> 3;
-      Bs[r * CPR + ((s & 7) ^ dl_swz(r))] = rb[j];
-    }
-  };
-
-  v4d cr[TM][TN], ci[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) cr[i][j][e] = ci[i][j][e] = 0.0;
-
-  const int kq = lane >> 4;
-  const int arow = wm * TM * 16 + (lane & 15);
-  const int brow = wn * TN * 16 + (lane & 15);
-
-  auto stage = [&](auto fast, auto cur, int it) {
-    constexpr bool FAST = decltype(fast)::value;
-    constexpr bool CUR = decltype(cur)::value;
-    const double2* As = abuf(cur);
-    const double2* Bs = bbuf(cur);
-    if constexpr (FAST) {
-      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
-      __builtin_amdgcn_sched_barrier(0);
-    } else if (it + 1 < nk) {
-      gload(kbeg + int64_t(it + 1) * BK);
-    }
-#pragma unroll
-    for (int g = 0; g < CPR / 4; ++g) {
-      double2 a2[TM], b2[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int r = arow + 16 * i;
-        a2[i] = As[r * CPR + ((4 * g + kq) ^ dl_swz(r))];
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int r = brow + 16 * j;
-        b2[j] = Bs[r * CPR + ((4 * g + kq) ^ dl_swz(r))];
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].x, b2[j].x, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].x, b2[j].y, ci[i][j], 0, 0, 0);
-        }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].y, -b2[j].y, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].y, b2[j].x, ci[i][j], 0, 0, 0);
-        }
-    }
-    if constexpr (FAST) {
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
-    } else if (it + 1 < nk) {
-      sstore(BoolTag<!CUR>{});
-    }
-    __syncthreads();
-  };
-
-  auto mainloop = [&](auto fast) {
-    constexpr bool FAST = decltype(fast)::value;
-    if (nk > 0) {
-      if constexpr (FAST) {
-        dma(BoolTag<false>{}, kbeg);
-        __builtin_amdgcn_s_waitcnt(0);
-      } else {
-        gload(kbeg);
-        sstore(BoolTag<false>{});
-      }
-    }
-    __syncthreads();
-    for (int it = 0; it < nk; it += 2) {
-      stage(fast, BoolTag<false>{}, it);
-      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
-    }
-  };
-  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
-
-  // 16x16 f64 accumulator layout: column lane % 16, rows 4*e + lane/16.
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int64_t row = row0 + wm * TM * 16 + i * 16 + 4 * e + (lane >> 4);
-        int64_t col = col0 + wn * TN * 16 + j * 16 + (lane & 15);
-        store_out<double>(p, b, split, row, col, 0, cr[i][j][e]);
-        store_out<double>(p, b, split, row, col, 1, ci[i][j][e]);
-      }
-}
-
-// FP64 Gauss (3M) with the direct-to-LDS staging of the FP64 tile: the chunk
-// (a_r, a_i) a lane reads feeds T1 = Ar Br, T2 = Ai Bi and
-// T3 = (Ar + Ai)(Br + Bi), three instructions per tile and complex k where
-// the 4M tile takes four; Re = T1 - T2, Im = T3 - T1 - T2.  Three
-// accumulators per 16 x 16 tile: 64 x 64 is the largest tile without spills
-// in the loop; it runs three waves per SIMD (32 KiB of LDS per workgroup).
-// An alternative FP64 tile (the FP64 default stays the 4M one).
-template <int WM, int WN, int TM, int TN, int BK>
-__device__ __forceinline__ void cgemm_f64_3mdl_body(const GemmParams& p, int tm, int tn,
-                                                  int split, int b) {
-  static_assert(WM * WN == 4, "four waves");
-  static_assert(BK == 8, "eight 16-byte chunks per LDS row");
-  constexpr int BM = WM * TM * 16;
-  constexpr int BN = WN * TN * 16;  // complex columns
-  constexpr int CPR = BK;           // chunks (complex) per row
-  constexpr int AV = BM * CPR;      // chunks per stage
-  constexpr int BV = BN * CPR;
-  static_assert(AV % 256 == 0 && BV % 256 == 0, "whole waves of chunks");
-  constexpr int NA = AV / 256;
-  constexpr int NB = BV / 256;
-  __shared__ __align__(16) double2 Ad0[AV], Ad1[AV];
-  __shared__ __align__(16) double2 Bd0[BV], Bd1[BV];
-  auto abuf = [&](auto t) -> double2* { if constexpr (decltype(t)::value) return Ad1; else return Ad0; };
-  auto bbuf = [&](auto t) -> double2* { if constexpr (decltype(t)::value) return Bd1; else return Bd0; };
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave / WN, wn = wave % WN;
-  const int64_t row0 = int64_t(tm) * BM;
-  const int64_t col0 = int64_t(tn) * BN;
-  const double2* __restrict__ Ag =
-      reinterpret_cast<const double2*>(p.A) + batch_off(p.a_bs, p.nbb, b);
-  const double2* __restrict__ Bg =
-      reinterpret_cast<const double2*>(p.B) + batch_off(p.b_bs, p.nbb, b);
-  const int64_t kbeg = int64_t(split) * p.kchunk;
-  const int64_t kend = min(p.K, kbeg + p.kchunk);
-  const int nk = (int)((kend - kbeg + BK - 1) / BK);
-  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
-
-  auto dma = [&](auto buf, int64_t k0) {
-    double2* As = abuf(buf);
-    double2* Bs = bbuf(buf);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
-      __builtin_amdgcn_global_load_lds(
-          Ag + (row0 + r) * p.lda + k0 + c,
-          (__attribute__((address_space(3))) void*)(As + 256 * j + 64 * wave), 16, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s >> 3, c = (s & 7) ^ dl_swz(r);
-      __builtin_amdgcn_global_load_lds(
-          Bg + (col0 + r) * p.ldb + k0 + c,
-          (__attribute__((address_space(3))) void*)(Bs + 256 * j + 64 * wave), 16, 0, 0);
-    }
-  };
-  double2 ra[NA], rb[NB];
-  auto gload = [&](int64_t k0) {
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j;
-      const int64_t gr = row0 + (s >> 3), gk = k0 + (s & 7);
-      ra[j] = (gr < p.M && gk < kend) ? Ag[gr * p.lda + gk] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j;
-      const int64_t gr = col0 + (s >> 3), gk = k0 + (s & 7);
-      rb[j] = (gr < p.N && gk < kend) ? Bg[gr * p.ldb + gk] : make_double2(0.0, 0.0);
-    }
-  };
-  auto sstore = [&](auto buf) {
-    double2* As = abuf(buf);
-    double2* Bs = bbuf(buf);
-#pragma unroll
-    for (int j = 0; j < NA; ++j) {
-      const int s = tid + 256 * j, r = s >> 3;
-      As[r * CPR + ((s & 7) ^ dl_swz(r))] = ra[j];
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int s = tid + 256 * j, r = s >> 3;
-      Bs[r * CPR + ((s & 7) ^ dl_swz(r))] = rb[j];
-    }
-  };
-
-  v4d t1[TM][TN], t2[TM][TN], t3[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) t1[i][j][e] = t2[i][j][e] = t3[i][j][e] = 0.0;
-
-  const int kq = lane >> 4;
-  const int arow = wm * TM * 16 + (lane & 15);
-  const int brow = wn * TN * 16 + (lane & 15);
-
-  auto stage = [&](auto fast, auto cur, int it) {
-    constexpr bool FAST = decltype(fast)::value;
-    constexpr bool CUR = decltype(cur)::value;
-    const double2* As = abuf(cur);
-    const double2* Bs = bbuf(cur);
-    if constexpr (FAST) {
-      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
-      __builtin_amdgcn_sched_barrier(0);
-    } else if (it + 1 < nk) {
-      gload(kbeg + int64_t(it + 1) * BK);
-    }
-#pragma unroll
-    for (int g = 0; g < CPR / 4; ++g) {
-      double2 a2[TM], b2[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int r = arow + 16 * i;
-        a2[i] = As[r * CPR + ((4 * g + kq) ^ dl_swz(r))];
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int r = brow + 16 * j;
-        b2[j] = Bs[r * CPR + ((4 * g + kq) ^ dl_swz(r))];
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          t1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].x, b2[j].x, t1[i][j], 0, 0, 0);
-          t2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].y, b2[j].y, t2[i][j], 0, 0, 0);
-          t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i].x + a2[i].y, b2[j].x + b2[j].y,
-                                                          t3[i][j], 0, 0, 0);
-        }
-    }
-    if constexpr (FAST) {
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
-    } else if (it + 1 < nk) {
-      sstore(BoolTag<!CUR>{});
-    }
-    __syncthreads();
-  };
-
-  auto mainloop = [&](auto fast) {
-    constexpr bool FAST = decltype(fast)::value;
-    if (nk > 0) {
-      if constexpr (FAST) {
-        dma(BoolTag<false>{}, kbeg);
-        __builtin_amdgcn_s_waitcnt(0);
-      } else {
-        gload(kbeg);
-        sstore(BoolTag<false>{});
-      }
-    }
-    __syncthreads();
-    for (int it = 0; it < nk; it += 2) {
-      stage(fast, BoolTag<false>{}, it);
-      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
-    }
-  };
-  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
-
-  // 16x16 f64 accumulator layout: column lane % 16, rows 4*e + lane/16.
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int64_t row = row0 + wm * TM * 16 + i * 16 + 4 * e + (lane >> 4);
-        int64_t col = col0 + wn * TN * 16 + j * 16 + (lane & 15);
-        const double a = t1[i][j][e], c = t2[i][j][e], d = t3[i][j][e];
-        store_out<double>(p, b, split, row, col, 0, a - c);
-        store_out<double>(p, b, split, row, col, 1, (d - a) - c);
-      }
-}
 
 // ---------------------------------------------------------------------------
 // Small problems: one thread per complex output, sequential K loop (FP64,
@@ -3633,96 +585,7 @@ static void skinny_orient(GemmParams& p) {
   for (int i = 0; i < RN_MAX_SLICED; ++i) std::swap(p.a_bs[i], p.b_bs[i]);
 }
 
-// ---------------------------------------------------------------------------
-// Kernel entry points.  Single problem: the grid is (tiles, splits, slice
-// batch).  Grouped: many problems in one launch; workgroup w serves problem
-// i with prefix[i] <= w < prefix[i+1] (problems ordered by decreasing work,
-// so the largest start first) and takes that problem's local tile.
-// ---------------------------------------------------------------------------
-struct GroupTable {
-  const GemmParams* probs;
-  const int32_t* prefix;  // n + 1 entries
-  int n;
-};
 
-__device__ __forceinline__ int group_find(const GroupTable& g, int bid) {
-  return find_job(g.prefix, g.n, bid);
-}
-
-#define RN_GEMM_ENTRY(NAME)                                                              \
-  template <int WM, int WN, int TM, int TN, int BK>                                     \
-  __global__ __launch_bounds__(256) void NAME(GemmParams p) {                           \
-    int tm, tn;                                                                         \
-    tile_coords(p.tiles_m, p.tiles_n, tm, tn);                                          \
-    NAME##_body<WM, WN, TM, TN, BK>(p, tm, tn, blockIdx.y, blockIdx.z);                 \
-  }                                                                                     \
-  template <int WM, int WN, int TM, int TN, int BK>                                     \
-  __global__ __launch_bounds__(256) void NAME##_grouped(GroupTable g) {                 \
-    const int i = group_find(g, blockIdx.x);                                            \
-    const GemmParams p = g.probs[i]; /* by value: uniform scalar loads, once */         \
-    const int local = blockIdx.x - g.prefix[i];                                         \
-    const int per = p.tiles_m * p.tiles_n; /* tiles per K split */                      \
-    NAME##_body<WM, WN, TM, TN, BK>(p, (local % per) / p.tiles_n, local % p.tiles_n,    \
-                                    local / per, 0);                                    \
-  }
-
-// Entry points whose register use is capped for WAVES waves per SIMD.
-#define RN_GEMM_ENTRY_OCC(NAME, WAVES)                                                              \
-  template <int WM, int WN, int TM, int TN, int BK>                                     \
-  __global__ __launch_bounds__(256, WAVES) void NAME(GemmParams p) {                           \
-    int tm, tn;                                                                         \
-    tile_coords(p.tiles_m, p.tiles_n, tm, tn);                                          \
-    NAME##_body<WM, WN, TM, TN, BK>(p, tm, tn, blockIdx.y, blockIdx.z);                 \
-  }                                                                                     \
-  template <int WM, int WN, int TM, int TN, int BK>                                     \
-  __global__ __launch_bounds__(256, WAVES) void NAME##_grouped(GroupTable g) {                 \
-    const int i = group_find(g, blockIdx.x);                                            \
-    const GemmParams p = g.probs[i]; /* by value: uniform scalar loads, once */         \
-    const int local = blockIdx.x - g.prefix[i];                                         \
-    const int per = p.tiles_m * p.tiles_n; /* tiles per K split */                      \
-    NAME##_body<WM, WN, TM, TN, BK>(p, (local % per) / p.tiles_n, local % p.tiles_n,    \
-                                    local / per, 0);                                    \
-  }
-
-RN_GEMM_ENTRY(cgemm_f32_4m)
-RN_GEMM_ENTRY(cgemm_f32_3m)
-RN_GEMM_ENTRY(cgemm_f64_4m)
-RN_GEMM_ENTRY(cgemm_bf16x3)
-RN_GEMM_ENTRY(cgemm_f32_ri)
-RN_GEMM_ENTRY(cgemm_bf16x3_ri)
-RN_GEMM_ENTRY(cgemm_f32_rp)
-RN_GEMM_ENTRY(cgemm_f64_rp)
-RN_GEMM_ENTRY(cgemm_f32_big)
-RN_GEMM_ENTRY(cgemm_f32_3mbig)
-// Two waves per SIMD for the 128 x 128 tiles, three for 128 x 64 (48 KiB of
-// LDS: three workgroups per CU), four for the 64 x 64 and 128 x 32 tiles.
-RN_GEMM_ENTRY_OCC(cgemm_f32_dl, (TM * TN * WM * WN <= 4 ? 4 : TM * TN * WM * WN <= 8 ? 3 : 2))
-RN_GEMM_ENTRY_OCC(cgemm_f64_dl, 2)
-RN_GEMM_ENTRY_OCC(cgemm_f64_3mdl, 3)
-RN_GEMM_ENTRY_OCC(cgemm_f32_3mdl, 2)
-RN_GEMM_ENTRY_OCC(cgemm_bf16x3_dl, 2)
-RN_GEMM_ENTRY_OCC(cgemm_f64_big, 2)
-
-// The large FP32 tiles take more than 64 KiB of dynamic LDS; raise each
-// kernel's limit once per process.
-static void big_tiles_setup() {
-  static const bool once = [] {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&cgemm_f32_big<2, 2, 2, 2, 16>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)big_lds_bytes<2, 2, 2, 2, 16>());
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&cgemm_f32_big_grouped<2, 2, 2, 2, 16>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)big_lds_bytes<2, 2, 2, 2, 16>());
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&cgemm_f32_big<1, 4, 4, 1, 16>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)big_lds_bytes<1, 4, 4, 1, 16>());
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&cgemm_f32_big_grouped<1, 4, 4, 1, 16>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)big_lds_bytes<1, 4, 4, 1, 16>());
-    return true;
-  }();
-  (void)once;
-}
 
 template <int MODE>
 __global__ __launch_bounds__(256) void cgemm_small(GemmParams p) {
@@ -4008,107 +871,11 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
     p.tiles_m = (int)tm;
     p.tiles_n = (int)tn;
     dim3 grid((unsigned)(tm * tn), (unsigned)g.splitk, nbatch);
-    if (g.mode == RN_FP64) {
-      if (tile == 1)
-        cgemm_f64_4m<2, 2, 4, 4, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 2)
-        cgemm_f64_4m<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 3)
-        cgemm_f64_rp<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 4)
-        cgemm_f64_rp<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 5)
-        cgemm_f64_big<2, 2, 4, 2, 8><<<grid, 256, big64_lds_bytes<2, 2, 4, 2, 8>(), s>>>(p);
-      else if (tile == 6)
-        cgemm_f64_big<2, 2, 2, 4, 8><<<grid, 256, big64_lds_bytes<2, 2, 2, 4, 8>(), s>>>(p);
-      else if (tile == 7)
-        cgemm_f64_big<2, 2, 2, 2, 8><<<grid, 256, big64_lds_bytes<2, 2, 2, 2, 8>(), s>>>(p);
-      else if (tile == 8)
-        cgemm_f64_dl<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 9)
-        cgemm_f64_dl<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(p);
-      else
-        cgemm_f64_3mdl<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
-    } else if (g.mode == RN_FP32_3M) {
-      if (tile == 1)
-        cgemm_f32_3m<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 2)
-        cgemm_f32_3m<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 3)
-        cgemm_f32_3mbig<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 4)
-        cgemm_f32_3mbig<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 5)
-        cgemm_f32_3mdl<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      else
-        cgemm_f32_3mdl<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(p);
-    } else if (g.mode == RN_BF16X3) {
-      if (tile == 1)
-        cgemm_bf16x3<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 2)
-        cgemm_bf16x3<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 3)
-        cgemm_bf16x3<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 4)
-        cgemm_bf16x3<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 5)
-        cgemm_bf16x3_ri<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 6)
-        cgemm_bf16x3_ri<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 7)
-        cgemm_bf16x3_ri<2, 2, 4, 1, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 8)
-        cgemm_bf16x3_ri<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 9)
-        cgemm_bf16x3_dl<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
-      else
-        cgemm_bf16x3_dl<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-    } else {
-      if (tile == 1)
-        cgemm_f32_4m<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 2)
-        cgemm_f32_4m<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 3)
-        cgemm_f32_4m<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 4)
-        cgemm_f32_4m<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 5)
-        cgemm_f32_ri<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 6)
-        cgemm_f32_ri<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 7)
-        cgemm_f32_rp<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 8)
-        cgemm_f32_rp<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(p);
-      else if (tile == 9)
-        cgemm_f32_rp<1, 4, 4, 1, 16><<<grid, 256, 0, s>>>(p);
-      else if (tile == 10) {
-        big_tiles_setup();
-        cgemm_f32_big<2, 2, 2, 2, 16><<<grid, 256, big_lds_bytes<2, 2, 2, 2, 16>(), s>>>(p);
-      } else if (tile == 11) {
-        cgemm_f32_big<2, 2, 2, 1, 16><<<grid, 256, big_lds_bytes<2, 2, 2, 1, 16>(), s>>>(p);
-      } else if (tile == 12) {
-        cgemm_f32_big<2, 2, 2, 1, 8><<<grid, 256, big_lds_bytes<2, 2, 2, 1, 8>(), s>>>(p);
-      } else if (tile == 13) {
-        cgemm_f32_big<2, 2, 2, 2, 8><<<grid, 256, big_lds_bytes<2, 2, 2, 2, 8>(), s>>>(p);
-      } else if (tile == 14) {
-        big_tiles_setup();
-        cgemm_f32_big<1, 4, 4, 1, 16><<<grid, 256, big_lds_bytes<1, 4, 4, 1, 16>(), s>>>(p);
-      } else if (tile == 15) {
-        cgemm_f32_dl<1, 4, 4, 1, 16><<<grid, 256, 0, s>>>(p);
-      } else if (tile == 16) {
-        cgemm_f32_dl<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
-      } else if (tile == 17) {
-        cgemm_f32_dl<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
-      } else if (tile == 18) {
-        cgemm_f32_dl<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(p);
-      } else if (tile == 19) {
-        cgemm_f32_dl<4, 1, 1, 1, 16><<<grid, 256, 0, s>>>(p);
-      } else if (tile == 20) {
-        cgemm_f32_dl<2, 2, 1, 1, 32><<<grid, 256, 0, s>>>(p);
-      } else {
-        cgemm_f32_dl<4, 1, 1, 1, 32><<<grid, 256, 0, s>>>(p);
-      }
+    switch (g.mode) {
+      case RN_FP64: launch_tiles_f64(tile, grid, p, s); break;
+      case RN_FP32_3M: launch_tiles_f32_3m(tile, grid, p, s); break;
+      case RN_BF16X3: launch_tiles_bf16x3(tile, grid, p, s); break;
+      default: launch_tiles_f32_4m(tile, grid, p, s); break;
     }
   }
   hipError_t e = hipGetLastError();
@@ -4202,95 +969,20 @@ hipError_t launch_gemm_grouped(const GroupedLaunch& G, const void* table_dev, hi
     launch_skinny_grouped(G.mode, mr, grid, t, s);
     return hipGetLastError();
   }
+  if (tile == 0) {
+    switch (G.mode) {
+      case RN_FP64: cgemm_small_grouped<RN_FP64><<<grid, 256, 0, s>>>(t); break;
+      case RN_FP32_3M: cgemm_small_grouped<RN_FP32_3M><<<grid, 256, 0, s>>>(t); break;
+      case RN_BF16X3: cgemm_small_grouped<RN_BF16X3><<<grid, 256, 0, s>>>(t); break;
+      default: cgemm_small_grouped<RN_FP32_4M><<<grid, 256, 0, s>>>(t); break;
+    }
+    return hipGetLastError();
+  }
   switch (G.mode) {
-    case RN_FP64:
-      if (tile == 0) cgemm_small_grouped<RN_FP64><<<grid, 256, 0, s>>>(t);
-      else if (tile == 1) cgemm_f64_4m_grouped<2, 2, 4, 4, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 2) cgemm_f64_4m_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 3) cgemm_f64_rp_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 4) cgemm_f64_rp_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 5)
-        cgemm_f64_big_grouped<2, 2, 4, 2, 8>
-            <<<grid, 256, big64_lds_bytes<2, 2, 4, 2, 8>(), s>>>(t);
-      else if (tile == 6)
-        cgemm_f64_big_grouped<2, 2, 2, 4, 8>
-            <<<grid, 256, big64_lds_bytes<2, 2, 2, 4, 8>(), s>>>(t);
-      else if (tile == 7)
-        cgemm_f64_big_grouped<2, 2, 2, 2, 8>
-            <<<grid, 256, big64_lds_bytes<2, 2, 2, 2, 8>(), s>>>(t);
-      else if (tile == 8)
-        cgemm_f64_dl_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 9)
-        cgemm_f64_dl_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
-      else
-        cgemm_f64_3mdl_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
-      break;
-    case RN_FP32_3M:
-      if (tile == 0) cgemm_small_grouped<RN_FP32_3M><<<grid, 256, 0, s>>>(t);
-      else if (tile == 1) cgemm_f32_3m_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 2) cgemm_f32_3m_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 3) cgemm_f32_3mbig_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 4) cgemm_f32_3mbig_grouped<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 5) cgemm_f32_3mdl_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      else cgemm_f32_3mdl_grouped<2, 2, 1, 2, 16><<<grid, 256, 0, s>>>(t);
-      break;
-    case RN_BF16X3:
-      if (tile == 0) cgemm_small_grouped<RN_BF16X3><<<grid, 256, 0, s>>>(t);
-      else if (tile == 1) cgemm_bf16x3_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 2) cgemm_bf16x3_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 3) cgemm_bf16x3_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 4) cgemm_bf16x3_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 5) cgemm_bf16x3_ri_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 6) cgemm_bf16x3_ri_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 7) cgemm_bf16x3_ri_grouped<2, 2, 4, 1, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 8) cgemm_bf16x3_ri_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 9) cgemm_bf16x3_dl_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
-      else cgemm_bf16x3_dl_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      break;
-    default:
-      if (tile == 0) cgemm_small_grouped<RN_FP32_4M><<<grid, 256, 0, s>>>(t);
-      else if (tile == 1) cgemm_f32_4m_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 2) cgemm_f32_4m_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 3) cgemm_f32_4m_grouped<2, 2, 4, 2, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 4) cgemm_f32_4m_grouped<2, 2, 2, 4, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 5) cgemm_f32_ri_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 6) cgemm_f32_ri_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 7) cgemm_f32_rp_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 8) cgemm_f32_rp_grouped<2, 2, 2, 2, 8><<<grid, 256, 0, s>>>(t);
-      else if (tile == 9) cgemm_f32_rp_grouped<1, 4, 4, 1, 16><<<grid, 256, 0, s>>>(t);
-      else if (tile == 10) {
-        big_tiles_setup();
-        cgemm_f32_big_grouped<2, 2, 2, 2, 16>
-            <<<grid, 256, big_lds_bytes<2, 2, 2, 2, 16>(), s>>>(t);
-      } else if (tile == 11) {
-        cgemm_f32_big_grouped<2, 2, 2, 1, 16>
-            <<<grid, 256, big_lds_bytes<2, 2, 2, 1, 16>(), s>>>(t);
-      } else if (tile == 12) {
-        cgemm_f32_big_grouped<2, 2, 2, 1, 8>
-            <<<grid, 256, big_lds_bytes<2, 2, 2, 1, 8>(), s>>>(t);
-      } else if (tile == 13) {
-        cgemm_f32_big_grouped<2, 2, 2, 2, 8>
-            <<<grid, 256, big_lds_bytes<2, 2, 2, 2, 8>(), s>>>(t);
-      } else if (tile == 14) {
-        big_tiles_setup();
-        cgemm_f32_big_grouped<1, 4, 4, 1, 16>
-            <<<grid, 256, big_lds_bytes<1, 4, 4, 1, 16>(), s>>>(t);
-      } else if (tile == 15) {
-        cgemm_f32_dl_grouped<1, 4, 4, 1, 16><<<grid, 256, 0, s>>>(t);
-      } else if (tile == 16) {
-        cgemm_f32_dl_grouped<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(t);
-      } else if (tile == 17) {
-        cgemm_f32_dl_grouped<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(t);
-      } else if (tile == 18) {
-        cgemm_f32_dl_grouped<2, 2, 1, 1, 16><<<grid, 256, 0, s>>>(t);
-      } else if (tile == 19) {
-        cgemm_f32_dl_grouped<4, 1, 1, 1, 16><<<grid, 256, 0, s>>>(t);
-      } else if (tile == 20) {
-        cgemm_f32_dl_grouped<2, 2, 1, 1, 32><<<grid, 256, 0, s>>>(t);
-      } else {
-        cgemm_f32_dl_grouped<4, 1, 1, 1, 32><<<grid, 256, 0, s>>>(t);
-      }
-      break;
+    case RN_FP64: launch_tiles_f64_grouped(tile, grid, t, s); break;
+    case RN_FP32_3M: launch_tiles_f32_3m_grouped(tile, grid, t, s); break;
+    case RN_BF16X3: launch_tiles_bf16x3_grouped(tile, grid, t, s); break;
+    default: launch_tiles_f32_4m_grouped(tile, grid, t, s); break;
   }
   return hipGetLastError();
 }

@@ -1,6 +1,6 @@
 """Index bounds of the large GEMM tiles, checked on the CPU.
 
-For every tile shape instantiated in kernels.hip, the unguarded loads of
+For every tile shape instantiated in the GEMM kernel files, the unguarded loads of
 interior tiles, the LDS staging stores and the per-lane LDS fragment reads
 are enumerated for all 256 threads (the same index arithmetic as the
 kernels) and must stay inside the tile, its K chunk and its LDS arrays.  A
@@ -12,7 +12,9 @@ import os
 import re
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = open(os.path.join(ROOT, "paper_2201_06620_amd", "csrc", "kernels.hip")).read()
+CSRC = os.path.join(ROOT, "paper_2201_06620_amd", "csrc")
+SRC = "".join(open(os.path.join(CSRC, f)).read() for f in sorted(os.listdir(CSRC))
+              if f.endswith(".hip"))
 
 
 def instances(name):
@@ -371,7 +373,7 @@ def test_fp64_gauss_tile_index():
     table = table[:table.index("};")]
     entries = re.findall(r"\{\d+, \d+, \d+\}", table)
     assert bench.FP64_GAUSS_TILE == len(entries) - 5
-    launch = SRC[SRC.index("hipError_t launch_gemm(const GemmLaunch& g"):]
-    launch = launch[:launch.index("} else if (g.mode == RN_FP32_3M)")]
+    launch = SRC[SRC.index("void launch_tiles_f64(int tile"):]
+    launch = launch[:launch.index("void launch_tiles_f64_grouped(")]
     assert re.search(r"else\s+cgemm_f64_3mdl<2, 2, 2, 2, 8>", launch)
     assert "tile == %d" % (bench.FP64_GAUSS_TILE - 1) in launch
