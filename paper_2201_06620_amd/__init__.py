@@ -155,6 +155,39 @@ def _arr32(x):
     return a, (a.ctypes.data if a.size else None)
 
 
+def _check_tensor(t, name, dtype=None, numel=None, min_numel=None, device=None, on_gpu=True):
+    """Raise RnError(RN_ERR_INVALID) unless t is a contiguous torch tensor of
+    this dtype and element count on GPU `device` (every check is made before
+    a pointer is handed to the library, so a wrong buffer never reaches a
+    kernel)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise RnError(1, f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if dtype is not None and t.dtype != dtype:
+        raise RnError(1, f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise RnError(1, f"{name}: not contiguous")
+    if numel is not None and t.numel() != numel:
+        raise RnError(1, f"{name}: {t.numel()} elements, expected {numel}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise RnError(1, f"{name}: {t.numel()} elements, at least {min_numel} needed")
+    if not on_gpu:
+        return
+    if not t.is_cuda:
+        raise RnError(1, f"{name}: not on the GPU")
+    if device is not None and t.device.index != device:
+        raise RnError(1, f"{name}: on cuda:{t.device.index}, the handle is on cuda:{device}")
+
+
+def _numel(dims) -> int:
+    return int(np.prod([int(d) for d in dims], dtype=np.int64)) if len(dims) else 1
+
+
+def _torch_dtype(mode):
+    import torch
+    return torch.complex128 if dtype_of_mode(mode) == C128 else torch.complex64
+
+
 def tile_count(mode) -> int:
     """Number of GEMM tile shapes of a mode (the autotuner's candidates)."""
     return int(lib().rn_tile_count(mode_id(mode)))
@@ -268,6 +301,7 @@ class Context:
         if nbytes == 0:
             return None, 0
         if workspace is not None:
+            _check_tensor(workspace, "workspace", device=self.device)
             if workspace.numel() * workspace.element_size() < nbytes:
                 raise RnError(4, "workspace too small")
             return workspace.data_ptr(), workspace.numel() * workspace.element_size()
@@ -295,10 +329,9 @@ class Context:
         """C (stored block-major, flat torch tensor), C dims, C grid."""
         import torch
         dt = dtype_of_mode(mode)
-        want = torch.complex128 if dt == C128 else torch.complex64
-        for x in (a, b):
-            if x.dtype != want or not x.is_cuda or not x.is_contiguous():
-                raise RnError(1, f"operands must be contiguous {want} tensors on the GPU")
+        want = _torch_dtype(mode)
+        _check_tensor(a, "a", want, _numel(dims_a), device=self.device)
+        _check_tensor(b, "b", want, _numel(dims_b), device=self.device)
         A = descriptor(dims_a, grid_a, dt, a.data_ptr())
         B = descriptor(dims_b, grid_b, dt, b.data_ptr())
         C = RnTensor()
@@ -313,6 +346,10 @@ class Context:
         n = int(np.prod(cdims, dtype=np.int64)) if cdims else 1
         if out is None:
             out = torch.empty(n, dtype=want, device=a.device)
+        _check_tensor(out, "out", want, n, device=self.device)
+        for x in (a, b):
+            if out.data_ptr() == x.data_ptr():
+                raise RnError(1, "out aliases an operand")
         C.data = out.data_ptr()
         wp, wn = self._workspace(ws_n.value, workspace)
         check(lib().rn_block_tensordot(self.h, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb,
@@ -350,8 +387,11 @@ class Context:
         cd, cg, ws_n, _, _ = self.plan_streamed(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b,
                                                  mode)
         n = int(np.prod(cd, dtype=np.int64)) if cd else 1
+        if a_host.numel() != _numel(dims_a) or b_host.numel() != _numel(dims_b):
+            raise RnError(1, "streamed operands: element count does not match dims")
         if out is None:
             out = torch.empty(n, dtype=want, device=torch.device("cuda", self.device))
+        _check_tensor(out, "out", want, n, device=self.device)
         A = descriptor(dims_a, grid_a, dt, a_host.data_ptr())
         B = descriptor(dims_b, grid_b, dt, b_host.data_ptr())
         C = descriptor(cd, cg, dt, out.data_ptr())
@@ -405,11 +445,17 @@ class Context:
     # -- networks ------------------------------------------------------------
     def _net_args(self, tensors, labels, mode):
         n = len(tensors)
+        if len(labels) != n:
+            raise RnError(1, f"{n} tensors but {len(labels)} label lists")
         dt = dtype_of_mode(mode)
+        want = _torch_dtype(mode)
         Ts = (RnTensor * n)()
         lab_arr = (ctypes.c_void_p * n)()
         keep = []
         for i, (t, l) in enumerate(zip(tensors, labels)):
+            if len(l) > 62:
+                raise RnError(1, f"tensor {i}: rank {len(l)} too large")
+            _check_tensor(t, f"tensor {i}", want, 1 << len(l), device=self.device)
             Ts[i] = descriptor([2] * len(l), None, dt, t.data_ptr())
             x, px = _arr32(l)
             keep.append(x)
@@ -440,6 +486,7 @@ class Context:
         dev = tensors[0].device
         if amp is None:
             amp = torch.zeros(2, dtype=torch.float64, device=dev)
+        _check_amp_slices(amp, slices, len(sliced), self.device)
         wp, wn = self._workspace(ws_n.value, workspace)
         check(lib().rn_contract_network(self.h, len(tensors), Ts, lab_arr, len(path), pp,
                                         len(sl), ps, mode_id(mode), wp, wn, self._stream(),
@@ -484,6 +531,14 @@ class Context:
         return out
 
 
+def _check_amp_slices(amp, slices, nsliced, device):
+    import torch
+    checks = [(amp, "amp", 2)] + ([(slices, "slices", 2 << nsliced)] if slices is not None else [])
+    for on_gpu in (False, True):   # every size check before any device check
+        for t, name, need in checks:
+            _check_tensor(t, name, torch.float64, min_numel=need, device=device, on_gpu=on_gpu)
+
+
 class Server:
     """Amplitude server (rn_server_*): submit networks with host tensors,
     collect amplitudes and latencies.  All GPU work runs in the library's
@@ -503,8 +558,12 @@ class Server:
         Ts = (RnTensor * n)()
         lab = (ctypes.c_void_p * n)()
         keep = []
+        if len(labels) != n:
+            raise RnError(1, f"{n} tensors but {len(labels)} label lists")
         for i, (t, l) in enumerate(zip(tensors, labels)):
             a = np.ascontiguousarray(np.asarray(t).reshape(-1), dtype=want)
+            if len(l) > 62 or a.size != (1 << len(l)):
+                raise RnError(1, f"tensor {i}: {a.size} elements for {len(l)} labels")
             keep.append(a)
             Ts[i] = descriptor([2] * len(l), None, dt, a.ctypes.data)
             x, px = _arr32(l)
@@ -576,7 +635,11 @@ class PreparedBatch:
         self._keep = []
         self.pa = (ctypes.c_void_p * max(n, 1))()
         self.pb = (ctypes.c_void_p * max(n, 1))()
+        if outs is not None and len(outs) != n:
+            raise RnError(1, f"{n} problems but {len(outs)} outputs")
         for i, (a, da, ga, b, db, gb, axa, axb) in enumerate(self.problems):
+            _check_tensor(a, f"problem {i} a", want, _numel(da), device=ctx.device)
+            _check_tensor(b, f"problem {i} b", want, _numel(db), device=ctx.device)
             self.As[i] = descriptor(da, ga, dt, a.data_ptr())
             self.Bs[i] = descriptor(db, gb, dt, b.data_ptr())
             x, px = _arr32(axa)
@@ -595,9 +658,10 @@ class PreparedBatch:
         for i in range(n):
             cd = [self.Cs[i].dims[j] for j in range(self.Cs[i].rank)]
             cg = [self.Cs[i].grid[j] for j in range(self.Cs[i].rank)]
+            nc = int(np.prod(cd, dtype=np.int64)) if cd else 1
             o = outs[i] if outs is not None else torch.empty(
-                int(np.prod(cd, dtype=np.int64)) if cd else 1, dtype=want,
-                device=self.problems[i][0].device)
+                nc, dtype=want, device=self.problems[i][0].device)
+            _check_tensor(o, f"problem {i} out", want, nc, device=ctx.device)
             self.Cs[i].data = o.data_ptr()
             self.results.append((o, cd, cg))
         self.outputs = [o for o, _, _ in self.results]
@@ -651,6 +715,7 @@ class PreparedNetwork:
         import torch
         if amp is None:
             amp = torch.zeros(2, dtype=torch.float64, device=self.tensors[0].device)
+        _check_amp_slices(amp, slices, len(self.sl), self.ctx.device)
         check(lib().rn_contract_network(self.ctx.h, len(self.tensors), self.Ts, self.lab_arr,
                                         self.nsteps, self.pp, len(self.sl), self.ps,
                                         mode_id(self.mode), self.workspace.data_ptr(),

@@ -2,9 +2,13 @@
 (all dims 2, 2^28 complex entries each), 14 contracted indices in seeded
 random order, contracted through the same call and default tiles the
 benchmark times.  The oracle computes sampled outputs one by one (two 32 x 32
-blocks of C viewed as M x N, plus the corners): within each mode's tolerance
-on complex normal inputs, and bit-exact on Gaussian-integer inputs, where
-every partial sum is an integer below 2^24 and so exact in every mode.
+blocks of C viewed as M x N, plus the corners).  Complex normal inputs: e_F
+and e_max within each mode's tolerance and every sampled entry within its
+rounding bound (tests/parity.py).  Bit-exact on Gaussian-integer inputs,
+where every partial sum is an integer below 2^24 and so exact in every mode,
+and on odd nine-bit integers against units {0, +-1, +-i} (either operand
+wide), whose bfloat16 split has nonzero low parts, so split BF16 is exact
+only with both of its cross terms.
 """
 import sys
 
@@ -12,6 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity
 from workloads import configs
 
 pytestmark = pytest.mark.gpu
@@ -37,7 +42,7 @@ def sample_index():
     return np.unique(np.asarray(idx, dtype=np.int64))
 
 
-def run_modes(p, idx, check):
+def run_modes(p, idx, check, absprod=False):
     import torch
     import paper_2201_06620_amd as rn
     assert torch.cuda.is_available()
@@ -47,6 +52,9 @@ def run_modes(p, idx, check):
     B = p.b.data.reshape(dims)
     log(f"oracle on {idx.size} sampled outputs")
     ref = oracle.tensordot_entries(A, B, p.axes_a, p.axes_b, idx)
+    if absprod:
+        log("oracle (|A||B|) on the same outputs")
+        ref = (ref, parity.abs_product_entries(A, B, p.axes_a, p.axes_b, idx))
     for dt, modes in ((torch.complex64, ("fp32_4m", "fp32_3m", "bf16x3")),
                       (torch.complex128, ("fp64",))):
         a = torch.from_numpy(p.a.data).to(dt).cuda()
@@ -70,16 +78,30 @@ def test_rank28_sampled_within_tolerance():
     idx = sample_index()
 
     def check(mode, got, ref):
-        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-        log(f"  e_F = {err:.3e}")
-        assert err < TOL[mode], (mode, err)
+        ref, absprod = ref
+        parity.check(got, ref, absprod, 2 ** K, mode, "rank-28 sampled")
 
-    run_modes(p, idx, check)
+    run_modes(p, idx, check, absprod=True)
 
 
 def test_rank28_sampled_integers_bitwise():
     log("generating rank-28 Gaussian-integer inputs")
     p = configs.config3(integer=True)
+    idx = sample_index()
+
+    def check(mode, got, ref):
+        assert np.array_equal(got, ref), mode
+
+    run_modes(p, idx, check)
+
+
+@pytest.mark.parametrize("values", [("wide", "unit"), ("unit", "wide")])
+def test_rank28_sampled_split_low_parts_bitwise(values):
+    # Every partial sum is an integer below 2^24 (|term| <= 511 in 4M and
+    # 1022 in Gauss, 2^14 terms), so every mode is exact; split BF16 only
+    # with its lo*hi (wide A) or hi*lo (wide B) products.
+    log(f"generating rank-28 inputs {values}")
+    p = configs.config3(values=values)
     idx = sample_index()
 
     def check(mode, got, ref):
@@ -97,11 +119,13 @@ def unitary_rank28(seed):
     rs = np.random.default_rng(seed)
     u = np.ones((1, 1), dtype=np.complex128)
     scale = 1.0
+    qs = []
     for _ in range(7):
         q, _ = np.linalg.qr(rs.normal(size=(4, 4)) + 1j * rs.normal(size=(4, 4)))
         u = np.kron(u, q)
+        qs.append(q)
         scale *= np.linalg.norm(np.abs(q).T @ np.abs(q))
-    return u.reshape([2] * RANK), scale, rs
+    return u.reshape([2] * RANK), scale, rs, qs
 
 
 def test_rank28_unitary_full_output():
@@ -113,11 +137,14 @@ def test_rank28_unitary_full_output():
     # 2^14 terms that cancel to 0 or 1, so the error is measured against the
     # scale of those terms, || |U|^T |U| ||_F (normwise, as rounding error
     # bounds are stated), with the mode's tolerance; the error relative to
-    # ||I||_F is logged too.
+    # ||I||_F is logged too.  Entry by entry, |C - I|_ij must stay within the
+    # mode's rounding bound g (tests/parity.py) times (|U|^T |U|)_ij, which
+    # is the Kronecker product of the seven |Q_i|^T |Q_i| with its column
+    # bits in the order C lists them.
     import torch
     import paper_2201_06620_amd as rn
     log("generating a rank-28 unitary")
-    u, scale, rs = unitary_rank28(2814)
+    u, scale, rs, qs = unitary_rank28(2814)
     perm = rs.permutation(RANK)            # stored axis j holds original axis perm[j]
     pos = np.argsort(perm)                 # original axis -> stored position
     rows = rs.permutation(K)               # pairing order of the row axes
@@ -129,7 +156,15 @@ def test_rank28_unitary_full_output():
     dims = [2] * RANK
     n = 2 ** (RANK - K)
     log(f"scale || |U|^T |U| ||_F = {scale:.4g}, ||I||_F = {np.sqrt(n):.4g}")
+    # C's axes: A's free (column) axes in stored order, then B's (the same).
+    cols = [int(perm[j]) - K for j in range(RANK) if j not in set(axes)]
+    w = torch.ones((1, 1), dtype=torch.float64, device="cuda")
+    for q in qs:
+        w = torch.kron(w, torch.from_numpy(np.abs(q).T @ np.abs(q)).cuda())
+    w = w.view([2] * RANK).permute(cols + [K + c for c in cols]).reshape(n, n).contiguous()
+    eye = torch.eye(n, dtype=torch.complex128, device="cuda")
     errs = {}
+    worst = {}
     for dt, modes in ((torch.complex64, ("fp32_4m", "fp32_3m", "bf16x3")),
                       (torch.complex128, ("fp64",))):
         a = torch.from_numpy(t).to(dt).cuda()
@@ -143,12 +178,20 @@ def test_rank28_unitary_full_output():
             err2 = (m.abs() ** 2).sum() - (d.abs() ** 2).sum() + ((d - 1).abs() ** 2).sum()
             err = float(err2.clamp(min=0).sqrt())
             errs[mode] = err / scale
-            log(f"  ||C - I||_F / scale = {err / scale:.3e}   / ||I||_F = {err / np.sqrt(n):.3e}")
-            del c, m, d
+            dev = (m - eye).abs()
+            g = parity.bound_factor(mode, 2 ** K)
+            over = int((dev > g * w).sum())
+            hig = float((dev / (2 ** K * parity.UNIT[mode] * w)).max())
+            worst[mode] = (over, hig)
+            log(f"  ||C - I||_F / scale = {err / scale:.3e}   / ||I||_F = {err / np.sqrt(n):.3e}"
+                f"   max higham = {hig:.3e} (bound {g / (2 ** K * parity.UNIT[mode]):.3g}),"
+                f" over bound: {over}")
+            del c, m, d, dev
         del a, b
         torch.cuda.empty_cache()
     for mode, e in errs.items():
         assert e < TOL[mode], (mode, e)
+        assert worst[mode][0] == 0, (mode, worst[mode])
 
 
 def test_outer_product_more_column_tiles_than_workgroups():

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity
 from workloads import circuits, configs, paths
 
 pytestmark = pytest.mark.gpu
@@ -113,10 +114,9 @@ def test_pair_split_matches_oracle(ctx, mode):
     # A footprint cap below one partial turns the split off again.
     ctx.set_option("split_footprint", 1)
     assert ws_of(ctx, p, mode) == ws_seq
+    absprod = parity.abs_product_blocked(p)
     for c in (c1, c2):
-        err = e_f(c, ref)
-        log(f"  e_F={err:.3e}")
-        assert err < TOL[mode]
+        parity.check(c, ref, absprod, 2 ** p.k, mode, "pair split")
 
 
 @pytest.mark.parametrize("mode", MODES)

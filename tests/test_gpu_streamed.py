@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity
 from workloads import configs, rng
 
 pytestmark = pytest.mark.gpu
@@ -78,9 +79,7 @@ def test_streamed_matches_oracle(ctx, mode, shape):
     ref, rd, rg = oracle.block_tensordot(p.a.data, p.a.dims, p.a.grid, p.b.data, p.b.dims,
                                          p.b.grid, p.axes_a, p.axes_b)
     assert cd == rd and cg == rg
-    err = e_f(c, ref)
-    log(f"  e_F={err:.3e}")
-    assert err < TOL[mode]
+    parity.check(c, ref, parity.abs_product_blocked(p), 2 ** k, mode, "streamed")
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -117,7 +116,7 @@ def test_streamed_many_pairs_and_blocks(ctx):
         c, _, _ = run(ctx, p, mode)
         ref, _, _ = oracle.block_tensordot(p.a.data, p.a.dims, p.a.grid, p.b.data, p.b.dims,
                                            p.b.grid, p.axes_a, p.axes_b)
-        assert e_f(c, ref) < TOL[mode]
+        parity.check(c, ref, parity.abs_product_blocked(p), 2 ** k, mode, "streamed")
 
 
 def test_streamed_equal_to_in_memory_for_single_pair(ctx):

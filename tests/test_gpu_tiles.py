@@ -1,12 +1,16 @@
 """Every GEMM tile shape of every mode, forced through a tune file, against
-the oracle: e_F within the mode's tolerance on normal inputs and bit-exact on
-Gaussian integers.  Shapes span several tiles with ragged edges."""
+the oracle: on normal inputs e_F and e_max within the mode's tolerance and
+every entry within its rounding bound (tests/parity.py); bit-exact on
+Gaussian integers and on odd nine-bit integers against units (nonzero
+bfloat16 low parts on either side).  Shapes span several tiles with ragged
+edges."""
 import sys
 
 import numpy as np
 import pytest
 
 import oracle
+import parity
 from workloads import configs, rng
 
 pytestmark = pytest.mark.gpu
@@ -23,10 +27,10 @@ def ctx():
     return rn.Context(0)
 
 
-def problem(ra, rb, k, seed, integer):
+def problem(ra, rb, k, seed, values):
     r = rng.SplitMix64(seed)
     return configs.make_problem(ra, rb, r.sample(ra, k), r.sample(rb, k), [1] * ra, [1] * rb,
-                                seed, integer)
+                                seed, values=values)
 
 
 def all_tiles():
@@ -52,8 +56,9 @@ def test_forced_tile(ctx, tmp_path, mode, tile, shape):
     ctx.tune_load(f)
     dt = torch.complex128 if mode == "fp64" else torch.complex64
     try:
-        for integer in (False, True):
-            p = problem(ra, rb, k, 300 + ra + rb + k, integer)
+        for values in (("normal", "normal"), ("integer", "integer"), ("wide", "unit"),
+                       ("unit", "wide")):
+            p = problem(ra, rb, k, 300 + ra + rb + k, values)
             a = torch.from_numpy(p.a.data).to(dt).cuda()
             b = torch.from_numpy(p.b.data).to(dt).cuda()
             c, cd, cg = ctx.block_tensordot(a, p.a.dims, p.a.grid, b, p.b.dims, p.b.grid,
@@ -62,9 +67,10 @@ def test_forced_tile(ctx, tmp_path, mode, tile, shape):
             got = c.cpu().numpy().astype(np.complex128)
             ref, _, _ = oracle.block_tensordot(p.a.data, p.a.dims, p.a.grid, p.b.data,
                                                p.b.dims, p.b.grid, p.axes_a, p.axes_b)
-            if integer:
-                assert np.array_equal(got, ref)
+            if values[0] != "normal":
+                assert np.array_equal(got, ref), values
             else:
-                assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < TOL[mode]
+                parity.check(got, ref, parity.abs_product_blocked(p), 2 ** k, mode,
+                             f"tile {tile} shape {shape}")
     finally:
         ctx.tune_clear()

@@ -53,3 +53,26 @@ void wl_gaussian_int(uint64_t seed, int64_t start, int64_t n, int64_t lo, int64_
     out[j] = (double)((int64_t)(wl_mix(seed + (c + 1) * WL_GAMMA) % span) + lo);
   }
 }
+
+/* Complex values whose re and im are odd integers 257..511 with random signs
+ * (re and im of element j from stream outputs 2j and 2j+1: magnitude from the
+ * low bits, sign from bit 40). */
+void wl_wide_odd(uint64_t seed, int64_t start, int64_t n, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < 2 * n; ++j) {
+    uint64_t z = wl_mix(seed + (uint64_t)(2 * start + j + 1) * WL_GAMMA);
+    double mag = (double)(257 + 2 * (int64_t)(z % 128));
+    out[j] = ((z >> 40) & 1) ? -mag : mag;
+  }
+}
+
+/* Complex values from {0, 1, -1, i, -i}, element j from stream output j. */
+void wl_unit_values(uint64_t seed, int64_t start, int64_t n, double* out) {
+  static const double re[5] = {0, 1, -1, 0, 0}, im[5] = {0, 0, 0, 1, -1};
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < n; ++j) {
+    uint64_t k = wl_mix(seed + (uint64_t)(start + j + 1) * WL_GAMMA) % 5;
+    out[2 * j] = re[k];
+    out[2 * j + 1] = im[k];
+  }
+}

@@ -26,7 +26,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import circuits, paths
-from .rng import SplitMix64, complex_normal, gaussian_integers, substream_seed
+from .rng import (SplitMix64, complex_normal, gaussian_integers, substream_seed,
+                  unit_values, wide_odd_integers)
 
 
 def seed_of(config: int, trial: int = 0) -> int:
@@ -53,16 +54,31 @@ class Problem:
         return len(self.axes_a)
 
 
-def _fill(seed: int, tag: int, n: int, integer: bool) -> np.ndarray:
+# Value distributions of operand entries: complex normals (re, im ~ N(0, 1/2)),
+# Gaussian integers in [-8, 8], odd integers of nine significant bits
+# (257..511 with signs: a bfloat16 split of each has a nonzero low part), and
+# units {0, +-1, +-i}.
+VALUE_KINDS = ("normal", "integer", "wide", "unit")
+
+
+def _fill(seed: int, tag: int, n: int, kind) -> np.ndarray:
     s = substream_seed(seed, tag)
-    return gaussian_integers(s, n) if integer else complex_normal(s, n)
+    if kind is True or kind == "integer":
+        return gaussian_integers(s, n)
+    if kind == "wide":
+        return wide_odd_integers(s, n)
+    if kind == "unit":
+        return unit_values(s, n)
+    return complex_normal(s, n)
 
 
 def make_problem(rank_a, rank_b, axes_a, axes_b, grid_a, grid_b, seed,
-                 integer=False) -> Problem:
+                 integer=False, values=None) -> Problem:
+    """values: (kind of A, kind of B) from VALUE_KINDS; overrides integer."""
+    ka, kb = values if values is not None else (integer, integer)
     da, db = [2] * rank_a, [2] * rank_b
-    a = Operand(da, list(grid_a), _fill(seed, 1, 1 << rank_a, integer))
-    b = Operand(db, list(grid_b), _fill(seed, 2, 1 << rank_b, integer))
+    a = Operand(da, list(grid_a), _fill(seed, 1, 1 << rank_a, ka))
+    b = Operand(db, list(grid_b), _fill(seed, 2, 1 << rank_b, kb))
     return Problem(a, b, list(axes_a), list(axes_b), seed)
 
 
@@ -84,13 +100,13 @@ def random_axes(rng: SplitMix64, rank_a: int, rank_b: int, k: int):
 
 
 def config3(trial: int = 0, rank: int = 28, k: int = 14, blocked: bool = False,
-            integer: bool = False) -> Problem:
+            integer: bool = False, values=None) -> Problem:
     seed = seed_of(3, trial)
     rng = SplitMix64(substream_seed(seed, 0))
     axes_a, axes_b = random_axes(rng, rank, rank, k)
     ga = split_first(rank) if blocked else [1] * rank
     gb = split_first(rank) if blocked else [1] * rank
-    return make_problem(rank, rank, axes_a, axes_b, ga, gb, seed, integer)
+    return make_problem(rank, rank, axes_a, axes_b, ga, gb, seed, integer, values)
 
 
 def config4_shapes(trial: int = 0, count: int = 256, max_out_rank: int = 24):

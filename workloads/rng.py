@@ -43,6 +43,8 @@ def _native():
         lib.wl_splitmix64.argtypes = [u64, i64, i64, p]
         lib.wl_complex_normal.argtypes = [u64, i64, i64, p]
         lib.wl_gaussian_int.argtypes = [u64, i64, i64, i64, i64, p]
+        lib.wl_wide_odd.argtypes = [u64, i64, i64, p]
+        lib.wl_unit_values.argtypes = [u64, i64, i64, p]
         _lib = lib
     return _lib
 
@@ -209,4 +211,47 @@ def gaussian_integers(seed: int, n: int, lo: int = -8, hi: int = 8) -> np.ndarra
     out = np.empty(n, dtype=np.complex128)
     if n:
         _native().wl_gaussian_int(seed & _MASK64, 0, n, lo, hi, out.ctypes.data)
+    return out
+
+
+def wide_odd_integers_numpy(seed: int, n: int) -> np.ndarray:
+    """n complex values whose re and im are odd integers of magnitude 257..511
+    with random signs.
+
+    Each has nine significant bits, one more than a bfloat16 holds, so its
+    nearest bfloat16 differs from it by exactly 1 (a nonzero low part of a
+    hi + lo bfloat16 split), while the value itself, and every product with
+    a value from ``unit_values``, is exact in FP32.
+    """
+    z = splitmix64_block(seed, 0, 2 * n)
+    mag = (257 + 2 * (z % np.uint64(128))).astype(np.int64)   # odd, 257 .. 511
+    sign = np.where(((z >> np.uint64(40)) & np.uint64(1)) == 1, -1, 1)
+    v = (mag * sign).astype(np.float64)
+    out = np.empty(n, dtype=np.complex128)
+    out.real = v[0::2]
+    out.imag = v[1::2]
+    return out
+
+
+def unit_values_numpy(seed: int, n: int) -> np.ndarray:
+    """n complex values drawn uniformly from {0, 1, -1, i, -i}: at most one
+    of re, im is nonzero, so |re| + |im| <= 1."""
+    z = splitmix64_block(seed, 0, n)
+    table = np.array([0, 1, -1, 1j, -1j], dtype=np.complex128)
+    return table[(z % np.uint64(5)).astype(np.int64)]
+
+
+def wide_odd_integers(seed: int, n: int) -> np.ndarray:
+    """Bulk C version of ``wide_odd_integers_numpy`` (same values)."""
+    out = np.empty(n, dtype=np.complex128)
+    if n:
+        _native().wl_wide_odd(seed & _MASK64, 0, n, out.ctypes.data)
+    return out
+
+
+def unit_values(seed: int, n: int) -> np.ndarray:
+    """Bulk C version of ``unit_values_numpy`` (same values)."""
+    out = np.empty(n, dtype=np.complex128)
+    if n:
+        _native().wl_unit_values(seed & _MASK64, 0, n, out.ctypes.data)
     return out
