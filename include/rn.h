@@ -160,7 +160,12 @@ rn_status rn_block_footprint(const rn_tensor* A, const rn_tensor* B, int32_t k,
                              const int32_t* axesA, const int32_t* axesB, double* eq1_elems,
                              double* eq2_elems);
 
-/* Many independent block tensordots in one call (same mode).  Plans every
+/* Many independent block tensordots in one call (same mode).  The paper runs
+ * the block-pair contractions of a block tensordot (Section II.C) and the
+ * copies of a sliced network (Section II.B) as independent tasks, and weighs
+ * block size against per-task overhead (Section IV.B); here independent
+ * problems share launches instead, so small ones do not each pay a launch.
+ * Plans every
  * problem first (any invalid problem fails the whole call before anything is
  * enqueued).  The problems are grouped by GEMM tile shape; per group one
  * grouped launch relayouts the operands that need it and one grouped launch
@@ -186,7 +191,10 @@ rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
                                    rn_tensor* C, rn_mode mode, void* ws, size_t ws_bytes,
                                    void* stream);
 
-/* Tile-shape autotuner for batches.  For every problem shape (mode,
+/* Tile-shape autotuner for batches.  Section IV.B's tuning system sizes each
+ * task's resources from its footprint before it runs; on the GPU the
+ * resource that decides speed is the GEMM tile shape, chosen here by
+ * measurement.  For every problem shape (mode,
  * log2 M, log2 N, log2 K) of the batch that is not tuned yet, times each GEMM
  * tile configuration on that problem (one warm-up and three timed launches,
  * HIP events) and keeps the fastest.  Runs synchronously on `stream` and
@@ -278,6 +286,10 @@ rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
 
 /* ------------------------------------------------------------------------
  * Amplitude server (continuous admission of sliced-network requests).
+ * Each request is one amplitude of a sliced network (Sections II.A, II.B).
+ * Admission follows the tuning rule of Section IV.B: work starts only when
+ * its memory requirement fits what is free, so a device filled with
+ * requests of similar size never runs out of memory.
  *
  * rn_server_create binds a server to a device with its own library handle,
  * a device arena of hbm_budget bytes (allocated once) and max_active slots
