@@ -52,6 +52,8 @@ extern "C" {
 
 #define RN_MAX_RANK 64
 #define RN_MAX_SLICED 15
+/* Bytes of the fixed device scratch array of rn_block_tensordot_noalloc. */
+#define RN_NOALLOC_SCRATCH_BYTES ((size_t)1 << 26)
 
 typedef enum {
   RN_OK = 0,
@@ -113,6 +115,24 @@ rn_status rn_block_tensordot_plan(rn_handle h, const rn_tensor* A, const rn_tens
 rn_status rn_block_tensordot(rn_handle h, const rn_tensor* A, const rn_tensor* B, int32_t k,
                              const int32_t* axesA, const int32_t* axesB, rn_tensor* C,
                              rn_mode mode, void* ws, size_t ws_bytes, void* stream);
+
+/* Block tensordot for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same contraction, plan, kernels and results as rn_block_tensordot, but
+ * its workspace is a fixed device array compiled into the library
+ * (RN_NOALLOC_SCRATCH_BYTES; each GPU the library runs on holds one until the
+ * process ends), so the call takes no ws argument and allocates nothing
+ * (no hipMalloc, hipFree, memset, event or stream creation; no kernel timing
+ * either).  A plan that needs more workspace than the array holds fails with
+ * RN_ERR_WORKSPACE before anything is enqueued.  Every call on one GPU shares
+ * that GPU's array: calls whose kernels may overlap on one device (several
+ * streams, or several threads without ordering) race and give undefined
+ * results.  Nothing in the array needs to start at zero: each call writes
+ * every workspace byte it reads.  The handle must have been created on that
+ * device (rn_create looks up the array's device address). */
+rn_status rn_block_tensordot_noalloc(rn_handle h, const rn_tensor* A, const rn_tensor* B,
+                                     int32_t k, const int32_t* axesA, const int32_t* axesB,
+                                     rn_tensor* C, rn_mode mode, void* stream);
 
 /* Streamed block tensordot, for operands larger than device memory: the
  * commutative reduction of Section IV.A (pairs loaded as needed, each

@@ -33,7 +33,8 @@ EXPORTS = ["rn_create", "rn_destroy", "rn_status_str", "rn_last_error",
            "rn_tune_load", "rn_tune_clear", "rn_tile_count", "rn_set_graphs", "rn_server_create",
            "rn_server_submit", "rn_server_poll", "rn_server_wait", "rn_server_stats",
            "rn_server_destroy", "rn_set_option", "rn_get_option",
-           "rn_block_tensordot_streamed_plan", "rn_block_tensordot_streamed"]
+           "rn_block_tensordot_streamed_plan", "rn_block_tensordot_streamed",
+           "rn_block_tensordot_noalloc"]
 
 # Handle options (rn_option).
 OPTIONS = {"graphs": 0, "pair_split_threshold": 1, "split_footprint": 2, "slice_sum": 3,
@@ -84,6 +85,7 @@ def lib():
         L.rn_block_tensordot_plan.argtypes = [p, T, T, i32, p, p, ctypes.c_int, T,
                                               ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_double)]
         L.rn_block_tensordot.argtypes = [p, T, T, i32, p, p, T, ctypes.c_int, p, sz, p]
+        L.rn_block_tensordot_noalloc.argtypes = [p, T, T, i32, p, p, T, ctypes.c_int, p]
         L.rn_block_pairs.argtypes = [p, T, T, i32, p, p, i64, p, i64, ctypes.POINTER(i64)]
         L.rn_block_footprint.argtypes = [T, T, i32, p, p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
@@ -355,6 +357,36 @@ class Context:
         check(lib().rn_block_tensordot(self.h, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb,
                                        ctypes.byref(C), mode_id(mode), wp, wn, self._stream()),
               "block_tensordot")
+        return out, cdims, cgrid
+
+    def block_tensordot_noalloc(self, a, dims_a, grid_a, b, dims_b, grid_b, axes_a, axes_b,
+                                mode="fp64", out=None):
+        """As block_tensordot through rn_block_tensordot_noalloc: the library's
+        fixed device scratch array is the workspace (nothing is allocated
+        when `out` is given)."""
+        import torch
+        dt = dtype_of_mode(mode)
+        want = _torch_dtype(mode)
+        _check_tensor(a, "a", want, _numel(dims_a), device=self.device)
+        _check_tensor(b, "b", want, _numel(dims_b), device=self.device)
+        A = descriptor(dims_a, grid_a, dt, a.data_ptr())
+        B = descriptor(dims_b, grid_b, dt, b.data_ptr())
+        C = RnTensor()
+        aa, pa = _arr32(axes_a)
+        ab, pb = _arr32(axes_b)
+        check(lib().rn_block_tensordot_plan(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
+                                            pa, pb, mode_id(mode), ctypes.byref(C), None, None),
+              "plan")
+        cdims = [C.dims[j] for j in range(C.rank)]
+        cgrid = [C.grid[j] for j in range(C.rank)]
+        n = _numel(cdims)
+        if out is None:
+            out = torch.empty(n, dtype=want, device=a.device)
+        _check_tensor(out, "out", want, n, device=self.device)
+        C.data = out.data_ptr()
+        check(lib().rn_block_tensordot_noalloc(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
+                                               pa, pb, ctypes.byref(C), mode_id(mode),
+                                               self._stream()), "block_tensordot_noalloc")
         return out, cdims, cgrid
 
     def plan_streamed(self, dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, mode="fp64"):

@@ -14,7 +14,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librosnet.so")
 SOURCES = ["gemm_f32_4m.hip", "gemm_f64.hip", "gemm_bf16x3.hip", "gemm_f32_3m.hip",
            "kernels.hip", "api.cpp", "plan.cpp", "network.cpp", "batch.cpp", "serve.cpp",
-           "stream.cpp"]
+           "stream.cpp", "noalloc.hip"]
 ARCH = os.environ.get("RN_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-result", "-pthread",

@@ -131,6 +131,8 @@ rn_status rn_create(rn_handle* h, int device) {
   if (device < 0 || device >= n) return fail(RN_ERR_INVALID, "device index out of range");
   e = hipSetDevice(device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  rn_status st = noalloc_init(device);
+  if (st != RN_OK) return st;
   rn_ctx* c = new rn_ctx();
   c->device = device;
   const char* g = getenv("RN_GRAPHS");

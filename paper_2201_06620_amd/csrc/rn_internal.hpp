@@ -208,6 +208,10 @@ rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor
                             const rn_tensor* C, void* ws, hipStream_t s, Profiler* prof,
                             int tile = -1);
 
+// Looks up the device address of the no-alloc scratch array on `device`
+// (current) once per device; rn_create calls it.
+rn_status noalloc_init(int device);
+
 hipError_t launch_norm2(const void* x, int64_t n, int dtype, double* out, double* scratch,
                         hipStream_t s);
 hipError_t launch_sum_c128(const double* vals, int64_t n, double* out, hipStream_t s);
