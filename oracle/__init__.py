@@ -18,6 +18,8 @@ Functions and the passage each follows:
   statevector          2^n state tensor evolved gate by gate (Section II.A)
   contract_network     sliced network contraction on a path, slices summed in
                        FP64 (Sections II.A, II.B)
+  contract_network_slices  the value of chosen single slices (one projection
+                       each, Section II.B)
   norm2                sum of squared magnitudes in FP64
 """
 from __future__ import annotations
@@ -31,7 +33,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+_SO_OMP = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
+_lib_omp = None
 
 ERRORS = {1: "invalid argument", 2: "shape mismatch", 3: "grid does not divide dims",
           5: "out of memory"}
@@ -41,14 +45,19 @@ class OracleError(RuntimeError):
     pass
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle (gcc, -O2 -ffp-contract=off, no fast-math)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        tmp = _SO + ".tmp%d" % os.getpid()
+def build(force: bool = False, openmp: bool = False) -> str:
+    """Compile the oracle (gcc, -O2 -ffp-contract=off, no fast-math).  The
+    OpenMP build (a second library, for the CPU baseline) runs the output
+    blocks of block_tensordot on several threads, each block summed in the
+    same order as the single-threaded build, so the results are identical."""
+    so = _SO_OMP if openmp else _SO
+    if force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(_SRC):
+        tmp = so + ".tmp%d" % os.getpid()
+        extra = ["-fopenmp", "-DORC_OPENMP"] if openmp else []
         subprocess.check_call(["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-Wall", _SRC, "-o", tmp])
-        os.replace(tmp, _SO)
-    return _SO
+                               "-fPIC", "-shared", "-Wall"] + extra + [_SRC, "-o", tmp])
+        os.replace(tmp, so)
+    return so
 
 
 def _L():
@@ -66,6 +75,8 @@ def _L():
         lib.orc_norm2.argtypes = [p, i64]
         lib.orc_norm2.restype = ctypes.c_double
         lib.orc_contract_network.argtypes = [i32, p, p, p, i32, p, i32, p, p, i64, p, p]
+        lib.orc_contract_network_range.argtypes = [i32, p, p, p, i32, p, i32, p, i64, i64, p,
+                                                   i64, p, p]
         _lib = lib
     return _lib
 
@@ -154,15 +165,28 @@ def from_blocked(blocked: np.ndarray, dims, grid) -> np.ndarray:
     return out
 
 
-def block_tensordot(a_blocked, dims_a, grid_a, b_blocked, dims_b, grid_b, axes_a, axes_b):
-    """(C block-major buffer, C dims, C grid) by the four steps of Section II.C."""
+def _L_omp():
+    global _lib_omp
+    if _lib_omp is None:
+        lib = ctypes.CDLL(build(openmp=True))
+        p, i32 = ctypes.c_void_p, ctypes.c_int32
+        lib.orc_block_tensordot.argtypes = [p, i32, p, p, p, i32, p, p, i32, p, p, p, p]
+        _lib_omp = lib
+    return _lib_omp
+
+
+def block_tensordot(a_blocked, dims_a, grid_a, b_blocked, dims_b, grid_b, axes_a, axes_b,
+                    openmp=False):
+    """(C block-major buffer, C dims, C grid) by the four steps of Section II.C
+    (openmp: output blocks on several threads, OMP_NUM_THREADS, same result)."""
     ab, bb = _c128(a_blocked).reshape(-1), _c128(b_blocked).reshape(-1)
     da, ga, db, gb = _i64(dims_a), _i32(grid_a), _i64(dims_b), _i32(grid_b)
     axa, axb = _i32(axes_a), _i32(axes_b)
     cdims = _out_shape(list(da), list(db), list(axa), list(axb))
     out = np.empty(int(np.prod(cdims, dtype=np.int64)), dtype=np.complex128)
     gc = np.zeros(max(1, len(cdims)), dtype=np.int32)
-    _check(_L().orc_block_tensordot(ab.ctypes.data, da.size, _ptr(da), _ptr(ga), bb.ctypes.data,
+    lib = _L_omp() if openmp else _L()
+    _check(lib.orc_block_tensordot(ab.ctypes.data, da.size, _ptr(da), _ptr(ga), bb.ctypes.data,
                                     db.size, _ptr(db), _ptr(gb), axa.size, _ptr(axa), _ptr(axb),
                                     out.ctypes.data, gc.ctypes.data), "block_tensordot")
     return out, list(cdims), [int(x) for x in gc[:len(cdims)]]
@@ -207,3 +231,31 @@ def contract_network(tensors, labels, path, sliced=()):
                                      olab.ctypes.data), "contract_network")
     r = int(orank[0])
     return out[:1 << r].reshape((2,) * r), [int(x) for x in olab[:r]]
+
+
+def contract_network_slices(tensors, labels, path, sliced, which):
+    """Scalar value of each slice s in `which` (slice s fixes sliced[i] to bit
+    nsliced-1-i of s) of a network that closes to a scalar."""
+    ranks = _i32([len(l) for l in labels])
+    for t, l in zip(tensors, labels):
+        if np.asarray(t).size != (1 << len(l)):
+            raise OracleError("contract_network_slices: every dim must be 2")
+    flat_l = _i32([x for l in labels for x in l] or [0])
+    data = _c128(np.concatenate([_c128(t).reshape(-1) for t in tensors]))
+    p = _i32([x for st in path for x in st] or [0])
+    sl = _i32(list(sliced) or [0])
+    res = []
+    for s in which:
+        out = np.zeros(1, dtype=np.complex128)
+        orank = np.zeros(1, dtype=np.int32)
+        olab = np.zeros(64, dtype=np.int32)
+        _check(_L().orc_contract_network_range(len(tensors), ranks.ctypes.data,
+                                               flat_l.ctypes.data, data.ctypes.data, len(path),
+                                               p.ctypes.data, len(sliced), sl.ctypes.data,
+                                               int(s), int(s) + 1, out.ctypes.data, 2,
+                                               orank.ctypes.data, olab.ctypes.data),
+               "contract_network_slices")
+        if orank[0] != 0:
+            raise OracleError("contract_network_slices: the network has open labels")
+        res.append(complex(out[0]))
+    return np.asarray(res, dtype=np.complex128)

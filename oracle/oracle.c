@@ -288,6 +288,57 @@ static void orc_extract(const double* blocked, int32_t rank, const int64_t* dims
  * counts), which leaves the result unchanged.  C's grid is A's free-axis grid
  * followed by B's.  Pairs are visited in ascending row-major order of their
  * contracted block coordinates.  gC receives C's grid (rank rA + rB - 2k). */
+typedef struct {
+  const orc_td* t;
+  const double *Ab, *Bb;
+  double* Cb;
+  int32_t rA, rB, k, crank;
+  const int64_t *dA, *dB;
+  const int32_t *gA, *gB, *axA, *axB;
+  const int64_t *cgrid, *pg, *extA, *extB;
+  int64_t csz, npair, asz, bsz;
+} orc_blk_job;
+
+/* The four steps of Section II.C for output block `blk` (row-major block
+ * index): pairs in ascending order, each contracted and added into the
+ * block's accumulator.  Returns nonzero when out of memory. */
+static int orc_block_of_c(const orc_blk_job* J, int64_t blk) {
+  const orc_td* t = J->t;
+  double* ablk = (double*)malloc(sizeof(double) * 2 * (size_t)J->asz);
+  double* bblk = (double*)malloc(sizeof(double) * 2 * (size_t)J->bsz);
+  double* part = (double*)malloc(sizeof(double) * 2 * (size_t)J->csz);
+  double* acc = (double*)calloc(2 * (size_t)J->csz, sizeof(double));
+  int rc = (!ablk || !bblk || !part || !acc) ? ORC_ENOMEM : ORC_OK;
+  int64_t cb[2 * ORC_MAX_RANK], pc[ORC_MAX_RANK], orgA[ORC_MAX_RANK], orgB[ORC_MAX_RANK];
+  if (!rc) {
+    orc_unravel(blk, J->crank, J->cgrid, cb);
+    /* Step 1: the free-axis coordinates of this C block fix the A and B
+     * block origins on the free axes. */
+    for (int32_t j = 0; j < t->nfa; ++j) orgA[t->fa[j]] = cb[j] * J->extA[t->fa[j]];
+    for (int32_t j = 0; j < t->nfb; ++j) orgB[t->fb[j]] = cb[t->nfa + j] * J->extB[t->fb[j]];
+  }
+  for (int64_t p = 0; p < J->npair && !rc; ++p) {
+    /* Step 2: pair p matches contracted block coordinates on both sides. */
+    orc_unravel(p, J->k, J->pg, pc);
+    for (int32_t i = 0; i < J->k; ++i) {
+      orgA[J->axA[i]] = pc[i] * J->extA[J->axA[i]];
+      orgB[J->axB[i]] = pc[i] * J->extB[J->axB[i]];
+    }
+    orc_extract(J->Ab, J->rA, J->dA, J->gA, orgA, J->extA, ablk);
+    orc_extract(J->Bb, J->rB, J->dB, J->gB, orgB, J->extB, bblk);
+    /* Step 3: local contraction of the pair. */
+    rc = orc_tensordot(ablk, J->rA, J->extA, bblk, J->rB, J->extB, J->k, J->axA, J->axB, part);
+    /* Step 4: add the partial block into the C block. */
+    for (int64_t e = 0; e < 2 * J->csz && !rc; ++e) acc[e] += part[e];
+  }
+  if (!rc) memcpy(J->Cb + 2 * blk * J->csz, acc, sizeof(double) * 2 * (size_t)J->csz);
+  free(ablk);
+  free(bblk);
+  free(part);
+  free(acc);
+  return rc;
+}
+
 int orc_block_tensordot(const double* Ab, int32_t rA, const int64_t* dA, const int32_t* gA,
                         const double* Bb, int32_t rB, const int64_t* dB, const int32_t* gB,
                         int32_t k, const int32_t* axA, const int32_t* axB, double* Cb,
@@ -329,50 +380,40 @@ int orc_block_tensordot(const double* Ab, int32_t rA, const int64_t* dA, const i
   for (int32_t j = 0; j < rA; ++j) extA[j] = dA[j] / rgA[j];
   for (int32_t j = 0; j < rB; ++j) extB[j] = dB[j] / rgB[j];
 
-  int64_t nCblk = orc_numel(crank, cgrid), csz = orc_numel(crank, cext);
-  int64_t npair = orc_numel(k, pg);
-  int64_t asz = orc_numel(rA, extA), bsz = orc_numel(rB, extB);
-  double* ablk = (double*)malloc(sizeof(double) * 2 * (size_t)asz);
-  double* bblk = (double*)malloc(sizeof(double) * 2 * (size_t)bsz);
-  double* part = (double*)malloc(sizeof(double) * 2 * (size_t)csz);
-  double* acc = (double*)malloc(sizeof(double) * 2 * (size_t)csz);
-  if (!ablk || !bblk || !part || !acc) {
-    free(ablk);
-    free(bblk);
-    free(part);
-    free(acc);
-    return ORC_ENOMEM;
-  }
-  int64_t cb[2 * ORC_MAX_RANK], pc[ORC_MAX_RANK], orgA[ORC_MAX_RANK], orgB[ORC_MAX_RANK];
+  orc_blk_job J;
+  J.t = &t;
+  J.Ab = Ab;
+  J.Bb = Bb;
+  J.Cb = Cb;
+  J.rA = rA;
+  J.rB = rB;
+  J.k = k;
+  J.dA = dA;
+  J.dB = dB;
+  J.gA = gA;
+  J.gB = gB;
+  J.axA = axA;
+  J.axB = axB;
+  J.crank = crank;
+  J.cgrid = cgrid;
+  J.pg = pg;
+  J.extA = extA;
+  J.extB = extB;
+  J.csz = orc_numel(crank, cext);
+  J.npair = orc_numel(k, pg);
+  J.asz = orc_numel(rA, extA);
+  J.bsz = orc_numel(rB, extB);
+  int64_t nCblk = orc_numel(crank, cgrid);
+  /* C blocks are independent: each is summed on its own, in the same order,
+   * whether the blocks run one after another or (built with ORC_OPENMP, the
+   * CPU-baseline build) on several threads. */
+#ifdef ORC_OPENMP
+#pragma omp parallel for schedule(dynamic, 1) reduction(max : rc)
+#endif
   for (int64_t blk = 0; blk < nCblk; ++blk) {
-    orc_unravel(blk, crank, cgrid, cb);
-    memset(acc, 0, sizeof(double) * 2 * (size_t)csz);
-    /* Step 1: the free-axis coordinates of this C block fix the A and B
-     * block origins on the free axes. */
-    for (int32_t j = 0; j < t.nfa; ++j) orgA[t.fa[j]] = cb[j] * extA[t.fa[j]];
-    for (int32_t j = 0; j < t.nfb; ++j) orgB[t.fb[j]] = cb[t.nfa + j] * extB[t.fb[j]];
-    for (int64_t p = 0; p < npair; ++p) {
-      /* Step 2: pair p matches contracted block coordinates on both sides. */
-      orc_unravel(p, k, pg, pc);
-      for (int32_t i = 0; i < k; ++i) {
-        orgA[axA[i]] = pc[i] * extA[axA[i]];
-        orgB[axB[i]] = pc[i] * extB[axB[i]];
-      }
-      orc_extract(Ab, rA, dA, gA, orgA, extA, ablk);
-      orc_extract(Bb, rB, dB, gB, orgB, extB, bblk);
-      /* Step 3: local contraction of the pair. */
-      rc = orc_tensordot(ablk, rA, extA, bblk, rB, extB, k, axA, axB, part);
-      if (rc) break;
-      /* Step 4: add the partial block into the C block. */
-      for (int64_t e = 0; e < 2 * csz; ++e) acc[e] += part[e];
-    }
-    if (rc) break;
-    memcpy(Cb + 2 * blk * csz, acc, sizeof(double) * 2 * (size_t)csz);
+    int r = orc_block_of_c(&J, blk);
+    if (r > rc) rc = r;
   }
-  free(ablk);
-  free(bblk);
-  free(part);
-  free(acc);
   return rc;
 }
 
@@ -463,7 +504,9 @@ double orc_norm2(const double* x, int64_t n) {
 /* most significant).  The copies are contracted independently and their      */
 /* results summed in FP64 in ascending s, which recovers the unsliced result. */
 /* out receives the summed final tensor (out_cap doubles available), with its */
-/* rank and labels.                                                           */
+/* rank and labels.  orc_contract_network_range sums only the slices          */
+/* s_begin <= s < s_end (one projection of Section II.B when s_end =          */
+/* s_begin + 1); orc_contract_network sums all of them.                       */
 /* ------------------------------------------------------------------------ */
 typedef struct {
   double* data;
@@ -533,11 +576,13 @@ static int orc_step(const orc_nt* a, const orc_nt* b, orc_nt* c) {
   return orc_tensordot(a->data, a->rank, dA, b->data, b->rank, dB, k, axA, axB, c->data);
 }
 
-int orc_contract_network(int32_t nt, const int32_t* ranks, const int32_t* labels,
-                         const double* data, int32_t nsteps, const int32_t* path,
-                         int32_t nsliced, const int32_t* sliced, double* out, int64_t out_cap,
-                         int32_t* out_rank, int32_t* out_labels) {
+int orc_contract_network_range(int32_t nt, const int32_t* ranks, const int32_t* labels,
+                               const double* data, int32_t nsteps, const int32_t* path,
+                               int32_t nsliced, const int32_t* sliced, int64_t s_begin,
+                               int64_t s_end, double* out, int64_t out_cap,
+                               int32_t* out_rank, int32_t* out_labels) {
   if (nt < 1 || nsteps != nt - 1 || nsliced < 0 || nsliced > 30) return ORC_EINVAL;
+  if (s_begin < 0 || s_end <= s_begin || s_end > ((int64_t)1 << nsliced)) return ORC_EINVAL;
   int32_t ntot = nt + nsteps;
   int64_t* doff = (int64_t*)malloc(sizeof(int64_t) * (size_t)nt);
   int64_t* loff = (int64_t*)malloc(sizeof(int64_t) * (size_t)nt);
@@ -562,9 +607,8 @@ int orc_contract_network(int32_t nt, const int32_t* ranks, const int32_t* labels
     l += ranks[i];
   }
   int rc = ORC_OK;
-  int64_t nslices = (int64_t)1 << nsliced;
   int first = 1;
-  for (int64_t s = 0; s < nslices && !rc; ++s) {
+  for (int64_t s = s_begin; s < s_end && !rc; ++s) {
     for (int32_t i = 0; i < nt && !rc; ++i)
       rc = orc_project(data + 2 * doff[i], ranks[i], labels + loff[i], nsliced, sliced, s,
                        &T[i]);
@@ -605,4 +649,13 @@ int orc_contract_network(int32_t nt, const int32_t* ranks, const int32_t* labels
   free(loff);
   free(T);
   return rc;
+}
+
+int orc_contract_network(int32_t nt, const int32_t* ranks, const int32_t* labels,
+                         const double* data, int32_t nsteps, const int32_t* path,
+                         int32_t nsliced, const int32_t* sliced, double* out, int64_t out_cap,
+                         int32_t* out_rank, int32_t* out_labels) {
+  if (nsliced < 0 || nsliced > 30) return ORC_EINVAL;
+  return orc_contract_network_range(nt, ranks, labels, data, nsteps, path, nsliced, sliced, 0,
+                                    (int64_t)1 << nsliced, out, out_cap, out_rank, out_labels);
 }

@@ -161,7 +161,12 @@ def test_rank28_unitary_full_output():
     w = torch.ones((1, 1), dtype=torch.float64, device="cuda")
     for q in qs:
         w = torch.kron(w, torch.from_numpy(np.abs(q).T @ np.abs(q)).cuda())
-    w = w.view([2] * RANK).permute(cols + [K + c for c in cols]).reshape(n, n).contiguous()
+    # Row/column index of C -> the original column index it stands for.
+    x = torch.arange(n, device="cuda")
+    orig = torch.zeros_like(x)
+    for pos_c, c in enumerate(cols):
+        orig |= ((x >> (K - 1 - pos_c)) & 1) << (K - 1 - c)
+    w = w[orig][:, orig].contiguous()
     eye = torch.eye(n, dtype=torch.complex128, device="cuda")
     errs = {}
     worst = {}

@@ -147,3 +147,60 @@ def test_sliced_request_fitted_to_budget():
     assert res["status"] == 0
     assert res["footprint"] <= budget
     assert abs(res["amp"] - ref) / max(abs(ref), 2.0 ** (-w.circuit.n / 2)) < 1e-12
+
+
+def fullsize_requests(count=3, scan=32):
+    """Serving-workload requests at their real size for the oracle check: the
+    first `count` of the first `scan` requests with at least 40 sites, at
+    least 2 sliced bonds and at most 6e9 flops per slice (so the oracle
+    finishes a slice in seconds), each checked on its own slicing."""
+    out = []
+    for i in range(scan):
+        w = configs.config5_request(0, i)
+        if (w.meta["sites"] >= 40 and len(w.sliced) >= 2
+                and w.meta["flops_per_slice"] <= 6e9):
+            out.append((i, w))
+            if len(out) == count:
+                break
+    assert len(out) == count
+    return out
+
+
+@pytest.fixture(scope="module")
+def fullsize():
+    return fullsize_requests()
+
+
+@pytest.mark.parametrize("mode", ["fp32_4m", "fp64"])
+def test_serving_requests_at_full_size_per_slice_vs_oracle(fullsize, mode):
+    # Config-5 requests (40-50 sites, 8-10 cycles, 4-6 sliced bonds) through
+    # rn_contract_network with per-slice values: the first and the last slice
+    # of each are compared with the oracle's single-slice projection (slice-
+    # subsampled: the other slices are checked only through the FP64 sum).
+    # FP32-4M on all three requests, FP64 on the first.
+    import torch
+    import paper_2201_06620_amd as rn
+    ctx = rn.Context(0)
+    tol = 1e-12 if mode == "fp64" else 1e-5
+    dt = torch.complex128 if mode == "fp64" else torch.complex64
+    picks = fullsize[:1] if mode == "fp64" else fullsize
+    for i, w in picks:
+        net, S = w.network, len(w.sliced)
+        log(f"request {i}: {w.meta['sites']} sites, {w.meta['cycles']} cycles, {S} sliced, "
+            f"max rank {w.meta['max_rank']}, {w.meta['flops_per_slice']:.3g} flops/slice")
+        ts = [torch.from_numpy(np.ascontiguousarray(t.reshape(-1))).to(dt).cuda()
+              for t in net.tensors]
+        sl = torch.zeros(2 << S, dtype=torch.float64, device="cuda")
+        amp = ctx.contract_network(ts, net.labels, w.path, w.sliced, mode, slices=sl)
+        torch.cuda.synchronize()
+        got = sl.cpu().numpy().view(np.complex128)
+        which = [0, (1 << S) - 1]
+        ref = oracle.contract_network_slices(net.tensors, net.labels, w.path, w.sliced, which)
+        # Amplitude scale 2^(-n/2), spread over 2^S slices of random phase.
+        scale = 2.0 ** (-(w.meta["sites"] + S) / 2)
+        for s, r in zip(which, ref):
+            err = abs(got[s] - r) / max(abs(r), scale)
+            log(f"  slice {s}: |a| = {abs(r):.3e}, e_amp = {err:.3e}")
+            assert err < tol, (i, s, err)
+        a = amp.cpu().numpy()
+        assert abs(complex(a[0], a[1]) - np.sum(got)) <= 1e-14 * max(np.sum(np.abs(got)), 1e-300)

@@ -262,6 +262,18 @@ def test_block_tensordot_equivalence(integer):
         assert rel_err(C, ref) < 1e-14
 
 
+def test_block_tensordot_openmp_build_identical():
+    # The CPU-baseline build runs output blocks on several threads; each block
+    # is summed in the same order, so the results are the same bits.
+    for p in (configs.config1(), configs.make_problem(
+            10, 9, [1, 7, 4], [8, 0, 3], [2, 2, 1, 1, 2, 1, 1, 2, 1, 1],
+            [1, 2, 2, 1, 1, 1, 1, 1, 2], 515)):
+        args = (p.a.data, p.a.dims, p.a.grid, p.b.data, p.b.dims, p.b.grid, p.axes_a, p.axes_b)
+        serial = oracle.block_tensordot(*args)
+        threaded = oracle.block_tensordot(*args, openmp=True)
+        assert np.array_equal(serial[0], threaded[0]) and serial[1:] == threaded[1:]
+
+
 def test_block_tensordot_outer_and_scalar():
     C, ref, _ = blocked_vs_unblocked(3, 2, [], [], [2, 1, 2], [2, 2], 91)
     assert rel_err(C, ref) < 1e-15
@@ -402,6 +414,40 @@ def test_network_config2_amplitude_vs_statevector():
     psi = oracle.statevector(w.circuit)
     x = int("".join(map(str, w.bitstring)), 2)
     assert abs(complex(amp) - psi[x]) < 1e-12 * max(abs(psi[x]), 2 ** -10)
+
+
+def test_network_single_slices_are_projections_and_sum_to_the_sliced_result():
+    # One slice of Section II.B is the network with each sliced bond fixed to
+    # one basis value: checked against an independent projection (numpy
+    # indexing of every tensor carrying the bond, the bond dropped from its
+    # labels) contracted without slicing; the FP64 sum of all single slices
+    # in ascending s is the sliced result bit for bit.  Slice s fixes
+    # sliced[i] to bit nsliced-1-i of s (first sliced label most significant).
+    w = configs.config2()
+    net, path, sliced = w.network, w.path, w.sliced
+    S = len(sliced)
+    vals = oracle.contract_network_slices(net.tensors, net.labels, path, sliced,
+                                          range(1 << S))
+    total, _ = oracle.contract_network(net.tensors, net.labels, path, sliced)
+    acc = 0j
+    for v in vals:
+        acc += v
+    assert complex(total) == acc
+    for s in (0, 5, (1 << S) - 1):
+        fix = {lab: (s >> (S - 1 - i)) & 1 for i, lab in enumerate(sliced)}
+        ts, ls = [], []
+        for t, l in zip(net.tensors, net.labels):
+            t = np.asarray(t).reshape((2,) * len(l))
+            keep = []
+            for j, lab in enumerate(l):
+                if lab in fix:
+                    t = np.take(t, fix[lab], axis=len(keep))
+                else:
+                    keep.append(lab)
+            ts.append(np.ascontiguousarray(t))
+            ls.append(keep)
+        proj, labels = oracle.contract_network(ts, ls, path)
+        assert labels == [] and complex(proj) == vals[s], s
 
 
 def test_network_rejects_bad_path():

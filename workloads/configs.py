@@ -16,8 +16,10 @@ dense tensor is simply whatever that buffer denotes.
      contracted counts uniform in [2, 10]; a draw is redone until
      k <= min(rA, rB) and rA + rB - 2k <= 24; blocked like workload 1.
   5. amplitude requests for random circuits on 30-53 sites, 8-14 cycles,
-     sliced until the largest intermediate has rank <= 30 with at most
-     6 sliced bonds (a circuit needing more is redrawn).
+     each carrying 1-64 slices (2^0 .. 2^6, uniform exponent) and sliced
+     further while its largest intermediate has rank above 30; a circuit
+     needing more than 6 sliced bonds, or more than 2e13 flops over all its
+     slices, is redrawn.
 """
 from __future__ import annotations
 
@@ -165,18 +167,32 @@ def config2(trial: int = 0, n_slices: int = 4) -> NetworkWorkload:
 
 def config5_request(trial: int, index: int, max_rank: int = 30, max_sliced: int = 6,
                     flops_cap: float = 2e13, sites=(30, 53), cycles=(8, 14)):
-    """One serving request: redraws (sites, cycles) until the sliced plan fits."""
+    """One serving request: draws (sites, cycles) and a slice count of 2^0 ..
+    2^max_sliced (uniform exponent), slices that many bonds greedily, slices
+    more while the largest intermediate is above max_rank, and redraws while
+    that needs more than max_sliced bonds or the request's total flops (all
+    slices) exceed flops_cap."""
     seed = substream_seed(seed_of(5, trial), 1000 + index)
     rng = SplitMix64(seed)
     for attempt in range(64):
         n = rng.randint(*sites)
         cyc = rng.randint(*cycles)
+        n_target = rng.randint(0, max_sliced)
         rows, cols = circuits.grid_shape(n)
-        wl = circuit_workload(rows, cols, cyc, substream_seed(seed, attempt),
-                              max_rank=max_rank, n_sites=n, restarts=2)
-        total = wl.meta["flops_per_slice"] * (1 << len(wl.sliced))
-        if len(wl.sliced) <= max_sliced and total <= flops_cap and len(wl.sliced) >= 0:
-            wl.meta.update({"sites": n, "cycles": cyc, "attempt": attempt,
+        wl = circuit_workload(rows, cols, cyc, substream_seed(seed, attempt), n_sites=n,
+                              restarts=2)
+        lab, path = wl.network.labels, wl.path
+        sl_seed = substream_seed(seed, 100 + attempt) & 0xFFFFFFFF
+        sliced = paths.greedy_slices(lab, path, sl_seed, n_slices=n_target) if n_target else []
+        if paths.path_stats(lab, path, sliced)[0] > max_rank:
+            sliced = paths.greedy_slices(lab, path, sl_seed, max_rank=max_rank,
+                                         max_sliced=max_sliced + 1)
+        mr, fl, _ = paths.path_stats(lab, path, sliced)
+        total = fl * (1 << len(sliced))
+        if len(sliced) <= max_sliced and mr <= max_rank and total <= flops_cap:
+            wl.sliced = sliced
+            wl.meta.update({"sites": n, "cycles": cyc, "attempt": attempt, "max_rank": mr,
+                            "flops_per_slice": fl, "n_sliced": len(sliced),
                             "total_flops": total})
             return wl
     raise RuntimeError("no feasible circuit drawn")
