@@ -89,24 +89,47 @@ def _make_request(i):
     return configs.config5_request(0, i)
 
 
+def _size_classes(values):
+    """Index lists of the lower, middle and upper third of `values`."""
+    order = np.argsort(values, kind="stable")
+    n = len(order)
+    return {"small": order[: n // 3].tolist(), "medium": order[n // 3: 2 * n // 3].tolist(),
+            "large": order[2 * n // 3:].tolist()}
+
+
+def _latency_summary(res, idx):
+    if not idx:
+        return None
+    lat = [1e3 * res[i]["latency_s"] for i in idx]
+    return {"n": len(idx), "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "mean_queue_ms": 1e3 * float(np.mean([res[i]["queue_s"] for i in idx])),
+            "mean_run_ms": 1e3 * float(np.mean([res[i]["run_s"] for i in idx])),
+            "p99_queue_ms": percentile([1e3 * res[i]["queue_s"] for i in idx], 99),
+            "p99_run_ms": percentile([1e3 * res[i]["run_s"] for i in idx], 99)}
+
+
 def run_serving(args, torch, rn, log):
     """Requests of the serving workload: seeded random circuits on 30-53-site
-    grids, 8-14 cycles, sliced until the largest intermediate has rank <= 30
-    (at most 6 sliced bonds), complex64 with FP64 slice sums.  First all
-    requests are queued at once (saturated throughput), then the same requests
-    arrive as a Poisson stream at a fraction of that rate."""
+    grids, 8-14 cycles, each with 1-64 slices and sliced further until its
+    largest intermediate has rank <= 30, complex64 with FP64 slice sums.
+    First all requests are queued at once (saturated throughput); then, for
+    each load in --serve-loads, the same requests arrive as a Poisson stream
+    at that fraction of the saturated rate.  Latency = completion - arrival,
+    split into queueing (arrival to admission) and running time, overall and
+    per size third (total flops).  A seeded tenth of the requests is checked
+    against the oracle, one slice each (see serving_oracle_sample)."""
     import threading
     from concurrent.futures import ProcessPoolExecutor
 
     t0 = time.time()
     with ProcessPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
         reqs = list(ex.map(_make_request, range(args.serve_requests)))
-    log(f"serving: {len(reqs)} requests planned in {time.time() - t0:.1f}s; sites "
-        f"{[w.meta['sites'] for w in reqs]}")
+    log(f"serving: {len(reqs)} requests planned in {time.time() - t0:.1f}s")
     free, total = torch.cuda.mem_get_info()
     budget = int(0.9 * free)
     srv = rn.Server(0, hbm_budget=budget, max_active=args.serve_slots)
     tensors = [[t.astype(np.complex64) for t in w.network.tensors] for w in reqs]
+    flops = [w.meta["total_flops"] for w in reqs]
 
     def submit(i):
         w = reqs[i]
@@ -119,38 +142,122 @@ def run_serving(args, torch, rn, log):
     sat = [srv.wait(tk) for tk in tickets]
     sat_s = time.perf_counter() - t
     thr = len(reqs) / sat_s
-    lam = args.serve_load * thr
-    gaps = np.random.default_rng(2201).exponential(1.0 / lam, size=len(reqs))
-    tk2 = [None] * len(reqs)
+    log(f"serving: saturated {thr:.1f} amplitudes/s ({sat_s:.2f} s for {len(reqs)})")
+    classes = _size_classes(flops)
+    sweep = []
+    for li, load in enumerate(args.serve_loads):
+        lam = load * thr
+        gaps = np.random.default_rng(2201 + li).exponential(1.0 / lam, size=len(reqs))
+        tk2 = [None] * len(reqs)
 
-    def client():
-        for i, g in enumerate(gaps):
-            time.sleep(float(g))
-            tk2[i] = submit(i)
+        def client():
+            for i, g in enumerate(gaps):
+                time.sleep(float(g))
+                tk2[i] = submit(i)
 
-    t = time.perf_counter()
-    th = threading.Thread(target=client)
-    th.start()
-    th.join()
-    res = [srv.wait(tk) for tk in tk2]
-    el = time.perf_counter() - t
+        t = time.perf_counter()
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        res = [srv.wait(tk) for tk in tk2]
+        el = time.perf_counter() - t
+        lat = [1e3 * r["latency_s"] for r in res]
+        same = sum(1 for a, b in zip(sat, res) if a["amp"] == b["amp"] and a["status"] == 0)
+        entry = {"load": load, "arrival_rate_per_s": lam, "p50_ms": percentile(lat, 50),
+                 "p99_ms": percentile(lat, 99), "amplitudes_per_s": len(reqs) / el,
+                 "mean_queue_ms": 1e3 * float(np.mean([r["queue_s"] for r in res])),
+                 "mean_run_ms": 1e3 * float(np.mean([r["run_s"] for r in res])),
+                 "by_size_third": {k: _latency_summary(res, v) for k, v in classes.items()},
+                 "identical_to_saturated_run": same,
+                 "statuses": sorted(set(r["status"] for r in res))}
+        # Achieved rate of the largest tenth of the requests while they ran
+        # (each request's flops over its own running time; other requests may
+        # have shared the GPU meanwhile).
+        top = np.argsort(flops)[-max(1, len(reqs) // 10):]
+        entry["largest_tenth_tflops_while_running"] = float(
+            sum(flops[i] for i in top) / sum(res[i]["run_s"] for i in top) / 1e12)
+        log(f"serving load {load}: p50 {entry['p50_ms']:.1f} ms, p99 {entry['p99_ms']:.1f} ms, "
+            f"{entry['amplitudes_per_s']:.1f}/s")
+        sweep.append(entry)
     srv.close()
-    lat = [1e3 * r["latency_s"] for r in res]
-    same = sum(1 for a, b in zip(sat, res) if a["amp"] == b["amp"] and a["status"] == 0)
+    hist_sites = {}
+    hist_slices = {}
+    for w in reqs:
+        key = f"{w.meta['sites']}x{w.meta['cycles']}"
+        hist_sites[key] = hist_sites.get(key, 0) + 1
+        hist_slices[str(1 << len(w.sliced))] = hist_slices.get(str(1 << len(w.sliced)), 0) + 1
     out = {"workload": "amplitude requests for seeded random circuits on 30-53-site grids, 8-14 "
-                       "cycles, sliced to largest intermediate rank <= 30 (<= 6 sliced bonds), "
-                       "complex64 FP32-4M with FP64 slice sums; HBM-footprint admission, "
-                       f"{args.serve_slots} concurrent slots",
+                       "cycles, 1-64 slices each (2^0..2^6) and sliced until the largest "
+                       "intermediate rank <= 30, complex64 FP32-4M with FP64 slice sums; "
+                       f"HBM-footprint admission, {args.serve_slots} concurrent slots",
            "requests": len(reqs), "saturated_amplitudes_per_s": thr,
-           "arrival_rate_per_s": lam, "load": args.serve_load,
-           "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
-           "amplitudes_per_s": len(reqs) / el,
-           "mean_queue_ms": 1e3 * float(np.mean([r["queue_s"] for r in res])),
-           "identical_to_saturated_run": same,
-           "total_flops": float(sum(w.meta["total_flops"] for w in reqs)),
-           "statuses": sorted(set(r["status"] for r in res))}
-    log(f"serving: {out}")
-    return out
+           "saturated_seconds": sat_s, "loads": sweep,
+           "total_flops": float(sum(flops)),
+           "accepted_sites_x_cycles": dict(sorted(hist_sites.items())),
+           "slices_per_request": dict(sorted(hist_slices.items(), key=lambda kv: int(kv[0]))),
+           "size_thirds_total_flops": {k: float(sum(flops[i] for i in v))
+                                       for k, v in classes.items()}}
+    return out, reqs
+
+
+def serving_oracle_sample(args, torch, rn, oracle, reqs, log):
+    """e_amp of a seeded tenth of the served requests against the oracle,
+    slice-subsampled: each sampled request runs once more through
+    rn_contract_network (FP32-4M, the kernels the server runs) with its
+    per-slice values returned, and one slice (seeded choice) is compared with
+    the oracle's projection of that slice.  A request whose slices cost more
+    than --oracle-slice-flops is sliced deeper for the check (more bonds,
+    chosen by the same greedy slicer) on both sides, and says so.  Error:
+    |a - a_ref| / max(|a_ref|, 2^-(n+S)/2), n sites, S sliced bonds."""
+    from workloads import paths
+    ctx = rn.Context(0)
+    rs = np.random.default_rng(5150)
+    pick = sorted(rs.choice(len(reqs), size=max(1, len(reqs) // 10), replace=False).tolist())
+    rows = []
+    t_or = 0.0
+    for i in pick:
+        w = reqs[i]
+        lab, path = w.network.labels, w.path
+        sliced = list(w.sliced)
+        mr, fl, _ = paths.path_stats(lab, path, sliced)
+        deeper = 0
+        while fl > args.oracle_slice_flops and len(sliced) < 14:
+            more = paths.greedy_slices(lab, path, 77 + i, n_slices=len(sliced) + 1)
+            extra = [x for x in more if x not in sliced]
+            if not extra:
+                break
+            sliced.append(extra[0])
+            deeper += 1
+            mr, fl, _ = paths.path_stats(lab, path, sliced)
+        S = len(sliced)
+        ts = [torch.from_numpy(np.ascontiguousarray(t.reshape(-1))).to(torch.complex64).cuda()
+              for t in w.network.tensors]
+        sl = torch.zeros(2 << S, dtype=torch.float64, device="cuda")
+        ctx.contract_network(ts, lab, path, sliced, "fp32_4m", slices=sl)
+        torch.cuda.synchronize()
+        got = sl.cpu().numpy().view(np.complex128)
+        s = int(rs.integers(0, 1 << S))
+        t = time.perf_counter()
+        ref = oracle.contract_network_slices(w.network.tensors, lab, path, sliced, [s])[0]
+        t_or += time.perf_counter() - t
+        n = w.meta["sites"]
+        err = abs(got[s] - ref) / max(abs(ref), 2.0 ** (-(n + S) / 2))
+        rows.append({"request": i, "sites": n, "cycles": w.meta["cycles"],
+                     "sliced_served": len(w.sliced), "sliced_for_check": S,
+                     "extra_sliced_for_check": deeper, "slice": s,
+                     "flops_per_slice_checked": fl, "e_amp": float(err)})
+        log(f"serving oracle check: request {i} ({n} sites, {S} sliced, +{deeper} for the "
+            f"check) slice {s}: e_amp {err:.2e}")
+        del ts, sl
+    ctx.close()
+    errs = [r["e_amp"] for r in rows]
+    return {"sampled": len(rows), "of_requests": len(reqs), "mode": "fp32_4m",
+            "tolerance": 1e-5, "max_e_amp": float(max(errs)),
+            "median_e_amp": float(np.median(errs)), "oracle_seconds": t_or,
+            "how": "one seeded slice per sampled request, GPU per-slice value vs the oracle's "
+                   "projection of that slice; requests above the per-slice flop cap sliced "
+                   "deeper for the check on both sides",
+            "rows": rows}
 
 
 def run_weak_share(args, torch, rn, log):
@@ -324,6 +431,114 @@ def run_weak_share(args, torch, rn, log):
     return results
 
 
+def host_info():
+    """CPU model and core counts of the host (for the CPU-baseline figures)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cores": aff}
+
+
+def network_roofline(labels, path, sliced, es, peak_tflops):
+    """Useful flops, algorithmic bytes and roofline time of a sliced network
+    as the library runs it: every step runs once per value combination of the
+    sliced bonds its operands depend on (slice-independent parts once), on
+    operands with the sliced labels projected out; per step
+    F = 8 * 2^|labels(a) | labels(b)| and B = es * (|a| + |b| + |out|), and
+    the roofline time is the sum over steps of max(F / peak, B / HBM)."""
+    sl = set(sliced)
+    live = [frozenset(l) - sl for l in labels]
+    deps = [frozenset(l) & sl for l in labels]
+    F = B = T = 0.0
+    for a, b in path:
+        la, lb = live[a], live[b]
+        out = la ^ lb
+        d = deps[a] | deps[b]
+        mult = float(1 << len(d))
+        f = 8.0 * (1 << len(la | lb)) * mult
+        by = es * float((1 << len(la)) + (1 << len(lb)) + (1 << len(out))) * mult
+        F += f
+        B += by
+        T += max(f / (peak_tflops * 1e12), by / (HBM_PEAK * 1e9))
+        live.append(out)
+        deps.append(d)
+    return F, B, T
+
+
+def run_config1(ctx, torch, oracle, parity, reps, log):
+    """Workload 1 (rank-16 x rank-16 complex, 8 contracted axes, first three
+    axes of each operand split in two: 64 coupled block pairs of 32 x 256 x
+    32): latency per call (plan + relayouts + GEMM, HIP-event and host-wall
+    time over `reps` calls after 3 warm-ups, synchronised each call) and the
+    error against the oracle, in every mode."""
+    from workloads import configs
+    p = configs.config1()
+    t = time.perf_counter()
+    ref, _, _ = oracle.block_tensordot(p.a.data, p.a.dims, p.a.grid, p.b.data, p.b.dims,
+                                       p.b.grid, p.axes_a, p.axes_b)
+    t_single = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    t = time.perf_counter()
+    ref_omp, _, _ = oracle.block_tensordot(p.a.data, p.a.dims, p.a.grid, p.b.data, p.b.dims,
+                                           p.b.grid, p.axes_a, p.axes_b, openmp=True)
+    t_omp = time.perf_counter() - t
+    absprod = parity.abs_product_blocked(p)
+    K = 2 ** p.k
+    flops = 8.0 * 2 ** 24
+    out = {"workload": "rank-16 x rank-16 complex, A's last 8 axes with B's first 8 in seeded "
+                       "order, first three axes of each operand split in two (64 block pairs "
+                       "of 32 x 256 x 32); one call = plan + relayouts + fused-pair GEMM",
+           "useful_flops": flops, "reps": reps}
+    for mode in ("fp64", "fp32_4m", "fp32_3m", "bf16x3"):
+        dt = torch.complex128 if mode == "fp64" else torch.complex64
+        a = torch.from_numpy(p.a.data).to(dt).cuda()
+        b = torch.from_numpy(p.b.data).to(dt).cuda()
+        cd, cg, ws, _ = ctx.plan_block_tensordot(p.a.dims, p.a.grid, p.b.dims, p.b.grid,
+                                                 p.axes_a, p.axes_b, mode)
+        c = torch.empty(2 ** 16, dtype=dt, device="cuda")
+        wsb = torch.empty(max(ws, 1), dtype=torch.uint8, device="cuda")
+        host, ev = [], []
+        for it in range(3 + reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            e0.record()
+            ctx.block_tensordot(a, p.a.dims, p.a.grid, b, p.b.dims, p.b.grid, p.axes_a,
+                                p.axes_b, mode, out=c, workspace=wsb)
+            e1.record()
+            torch.cuda.synchronize()
+            if it >= 3:
+                host.append(1e6 * (time.perf_counter() - t))
+                ev.append(1e3 * e0.elapsed_time(e1))
+        r = parity.report(c.cpu().numpy().astype(np.complex128), ref, absprod, K, mode)
+        out[mode] = {"p50_us_host": percentile(host, 50), "p10_us_host": percentile(host, 10),
+                     "p90_us_host": percentile(host, 90), "p50_us_gpu_events": percentile(ev, 50),
+                     "e_F": r["e_F"], "e_max": r["e_max"], "higham_max": r["higham"],
+                     "higham_bound": r["higham_bound"], "tolerance": parity.TOL[mode]}
+        log(f"config1 {mode}: p50 {out[mode]['p50_us_host']:.1f} us host, "
+            f"{out[mode]['p50_us_gpu_events']:.1f} us events, e_F {r['e_F']:.2e}")
+        del a, b, c, wsb
+    out["oracle"] = {"single_thread_s": t_single,
+                     "single_thread_gflops": flops / t_single / 1e9,
+                     "openmp_s": t_omp, "openmp_threads": min(threads, 8),
+                     "openmp_gflops": flops / t_omp / 1e9,
+                     "openmp_note": "output blocks on threads; workload 1 has 8 output blocks, "
+                                    "so at most 8 threads have work",
+                     "openmp_identical_to_single_thread": bool(np.array_equal(ref, ref_omp))}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,13 +550,19 @@ def main() -> int:
     ap.add_argument("--k", type=int, default=14)
     ap.add_argument("--amp-requests", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sample-blocks", type=int, default=40,
+                    help="64 x 64 blocks of C the oracle computes for the CPU baseline")
+    ap.add_argument("--config1-reps", type=int, default=30)
     ap.add_argument("--no-side", action="store_true")
     ap.add_argument("--no-batch", dest="batch", action="store_false")
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=4,
                     help="requests the server runs concurrently (1-16)")
-    ap.add_argument("--serve-load", type=float, default=0.75,
-                    help="Poisson arrival rate as a fraction of the saturated throughput")
+    ap.add_argument("--serve-loads", type=lambda x: [float(v) for v in x.split(",") if v],
+                    default=[0.25, 0.5, 0.75, 1.0],
+                    help="Poisson arrival rates as fractions of the saturated throughput")
+    ap.add_argument("--oracle-slice-flops", type=float, default=3e9,
+                    help="largest per-slice cost the serving oracle check contracts")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one plain 1 GiB copy kernel first (HBM counter calibration)")
     ap.add_argument("--weak", action="store_true",
@@ -368,6 +589,8 @@ def main() -> int:
     import oracle
     import paper_2201_06620_amd as rn
     from workloads import configs
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import parity  # element-wise error bounds (test infrastructure, CPU side)
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -388,10 +611,10 @@ def main() -> int:
     K = 2 ** args.k
     flops = 8.0 * M * N * K
 
-    # Sampled outputs: four 64 x 64 blocks of C viewed as M x N (row-major C).
+    # Sampled outputs: --sample-blocks 64 x 64 blocks of C viewed as M x N (row-major C).
     rs = np.random.default_rng(2201)
     sample = []
-    for _ in range(4):
+    for _ in range(args.sample_blocks):
         r0 = int(rs.integers(0, M // 64)) * 64
         c0 = int(rs.integers(0, N // 64)) * 64
         rr, cc = np.meshgrid(np.arange(r0, r0 + 64), np.arange(c0, c0 + 64), indexing="ij")
@@ -471,6 +694,7 @@ def main() -> int:
     # ------------------------------------------------ oracle on the sample
     cpu = None
     ref = None
+    absprod = None
     if not args.no_cpu_baseline:
         A = p.a.data.reshape(dims)
         B = p.b.data.reshape(dims)
@@ -478,18 +702,33 @@ def main() -> int:
         t = time.perf_counter()
         ref = oracle.tensordot_entries(A, B, p.axes_a, p.axes_b, sample)
         el = time.perf_counter() - t
+        hi = host_info()
         cpu = {"value": 8.0 * K * sample.size / el / 1e12, "unit": "TFLOP/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"{sample.size} output entries (four 64x64 blocks of C) of the same "
-                         f"rank-{args.rank} contraction, each a {K}-term complex128 sum; "
-                         f"{el:.1f} s"}
-        log(f"  {el:.1f}s -> {cpu['value'] * 1e3:.4f} GFLOP/s")
+               "sample": f"{sample.size} output entries ({args.sample_blocks} 64x64 blocks of C) "
+                         f"of the same rank-{args.rank} contraction, each a {K}-term complex128 "
+                         f"sum; {el:.1f} s",
+               "cpu_model": hi["cpu_model"], "nproc": hi["nproc"],
+               "affinity_cores": hi["affinity_cores"],
+               "extrapolated_full_contraction_s": el / sample.size * M * N,
+               "extrapolation_note": "seconds per sampled entry times all M*N entries, one "
+                                     "thread (an extrapolation, not a run)"}
+        log(f"  {el:.1f}s -> {cpu['value'] * 1e3:.4f} GFLOP/s; full contraction extrapolated "
+            f"to {cpu['extrapolated_full_contraction_s'] / 3600:.1f} h")
+        absprod = parity.abs_product_entries(A, B, p.axes_a, p.axes_b, sample)
 
     errors = {}
     if ref is not None:
         for mode, g in gots.items():
-            errors[mode] = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
-        log(f"sampled e_F vs oracle: {errors}")
+            pm = "fp64" if mode.startswith("fp64") else mode
+            r = parity.report(g, ref, absprod, K, pm)
+            errors[mode] = {"e_F": r["e_F"], "e_max": r["e_max"], "higham_max": r["higham"],
+                            "higham_bound": r["higham_bound"],
+                            "entries_over_bound": r["over_bound"]}
+        log(f"sampled errors vs oracle: {errors}")
+    config1 = None
+    if not args.no_cpu_baseline and args.config1_reps > 0:
+        config1 = run_config1(ctx, torch, oracle, parity, args.config1_reps, log)
 
     # ------------------------------------------- amplitude latency (16 slices)
     amp = None
@@ -529,12 +768,39 @@ def main() -> int:
         ctx.set_option("slice_sum", 0)
         from workloads import paths as _paths
         _, unsliced, _ = _paths.path_stats(w.network.labels, w.path)
+        # Roofline of the batched-slice runs: each step at max(F / peak,
+        # B / HBM), the steps back to back.
+        for key in ("fp64", "fp32_4m"):
+            es, peak = (16, FP64_PEAK) if key == "fp64" else (8, FP32_PEAK)
+            F, B, T = network_roofline(w.network.labels, w.path, w.sliced, es, peak)
+            lat[key].update({"model_flops": F, "model_bytes": B, "roofline_time_ms": 1e3 * T,
+                             "roofline_frac_of_p50": 1e3 * T / lat[key]["p50_ms"]})
+        if not args.no_cpu_baseline:
+            t = time.perf_counter()
+            ref_amp = complex(oracle.contract_network(w.network.tensors, w.network.labels,
+                                                      w.path, w.sliced)[0])
+            t_net = time.perf_counter() - t
+            t = time.perf_counter()
+            psi = oracle.statevector(w.circuit)
+            t_sv = time.perf_counter() - t
+            sv = complex(psi[int("".join(map(str, w.bitstring)), 2)])
+            floor = 2.0 ** (-w.circuit.n / 2)
+            for key, v in lat.items():
+                a_ = complex(*v["amplitude"])
+                v["e_amp_vs_oracle"] = abs(a_ - ref_amp) / max(abs(ref_amp), floor)
+                v["e_amp_vs_statevector"] = abs(a_ - sv) / max(abs(sv), floor)
+                v["tolerance"] = 1e-12 if key.startswith("fp64") else 1e-5
+            lat["oracle"] = {"network_s": t_net, "statevector_s": t_sv,
+                             "amplitude": [ref_amp.real, ref_amp.imag],
+                             "statevector_amplitude": [sv.real, sv.imag],
+                             "oracle_vs_statevector": abs(ref_amp - sv) / max(abs(sv), floor)}
         amp = {"workload": "one amplitude of a 20-qubit random circuit (4x5 grid, 12 cycles), "
                            "greedy path, 4 sliced bonds = 16 slices batched, FP64 slice sum; "
                            "one request at a time.  *_slice_sum: each sliced bond summed in "
                            "the step that contracts it (slices as blocks)", **lat,
                "flops": {"independent_slices": w.meta["flops_per_slice"] * (1 << len(w.sliced)),
                          "batched_broadcast": lat["fp64"]["flops_per_amplitude"],
+                         "batched_broadcast_model": lat["fp64"]["model_flops"],
                          "slice_sum": lat["fp64_slice_sum"]["flops_per_amplitude"],
                          "unsliced_same_path": unsliced}}
         log(f"amplitude latency: {amp}")
@@ -631,18 +897,20 @@ def main() -> int:
     # ------------------------------- serving: Poisson stream of requests
     serving = None
     if args.serve_requests > 0:
-        serving = run_serving(args, torch, rn, log)
+        serving, reqs = run_serving(args, torch, rn, log)
+        if not args.no_cpu_baseline:
+            serving["oracle_check"] = serving_oracle_sample(args, torch, rn, oracle, reqs, log)
 
     k = main_res["kernels"]
     gemm_ms = k["gemm"][0] / max(k["gemm"][1], 1)
     achieved = flops / (gemm_ms * 1e-3) / 1e12
     traffic = traffic_from_profiles("cgemm_f32_4m", 1)
     modes = {"fp32_4m": {"tflops": main_res["tflops"], "ms_per_step": main_res["ms_per_step"],
-                         "e_F_sampled": errors.get("fp32_4m"), "tolerance": 1e-5,
+                         "errors_sampled": errors.get("fp32_4m"), "tolerance": 1e-5,
                          "frac_of_fp32_peak": main_res["tflops"] / FP32_PEAK}}
     for mode, r in side.items():
         modes[mode] = {"tflops": r["tflops"], "ms_per_step": r["ms_per_step"],
-                       "e_F_sampled": errors.get(mode),
+                       "errors_sampled": errors.get(mode),
                        "tolerance": {"fp64": 1e-12, "fp64_gauss": 1e-12,
                                      "fp32_3m": 1e-5}.get(mode, 1e-3)}
     if "fp64" in side:
@@ -683,6 +951,7 @@ def main() -> int:
                      "kernel_ms": gemm_ms},
         "cpu_baseline": cpu,
         "modes": modes,
+        "config1": config1,
         "amplitude_latency": amp,
         "batch": batch,
         "serving": serving,
