@@ -144,41 +144,49 @@ def run_serving(args, torch, rn, log):
     thr = len(reqs) / sat_s
     log(f"serving: saturated {thr:.1f} amplitudes/s ({sat_s:.2f} s for {len(reqs)})")
     classes = _size_classes(flops)
-    sweep = []
-    for li, load in enumerate(args.serve_loads):
-        lam = load * thr
-        gaps = np.random.default_rng(2201 + li).exponential(1.0 / lam, size=len(reqs))
-        tk2 = [None] * len(reqs)
 
-        def client():
-            for i, g in enumerate(gaps):
-                time.sleep(float(g))
-                tk2[i] = submit(i)
+    def sweep_loads(loads, tag):
+        out = []
+        for li, load in enumerate(loads):
+            lam = load * thr
+            gaps = np.random.default_rng(2201 + li).exponential(1.0 / lam, size=len(reqs))
+            tk2 = [None] * len(reqs)
 
-        t = time.perf_counter()
-        th = threading.Thread(target=client)
-        th.start()
-        th.join()
-        res = [srv.wait(tk) for tk in tk2]
-        el = time.perf_counter() - t
-        lat = [1e3 * r["latency_s"] for r in res]
-        same = sum(1 for a, b in zip(sat, res) if a["amp"] == b["amp"] and a["status"] == 0)
-        entry = {"load": load, "arrival_rate_per_s": lam, "p50_ms": percentile(lat, 50),
-                 "p99_ms": percentile(lat, 99), "amplitudes_per_s": len(reqs) / el,
-                 "mean_queue_ms": 1e3 * float(np.mean([r["queue_s"] for r in res])),
-                 "mean_run_ms": 1e3 * float(np.mean([r["run_s"] for r in res])),
-                 "by_size_third": {k: _latency_summary(res, v) for k, v in classes.items()},
-                 "identical_to_saturated_run": same,
-                 "statuses": sorted(set(r["status"] for r in res))}
-        # Achieved rate of the largest tenth of the requests while they ran
-        # (each request's flops over its own running time; other requests may
-        # have shared the GPU meanwhile).
-        top = np.argsort(flops)[-max(1, len(reqs) // 10):]
-        entry["largest_tenth_tflops_while_running"] = float(
-            sum(flops[i] for i in top) / sum(res[i]["run_s"] for i in top) / 1e12)
-        log(f"serving load {load}: p50 {entry['p50_ms']:.1f} ms, p99 {entry['p99_ms']:.1f} ms, "
-            f"{entry['amplitudes_per_s']:.1f}/s")
-        sweep.append(entry)
+            def client():
+                for i, g in enumerate(gaps):
+                    time.sleep(float(g))
+                    tk2[i] = submit(i)
+
+            t = time.perf_counter()
+            th = threading.Thread(target=client)
+            th.start()
+            th.join()
+            res = [srv.wait(tk) for tk in tk2]
+            el = time.perf_counter() - t
+            lat = [1e3 * r["latency_s"] for r in res]
+            same = sum(1 for a, b in zip(sat, res) if a["amp"] == b["amp"] and a["status"] == 0)
+            entry = {"load": load, "arrival_rate_per_s": lam, "p50_ms": percentile(lat, 50),
+                     "p99_ms": percentile(lat, 99), "amplitudes_per_s": len(reqs) / el,
+                     "mean_queue_ms": 1e3 * float(np.mean([r["queue_s"] for r in res])),
+                     "mean_run_ms": 1e3 * float(np.mean([r["run_s"] for r in res])),
+                     "by_size_third": {k: _latency_summary(res, v) for k, v in classes.items()},
+                     "identical_to_saturated_run": same,
+                     "statuses": sorted(set(r["status"] for r in res))}
+            # Achieved rate of the largest tenth of the requests while they ran
+            # (each request's flops over its own running time; other requests
+            # may have shared the GPU meanwhile).
+            top = np.argsort(flops)[-max(1, len(reqs) // 10):]
+            entry["largest_tenth_tflops_while_running"] = float(
+                sum(flops[i] for i in top) / sum(res[i]["run_s"] for i in top) / 1e12)
+            log(f"serving {tag} load {load}: p50 {entry['p50_ms']:.1f} ms, "
+                f"p99 {entry['p99_ms']:.1f} ms, {entry['amplitudes_per_s']:.1f}/s")
+            out.append(entry)
+        return out
+
+    sweep = sweep_loads(args.serve_loads, "smallest-first")
+    srv.set_admission("fifo")
+    sweep_fifo = sweep_loads([x for x in args.serve_loads if x >= 0.75], "arrival-order")
+    srv.set_admission("smallest")
     srv.close()
     hist_sites = {}
     hist_slices = {}
@@ -191,7 +199,9 @@ def run_serving(args, torch, rn, log):
                        "intermediate rank <= 30, complex64 FP32-4M with FP64 slice sums; "
                        f"HBM-footprint admission, {args.serve_slots} concurrent slots",
            "requests": len(reqs), "saturated_amplitudes_per_s": thr,
-           "saturated_seconds": sat_s, "loads": sweep,
+           "saturated_seconds": sat_s, "admission": "smallest planned flops first, a request "
+                                                    "overtaken 8 times goes next",
+           "loads": sweep, "loads_arrival_order_admission": sweep_fifo,
            "total_flops": float(sum(flops)),
            "accepted_sites_x_cycles": dict(sorted(hist_sites.items())),
            "slices_per_request": dict(sorted(hist_slices.items(), key=lambda kv: int(kv[0]))),

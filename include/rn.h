@@ -316,10 +316,15 @@ rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
  * (HIP streams, 1..16).  rn_server_submit copies a request -- a network as
  * for rn_contract_network but with HOST tensor data -- into the server's
  * queue and returns a ticket; it never blocks on the GPU.  A worker thread
- * admits queued requests in arrival order whenever a slot is free and the
- * request's footprint (its tensors + the planned workspace + 256 bytes)
- * fits the free arena; admitted requests run concurrently on their slots
- * and keep their tensors resident until they finish.  A request whose
+ * admits queued requests whenever a slot is free and the request's footprint
+ * (its tensors + the planned workspace + 256 bytes) fits the free arena;
+ * admitted requests run concurrently on their slots and keep their tensors
+ * resident until they finish.  Admission order (rn_server_set_admission):
+ * policy 0 admits in arrival order (the head waits for memory and blocks the
+ * rest); policy 1, the default, admits the request with the fewest planned
+ * flops first, except that a request overtaken max_overtakes times (default
+ * 8) by later arrivals goes next, and while it does not fit the free memory
+ * nothing else is admitted, so no request waits forever.  A request whose
  * footprint exceeds the whole budget completes with status RN_ERR_OOM.
  * Results: amplitude, latency = completion - submit, and its split into
  * queueing and running time.  A request's amplitude does not depend on what
@@ -334,12 +339,15 @@ typedef struct {
   double run_s;           /* completion - admission */
   double footprint_bytes; /* arena bytes the request held */
   int32_t status;         /* RN_OK, RN_ERR_OOM, or the error of the enqueue */
+  double start_s;         /* admission time, seconds since rn_server_create */
+  double done_s;          /* completion time, seconds since rn_server_create */
 } rn_result;
 rn_status rn_server_create(int device, size_t hbm_budget, int32_t max_active, rn_server_t* srv);
 rn_status rn_server_submit(rn_server_t srv, int32_t nt, const rn_tensor* T,
                            const int32_t* const* labels, int32_t nsteps, const int32_t* path,
                            int32_t nsliced, const int32_t* sliced, rn_mode mode,
                            uint64_t* ticket);
+rn_status rn_server_set_admission(rn_server_t srv, int32_t policy, int32_t max_overtakes);
 rn_status rn_server_poll(rn_server_t srv, uint64_t ticket, int32_t* done, rn_result* res);
 rn_status rn_server_wait(rn_server_t srv, uint64_t ticket, rn_result* res);
 rn_status rn_server_stats(rn_server_t srv, int64_t* queued, int64_t* active, int64_t* completed,

@@ -34,7 +34,7 @@ EXPORTS = ["rn_create", "rn_destroy", "rn_status_str", "rn_last_error",
            "rn_server_submit", "rn_server_poll", "rn_server_wait", "rn_server_stats",
            "rn_server_destroy", "rn_set_option", "rn_get_option",
            "rn_block_tensordot_streamed_plan", "rn_block_tensordot_streamed",
-           "rn_block_tensordot_noalloc"]
+           "rn_block_tensordot_noalloc", "rn_server_set_admission"]
 
 # Handle options (rn_option).
 OPTIONS = {"graphs": 0, "pair_split_threshold": 1, "split_footprint": 2, "slice_sum": 3,
@@ -50,7 +50,8 @@ class RnError(RuntimeError):
 class RnResult(ctypes.Structure):
     _fields_ = [("amp", ctypes.c_double * 2), ("latency_s", ctypes.c_double),
                 ("queue_s", ctypes.c_double), ("run_s", ctypes.c_double),
-                ("footprint_bytes", ctypes.c_double), ("status", ctypes.c_int32)]
+                ("footprint_bytes", ctypes.c_double), ("status", ctypes.c_int32),
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
 
 
 class RnTensor(ctypes.Structure):
@@ -117,6 +118,7 @@ def lib():
         L.rn_server_create.argtypes = [ctypes.c_int, sz, i32, ctypes.POINTER(p)]
         L.rn_server_submit.argtypes = [p, i32, T, pp, i32, p, i32, p, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_uint64)]
+        L.rn_server_set_admission.argtypes = [p, i32, i32]
         L.rn_server_poll.argtypes = [p, ctypes.c_uint64, ctypes.POINTER(i32),
                                      ctypes.POINTER(RnResult)]
         L.rn_server_wait.argtypes = [p, ctypes.c_uint64, ctypes.POINTER(RnResult)]
@@ -612,7 +614,13 @@ class Server:
     def _res(r):
         return {"amp": complex(r.amp[0], r.amp[1]), "latency_s": r.latency_s,
                 "queue_s": r.queue_s, "run_s": r.run_s, "footprint": r.footprint_bytes,
-                "status": r.status}
+                "status": r.status, "start_s": r.start_s, "done_s": r.done_s}
+
+    def set_admission(self, policy: str = "smallest", max_overtakes: int = 8) -> None:
+        """Admission order: "fifo" (arrival order) or "smallest" (fewest
+        planned flops first, a request overtaken max_overtakes times next)."""
+        check(lib().rn_server_set_admission(self.s, {"fifo": 0, "smallest": 1}[policy],
+                                            int(max_overtakes)), "set_admission")
 
     def poll(self, ticket):
         d = ctypes.c_int32()

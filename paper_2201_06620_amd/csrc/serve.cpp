@@ -1,10 +1,13 @@
 // Amplitude server: continuous admission of sliced-network requests.
 //
 // Requests (a tensor network, its path and sliced bonds; Sections II.A-II.B)
-// are queued by rn_server_submit.  A worker thread admits them in arrival
-// order whenever a slot (a HIP stream) is free and the request's footprint
-// -- its tensors plus the network workspace the planner reports -- fits the
-// HBM budget; admitted requests copy their tensors into a device arena,
+// are queued by rn_server_submit.  A worker thread admits them whenever a
+// slot (a HIP stream) is free and the request's footprint -- its tensors plus
+// the network workspace the planner reports -- fits the HBM budget, either
+// in arrival order or smallest first (planned flops) with an aging bound: a
+// request overtaken max_overtakes times goes next, and while it does not fit
+// the free memory nothing else is admitted.  Admitted requests copy their
+// tensors into a device arena,
 // where they stay until the request completes, and run concurrently on
 // their slot streams, so a request arriving while others are on the GPU
 // starts as soon as memory and a slot free up.  Completion is detected with
@@ -12,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -71,6 +75,8 @@ struct Request {
   std::vector<std::vector<int32_t>> labels;
   std::vector<int32_t> path, sliced;
   size_t ws_bytes = 0, tensor_bytes = 0, footprint = 0;
+  double flops = 0;    // planned useful flops (admission order)
+  int overtaken = 0;   // later requests admitted before this one
   NetOpts opts;  // batched-slice count fitted to the budget at submission
   std::shared_ptr<void> plan;  // made at submission, run by the worker
   Clock::time_point t_submit, t_start, t_done;
@@ -99,6 +105,9 @@ struct rn_server {
   std::map<uint64_t, rn_result> results;
   uint64_t next_ticket = 1;
   int64_t completed = 0;
+  int policy = 1;           // 0 arrival order, 1 smallest first with aging
+  int max_overtakes = 8;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   bool stop = false;
   std::thread worker;
 };
@@ -120,6 +129,8 @@ void finish(rn_server* S, Request* r, int32_t status, const double amp[2]) {
   res.queue_s = status == RN_OK ? sec(r->t_start - r->t_submit) : 0.0;
   res.run_s = status == RN_OK ? sec(r->t_done - r->t_start) : 0.0;
   res.footprint_bytes = (double)r->footprint;
+  res.start_s = status == RN_OK ? sec(r->t_start - S->t0) : 0.0;
+  res.done_s = sec(r->t_done - S->t0);
   S->results[r->ticket] = res;
   if (r->done_ev) hipEventDestroy(r->done_ev);
   delete r;
@@ -182,25 +193,60 @@ void worker_loop(rn_server* S) {
         ++i;
       }
     }
-    // Admit in arrival order while a slot and memory are free.
-    while (!S->queue.empty()) {
-      Request* r = S->queue.front();
-      if (r->footprint > S->budget) {
-        S->queue.pop_front();
-        r->t_done = Clock::now();
-        finish(S, r, RN_ERR_OOM, nullptr);
-        progress = true;
-        continue;
+    // Admit while a slot and memory are free.
+    for (;;) {
+      // Requests that can never fit the budget complete with RN_ERR_OOM.
+      for (size_t qi = 0; qi < S->queue.size();) {
+        Request* r = S->queue[qi];
+        if (r->footprint > S->budget) {
+          S->queue.erase(S->queue.begin() + qi);
+          r->t_done = Clock::now();
+          finish(S, r, RN_ERR_OOM, nullptr);
+          progress = true;
+        } else {
+          ++qi;
+        }
       }
+      if (S->queue.empty()) break;
       int slot = -1;
       for (int q = 0; q < (int)S->slot_busy.size(); ++q)
         if (!S->slot_busy[q]) {
           slot = q;
           break;
         }
-      size_t off = 0;
-      if (slot < 0 || !S->free.alloc(r->footprint, &off)) break;
-      S->queue.pop_front();
+      if (slot < 0) break;
+      // Candidates in admission order: arrival order; or an aged request
+      // first, then smallest planned flops (ties: arrival).
+      std::vector<size_t> cand(S->queue.size());
+      for (size_t qi = 0; qi < cand.size(); ++qi) cand[qi] = qi;
+      if (S->policy == 1) {
+        std::stable_sort(cand.begin(), cand.end(), [&](size_t a, size_t b) {
+          const Request* ra = S->queue[a];
+          const Request* rb = S->queue[b];
+          const bool aa = ra->overtaken >= S->max_overtakes;
+          const bool ab = rb->overtaken >= S->max_overtakes;
+          if (aa != ab) return aa;
+          if (aa) return ra->ticket < rb->ticket;
+          if (ra->flops != rb->flops) return ra->flops < rb->flops;
+          return ra->ticket < rb->ticket;
+        });
+      }
+      size_t pick = SIZE_MAX, off = 0;
+      for (size_t c : cand) {
+        Request* r = S->queue[c];
+        if (S->free.alloc(r->footprint, &off)) {
+          pick = c;
+          break;
+        }
+        // Arrival order, or an aged request: wait for memory, admit nothing
+        // past it.
+        if (S->policy == 0 || r->overtaken >= S->max_overtakes) break;
+      }
+      if (pick == SIZE_MAX) break;
+      Request* r = S->queue[pick];
+      for (Request* q : S->queue)
+        if (q->ticket < r->ticket) ++q->overtaken;
+      S->queue.erase(S->queue.begin() + pick);
       r->arena_off = off;
       r->slot = slot;
       r->t_start = Clock::now();
@@ -329,6 +375,7 @@ rn_status rn_server_submit(rn_server_t S, int32_t nt, const rn_tensor* T,
   r->path.assign(path, path + 2 * nsteps);
   r->sliced.assign(sliced, sliced + nsliced);
   r->ws_bytes = ws;
+  r->flops = flops;
   r->footprint = r->tensor_bytes + 256 + al256(ws);
   r->t_submit = t0;
   {
@@ -338,6 +385,16 @@ rn_status rn_server_submit(rn_server_t S, int32_t nt, const rn_tensor* T,
     S->queue.push_back(r);
   }
   S->cv.notify_all();
+  return RN_OK;
+}
+
+rn_status rn_server_set_admission(rn_server_t S, int32_t policy, int32_t max_overtakes) {
+  if (!S) return fail(RN_ERR_INVALID, "null server");
+  if (policy < 0 || policy > 1 || max_overtakes < 0)
+    return fail(RN_ERR_INVALID, "policy is 0 or 1, max_overtakes >= 0");
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->policy = policy;
+  S->max_overtakes = max_overtakes;
   return RN_OK;
 }
 

@@ -66,12 +66,33 @@ def test_server_results_match_oracle(requests_, oracle_amps, mode):
     srv.close()
 
 
+def overlapping_pairs(results):
+    """Pairs of requests whose running intervals [start, done] overlap."""
+    n = 0
+    for i in range(len(results)):
+        for j in range(i + 1, len(results)):
+            a, b = results[i], results[j]
+            if a["start_s"] < b["done_s"] and b["start_s"] < a["done_s"]:
+                n += 1
+    return n
+
+
 def test_alone_equals_in_mix(requests_):
     import paper_2201_06620_amd as rn
     srv = rn.Server(0, hbm_budget=1 << 30, max_active=4)
     alone = []
     for w in requests_:
         alone.append(srv.wait(submit(srv, w, "fp32_4m"))["amp"])
+    # A burst: every request queued at once, so up to four run at the same
+    # time on their slots; the run intervals must overlap, and every
+    # amplitude must be the same bits as alone.
+    tk = [submit(srv, w, "fp32_4m") for w in requests_]
+    burst = [srv.wait(t) for t in tk]
+    pairs = overlapping_pairs(burst)
+    log(f"  burst: {pairs} overlapping pairs of running requests")
+    assert pairs > 0
+    for i, r in enumerate(burst):
+        assert r["status"] == 0 and r["amp"] == alone[i], i
     # The same requests again, arriving as a Poisson stream from another
     # thread while earlier ones are still on the GPU, in a shuffled order.
     order = rng.SplitMix64(5).permutation(len(requests_))
@@ -91,6 +112,37 @@ def test_alone_equals_in_mix(requests_):
         assert res["status"] == 0
         assert res["amp"] == alone[i], i
     srv.close()
+
+
+@pytest.mark.parametrize("policy", ["fifo", "smallest", "aged"])
+def test_admission_order(policy):
+    # One slot: a large request runs first; a big and a small one arrive
+    # while it runs.  Arrival order admits the big one next; smallest-first
+    # admits the small one first; with max_overtakes = 0 every waiting
+    # request counts as aged, which is arrival order again.
+    import paper_2201_06620_amd as rn
+    blocker = configs.config5_request(0, 16)              # ~1.4e13 flops
+    big = configs.circuit_workload(5, 6, 10, 9191, max_rank=24, restarts=1)
+    small = configs.circuit_workload(2, 3, 4, 9192, restarts=1)
+    srv = rn.Server(0, hbm_budget=16 << 30, max_active=1)
+    if policy == "fifo":
+        srv.set_admission("fifo")
+    elif policy == "aged":
+        srv.set_admission("smallest", 0)
+    t0 = submit(srv, blocker, "fp32_4m")
+    t1 = submit(srv, big, "fp32_4m")
+    t2 = submit(srv, small, "fp32_4m")
+    r0, r1, r2 = srv.wait(t0), srv.wait(t1), srv.wait(t2)
+    srv.close()
+    assert r0["status"] == r1["status"] == r2["status"] == 0
+    sub1, sub2 = r1["start_s"] - r1["queue_s"], r2["start_s"] - r2["queue_s"]
+    log(f"  {policy}: blocker done {r0['done_s']:.4f}s, big submitted {sub1:.4f}s start "
+        f"{r1['start_s']:.4f}s, small submitted {sub2:.4f}s start {r2['start_s']:.4f}s")
+    assert max(sub1, sub2) < r0["done_s"], "both arrived while the blocker ran"
+    if policy == "smallest":
+        assert r2["start_s"] < r1["start_s"]
+    else:
+        assert r1["start_s"] < r2["start_s"]
 
 
 def test_request_over_budget_is_rejected():
