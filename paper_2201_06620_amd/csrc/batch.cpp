@@ -25,10 +25,21 @@ namespace rn {
 const std::string& last_error();
 
 uint64_t hash_bytes(uint64_t h, const void* p, size_t n) {
+  // Eight bytes per round (xor, multiply by an odd constant, xor-shift: each
+  // round is a bijection of h), then FNV-1a over the tail bytes.  Keys of
+  // network calls span tens of kilobytes, so a byte-wise loop would cost
+  // tens of microseconds per call.
   const unsigned char* b = static_cast<const unsigned char*>(p);
-  for (size_t i = 0; i < n; ++i) {
+  size_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+    uint64_t w;
+    memcpy(&w, b + i, 8);
+    h = (h ^ w) * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+  }
+  for (; i < n; ++i) {
     h ^= b[i];
-    h *= 1099511628211ull;  // FNV-1a
+    h *= 1099511628211ull;
   }
   return h;
 }
@@ -432,6 +443,7 @@ uint64_t hash_tensor(uint64_t x, const rn_tensor& t) {
 }
 
 static uint64_t g_tune_version = 0;
+uint64_t tune_version() { return g_tune_version; }
 
 }  // namespace rn
 

@@ -1035,33 +1035,24 @@ hipError_t launch_reduce_grouped(const GroupedLaunch& G, const void* table_dev, 
 // workgroup computes 256 consecutive outputs of one slice batch; the K-part
 // offsets of both operands are tabulated in LDS once per workgroup.  All
 // independent small steps of one dependency level of the path share one
-// launch.
+// launch, and so do subtrees of tiny steps, each run whole by one workgroup.
 // ===========================================================================
 static_assert(sizeof(DirectStep) % 4 == 0 && sizeof(DirectStep) <= 4 * 256,
               "step copied by one word per thread");
+static_assert(sizeof(TinyStep) % 4 == 0, "tiny steps copied by words");
 struct DirectTable {
   const DirectStep* steps;
+  const TinyStep* tiny;
+  const int32_t* maps;
+  const DirectJob* jobs;
   const int32_t* prefix;
-  int n;
+  int n;  // jobs
   int nout;
   int64_t pass;
 };
 
-template <int MODE>
-__global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
-  __shared__ int32_t koa[kDirectMaxK];
-  __shared__ int32_t kob[kDirectMaxK];
-  const int bid = blockIdx.x;
-  const int lo = find_job(g.prefix, g.n, bid);
-  // The step's bit maps are read per output; copy them into LDS once.
-  __shared__ __align__(16) uint32_t d_raw[sizeof(DirectStep) / 4];
-  if (threadIdx.x < sizeof(DirectStep) / 4)
-    d_raw[threadIdx.x] = reinterpret_cast<const uint32_t*>(&g.steps[lo])[threadIdx.x];
-  __syncthreads();
-  const DirectStep& d = *reinterpret_cast<const DirectStep*>(d_raw);
-  const int local = bid - g.prefix[lo];
-  const int b = local / d.blocks_per_batch;
-  const int64_t e = int64_t(local % d.blocks_per_batch) * 256 + threadIdx.x;
+// K-part offsets of both operands of step d, for k < K.
+__device__ __forceinline__ void direct_ktab(const DirectStep& d, int32_t* koa, int32_t* kob) {
   for (int k = threadIdx.x; k < d.K; k += 256) {
     int32_t oa = 0, ob = 0;
     for (int i = 0; i < d.kbits; ++i)
@@ -1072,54 +1063,61 @@ __global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
     koa[k] = oa;
     kob[k] = ob;
   }
-  __syncthreads();
-  if (e >= d.M * d.N) return;
-  const int64_t m = e >> d.nbits, n = e & (d.N - 1);
-  int64_t ao = 0, bo = 0;
-  for (int i = 0; i < d.nbb; ++i)
-    if ((b >> i) & 1) {
-      ao += d.a_bs[i];
-      bo += d.b_bs[i];
+}
+
+// The K terms of one output, in k order.  Eight operand pairs are loaded
+// before any is used (the loads are independent, so their memory latency is
+// paid once per eight terms, not per term); past K the index is clamped, so
+// the extra loads stay in bounds and their terms are skipped.
+template <typename T, typename F>
+__device__ __forceinline__ void direct_kloop(const T* A, const T* B, int K, const int32_t* koa,
+                                             const int32_t* kob, F&& term) {
+  constexpr int U = 8;
+  for (int k0 = 0; k0 < K; k0 += U) {
+    T a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = min(k0 + u, K - 1);
+      a[u] = A[koa[k]];
+      b[u] = B[kob[k]];
     }
-  for (int i = 0; i < g.nout; ++i)
-    if ((g.pass >> (g.nout - 1 - i)) & 1) {
-      if (d.a_pp[i]) ao += int64_t(1) << (d.a_pp[i] - 1);
-      if (d.b_pp[i]) bo += int64_t(1) << (d.b_pp[i] - 1);
-    }
-  for (int i = 0; i < d.mbits; ++i)
-    if ((m >> i) & 1) ao += int64_t(1) << d.am[i];
-  for (int i = 0; i < d.nbits; ++i)
-    if ((n >> i) & 1) bo += int64_t(1) << d.bn[i];
-  const int64_t co = int64_t(b) * d.M * d.N + e;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u < K) term(a[u], b[u]);
+  }
+}
+
+// C[co] = sum_k A[ao + koa[k]] * B[bo + kob[k]] in the mode's arithmetic.
+template <int MODE>
+__device__ __forceinline__ void direct_dot(const void* Av, const void* Bv, int64_t ao, int64_t bo,
+                                           int K, const int32_t* koa, const int32_t* kob,
+                                           void* C, int64_t co) {
   if constexpr (MODE == RN_FP64) {
-    const double2* A = reinterpret_cast<const double2*>(d.A) + ao;
-    const double2* B = reinterpret_cast<const double2*>(d.B) + bo;
+    const double2* A = reinterpret_cast<const double2*>(Av) + ao;
+    const double2* B = reinterpret_cast<const double2*>(Bv) + bo;
     double re = 0.0, im = 0.0;
-    for (int k = 0; k < d.K; ++k) {
-      double2 a = A[koa[k]], bb = B[kob[k]];
+    direct_kloop(A, B, K, koa, kob, [&](double2 a, double2 bb) {
       re = fma(a.x, bb.x, re);
       re = fma(-a.y, bb.y, re);
       im = fma(a.x, bb.y, im);
       im = fma(a.y, bb.x, im);
-    }
-    reinterpret_cast<double2*>(d.C)[co] = make_double2(re, im);
+    });
+    reinterpret_cast<double2*>(C)[co] = make_double2(re, im);
   } else {
-    const float2* A = reinterpret_cast<const float2*>(d.A) + ao;
-    const float2* B = reinterpret_cast<const float2*>(d.B) + bo;
+    const float2* A = reinterpret_cast<const float2*>(Av) + ao;
+    const float2* B = reinterpret_cast<const float2*>(Bv) + bo;
     float re = 0.f, im = 0.f;
     if constexpr (MODE == RN_FP32_3M) {
       float t1 = 0.f, t2 = 0.f, t3 = 0.f;
-      for (int k = 0; k < d.K; ++k) {
-        float2 a = A[koa[k]], bb = B[kob[k]];
+      direct_kloop(A, B, K, koa, kob, [&](float2 a, float2 bb) {
         t1 = fmaf(a.x, bb.x, t1);
         t2 = fmaf(a.y, bb.y, t2);
         t3 = fmaf(a.x + a.y, bb.x + bb.y, t3);
-      }
+      });
       re = t1 - t2;
       im = (t3 - t1) - t2;
     } else if constexpr (MODE == RN_BF16X3) {
-      for (int k = 0; k < d.K; ++k) {
-        float2 a = A[koa[k]], bb = B[kob[k]];
+      direct_kloop(A, B, K, koa, kob, [&](float2 a, float2 bb) {
         uint32_t h0, l0, h1, l1, h2, l2, h3, l3;
         bf16_split(a.x, h0, l0);
         bf16_split(a.y, h1, l1);
@@ -1135,17 +1133,110 @@ __global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
         im = fmaf(ahr, bli, im); im = fmaf(ahi, blr, im);
         re = fmaf(ahr, bhr, re); re = fmaf(-ahi, bhi, re);
         im = fmaf(ahr, bhi, im); im = fmaf(ahi, bhr, im);
-      }
+      });
     } else {
-      for (int k = 0; k < d.K; ++k) {
-        float2 a = A[koa[k]], bb = B[kob[k]];
+      direct_kloop(A, B, K, koa, kob, [&](float2 a, float2 bb) {
         re = fmaf(a.x, bb.x, re);
         re = fmaf(-a.y, bb.y, re);
         im = fmaf(a.x, bb.y, im);
         im = fmaf(a.y, bb.x, im);
-      }
+      });
     }
-    reinterpret_cast<float2*>(d.C)[co] = make_float2(re, im);
+    reinterpret_cast<float2*>(C)[co] = make_float2(re, im);
+  }
+}
+
+// Output e (< M*N) of slice batch b of step d.
+template <int MODE>
+__device__ __forceinline__ void direct_out(const DirectStep& d, int b, int64_t e, int nout,
+                                           int64_t pass, const int32_t* koa,
+                                           const int32_t* kob) {
+  const int64_t m = e >> d.nbits, n = e & (d.N - 1);
+  int64_t ao = 0, bo = 0;
+  for (int i = 0; i < d.nbb; ++i)
+    if ((b >> i) & 1) {
+      ao += d.a_bs[i];
+      bo += d.b_bs[i];
+    }
+  for (int i = 0; i < nout; ++i)
+    if ((pass >> (nout - 1 - i)) & 1) {
+      if (d.a_pp[i]) ao += int64_t(1) << (d.a_pp[i] - 1);
+      if (d.b_pp[i]) bo += int64_t(1) << (d.b_pp[i] - 1);
+    }
+  for (int i = 0; i < d.mbits; ++i)
+    if ((m >> i) & 1) ao += int64_t(1) << d.am[i];
+  for (int i = 0; i < d.nbits; ++i)
+    if ((n >> i) & 1) bo += int64_t(1) << d.bn[i];
+  direct_dot<MODE>(d.A, d.B, ao, bo, (int)d.K, koa, kob, d.C, int64_t(b) * d.M * d.N + e);
+}
+
+// Output u (slice batch major, then row, then column: also its index in C)
+// of tiny step d, with d's maps at mp.
+template <int MODE>
+__device__ __forceinline__ void tiny_out(const TinyStep& d, int u, const int32_t* mp, int nout,
+                                         int64_t pass) {
+  const int sh = d.mbits + d.nbits;
+  const int b = u >> sh, e = u & ((1 << sh) - 1);
+  const int M = 1 << d.mbits, N = 1 << d.nbits, K = d.K;
+  const int32_t* bat = mp + M + N + 2 * K;
+  int64_t ao = mp[e >> d.nbits] + bat[b];
+  int64_t bo = mp[M + (e & (N - 1))] + bat[(1 << d.nbb) + b];
+  for (int i = 0; i < nout; ++i)
+    if ((pass >> (nout - 1 - i)) & 1) {
+      if (d.a_pp[i]) ao += int64_t(1) << (d.a_pp[i] - 1);
+      if (d.b_pp[i]) bo += int64_t(1) << (d.b_pp[i] - 1);
+    }
+  direct_dot<MODE>(d.A, d.B, ao, bo, K, mp + M + N, mp + M + N + K, d.C, u);
+}
+
+constexpr int kDirectW = sizeof(DirectStep) / 4, kTinyW = sizeof(TinyStep) / 4;
+constexpr int kDirectLdsWords =
+    std::max<int>(kDirectW + 2 * (int)kDirectMaxK, kClusterMaxSteps * kTinyW + kClusterMapWords);
+
+template <int MODE>
+__global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
+  __shared__ __align__(16) uint32_t lds[kDirectLdsWords];
+  const int bid = blockIdx.x;
+  const int j = find_job(g.prefix, g.n, bid);
+  const DirectJob job = g.jobs[j];
+  if (job.count == 1) {
+    // The step's bit maps are read per output; copy them into LDS once.
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(g.steps + job.first);
+    if (threadIdx.x < kDirectW) lds[threadIdx.x] = src[threadIdx.x];
+    __syncthreads();
+    const DirectStep& d = *reinterpret_cast<const DirectStep*>(lds);
+    int32_t* koa = reinterpret_cast<int32_t*>(lds + kDirectW);
+    int32_t* kob = koa + kDirectMaxK;
+    const int local = bid - g.prefix[j];
+    const int b = local / d.blocks_per_batch;
+    const int64_t e = int64_t(local % d.blocks_per_batch) * 256 + threadIdx.x;
+    direct_ktab(d, koa, kob);
+    __syncthreads();
+    if (e < d.M * d.N) direct_out<MODE>(d, b, e, g.nout, g.pass, koa, kob);
+    return;
+  }
+  // A subtree: its steps and maps into LDS, then one height at a time (the
+  // steps of a height are independent), the height's outputs dealt round
+  // robin over the workgroup; the barrier after a height makes its results
+  // visible to the next one.
+  const TinyStep* ts = reinterpret_cast<const TinyStep*>(lds);
+  int32_t* map = reinterpret_cast<int32_t*>(lds + kClusterMaxSteps * kTinyW);
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(g.tiny + job.first);
+    for (int i = threadIdx.x; i < job.count * kTinyW; i += 256) lds[i] = src[i];
+    const int32_t* msrc = g.maps + job.map_first;
+    for (int i = threadIdx.x; i < job.map_words; i += 256) map[i] = msrc[i];
+  }
+  __syncthreads();
+  for (int q = 0; q < job.count;) {
+    const int r = ts[q].run_end, total = ts[q].run_total;
+    const uint8_t* sel = reinterpret_cast<const uint8_t*>(map + ts[q].sel);
+    for (int t = threadIdx.x; t < total; t += 256) {
+      const TinyStep& d = ts[sel[t]];  // the step output t belongs to
+      tiny_out<MODE>(d, t - d.ooff, map + d.map, g.nout, g.pass);
+    }
+    __syncthreads();
+    q = r;
   }
 }
 
@@ -1154,29 +1245,51 @@ size_t grouped_perm_bound(int n) {
   return al(size_t(n) * sizeof(PermParams)) + al((size_t(n) + 1) * sizeof(int32_t));
 }
 
-size_t grouped_direct_bound(int n) {
+size_t grouped_direct_bound(int n, int64_t map_words) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  return al(size_t(n) * sizeof(DirectStep)) + al((size_t(n) + 1) * sizeof(int32_t));
+  return al(size_t(n) * sizeof(DirectStep)) + al(size_t(n) * sizeof(TinyStep)) +
+         al(size_t(map_words) * sizeof(int32_t)) + al(size_t(n) * sizeof(DirectJob)) +
+         al((size_t(n) + 1) * sizeof(int32_t));
 }
 
-size_t grouped_direct_build(const std::vector<DirectStep>& steps, rn_mode mode,
+size_t grouped_direct_build(const std::vector<DirectStep>& steps,
+                            const std::vector<TinyStep>& tiny, const std::vector<int32_t>& maps,
+                            const std::vector<DirectJob>& jobs, rn_mode mode,
                             std::vector<char>& table, GroupedLaunch& G) {
   G = GroupedLaunch{};
-  G.n = (int)steps.size();
+  G.n = (int)jobs.size();
   G.mode = mode;
-  if (steps.empty()) return 0;
-  std::vector<int32_t> prefix(steps.size() + 1, 0);
+  if (jobs.empty()) return 0;
+  std::vector<int32_t> prefix(jobs.size() + 1, 0);
   int64_t total = 0;
-  for (size_t i = 0; i < steps.size(); ++i) {
-    total += int64_t(steps[i].blocks_per_batch) << steps[i].nbb;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const DirectJob& jb = jobs[i];
+    bool ok = jb.count >= 1 && jb.first >= 0;
+    if (ok && jb.count == 1) ok = size_t(jb.first) < steps.size();
+    if (ok && jb.count > 1)
+      ok = jb.count <= kClusterMaxSteps && size_t(jb.first) + size_t(jb.count) <= tiny.size() &&
+           jb.map_first >= 0 && jb.map_words >= 0 && jb.map_words <= kClusterMapWords &&
+           size_t(jb.map_first) + size_t(jb.map_words) <= maps.size();
+    if (!ok) {
+      G.blocks = -1;  // refused at launch
+      return 0;
+    }
+    total += jb.count == 1 ? int64_t(steps[jb.first].blocks_per_batch) << steps[jb.first].nbb : 1;
     prefix[i + 1] = prefix_entry(total);
   }
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   G.blocks = grouped_blocks(total);
   G.params_off = 0;
-  G.prefix_off = (steps.size() * sizeof(DirectStep) + 255) & ~size_t(255);
-  size_t bytes = (G.prefix_off + prefix.size() * sizeof(int32_t) + 255) & ~size_t(255);
+  G.tiny_off = al(steps.size() * sizeof(DirectStep));
+  G.maps_off = G.tiny_off + al(tiny.size() * sizeof(TinyStep));
+  G.jobs_off = G.maps_off + al(maps.size() * sizeof(int32_t));
+  G.prefix_off = G.jobs_off + al(jobs.size() * sizeof(DirectJob));
+  const size_t bytes = G.prefix_off + al(prefix.size() * sizeof(int32_t));
   table.assign(bytes, 0);
-  memcpy(table.data(), steps.data(), steps.size() * sizeof(DirectStep));
+  if (!steps.empty()) memcpy(table.data(), steps.data(), steps.size() * sizeof(DirectStep));
+  if (!tiny.empty()) memcpy(table.data() + G.tiny_off, tiny.data(), tiny.size() * sizeof(TinyStep));
+  if (!maps.empty()) memcpy(table.data() + G.maps_off, maps.data(), maps.size() * sizeof(int32_t));
+  memcpy(table.data() + G.jobs_off, jobs.data(), jobs.size() * sizeof(DirectJob));
   memcpy(table.data() + G.prefix_off, prefix.data(), prefix.size() * sizeof(int32_t));
   return bytes;
 }
@@ -1191,6 +1304,9 @@ hipError_t launch_direct_grouped(const GroupedLaunch& G, const void* table_dev, 
   t.nout = nout;
   t.steps = reinterpret_cast<const DirectStep*>(static_cast<const char*>(table_dev) + G.params_off);
   t.prefix = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.prefix_off);
+  t.jobs = reinterpret_cast<const DirectJob*>(static_cast<const char*>(table_dev) + G.jobs_off);
+  t.tiny = reinterpret_cast<const TinyStep*>(static_cast<const char*>(table_dev) + G.tiny_off);
+  t.maps = reinterpret_cast<const int32_t*>(static_cast<const char*>(table_dev) + G.maps_off);
   t.n = G.n;
   switch (G.mode) {
     case RN_FP64: direct_grouped<RN_FP64><<<G.blocks, 256, 0, s>>>(t); break;

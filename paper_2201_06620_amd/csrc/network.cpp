@@ -92,7 +92,9 @@ struct NStep {
   int64_t abytes = 0, bbytes = 0, pbytes = 0;  // temporaries
   bool direct = false;  // small step: evaluated from the stored layouts
   DirectStep dstep;     // its bit maps (pointers filled at enqueue time)
-  int level = 0;        // 1 + max level of its operands (inputs: 0)
+  int level = 0;        // dependency level of its launch (1 = inputs only)
+  int cluster = -1;     // subtree run by one workgroup (index), or -1
+  int height = 0;       // height inside that subtree
 };
 
 struct NetPlan {
@@ -111,6 +113,7 @@ struct NetPlan {
   double flops = 0;
   int max_rank = 0;
   std::vector<std::vector<int>> levels;  // step indices per dependency level
+  std::vector<std::vector<int>> clusters;  // subtrees of tiny steps, by height
   int64_t table_off = 0;                 // grouped small-step tables in ws
 };
 
@@ -141,6 +144,131 @@ int pos_of_slice(const NTensor& t, int sidx, const std::vector<int>& sliced) {
   int above = 0;
   for (int i = sidx + 1; i < 32; ++i) above += (t.dmask >> i) & 1;
   return r + above;
+}
+
+// Launch levels of the path's steps, grouping tiny small steps into
+// subtrees that one workgroup runs whole.
+//
+// The path is a tree (each intermediate feeds exactly one later step).  In
+// path order, a tiny step (small, within kClusterStepRounds and
+// kClusterStepWork) absorbs the subtrees
+// rooted at its operands when they are tiny too and the union stays within
+// the subtree limits (both operands if that fits, else the lighter one, else
+// neither); its index maps are tabulated (tiny_map_words).  A subtree is one launch unit; its level is 1 + the highest
+// level among the units that produce its outside operands, so a chain of
+// dependent tiny steps costs workgroup barriers instead of one launch per
+// dependency level.  Every other step is a unit of its own.
+struct ClusterAcc {
+  int steps = 0;
+  int64_t work = 0, words = 0;  // multiply-adds, map words
+  std::vector<int> cnt, ksum;  // steps and summed K per height (index h-1)
+};
+
+void form_clusters(NetPlan& P, int nt) {
+  const int ns = (int)P.steps.size();
+  auto tiny = [&](int s) {
+    const NStep& st = P.steps[s];
+    const int64_t out = (st.M * st.N) << st.nbb;
+    return st.direct && ((out + 255) / 256) * ((st.K + 7) / 8) <= kClusterStepRounds &&
+           out * st.K <= kClusterStepWork;
+  };
+  std::vector<int> root(ns);
+  std::vector<int> height(ns, 1);
+  std::vector<ClusterAcc> acc(ns);
+  std::vector<std::vector<int>> members(ns);
+  for (int s = 0; s < ns; ++s) {
+    root[s] = s;
+    members[s] = {s};
+    NStep& st = P.steps[s];
+    if (!tiny(s)) continue;
+    const int64_t own = ((st.M * st.N) << st.nbb) * st.K;
+    const int64_t own_words = tiny_map_words(st.M, st.N, st.K, st.nbb);
+    std::vector<int> kids;
+    for (int x : {st.a, st.b})
+      if (x >= nt && tiny(x - nt)) kids.push_back(x - nt);  // root of its subtree
+    // Try both operands' subtrees, then each alone (lighter first).
+    std::sort(kids.begin(), kids.end(), [&](int u, int v) { return acc[u].work < acc[v].work; });
+    std::vector<std::vector<int>> tries;
+    if (kids.size() == 2) tries.push_back(kids);
+    for (int k : kids) tries.push_back({k});
+    ClusterAcc mine;
+    mine.steps = 1;
+    mine.work = own;
+    mine.words = own_words;
+    mine.cnt = {1};
+    mine.ksum = {(int)st.K};
+    std::vector<int> take;
+    for (auto& t : tries) {
+      ClusterAcc c;
+      c.steps = 1;
+      c.work = own;
+      c.words = own_words;
+      int h = 1;
+      for (int k : t) {
+        c.steps += acc[k].steps;
+        c.work += acc[k].work;
+        c.words += acc[k].words;
+        h = std::max(h, height[k] + 1);
+        if (c.cnt.size() < acc[k].cnt.size()) {
+          c.cnt.resize(acc[k].cnt.size(), 0);
+          c.ksum.resize(acc[k].ksum.size(), 0);
+        }
+        for (size_t i = 0; i < acc[k].cnt.size(); ++i) {
+          c.cnt[i] += acc[k].cnt[i];
+          c.ksum[i] += acc[k].ksum[i];
+        }
+      }
+      if ((int)c.cnt.size() < h) {
+        c.cnt.resize(h, 0);
+        c.ksum.resize(h, 0);
+      }
+      c.cnt[h - 1] += 1;
+      c.ksum[h - 1] += (int)st.K;
+      bool ok = c.steps <= kClusterMaxSteps && c.work <= kClusterWork &&
+                c.words <= kClusterMapWords;
+      for (size_t i = 0; ok && i < c.cnt.size(); ++i)
+        ok = c.cnt[i] <= kClusterMaxWidth && c.ksum[i] <= kDirectMaxK;
+      if (ok) {
+        mine = std::move(c);
+        take = t;
+        height[s] = h;
+        break;
+      }
+    }
+    for (int k : take) {
+      for (int m : members[k]) root[m] = s;
+      members[s].insert(members[s].end(), members[k].begin(), members[k].end());
+      members[k].clear();
+    }
+    acc[s] = std::move(mine);
+  }
+  // Levels, unit by unit in path order (a subtree's root comes last in it,
+  // and every outside operand's unit comes before).
+  std::vector<int> tl(nt + ns, 0);
+  P.levels.clear();
+  P.clusters.clear();
+  for (int s = 0; s < ns; ++s) {
+    if (root[s] != s) continue;
+    std::vector<int>& mem = members[s];
+    std::sort(mem.begin(), mem.end(), [&](int u, int v) {
+      return height[u] != height[v] ? height[u] < height[v] : u < v;
+    });
+    int L = 0;
+    for (int m : mem)
+      for (int x : {P.steps[m].a, P.steps[m].b})
+        if (x < nt || root[x - nt] != s) L = std::max(L, tl[x]);
+    ++L;
+    if ((int)P.levels.size() < L) P.levels.resize(L);
+    const int cid = mem.size() > 1 ? (int)P.clusters.size() : -1;
+    if (cid >= 0) P.clusters.push_back(mem);
+    for (int m : mem) {
+      tl[nt + m] = L;
+      P.steps[m].level = L;
+      P.steps[m].cluster = cid;
+      P.steps[m].height = cid >= 0 ? height[m] : 0;
+      P.levels[L - 1].push_back(m);
+    }
+  }
 }
 
 rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* labels,
@@ -212,7 +340,6 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
   };
   for (int i = 0; i < nt; ++i) P.max_rank = std::max(P.max_rank, (int)eff(P.T[i]).size());
   const bool split_prec = (mode == RN_BF16X3);
-  std::vector<int> level(nt, 0);
   for (int s = 0; s < nsteps; ++s) {
     int a = path[2 * s], b = path[2 * s + 1];
     if (a < 0 || b < 0 || a >= nt + s || b >= nt + s || a == b || !alive[a] || !alive[b])
@@ -332,16 +459,13 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
     tc.bytes = nbatch * st.M * st.N * P.es;
     P.max_rank = std::max(P.max_rank, mb + nbits);
     P.flops += 8.0 * double(st.M) * double(st.N) * double(st.K) * double(nbatch);
-    st.level = 1 + std::max(level[a], level[b]);
-    level.push_back(st.level);
-    if ((int)P.levels.size() < st.level) P.levels.resize(st.level);
-    P.levels[st.level - 1].push_back(s);
     P.T.push_back(tc);
     P.steps.push_back(st);
     alive[nt + s] = true;
   }
   const NTensor& fin = P.T.back();
   if (!eff(fin).empty()) return fail(RN_ERR_INVALID, "network does not close to a scalar");
+  form_clusters(P, nt);
   // Workspace in execution order: level by level; the small steps of a
   // level run together in one launch, so their results are all live at once
   // and their operands are released only after that launch; then one grouped
@@ -399,12 +523,14 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
   int64_t tbytes = 0;
   for (auto& lv : P.levels) {
     int nd = 0, np = 0;
+    int64_t words = 0;
     for (int si : lv) {
       const NStep& st = P.steps[si];
       nd += st.direct ? 1 : 0;
       np += st.direct ? 0 : (st.permuteA ? 1 : 0) + (st.permuteB ? 1 : 0);
+      if (st.cluster >= 0) words += tiny_map_words(st.M, st.N, st.K, st.nbb);
     }
-    if (nd) tbytes += (int64_t)grouped_direct_bound(nd);
+    if (nd) tbytes += (int64_t)grouped_direct_bound(nd, words);
     if (np && P.nout == 0) tbytes += (int64_t)grouped_perm_bound(np);
   }
   P.ws_bytes = P.table_off + tbytes;
@@ -431,6 +557,7 @@ static const void* tensor_ptr(const NetPlan& P, const rn_tensor* T, char* w, int
 // pass, the permutes of the large steps' operands.
 struct LevelLaunches {
   std::vector<GroupedLaunch> direct, perm;
+  std::vector<int> tile;  // per step: GEMM tile from the handle's tune table, or -1
 };
 static void build_net_tables(const NetPlan& P, const rn_tensor* T, void* ws,
                              std::vector<char>& blob, LevelLaunches& per_level) {
@@ -442,11 +569,98 @@ static void build_net_tables(const NetPlan& P, const rn_tensor* T, void* ws,
   per_level.perm.assign(P.levels.size(), GroupedLaunch{});
   std::vector<char> part;
   auto ptr = [&](int id) { return tensor_ptr(P, T, w, id, 0); };
+  auto direct_of = [&](int si) {
+    const NStep& st = P.steps[si];
+    DirectStep d = st.dstep;
+    d.A = ptr(st.a);
+    d.B = ptr(st.b);
+    d.C = w + P.T[nt + si].off;
+    return d;
+  };
   for (size_t L = 0; L < P.levels.size(); ++L) {
     std::vector<DirectStep> ds;
+    std::vector<TinyStep> tiny;
+    std::vector<int32_t> maps;
+    std::vector<DirectJob> jobs;
     std::vector<PermLaunch> pj;
+    // Subtrees first (one workgroup each, the longest-running jobs), their
+    // steps by height, each with its height's run, its offset among that
+    // height's outputs and its index maps.
+    std::vector<int> seen;
+    for (int si : P.levels[L]) {
+      const int c = P.steps[si].cluster;
+      if (c < 0 || std::find(seen.begin(), seen.end(), c) != seen.end()) continue;
+      seen.push_back(c);
+      const std::vector<int>& mem = P.clusters[c];
+      DirectJob job{(int32_t)mem.size(), (int32_t)tiny.size(), (int32_t)maps.size(), 0};
+      size_t run = tiny.size();
+      int ooff = 0;
+      std::vector<uint8_t> sel;  // the current height's byte table
+      auto close_run = [&]() {
+        tiny[run].run_end = (int32_t)(tiny.size() - job.first);
+        tiny[run].run_total = ooff;
+        tiny[run].sel = (int32_t)(maps.size() - job.map_first);
+        sel.resize((sel.size() + 3) & ~size_t(3), 0);
+        for (size_t i = 0; i < sel.size(); i += 4)
+          maps.push_back((int32_t)(uint32_t(sel[i]) | uint32_t(sel[i + 1]) << 8 |
+                                   uint32_t(sel[i + 2]) << 16 | uint32_t(sel[i + 3]) << 24));
+        sel.clear();
+      };
+      for (size_t q = 0; q < mem.size(); ++q) {
+        const int m = mem[q];
+        const DirectStep d = direct_of(m);
+        if (q > 0 && P.steps[m].height != P.steps[mem[q - 1]].height) {
+          close_run();
+          run = tiny.size();
+          ooff = 0;
+        }
+        TinyStep t;
+        t.A = d.A;
+        t.B = d.B;
+        t.C = d.C;
+        t.mbits = d.mbits;
+        t.nbits = d.nbits;
+        t.K = (int32_t)d.K;
+        t.nbb = d.nbb;
+        t.ooff = ooff;
+        t.map = (int32_t)(maps.size() - job.map_first);
+        for (int i = 0; i < RN_MAX_SLICED; ++i) {
+          t.a_pp[i] = d.a_pp[i];
+          t.b_pp[i] = d.b_pp[i];
+        }
+        auto scatter = [](int64_t x, int bits, const int8_t* pos) {
+          int64_t o = 0;
+          for (int i = 0; i < bits; ++i)
+            if ((x >> i) & 1) o += int64_t(1) << pos[i];
+          return (int32_t)o;
+        };
+        for (int64_t x = 0; x < d.M; ++x) maps.push_back(scatter(x, d.mbits, d.am));
+        for (int64_t x = 0; x < d.N; ++x) maps.push_back(scatter(x, d.nbits, d.bn));
+        for (int64_t x = 0; x < d.K; ++x) maps.push_back(scatter(x, d.kbits, d.ak));
+        for (int64_t x = 0; x < d.K; ++x) maps.push_back(scatter(x, d.kbits, d.bk));
+        for (int side = 0; side < 2; ++side)
+          for (int64_t x = 0; x < (int64_t(1) << d.nbb); ++x) {
+            int64_t o = 0;
+            for (int i = 0; i < d.nbb; ++i)
+              if ((x >> i) & 1) o += side ? d.b_bs[i] : d.a_bs[i];
+            maps.push_back((int32_t)o);
+          }
+        const int nout_step = (int)((d.M * d.N) << d.nbb);
+        sel.insert(sel.end(), nout_step, (uint8_t)q);
+        ooff += nout_step;
+        tiny.push_back(t);
+      }
+      close_run();
+      job.map_words = (int32_t)(maps.size() - job.map_first);
+      jobs.push_back(job);
+    }
     for (int si : P.levels[L]) {
       const NStep& st = P.steps[si];
+      if (st.direct && st.cluster < 0) {
+        jobs.push_back(DirectJob{1, (int32_t)ds.size(), 0, 0});
+        ds.push_back(direct_of(si));
+        continue;
+      }
       if (!st.direct) {
         if (P.nout != 0) continue;
         for (int side = 0; side < 2; ++side) {
@@ -462,17 +676,15 @@ static void build_net_tables(const NetPlan& P, const rn_tensor* T, void* ws,
         }
         continue;
       }
-      DirectStep d = st.dstep;
-      d.A = ptr(st.a);
-      d.B = ptr(st.b);
-      d.C = w + P.T[nt + si].off;
-      ds.push_back(d);
     }
-    if (!ds.empty()) {
+    if (!jobs.empty()) {
       GroupedLaunch G;
       size_t base = blob.size();
-      grouped_direct_build(ds, P.mode, part, G);
+      grouped_direct_build(ds, tiny, maps, jobs, P.mode, part, G);
       G.params_off += base;
+      G.tiny_off += base;
+      G.maps_off += base;
+      G.jobs_off += base;
       G.prefix_off += base;
       blob.insert(blob.end(), part.begin(), part.end());
       per_level.direct[L] = G;
@@ -486,6 +698,19 @@ static void build_net_tables(const NetPlan& P, const rn_tensor* T, void* ws,
       blob.insert(blob.end(), part.begin(), part.end());
       per_level.perm[L] = G;
     }
+  }
+}
+
+// The GEMM tile of each large step from the handle's tune table (keyed by
+// mode and log2 of M, N, K), -1 where there is no valid entry.
+static void tuned_tiles(const rn_ctx* h, const NetPlan& P, LevelLaunches& L) {
+  L.tile.assign(P.steps.size(), -1);
+  for (size_t si = 0; si < P.steps.size(); ++si) {
+    const NStep& st = P.steps[si];
+    if (st.direct) continue;
+    const int t = tuned_tile(h, P.mode, __builtin_ctzll((uint64_t)st.M),
+                             __builtin_ctzll((uint64_t)st.N), __builtin_ctzll((uint64_t)st.K));
+    if (gemm_tile_valid(P.mode, t, st.M, st.N)) L.tile[si] = t;
   }
 }
 
@@ -589,6 +814,14 @@ static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hi
       }
       g.splitk = st.splitk;
       g.partial = st.splitk > 1 ? w + st.offPart : nullptr;
+      if (si < (int)per_level.tile.size() && per_level.tile[si] >= 0) {
+        // A tuned tile; the planned split (and its partials) only if it splits.
+        g.tile = per_level.tile[si];
+        if (!gemm_tile_splits(P.mode, g.tile)) {
+          g.splitk = 1;
+          g.partial = nullptr;
+        }
+      }
       if ((e = launch_gemm(g, s, prof)) != hipSuccess)
         return fail(RN_ERR_HIP, std::string("network GEMM: ") + hipGetErrorString(e));
     }
@@ -655,6 +888,9 @@ static bool net_signature(int32_t nt, const rn_tensor* T, const int32_t* const* 
       (nsliced > 0 && !sliced))
     return false;
   sig.clear();
+  size_t words = 7 + 2 * size_t(nt) + 2 * size_t(nsteps) + size_t(nsliced);
+  for (int i = 0; i < nt; ++i) words += 3 * size_t(std::max(0, T[i].rank));
+  sig.reserve(words);
   sig.push_back(mode);
   sig.push_back(o.slice_sum);
   sig.push_back(o.batch_bits);
@@ -813,12 +1049,17 @@ static rn_status run_planned(rn_ctx* h, const NetPlan& P, int32_t nt, const rn_t
     key = hash_bytes(key, &amp_dev, sizeof(amp_dev));
     key = hash_bytes(key, &slices_dev, sizeof(slices_dev));
     key = hash_bytes(key, &s, sizeof(s));
+    const uint64_t tv = tune_version();
+    key = hash_bytes(key, &tv, sizeof(tv));
     bool done = false;
     if ((st = replay_graph(h, key, s, &done)) != RN_OK || done) return st;
     if (seen_before(h, key)) {
       std::vector<char> blob;
       LevelLaunches launches;
       build_net_tables(P, T, ws, blob, launches);
+      tuned_tiles(h, P, launches);
+      if ((int64_t)blob.size() > P.ws_bytes - P.table_off)
+        return fail(RN_ERR_WORKSPACE, "network parameter table exceeds its planned bound");
       char* tdev = static_cast<char*>(ws) + P.table_off;
       return capture_and_launch(h, key, blob, tdev, s, [&](hipStream_t cs) {
         return enqueue_network(P, T, ws, cs, amp_dev, slices_dev, &h->prof, launches);
@@ -828,6 +1069,9 @@ static rn_status run_planned(rn_ctx* h, const NetPlan& P, int32_t nt, const rn_t
   std::vector<char> blob;
   LevelLaunches launches;
   build_net_tables(P, T, ws, blob, launches);
+  tuned_tiles(h, P, launches);
+  if ((int64_t)blob.size() > P.ws_bytes - P.table_off)
+    return fail(RN_ERR_WORKSPACE, "network parameter table exceeds its planned bound");
   if ((st = upload_table(h, blob, static_cast<char*>(ws) + P.table_off, s)) != RN_OK) return st;
   return enqueue_network(P, T, ws, s, amp_dev, slices_dev, &h->prof, launches);
 }

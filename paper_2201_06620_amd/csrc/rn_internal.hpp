@@ -164,6 +164,7 @@ struct GroupedLaunch {
   int blocks = 0;
   size_t lds = 0;
   size_t params_off = 0, prefix_off = 0;
+  size_t jobs_off = 0, tiny_off = 0, maps_off = 0;  // small steps
 };
 size_t grouped_perm_build(const std::vector<PermLaunch>& jobs, std::vector<char>& table,
                           GroupedLaunch& G);
@@ -186,11 +187,65 @@ struct DirectStep {
   // (slice index i of the fixed ones), 0 when the operand does not carry it.
   int8_t a_pp[RN_MAX_SLICED] = {0}, b_pp[RN_MAX_SLICED] = {0};
 };
+// A step of a subtree of tiny steps that one workgroup runs whole, height
+// by height (height 1: every operand comes from outside the subtree).  Its
+// index maps are tabulated on the host: in the job's map area from word
+// `map` on, amap[M] (element offset in A of row m), bmap[N], koa[K], kob[K],
+// abat[2^nbb], bbat[2^nbb] (offsets of slice batch b), all int32.  Each
+// height also has a byte table in the map area, from word `sel` of its first
+// step: entry t is the job index of the step that output t of the height
+// belongs to.
+struct TinyStep {
+  const void* A = nullptr;
+  const void* B = nullptr;
+  void* C = nullptr;
+  int32_t mbits = 0, nbits = 0, K = 1, nbb = 0;
+  int32_t ooff = 0;       // first output of the step among its height's outputs
+  int32_t run_end = 0;    // first step of a height: index past that height's steps
+  int32_t run_total = 0;  // first step of a height: outputs of that height
+  int32_t map = 0;        // word offset of its maps in the job's map area
+  int32_t sel = 0;        // first step of a height: word offset of its byte table
+  int32_t pad0 = 0;
+  int8_t a_pp[RN_MAX_SLICED] = {0}, b_pp[RN_MAX_SLICED] = {0};
+  int8_t pad[2] = {0, 0};
+};
+// Map words of a tiny step with these shapes, with its share of its
+// height's byte table (rounded up by a word).
+inline int64_t tiny_map_words(int64_t M, int64_t N, int64_t K, int nbb) {
+  return 1 + M + N + 2 * K + 2 * (int64_t(1) << nbb) + ((M * N) << nbb) / 4;
+}
+// A job of a grouped small-step launch.  count == 1: entry `first` of the
+// step list, one step whose outputs are spread over workgroups (256 per
+// workgroup and slice batch).  count > 1: entries first .. first+count-1 of
+// the tiny-step list, sorted by height, with their maps at words map_first
+// .. map_first+map_words-1 of the map list: a subtree that one workgroup runs
+// height by height with a workgroup barrier in between, so a chain of
+// dependent tiny steps costs barriers instead of launches.
+struct DirectJob {
+  int32_t count, first, map_first, map_words;
+};
 constexpr int64_t kDirectMaxK = 4096;
-size_t grouped_direct_bound(int n);
+// Subtrees: at most kClusterMaxSteps steps and kClusterMapWords map words
+// (both held in LDS), at most kClusterMaxWidth steps per height; a step
+// joins one only if its outputs (all slice batches) take at most
+// kClusterStepRounds rounds of the workgroup's 256 lanes times groups of 8
+// K terms (each round costs a memory round trip in one workgroup, while a
+// step of its own spreads over many) and at most kClusterStepWork
+// multiply-adds; a subtree holds at most kClusterWork multiply-adds.
+constexpr int kClusterMaxSteps = 64;
+constexpr int kClusterMaxWidth = 32;
+constexpr int kClusterMapWords = 8192;
+constexpr int64_t kClusterStepRounds = 4;
+constexpr int64_t kClusterStepWork = int64_t(1) << 16;
+constexpr int64_t kClusterWork = int64_t(1) << 18;
+// Table bytes of a grouped small-step launch over n steps (any job split)
+// whose subtrees hold map_words map words.
+size_t grouped_direct_bound(int n, int64_t map_words);
 // Bytes of the table of one grouped permute of n jobs.
 size_t grouped_perm_bound(int n);
-size_t grouped_direct_build(const std::vector<DirectStep>& steps, rn_mode mode,
+size_t grouped_direct_build(const std::vector<DirectStep>& steps,
+                            const std::vector<TinyStep>& tiny, const std::vector<int32_t>& maps,
+                            const std::vector<DirectJob>& jobs, rn_mode mode,
                             std::vector<char>& table, GroupedLaunch& G);
 // pass / nout: the pass index and the number of sliced bonds a pass fixes
 // (bit nout-1-i of pass is the value of fixed bond i).
@@ -265,6 +320,8 @@ struct rn_ctx {
 
 namespace rn {
 int tuned_tile(const rn_ctx* h, rn_mode mode, int mbits, int nbits, int kbits);
+// Bumped whenever a handle's tune table changes (graph keys include it).
+uint64_t tune_version();
 // Stage `bytes` of host table data and copy them to `dev` on stream s.
 rn_status upload_table(rn_ctx* h, const std::vector<char>& table, void* dev, hipStream_t s);
 uint64_t hash_bytes(uint64_t h, const void* p, size_t n);
