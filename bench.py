@@ -759,14 +759,12 @@ def main() -> int:
             ampt = torch.zeros(2, dtype=torch.float64, device=dev)
             torch.cuda.synchronize()
             for _ in range(3):
-                with torch.cuda.stream(side_stream):
-                    net.run(amp=ampt)
+                net.run(amp=ampt, stream=side_stream)
                 side_stream.synchronize()
             xs = []
             for _ in range(args.amp_requests):
                 t = time.perf_counter()
-                with torch.cuda.stream(side_stream):
-                    net.run(amp=ampt)
+                net.run(amp=ampt, stream=side_stream)
                 side_stream.synchronize()
                 xs.append(1e3 * (time.perf_counter() - t))
             a_ = ampt.cpu().numpy()

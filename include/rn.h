@@ -304,6 +304,25 @@ rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
                               int32_t nsliced, const int32_t* sliced, rn_mode mode, void* ws,
                               size_t ws_bytes, void* stream, double* amp_dev, double* slices_dev);
 
+/* Prepared network call, for repeated amplitudes of one circuit (the
+ * contraction of Sections II.A and II.B, as rn_contract_network).
+ * rn_network_prepare copies the descriptors (tensors with their data
+ * pointers, labels, path, sliced), plans under the handle's current options
+ * and hashes the descriptors once; *ws_bytes receives the workspace size.
+ * rn_network_execute runs it on `stream` with the given workspace and
+ * outputs (same meaning and errors as rn_contract_network); the tensors'
+ * contents may change between calls, their addresses may not.  A prepared
+ * call belongs to its handle (one thread at a time, destroyed before it);
+ * rn_network_release frees it (NULL is accepted). */
+typedef struct rn_prepared_net* rn_prepared;
+rn_status rn_network_prepare(rn_handle h, int32_t nt, const rn_tensor* T,
+                             const int32_t* const* labels, int32_t nsteps, const int32_t* path,
+                             int32_t nsliced, const int32_t* sliced, rn_mode mode,
+                             rn_prepared* out, size_t* ws_bytes);
+rn_status rn_network_execute(rn_prepared p, void* ws, size_t ws_bytes, void* stream,
+                             double* amp_dev, double* slices_dev);
+rn_status rn_network_release(rn_prepared p);
+
 /* ------------------------------------------------------------------------
  * Amplitude server (continuous admission of sliced-network requests).
  * Each request is one amplitude of a sliced network (Sections II.A, II.B).

@@ -34,7 +34,8 @@ EXPORTS = ["rn_create", "rn_destroy", "rn_status_str", "rn_last_error",
            "rn_server_submit", "rn_server_poll", "rn_server_wait", "rn_server_stats",
            "rn_server_destroy", "rn_set_option", "rn_get_option",
            "rn_block_tensordot_streamed_plan", "rn_block_tensordot_streamed",
-           "rn_block_tensordot_noalloc", "rn_server_set_admission"]
+           "rn_block_tensordot_noalloc", "rn_server_set_admission", "rn_network_prepare",
+           "rn_network_execute", "rn_network_release"]
 
 # Handle options (rn_option).
 OPTIONS = {"graphs": 0, "pair_split_threshold": 1, "split_footprint": 2, "slice_sum": 3,
@@ -99,6 +100,10 @@ def lib():
                                                ctypes.POINTER(i32)]
         L.rn_contract_network.argtypes = [p, i32, T, pp, i32, p, i32, p, ctypes.c_int, p, sz, p,
                                           p, p]
+        L.rn_network_prepare.argtypes = [p, i32, T, pp, i32, p, i32, p, ctypes.c_int,
+                                         ctypes.POINTER(p), ctypes.POINTER(sz)]
+        L.rn_network_execute.argtypes = [p, p, sz, p, p, p]
+        L.rn_network_release.argtypes = [p]
         L.rn_norm2.argtypes = [p, T, p, p]
         L.rn_sum_c128.argtypes = [p, i64, p, p, p]
         L.rn_profile_enable.argtypes = [p, ctypes.c_int]
@@ -726,7 +731,8 @@ class PreparedBatch:
 
 
 class PreparedNetwork:
-    """Argument arrays of one network contraction, kept for repeated calls.
+    """A network call prepared once (rn_network_prepare: descriptors copied,
+    planned and hashed), for repeated amplitudes of one circuit.
 
     The tensors passed in must stay alive and keep their storage; their
     contents may change between calls.
@@ -736,30 +742,42 @@ class PreparedNetwork:
         self.ctx = ctx
         self.tensors = list(tensors)
         self.mode = mode
-        self.Ts, self.lab_arr, self._keep = ctx._net_args(self.tensors, labels, mode)
-        self.pth, self.pp = _arr32([x for st in path for x in st])
-        self.sl, self.ps = _arr32(sliced)
-        self.nsteps = len(path)
-        ws_n, fl, mr = ctypes.c_size_t(), ctypes.c_double(), ctypes.c_int32()
-        check(lib().rn_contract_network_plan(ctx.h, len(self.tensors), self.Ts, self.lab_arr,
-                                             self.nsteps, self.pp, len(self.sl), self.ps,
-                                             mode_id(mode), ctypes.byref(ws_n), ctypes.byref(fl),
-                                             ctypes.byref(mr)), "network plan")
-        self.ws_bytes, self.flops, self.max_rank = ws_n.value, fl.value, mr.value
+        Ts, lab_arr, keep = ctx._net_args(self.tensors, labels, mode)
+        _, pp = _arr32([x for st in path for x in st])
+        sl, ps = _arr32(sliced)
+        self.nsliced = len(sl)
+        prep, ws_n = ctypes.c_void_p(), ctypes.c_size_t()
+        check(lib().rn_network_prepare(ctx.h, len(self.tensors), Ts, lab_arr, len(path), pp,
+                                       len(sl), ps, mode_id(mode), ctypes.byref(prep),
+                                       ctypes.byref(ws_n)), "network prepare")
+        self.prep = prep
+        self.ws_bytes = ws_n.value
+        fl, mr = ctypes.c_double(), ctypes.c_int32()
+        check(lib().rn_contract_network_plan(ctx.h, len(self.tensors), Ts, lab_arr, len(path),
+                                             pp, len(sl), ps, mode_id(mode), None,
+                                             ctypes.byref(fl), ctypes.byref(mr)), "network plan")
+        self.flops, self.max_rank = fl.value, mr.value
         import torch
         dev = self.tensors[0].device
         self.workspace = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+        self._ws = ctypes.c_void_p(self.workspace.data_ptr())
 
-    def run(self, amp=None, slices=None):
-        """Amplitude (device tensor of 2 doubles) on the current stream."""
+    def run(self, amp=None, slices=None, stream=None):
+        """Amplitude (device tensor of 2 doubles) on `stream` (a torch stream;
+        default: the current stream)."""
         import torch
         if amp is None:
             amp = torch.zeros(2, dtype=torch.float64, device=self.tensors[0].device)
-        _check_amp_slices(amp, slices, len(self.sl), self.ctx.device)
-        check(lib().rn_contract_network(self.ctx.h, len(self.tensors), self.Ts, self.lab_arr,
-                                        self.nsteps, self.pp, len(self.sl), self.ps,
-                                        mode_id(self.mode), self.workspace.data_ptr(),
-                                        self.ws_bytes, self.ctx._stream(), amp.data_ptr(),
-                                        slices.data_ptr() if slices is not None else None),
-              "contract_network")
+        _check_amp_slices(amp, slices, self.nsliced, self.ctx.device)
+        sp = self.ctx._stream() if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        check(lib().rn_network_execute(self.prep, self._ws, self.ws_bytes, sp,
+                                       amp.data_ptr(),
+                                       slices.data_ptr() if slices is not None else None),
+              "network execute")
         return amp
+
+    def __del__(self):
+        prep = getattr(self, "prep", None)
+        if prep is not None and prep.value and _lib is not None:
+            _lib.rn_network_release(prep)
+            self.prep = None

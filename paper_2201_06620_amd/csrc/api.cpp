@@ -164,9 +164,11 @@ rn_status rn_destroy(rn_handle h) {
     hipEventDestroy(r.b);
   }
   for (hipEvent_t e : h->prof.pool) hipEventDestroy(e);
+  if (!h->graphs.empty()) hipDeviceSynchronize();  // a replay may still run
   for (auto& g : h->graphs) {
     hipGraphExecDestroy(g.exec);
     if (g.pinned) hipHostFree(g.pinned);
+    if (g.table) hipFree(g.table);
   }
   if (h->pinned_done) {
     hipEventSynchronize(h->pinned_done);

@@ -362,35 +362,48 @@ void evict_graphs(rn_ctx* h, size_t keep) {
                                });
     hipGraphExecDestroy(it->exec);
     if (it->pinned) hipHostFree(it->pinned);
+    if (it->table) hipFree(it->table);
     h->graphs.erase(it);
   }
 }
 
 }  // namespace
 
-// Record `enqueue` on stream s as a graph (with the table copied from a
-// pinned buffer owned by the cache entry), keep it under `key`, launch it.
+// Copy the table once into device memory owned by a new cache entry, record
+// enqueue(s, that copy) as a graph, keep it under `key` and launch it.
 rn_status capture_and_launch(rn_ctx* h, uint64_t key, const std::vector<char>& table,
-                             void* table_dev, hipStream_t s,
-                             const std::function<rn_status(hipStream_t)>& enqueue) {
+                             hipStream_t s,
+                             const std::function<rn_status(hipStream_t, char*)>& enqueue) {
   GraphEntry ent;
   ent.key = key;
   hipError_t e;
+  auto drop = [&]() {
+    if (ent.table) {
+      hipStreamSynchronize(s);  // the copy may still read the staging
+      hipFree(ent.table);
+    }
+    if (ent.pinned) hipHostFree(ent.pinned);
+  };
   if (!table.empty()) {
     if ((e = hipHostMalloc(&ent.pinned, table.size(), hipHostMallocDefault)) != hipSuccess)
       return hipf(e, "hipHostMalloc");
     memcpy(ent.pinned, table.data(), table.size());
+    if ((e = hipMalloc(&ent.table, table.size())) != hipSuccess) {
+      ent.table = nullptr;
+      drop();
+      return hipf(e, "hipMalloc (graph table)");
+    }
+    e = hipMemcpyAsync(ent.table, ent.pinned, table.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+      drop();
+      return hipf(e, "hipMemcpyAsync (graph table)");
+    }
   }
   if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
-    if (ent.pinned) hipHostFree(ent.pinned);
+    drop();
     return hipf(e, "hipStreamBeginCapture");
   }
-  rn_status st = RN_OK;
-  if (!table.empty()) {
-    e = hipMemcpyAsync(table_dev, ent.pinned, table.size(), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) st = hipf(e, "hipMemcpyAsync (capture)");
-  }
-  if (st == RN_OK) st = enqueue(s);
+  rn_status st = enqueue(s, static_cast<char*>(ent.table));
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(s, &graph);
   if (st == RN_OK && e != hipSuccess) st = hipf(e, "hipStreamEndCapture");
@@ -400,12 +413,12 @@ rn_status capture_and_launch(rn_ctx* h, uint64_t key, const std::vector<char>& t
   }
   if (graph) hipGraphDestroy(graph);
   if (st != RN_OK) {
-    if (ent.pinned) hipHostFree(ent.pinned);
+    drop();
     return st;
   }
   if ((e = hipGraphLaunch(ent.exec, s)) != hipSuccess) {
     hipGraphExecDestroy(ent.exec);
-    if (ent.pinned) hipHostFree(ent.pinned);
+    drop();
     return hipf(e, "hipGraphLaunch");
   }
   ent.last_use = ++h->use_clock;
@@ -545,8 +558,8 @@ rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
   if (n == 0) return RN_OK;
   char* table_dev = static_cast<char*>(ws) + bp.table_off;
   if (graphs && seen_before(h, key))
-    return capture_and_launch(h, key, L.table, table_dev, s, [&](hipStream_t cs) {
-      return launch_all(h, L, table_dev, cs, false);
+    return capture_and_launch(h, key, L.table, s, [&](hipStream_t cs, char* tab) {
+      return launch_all(h, L, tab, cs, false);
     });
   if ((st = upload_table(h, L.table, table_dev, s)) != RN_OK) return st;
   return launch_all(h, L, table_dev, s, h->prof.on);

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -714,9 +715,11 @@ static void tuned_tiles(const rn_ctx* h, const NetPlan& P, LevelLaunches& L) {
   }
 }
 
+// tab: device copy of the parameter table (in the workspace, or owned by a
+// graph).
 static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hipStream_t s,
                               int64_t pass, double* sum_dev, double* slices_dev, Profiler* prof,
-                              const LevelLaunches& per_level) {
+                              const LevelLaunches& per_level, const char* tab) {
   char* w = static_cast<char*>(ws);
   const bool split_prec = (P.mode == RN_BF16X3);
   auto ptr = [&](int id) { return tensor_ptr(P, T, w, id, pass); };
@@ -727,7 +730,7 @@ static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hi
     // large steps in one launch, then the large steps' GEMMs.
     if (per_level.direct[L].n > 0) {
       int ev = prof->begin(1, s);
-      e = launch_direct_grouped(per_level.direct[L], w + P.table_off, pass, P.nout, s);
+      e = launch_direct_grouped(per_level.direct[L], tab, pass, P.nout, s);
       prof->end(ev, s);
       if (e != hipSuccess)
         return fail(RN_ERR_HIP, std::string("network small steps: ") + hipGetErrorString(e));
@@ -735,7 +738,7 @@ static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hi
     const bool grouped_perm = per_level.perm[L].n > 0;
     if (grouped_perm) {
       int ev = prof->begin(0, s);
-      e = launch_permute_grouped(per_level.perm[L], w + P.table_off, s);
+      e = launch_permute_grouped(per_level.perm[L], tab, s);
       prof->end(ev, s);
       if (e != hipSuccess)
         return fail(RN_ERR_HIP, std::string("network permutes: ") + hipGetErrorString(e));
@@ -840,14 +843,14 @@ static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hi
 // one more launch adds those in ascending pass order.
 static rn_status enqueue_network(const NetPlan& P, const rn_tensor* T, void* ws, hipStream_t s,
                                  double* amp_dev, double* slices_dev, Profiler* prof,
-                                 const LevelLaunches& launches) {
+                                 const LevelLaunches& launches, const char* tab) {
   const int64_t npass = int64_t(1) << P.nout;
   char* w = static_cast<char*>(ws);
   double* sums = reinterpret_cast<double*>(w + P.sums_off);
   rn_status st;
   for (int64_t pass = 0; pass < npass; ++pass) {
     double* out = npass > 1 ? sums + 2 * pass : amp_dev;
-    if ((st = enqueue_pass(P, T, ws, s, pass, out, slices_dev, prof, launches)) != RN_OK)
+    if ((st = enqueue_pass(P, T, ws, s, pass, out, slices_dev, prof, launches, tab)) != RN_OK)
       return st;
   }
   if (npass > 1) {
@@ -975,7 +978,7 @@ static rn_status run_planned(rn_ctx* h, const NetPlan& P, int32_t nt, const rn_t
                              const int32_t* const* labels, int32_t nsteps, const int32_t* path,
                              int32_t nsliced, const int32_t* sliced, rn_mode mode, void* ws,
                              size_t ws_bytes, hipStream_t s, double* amp_dev,
-                             double* slices_dev);
+                             double* slices_dev, const uint64_t* base_key = nullptr);
 
 rn_status network_run(rn_ctx* h, int32_t nt, const rn_tensor* T, const int32_t* const* labels,
                       int32_t nsteps, const int32_t* path, int32_t nsliced,
@@ -1017,12 +1020,45 @@ rn_status network_run_planned(rn_ctx* h, const std::shared_ptr<void>& plan, int3
                      nsliced, sliced, mode, ws, ws_bytes, s, amp_dev, slices_dev);
 }
 
-// Run a planned network (the plan matches these arguments).
+// Graph keys of network calls: the part fixed by the call's descriptors
+// (what a prepared call hashes once), then the per-call pointers, stream and
+// tuning state.
+static uint64_t net_key_base(const NetPlan& P, rn_mode mode, int32_t nt, const rn_tensor* T,
+                             const int32_t* const* labels, int32_t nsteps, const int32_t* path,
+                             int32_t nsliced, const int32_t* sliced) {
+  uint64_t key = 1469598103934665603ull;
+  key = hash_bytes(key, "network", 7);
+  key = hash_bytes(key, &mode, sizeof(mode));
+  key = hash_bytes(key, &P.slice_sum, sizeof(P.slice_sum));
+  key = hash_bytes(key, &P.nout, sizeof(P.nout));
+  key = hash_bytes(key, &nt, sizeof(nt));
+  for (int i = 0; i < nt; ++i) {
+    key = hash_tensor(key, T[i]);
+    key = hash_bytes(key, labels[i], sizeof(int32_t) * (size_t)T[i].rank);
+  }
+  key = hash_bytes(key, path, sizeof(int32_t) * 2 * (size_t)nsteps);
+  key = hash_bytes(key, &nsliced, sizeof(nsliced));
+  key = hash_bytes(key, sliced, sizeof(int32_t) * (size_t)nsliced);
+  return key;
+}
+
+static uint64_t net_key_call(uint64_t key, void* ws, double* amp_dev, double* slices_dev,
+                             hipStream_t s) {
+  key = hash_bytes(key, &ws, sizeof(ws));
+  key = hash_bytes(key, &amp_dev, sizeof(amp_dev));
+  key = hash_bytes(key, &slices_dev, sizeof(slices_dev));
+  key = hash_bytes(key, &s, sizeof(s));
+  const uint64_t tv = tune_version();
+  return hash_bytes(key, &tv, sizeof(tv));
+}
+
+// Run a planned network (the plan matches these arguments).  base_key: the
+// call's net_key_base when the caller has it.
 static rn_status run_planned(rn_ctx* h, const NetPlan& P, int32_t nt, const rn_tensor* T,
                              const int32_t* const* labels, int32_t nsteps, const int32_t* path,
                              int32_t nsliced, const int32_t* sliced, rn_mode mode, void* ws,
                              size_t ws_bytes, hipStream_t s, double* amp_dev,
-                             double* slices_dev) {
+                             double* slices_dev, const uint64_t* base_key) {
   rn_status st;
   if (P.slice_sum && slices_dev && nsliced > 0)
     return fail(RN_ERR_INVALID, "per-slice values do not exist in slice-sum mode");
@@ -1032,25 +1068,10 @@ static rn_status run_planned(rn_ctx* h, const NetPlan& P, int32_t nt, const rn_t
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return fail(RN_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
   if (use_graphs(h, s)) {
-    uint64_t key = 1469598103934665603ull;
-    key = hash_bytes(key, "network", 7);
-    key = hash_bytes(key, &mode, sizeof(mode));
-    key = hash_bytes(key, &P.slice_sum, sizeof(P.slice_sum));
-    key = hash_bytes(key, &P.nout, sizeof(P.nout));
-    key = hash_bytes(key, &nt, sizeof(nt));
-    for (int i = 0; i < nt; ++i) {
-      key = hash_tensor(key, T[i]);
-      key = hash_bytes(key, labels[i], sizeof(int32_t) * (size_t)T[i].rank);
-    }
-    key = hash_bytes(key, path, sizeof(int32_t) * 2 * (size_t)nsteps);
-    key = hash_bytes(key, &nsliced, sizeof(nsliced));
-    key = hash_bytes(key, sliced, sizeof(int32_t) * (size_t)nsliced);
-    key = hash_bytes(key, &ws, sizeof(ws));
-    key = hash_bytes(key, &amp_dev, sizeof(amp_dev));
-    key = hash_bytes(key, &slices_dev, sizeof(slices_dev));
-    key = hash_bytes(key, &s, sizeof(s));
-    const uint64_t tv = tune_version();
-    key = hash_bytes(key, &tv, sizeof(tv));
+    const uint64_t base =
+        base_key ? *base_key
+                 : net_key_base(P, mode, nt, T, labels, nsteps, path, nsliced, sliced);
+    const uint64_t key = net_key_call(base, ws, amp_dev, slices_dev, s);
     bool done = false;
     if ((st = replay_graph(h, key, s, &done)) != RN_OK || done) return st;
     if (seen_before(h, key)) {
@@ -1060,9 +1081,8 @@ static rn_status run_planned(rn_ctx* h, const NetPlan& P, int32_t nt, const rn_t
       tuned_tiles(h, P, launches);
       if ((int64_t)blob.size() > P.ws_bytes - P.table_off)
         return fail(RN_ERR_WORKSPACE, "network parameter table exceeds its planned bound");
-      char* tdev = static_cast<char*>(ws) + P.table_off;
-      return capture_and_launch(h, key, blob, tdev, s, [&](hipStream_t cs) {
-        return enqueue_network(P, T, ws, cs, amp_dev, slices_dev, &h->prof, launches);
+      return capture_and_launch(h, key, blob, s, [&](hipStream_t cs, char* tab) {
+        return enqueue_network(P, T, ws, cs, amp_dev, slices_dev, &h->prof, launches, tab);
       });
     }
   }
@@ -1072,8 +1092,9 @@ static rn_status run_planned(rn_ctx* h, const NetPlan& P, int32_t nt, const rn_t
   tuned_tiles(h, P, launches);
   if ((int64_t)blob.size() > P.ws_bytes - P.table_off)
     return fail(RN_ERR_WORKSPACE, "network parameter table exceeds its planned bound");
-  if ((st = upload_table(h, blob, static_cast<char*>(ws) + P.table_off, s)) != RN_OK) return st;
-  return enqueue_network(P, T, ws, s, amp_dev, slices_dev, &h->prof, launches);
+  char* tab = static_cast<char*>(ws) + P.table_off;
+  if ((st = upload_table(h, blob, tab, s)) != RN_OK) return st;
+  return enqueue_network(P, T, ws, s, amp_dev, slices_dev, &h->prof, launches, tab);
 }
 
 }  // namespace rn
@@ -1100,6 +1121,70 @@ rn_status rn_contract_network(rn_handle h, int32_t nt, const rn_tensor* T,
   if (!h) return fail(RN_ERR_INVALID, "null handle");
   return network_run(h, nt, T, labels, nsteps, path, nsliced, sliced, mode, h->net, ws, ws_bytes,
                      static_cast<hipStream_t>(stream), amp_dev, slices_dev);
+}
+
+// A prepared network call: descriptors copied, planned and hashed once.
+struct rn_prepared_net {
+  rn_ctx* h = nullptr;
+  rn_mode mode = RN_FP64;
+  std::vector<rn_tensor> T;
+  std::vector<std::vector<int32_t>> lab;
+  std::vector<const int32_t*> labp;
+  std::vector<int32_t> path, sliced;
+  std::shared_ptr<NetPlan> plan;
+  uint64_t base_key = 0;
+};
+
+rn_status rn_network_prepare(rn_handle h, int32_t nt, const rn_tensor* T,
+                             const int32_t* const* labels, int32_t nsteps, const int32_t* path,
+                             int32_t nsliced, const int32_t* sliced, rn_mode mode,
+                             rn_prepared* out, size_t* ws_bytes) {
+  if (!h || !out) return fail(RN_ERR_INVALID, "null handle or output");
+  *out = nullptr;
+  if (nt < 1 || !T || !labels || nsteps < 0 || (nsteps > 0 && !path) || nsliced < 0 ||
+      nsliced > RN_MAX_SLICED || (nsliced > 0 && !sliced))
+    return fail(RN_ERR_INVALID, "bad network arguments");
+  for (int j = 0; j < nt; ++j) {
+    if (T[j].rank < 0 || T[j].rank > RN_MAX_RANK || (T[j].rank > 0 && !labels[j]))
+      return fail(RN_ERR_INVALID, "bad tensor " + std::to_string(j));
+    if (!T[j].data) return fail(RN_ERR_INVALID, "null tensor data");
+  }
+  auto p = std::make_unique<rn_prepared_net>();
+  p->h = h;
+  p->mode = mode;
+  p->T.assign(T, T + nt);
+  p->lab.resize(nt);
+  p->labp.resize(nt);
+  for (int j = 0; j < nt; ++j) {
+    p->lab[j].assign(labels[j], labels[j] + std::max(0, T[j].rank));
+    p->labp[j] = p->lab[j].data();
+  }
+  p->path.assign(path, path + 2 * (size_t)nsteps);
+  p->sliced.assign(sliced, sliced + nsliced);
+  rn_status st = cached_plan(h, nt, p->T.data(), p->labp.data(), nsteps, p->path.data(),
+                             nsliced, p->sliced.data(), mode, h->net, &p->plan);
+  if (st != RN_OK) return st;
+  p->base_key = net_key_base(*p->plan, mode, nt, p->T.data(), p->labp.data(), nsteps,
+                             p->path.data(), nsliced, p->sliced.data());
+  if (ws_bytes) *ws_bytes = (size_t)p->plan->ws_bytes;
+  *out = p.release();
+  return RN_OK;
+}
+
+rn_status rn_network_execute(rn_prepared p, void* ws, size_t ws_bytes, void* stream,
+                             double* amp_dev, double* slices_dev) {
+  if (!p) return fail(RN_ERR_INVALID, "null prepared call");
+  if (!amp_dev) return fail(RN_ERR_INVALID, "null amplitude buffer");
+  const int32_t nt = (int32_t)p->T.size();
+  return run_planned(p->h, *p->plan, nt, p->T.data(), p->labp.data(),
+                     (int32_t)(p->path.size() / 2), p->path.data(), (int32_t)p->sliced.size(),
+                     p->sliced.data(), p->mode, ws, ws_bytes, static_cast<hipStream_t>(stream),
+                     amp_dev, slices_dev, &p->base_key);
+}
+
+rn_status rn_network_release(rn_prepared p) {
+  delete p;
+  return RN_OK;
 }
 
 }  // extern "C"

@@ -281,7 +281,8 @@ hipError_t launch_sum_slices(const void* vals, int es, int64_t n, double* out_su
 struct GraphEntry {
   uint64_t key = 0;
   hipGraphExec_t exec = nullptr;
-  void* pinned = nullptr;
+  void* pinned = nullptr;  // staging of the parameter table
+  void* table = nullptr;   // device copy of the table the graph's kernels read
   uint64_t last_use = 0;
 };
 
@@ -327,9 +328,10 @@ rn_status upload_table(rn_ctx* h, const std::vector<char>& table, void* dev, hip
 uint64_t hash_bytes(uint64_t h, const void* p, size_t n);
 uint64_t hash_tensor(uint64_t x, const rn_tensor& t);
 // Graph cache: replay_graph launches the graph stored under `key` if any
-// (*done = true); capture_and_launch records `enqueue` (preceded by a copy of
-// `table` to `table_dev` from a pinned buffer the entry owns), stores and
-// launches it.  use_graphs: graphs are enabled, the stream is not the null
+// (*done = true); capture_and_launch copies `table` once into device memory
+// the entry owns (on stream s, before the capture), records
+// enqueue(stream, that copy), stores and launches it: replays read the same
+// copy, so a replay is the kernels alone.  use_graphs: graphs are enabled, the stream is not the null
 // stream, not already capturing, and kernel timing is off.
 bool use_graphs(const rn_ctx* h, hipStream_t s);
 // Network plan and run under explicit options (the C entry points pass the
@@ -363,6 +365,6 @@ rn_status replay_graph(rn_ctx* h, uint64_t key, hipStream_t s, bool* done);
 // True when `key` was run before (directly); otherwise remembers it.
 bool seen_before(rn_ctx* h, uint64_t key);
 rn_status capture_and_launch(rn_ctx* h, uint64_t key, const std::vector<char>& table,
-                             void* table_dev, hipStream_t s,
-                             const std::function<rn_status(hipStream_t)>& enqueue);
+                             hipStream_t s,
+                             const std::function<rn_status(hipStream_t, char*)>& enqueue);
 }  // namespace rn

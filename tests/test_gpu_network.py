@@ -141,6 +141,18 @@ def test_prepared_network_repeats_and_new_values(ctx):
         a = amp.cpu().numpy()
         x = int("".join(map(str, bits)), 2)
         assert amp_err(complex(a[0], a[1]), psi[x], circ.n) < 1e-12
+    # The prepared call (rn_network_execute) and the plain call
+    # (rn_contract_network) give the same bits, per-slice values included.
+    sl_p = torch.zeros(2 << len(sliced), dtype=torch.float64, device="cuda")
+    sl_c = torch.zeros_like(sl_p)
+    for _ in range(3):  # direct, captured, replayed; the stream passed explicitly
+        prep.run(amp=amp, slices=sl_p, stream=s)
+        s.synchronize()
+    amp_c = ctx.contract_network(ts, net0.labels, path, sliced, "fp64", slices=sl_c)
+    torch.cuda.synchronize()
+    assert np.array_equal(amp.cpu().numpy(), amp_c.cpu().numpy())
+    assert np.array_equal(sl_p.cpu().numpy(), sl_c.cpu().numpy())
+    del prep  # rn_network_release
 
 
 @pytest.mark.parametrize("mode", ["fp64", "fp32_4m"])
