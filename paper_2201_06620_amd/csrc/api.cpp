@@ -45,6 +45,21 @@ rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor
                             const rn_tensor* C, void* ws, hipStream_t s, Profiler* prof,
                             int tile) {
   const bool split_prec = (P.mode == RN_BF16X3);
+  // Split BF16 on a plan sized for it: the planar Gauss tile when tuned to
+  // it, or by default for large outputs; else the packed form.
+  bool planar = false;
+  if (split_prec && P.planar_ok) {
+    if (gemm_tile_planar(P.mode, tile)) {
+      planar = true;
+    } else if (!gemm_tile_valid(P.mode, tile, P.M, P.N)) {
+      const int t = gemm_planar_default(P.mode, P.M, P.N, P.K);
+      if (t >= 0) {
+        planar = true;
+        tile = t;
+      }
+    }
+  }
+  if (!planar && gemm_tile_planar(P.mode, tile)) tile = -1;  // plan without planar room
   const void* am = A->data;
   const void* bm = B->data;
   const void* am2 = nullptr;
@@ -54,10 +69,11 @@ rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor
     PermLaunch L;
     L.in = A->data;
     L.out = ws_at(ws, P.off_a);
-    L.out2 = split_prec ? ws_at(ws, P.off_a2) : nullptr;
+    L.out2 = split_prec && !planar ? ws_at(ws, P.off_a2) : nullptr;
     L.perm = P.permA;
     L.in_es = P.es;
-    L.kind = split_prec ? 1 : 0;
+    L.kind = planar ? 2 : split_prec ? 1 : 0;
+    L.gw = std::min<int64_t>(P.K, 16);
     int ev = prof ? prof->begin(0, s) : -1;
     e = launch_permute(L, s);
     if (prof) prof->end(ev, s);
@@ -69,10 +85,11 @@ rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor
     PermLaunch L;
     L.in = B->data;
     L.out = ws_at(ws, P.off_b);
-    L.out2 = split_prec ? ws_at(ws, P.off_b2) : nullptr;
+    L.out2 = split_prec && !planar ? ws_at(ws, P.off_b2) : nullptr;
     L.perm = P.permB;
     L.in_es = P.es;
-    L.kind = split_prec ? 1 : 0;
+    L.kind = planar ? 2 : split_prec ? 1 : 0;
+    L.gw = std::min<int64_t>(P.K, 16);
     int ev = prof ? prof->begin(0, s) : -1;
     e = launch_permute(L, s);
     if (prof) prof->end(ev, s);
@@ -97,6 +114,8 @@ rn_status enqueue_tensordot(const TdPlan& P, const rn_tensor* A, const rn_tensor
   g.splitk = P.splitk;
   g.partial = P.splitk > 1 ? ws_at(ws, P.off_part) : nullptr;
   g.tile = tile;
+  g.planar = planar;
+  if (planar && P.splitk > 1 && !gemm_tile_splits(P.mode, tile)) g.splitk = 1;
   if ((e = launch_gemm(g, s, prof)) != hipSuccess) return hip_fail(e, "complex GEMM");
   return RN_OK;
 }
@@ -213,7 +232,8 @@ rn_status rn_block_tensordot_plan(rn_handle h, const rn_tensor* A, const rn_tens
                                   const int32_t* axesA, const int32_t* axesB, rn_mode mode,
                                   rn_tensor* C, size_t* ws_bytes, double* flops) {
   TdPlan P;
-  rn_status st = plan_tensordot(A, B, k, axesA, axesB, mode, &P, true, h ? &h->split : nullptr);
+  rn_status st =
+      plan_tensordot(A, B, k, axesA, axesB, mode, &P, true, h ? &h->split : nullptr, true);
   if (st != RN_OK) return st;
   if (C) fill_c(P, A->dtype, C);
   if (ws_bytes) *ws_bytes = P.ws_bytes;
@@ -227,7 +247,8 @@ rn_status rn_block_tensordot(rn_handle h, const rn_tensor* A, const rn_tensor* B
   if (!h) return fail(RN_ERR_INVALID, "null handle");
   TdPlan P;
   rn_status st;
-  if ((st = plan_tensordot(A, B, k, axesA, axesB, mode, &P, true, &h->split)) != RN_OK) return st;
+  if ((st = plan_tensordot(A, B, k, axesA, axesB, mode, &P, true, &h->split, true)) != RN_OK)
+    return st;
   if ((st = check_c(P, C)) != RN_OK) return st;
   if (!A->data || !B->data) return fail(RN_ERR_INVALID, "null operand data");
   if (C->data == A->data || C->data == B->data) return fail(RN_ERR_INVALID, "C aliases an operand");

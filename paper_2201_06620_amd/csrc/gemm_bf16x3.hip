@@ -612,6 +612,215 @@ RN_GEMM_ENTRY(cgemm_bf16x3)
 RN_GEMM_ENTRY(cgemm_bf16x3_ri)
 RN_GEMM_ENTRY_OCC(cgemm_bf16x3_dl, 2)
 
+// Split-BF16x3 in the Gauss (3M) form, direct-to-LDS.  Operands come from
+// permute kind 2 in the planar-group layout: per row, per group of W = min(16,
+// K) consecutive k, six planes of W bf16 each -- re hi, im hi, (re + im) hi,
+// re lo, im lo, (re + im) lo -- so row r, plane q, k sits at element
+// r * 6K + 6W (k / W) + q W + k % W, and a stage of 16 k of one row is 192
+// contiguous bytes.  Per 16 complex k and 32 x 32 subtile, T1 = Ar.Br,
+// T2 = Ai.Bi and T3 = (Ar + Ai).(Br + Bi), each lo*hi + hi*lo + hi*hi on
+// v_mfma_f32_32x32x16_bf16 (nine MFMAs where the 4M form needs twelve);
+// C = (T1 - T2) + i ((T3 - T1) - T2).  LDS per buffer and operand: R rows of
+// 12 chunks of 16 bytes (chunk j = 2 * plane + half), logical chunk j of row
+// r stored at j ^ f(r) (f < 4 keeps it in its group of four), which puts 16
+// or 32 consecutive rows read at one chunk on distinct bank groups; slot s
+// of a stage is row s / 12, stored chunk s % 12, and a wave's copies fill 64
+// consecutive slots (about five rows of 192 contiguous bytes each).  Four
+// waves (128 x 64) or eight (128 x 128, two waves per SIMD, one workgroup
+// per CU) per workgroup.  Unbatched problems only.
+template <int WM, int WN, int TM, int TN, int BK>
+__device__ __forceinline__ void cgemm_bf16g_dl_body(const GemmParams& p, int tm, int tn,
+                                                    int split, int b) {
+  static_assert(WM * WN == 4 || WM * WN == 8, "four or eight waves");
+  static_assert(BK == 16, "one MFMA k-step of 16 per stage");
+  constexpr int NT = 64 * WM * WN;   // threads
+  constexpr int BM = WM * TM * 32;
+  constexpr int BN = WN * TN * 32;
+  constexpr int RWD = 48;            // words per LDS row (12 chunks)
+  constexpr int AW = BM * RWD;       // words per buffer
+  constexpr int BW = BN * RWD;
+  constexpr int NA = 12 * BM / NT;   // 16-byte slots per thread and stage
+  constexpr int NB = 12 * BN / NT;
+  static_assert((12 * BM) % NT == 0 && (12 * BN) % NT == 0, "whole waves of slots");
+  auto f = [](int r) -> int { return (((r >> 2) ^ (r >> 4)) & 1) | (((r >> 3) & 1) << 1); };
+  __shared__ __align__(16) uint32_t A0[AW], A1[AW], B0[BW], B1[BW];
+  auto pick = [](auto t, uint32_t* x0, uint32_t* x1) -> uint32_t* {
+    if constexpr (decltype(t)::value) return x1; else return x0;
+  };
+  (void)b;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t row0 = int64_t(tm) * BM;
+  const int64_t col0 = int64_t(tn) * BN;
+  const uint16_t* __restrict__ Ag = reinterpret_cast<const uint16_t*>(p.A);
+  const uint16_t* __restrict__ Bg = reinterpret_cast<const uint16_t*>(p.B);
+  const int64_t rsA = 6 * p.lda, rsB = 6 * p.ldb;  // elements per row
+  const int64_t W = min(p.K, int64_t(16));          // k per plane group
+  const int64_t kbeg = int64_t(split) * p.kchunk;
+  const int64_t kend = min(p.K, kbeg + p.kchunk);
+  const int nk = (int)((kend - kbeg + BK - 1) / BK);
+  const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0 &&
+                        kbeg % BK == 0 && p.K % BK == 0;
+
+  auto dma = [&](auto buf, int64_t k0) {
+    uint32_t* a = pick(buf, A0, A1);
+    uint32_t* bb = pick(buf, B0, B1);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + NT * j, r = s / 12, ch = (s % 12) ^ f(r);
+      const uint16_t* src = Ag + (row0 + r) * rsA + 6 * k0 + 8 * ch;
+      __builtin_amdgcn_global_load_lds(src,
+                                       (__attribute__((address_space(3))) void*)(a + 4 * (NT * j + 64 * wave)),
+                                       16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + NT * j, r = s / 12, ch = (s % 12) ^ f(r);
+      const uint16_t* src = Bg + (col0 + r) * rsB + 6 * k0 + 8 * ch;
+      __builtin_amdgcn_global_load_lds(src,
+                                       (__attribute__((address_space(3))) void*)(bb + 4 * (NT * j + 64 * wave)),
+                                       16, 0, 0);
+    }
+  };
+  // Edge tiles: the same slots through registers, element by element, zero
+  // outside M, N or the K chunk.
+  uint4 ra[NA], rb[NB];
+  auto ld8 = [&](const uint16_t* X, int64_t gr, int64_t rs, int q, int64_t gk) -> uint4 {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = gk + e;
+      if (k < kend)
+        w[e >> 1] |= uint32_t(X[gr * rs + 6 * W * (k / W) + q * W + (k % W)]) << (16 * (e & 1));
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+  };
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int j = 0; j < NA; ++j) {
+      const int s = tid + NT * j, r = s / 12, ch = (s % 12) ^ f(r);
+      ra[j] = row0 + r < p.M ? ld8(Ag, row0 + r, rsA, ch >> 1, k0 + 8 * (ch & 1))
+                             : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int s = tid + NT * j, r = s / 12, ch = (s % 12) ^ f(r);
+      rb[j] = col0 + r < p.N ? ld8(Bg, col0 + r, rsB, ch >> 1, k0 + 8 * (ch & 1))
+                             : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto sstore = [&](auto buf) {
+    uint32_t* a = pick(buf, A0, A1);
+    uint32_t* bb = pick(buf, B0, B1);
+#pragma unroll
+    for (int j = 0; j < NA; ++j) *reinterpret_cast<uint4*>(a + 4 * (tid + NT * j)) = ra[j];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) *reinterpret_cast<uint4*>(bb + 4 * (tid + NT * j)) = rb[j];
+  };
+
+  v16f t1[TM][TN], t2[TM][TN], t3[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) t1[i][j][e] = t2[i][j][e] = t3[i][j][e] = 0.f;
+
+  // Lane l reads row l % 32 of its subtile, half l / 32 (k 0-7 or 8-15 of
+  // the stage), in each of the six planes.
+  const int hf = lane >> 5;
+  auto frag = [&](const uint32_t* x, int q, int r) -> v8bf {
+    return __builtin_bit_cast(
+        v8bf, *reinterpret_cast<const v4u*>(x + r * RWD + (((2 * q + hf) ^ f(r)) << 2)));
+  };
+
+  auto stage = [&](auto fast, auto cur, int it) {
+    constexpr bool FAST = decltype(fast)::value;
+    constexpr bool CUR = decltype(cur)::value;
+    const uint32_t* as = pick(cur, A0, A1);
+    const uint32_t* bs = pick(cur, B0, B1);
+    if constexpr (FAST) {
+      dma(BoolTag<!CUR>{}, kbeg + int64_t(it + 1 < nk ? it + 1 : it) * BK);
+      __builtin_amdgcn_sched_barrier(0);
+    } else if (it + 1 < nk) {
+      gload(kbeg + int64_t(it + 1) * BK);
+    }
+    // Planes: 0 re hi, 1 im hi, 2 (re + im) hi, 3 re lo, 4 im lo, 5 (re + im) lo.
+    v8bf a[TM][6], bv[TN][6];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) a[i][q] = frag(as, q, wm * TM * 32 + i * 32 + (lane & 31));
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int q = 0; q < 6; ++q) bv[j][q] = frag(bs, q, wn * TN * 32 + j * 32 + (lane & 31));
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][3], bv[j][0], t1[i][j], 0, 0, 0);
+        t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][4], bv[j][1], t2[i][j], 0, 0, 0);
+        t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][5], bv[j][2], t3[i][j], 0, 0, 0);
+        t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], bv[j][3], t1[i][j], 0, 0, 0);
+        t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], bv[j][4], t2[i][j], 0, 0, 0);
+        t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], bv[j][5], t3[i][j], 0, 0, 0);
+        t1[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][0], bv[j][0], t1[i][j], 0, 0, 0);
+        t2[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][1], bv[j][1], t2[i][j], 0, 0, 0);
+        t3[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i][2], bv[j][2], t3[i][j], 0, 0, 0);
+      }
+    if constexpr (FAST) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies have landed
+    } else if (it + 1 < nk) {
+      sstore(BoolTag<!CUR>{});
+    }
+    __syncthreads();
+  };
+
+  auto mainloop = [&](auto fast) {
+    constexpr bool FAST = decltype(fast)::value;
+    if (nk > 0) {
+      if constexpr (FAST) {
+        dma(BoolTag<false>{}, kbeg);
+        __builtin_amdgcn_s_waitcnt(0);
+      } else {
+        gload(kbeg);
+        sstore(BoolTag<false>{});
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < nk; it += 2) {
+      stage(fast, BoolTag<false>{}, it);
+      if (it + 1 < nk) stage(fast, BoolTag<true>{}, it + 1);
+    }
+  };
+  if (interior) mainloop(BoolTag<true>{}); else mainloop(BoolTag<false>{});
+
+  const int khalf = lane >> 5;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t row = row0 + wm * TM * 32 + i * 32 + 8 * (e >> 2) + 4 * khalf + (e & 3);
+        const int64_t col = col0 + wn * TN * 32 + j * 32 + (lane & 31);
+        const float x1 = t1[i][j][e], x2 = t2[i][j][e];
+        store_out<float>(p, 0, split, row, col, 0, x1 - x2);
+        store_out<float>(p, 0, split, row, col, 1, (t3[i][j][e] - x1) - x2);
+      }
+}
+
+// Entry with 64 * WM * WN threads (four or eight waves), two waves per SIMD.
+template <int WM, int WN, int TM, int TN, int BK>
+__global__ __launch_bounds__(64 * WM * WN, 2) void cgemm_bf16g_dl(GemmParams p) {
+  int tm, tn;
+  tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+  cgemm_bf16g_dl_body<WM, WN, TM, TN, BK>(p, tm, tn, blockIdx.y, blockIdx.z);
+}
+
 // MFMA tile `tile` (index into this mode's tile table, not the one-thread
 // or skinny kernels) over `grid` workgroups; errors via hipGetLastError.
 void launch_tiles_bf16x3(int tile, dim3 grid, const GemmParams& p, hipStream_t s) {
@@ -633,6 +842,10 @@ void launch_tiles_bf16x3(int tile, dim3 grid, const GemmParams& p, hipStream_t s
     cgemm_bf16x3_ri<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
   else if (tile == 9)
     cgemm_bf16x3_dl<2, 2, 2, 2, 16><<<grid, 256, 0, s>>>(p);
+  else if (tile == 11)  // planar operands (Gauss form), four waves
+    cgemm_bf16g_dl<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
+  else if (tile == 12)  // planar operands (Gauss form), eight waves
+    cgemm_bf16g_dl<2, 4, 2, 1, 16><<<grid, 512, 0, s>>>(p);
   else
     cgemm_bf16x3_dl<2, 2, 2, 1, 16><<<grid, 256, 0, s>>>(p);
 }

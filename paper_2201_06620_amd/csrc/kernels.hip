@@ -56,6 +56,7 @@ struct PermParams {
   int64_t hi_in[16];
   int64_t hi_out[16];
   int32_t hi_lds[16];
+  int64_t gw;  // KIND 2: k per plane group (W = min(16, K), a power of two)
 };
 
 // Thread-fixed low parts of the tile-local index u = tid + 256 * j.
@@ -111,12 +112,29 @@ __device__ __forceinline__ void permute_tile(const PermParams& p, int64_t t, T* 
       const int64_t oo = ob + out_lo + p.hi_out[j];
       if constexpr (KIND == 0) {
         reinterpret_cast<T*>(p.out)[oo] = v[j];
-      } else {
+      } else if constexpr (KIND == 1) {
         uint32_t hr, lr, hi_, li_;
         bf16_split(v[j].x, hr, lr);
         bf16_split(v[j].y, hi_, li_);
         reinterpret_cast<uint32_t*>(p.out)[oo] = hr | (hi_ << 16);
         reinterpret_cast<uint32_t*>(p.out2)[oo] = lr | (li_ << 16);
+      } else {
+        // Planar-group split for the Gauss form: element oo = r K + k of the
+        // K-contiguous operand goes to 6 (oo - w) + q W + w, w = oo % W, in
+        // plane q = re hi, im hi, (re + im) hi, re lo, im lo, (re + im) lo
+        // (the sum rounded once in FP32); one output array.
+        uint32_t hr, lr, hi_, li_, hs, ls;
+        bf16_split(v[j].x, hr, lr);
+        bf16_split(v[j].y, hi_, li_);
+        bf16_split(v[j].x + v[j].y, hs, ls);
+        const int64_t w = oo & (p.gw - 1);
+        uint16_t* o = reinterpret_cast<uint16_t*>(p.out) + 6 * (oo - w) + w;
+        o[0] = (uint16_t)hr;
+        o[p.gw] = (uint16_t)hi_;
+        o[2 * p.gw] = (uint16_t)hs;
+        o[3 * p.gw] = (uint16_t)lr;
+        o[4 * p.gw] = (uint16_t)li_;
+        o[5 * p.gw] = (uint16_t)ls;
       }
     }
   }
@@ -183,6 +201,7 @@ static void perm_setup(const PermLaunch& L, PermParams& p) {
   p.out = L.out;
   p.out2 = L.out2;
   p.in_base = L.in_base;
+  p.gw = L.gw;
   const int tlow = (L.in_es == 16) ? 5 : 6;
   bool inS[64] = {false};
   if (R <= 2 * tlow) {
@@ -256,8 +275,12 @@ hipError_t launch_permute(const PermLaunch& L, hipStream_t s) {
   // complex64 relayout measured 0.84 ms here against 0.86-0.89 ms with 2, 4 or
   // 16 per CU and 0.89 ms with one tile per workgroup.
   unsigned grid = (unsigned)std::min<int64_t>(p.ntiles, 256 * 64);
+  if (L.kind == 2 && (L.in_es != 8 || L.gw < 1 || L.gw > 16 || (L.gw & (L.gw - 1))))
+    return hipErrorInvalidValue;
   if (L.kind == 1)
     launch_perm_e<float2, 1>(p, E, grid, lds, s);
+  else if (L.kind == 2)
+    launch_perm_e<float2, 2>(p, E, grid, lds, s);
   else if (L.in_es == 16)
     launch_perm_e<double2, 0>(p, E, grid, lds, s);
   else
@@ -719,11 +742,14 @@ static const TileCfg kF64Tiles[] = {{1, 1, 1},   {128, 64, 8}, {64, 32, 8},  {12
                                     {64, 64, 8},  {128, 64, 8}, {64, 128, 8}, {64, 64, 8},
                                     {128, 64, 8}, {64, 128, 8}, {64, 64, 8},  {1, 16, 64},
                                     {2, 16, 64},  {4, 16, 64},  {8, 16, 64}};
+// Split-BF16 tiles 11 and 12 are the Gauss form on planar operands (permute
+// kind 2): only the single block tensordot runs them (see gemm_tile_planar).
 static const TileCfg kBF16Tiles[] = {{1, 1, 1},      {128, 64, 16},  {64, 32, 16},
                                      {256, 64, 8},   {128, 128, 8},  {128, 64, 16},
                                      {128, 128, 8},  {256, 64, 8},   {128, 128, 16},
-                                     {128, 128, 16}, {128, 64, 16},  {1, 16, 64},
-                                     {2, 16, 64},    {4, 16, 64},    {8, 16, 64}};
+                                     {128, 128, 16}, {128, 64, 16},  {128, 64, 16},
+                                     {128, 128, 16}, {1, 16, 64},    {2, 16, 64},
+                                     {4, 16, 64},    {8, 16, 64}};
 static const TileCfg k3MTiles[] = {{1, 1, 1},    {128, 64, 16}, {64, 64, 16}, {128, 64, 16},
                                    {64, 128, 16}, {128, 64, 16}, {64, 128, 16}, {1, 16, 64},
                                    {2, 16, 64},   {4, 16, 64},   {8, 16, 64}};
@@ -824,12 +850,29 @@ static int tile_count_of(rn_mode mode) {
 
 int gemm_tile_count(rn_mode mode) { return tile_count_of(mode); }
 
+bool gemm_tile_planar(rn_mode mode, int tile) {
+  return mode == RN_BF16X3 && (tile == 11 || tile == 12);
+}
+
 // The skinny tiles run problems whose shorter output side has at most their
-// row count.
+// row count; planar-operand tiles need the planar permute and are not valid
+// for a GEMM on packed operands.
 bool gemm_tile_valid(rn_mode mode, int tile, int64_t M, int64_t N) {
   if (tile < 0 || tile >= tile_count_of(mode)) return false;
+  if (gemm_tile_planar(mode, tile)) return false;
   if (const int mr = skinny_rows(mode, tile)) return std::min(M, N) <= mr;
   return true;
+}
+
+// No shape defaults to a planar tile: on the rank-28 pair the Gauss tiles
+// ran at 352 useful TFLOP/s against 407 for the 4M 128 x 128 tile; a tune
+// entry selects them.
+int gemm_planar_default(rn_mode mode, int64_t M, int64_t N, int64_t K) {
+  (void)mode;
+  (void)M;
+  (void)N;
+  (void)K;
+  return -1;
 }
 
 bool gemm_tile_splits(rn_mode mode, int tile) {
@@ -844,7 +887,9 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
   GemmParams p;
   fill_params(g, p);
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  const int tile = gemm_tile_valid(g.mode, g.tile, g.M, g.N)
+  if (g.planar != gemm_tile_planar(g.mode, g.tile) || (g.planar && g.nbb != 0))
+    return hipErrorInvalidValue;  // planar operands need a planar tile, unbatched
+  const int tile = g.planar || gemm_tile_valid(g.mode, g.tile, g.M, g.N)
                        ? g.tile
                        : choose_tile(g.mode, g.M, g.N, g.K, int64_t(1) << g.nbb);
   const TileCfg& c = tile_of(g.mode, tile);

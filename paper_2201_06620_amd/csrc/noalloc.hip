@@ -53,7 +53,8 @@ extern "C" rn_status rn_block_tensordot_noalloc(rn_handle h, const rn_tensor* A,
   if (!h) return fail(RN_ERR_INVALID, "null handle");
   TdPlan P;
   rn_status st;
-  if ((st = plan_tensordot(A, B, k, axesA, axesB, mode, &P, true, &h->split)) != RN_OK) return st;
+  if ((st = plan_tensordot(A, B, k, axesA, axesB, mode, &P, true, &h->split, true)) != RN_OK)
+    return st;
   if ((st = check_c(P, C)) != RN_OK) return st;
   if (!A->data || !B->data) return fail(RN_ERR_INVALID, "null operand data");
   if (C->data == A->data || C->data == B->data) return fail(RN_ERR_INVALID, "C aliases an operand");

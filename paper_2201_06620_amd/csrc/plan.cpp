@@ -83,7 +83,8 @@ static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
                          const int32_t* axesA, const int32_t* axesB, rn_mode mode,
-                         TdPlan* P, bool allow_splitk, const SplitPolicy* policy) {
+                         TdPlan* P, bool allow_splitk, const SplitPolicy* policy,
+                         bool planar_ok) {
   Layout LA, LB;
   rn_status st;
   if ((st = make_layout(A, "A", &LA)) != RN_OK) return st;
@@ -199,24 +200,27 @@ rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
   p.permuteA = split_prec || !p.permA.identity();
   p.permuteB = split_prec || !p.permB.identity();
   int64_t off = 0;
+  // Split BF16: hi and lo arrays of 4 bytes per complex (packed pairs); when
+  // the planar Gauss form may run, one region of 12 bytes per complex holds
+  // either its six planes or the two packed arrays.
+  p.planar_ok = split_prec && planar_ok;
   int64_t abytes = p.M * p.K * (split_prec ? 4 : p.es);
   int64_t bbytes = p.N * p.K * (split_prec ? 4 : p.es);
-  if (p.permuteA) {
-    p.off_a = off;
-    off = align256(off + abytes);
-    if (split_prec) {
-      p.off_a2 = off;
-      off = align256(off + abytes);
+  auto operand = [&](int64_t bytes, int64_t& o1, int64_t& o2) {
+    o1 = off;
+    if (p.planar_ok) {
+      o2 = off + align256(bytes);
+      off = align256(std::max(o1 + 3 * bytes, o2 + bytes));
+      return;
     }
-  }
-  if (p.permuteB) {
-    p.off_b = off;
-    off = align256(off + bbytes);
+    off = align256(off + bytes);
     if (split_prec) {
-      p.off_b2 = off;
-      off = align256(off + bbytes);
+      o2 = off;
+      off = align256(off + bytes);
     }
-  }
+  };
+  if (p.permuteA) operand(abytes, p.off_a, p.off_a2);
+  if (p.permuteB) operand(bbytes, p.off_b, p.off_b2);
   p.splitk = allow_splitk ? choose_splitk(mode, p.M, p.N, p.K, 1) : 1;
   const int64_t bk = int64_t(1) << p.pairbits;
   if (allow_splitk && policy && policy->pair_threshold > 0) {

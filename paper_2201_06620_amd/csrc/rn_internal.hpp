@@ -73,6 +73,7 @@ struct TdPlan {
   int pair_cbits[RN_MAX_RANK];  // refined contracted grid bits, pair order
   // Workspace sub-buffers (byte offsets; -1 when unused).
   int64_t off_a = -1, off_b = -1, off_a2 = -1, off_b2 = -1, off_part = -1;
+  bool planar_ok = false;  // workspace holds planar split-BF16 operands
   int splitk = 1;
   size_t ws_bytes = 0;
   double flops = 0;
@@ -91,10 +92,14 @@ struct SplitPolicy {
   int64_t footprint = int64_t(1) << 30;       // bytes of partial sums
 };
 
+// planar_ok: the call may stage split-BF16 operands in the planar Gauss form
+// (six bf16 planes in one array, 12 bytes per complex instead of 8): the
+// single block tensordot entry points; their workspace is sized for it (the
+// packed form's hi and lo arrays then sit inside that region).
 rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
                          const int32_t* axesA, const int32_t* axesB, rn_mode mode,
                          TdPlan* P, bool allow_splitk = true,
-                         const SplitPolicy* policy = nullptr);
+                         const SplitPolicy* policy = nullptr, bool planar_ok = false);
 rn_status check_c(const TdPlan& P, const rn_tensor* C);
 
 // Optional per-launch event timing (rn_profile_enable).
@@ -121,7 +126,9 @@ struct PermLaunch {
   int64_t in_base = 0;       // element offset added to every input index
   BitPerm perm;              // output bit -> input bit
   int in_es = 8;             // input element bytes (8 or 16)
-  int kind = 0;              // 0 copy, 1 split complex64 -> bf16 hi/lo
+  int kind = 0;              // 0 copy, 1 split complex64 -> bf16 hi/lo (packed
+                             // pairs), 2 planar-group split (Gauss form)
+  int64_t gw = 0;            // kind 2: k per plane group, min(16, K)
 };
 hipError_t launch_permute(const PermLaunch& p, hipStream_t s);
 
@@ -142,6 +149,8 @@ struct GemmLaunch {
   int splitk = 1;
   void* partial = nullptr;   // splitk > 1: [splitk][batch][M][N] complex, fp32/fp64
   int tile = -1;             // tile config index, -1 = choose
+  bool planar = false;       // operands in planar Gauss form (permute kind 2;
+                             // tile must be a planar one)
 };
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof = nullptr);
 int gemm_tile_count(rn_mode mode);
@@ -152,6 +161,14 @@ int gemm_default_tile(rn_mode mode, int64_t M, int64_t N, int64_t K);
 // Whether tile index `tile` can split K across workgroups (the MFMA tiles;
 // not the one-thread or skinny kernels).
 bool gemm_tile_splits(rn_mode mode, int tile);
+// Tiles that read planar operands (split-BF16 Gauss form: hi and lo planes
+// re, im, re + im in groups of min(16, K) k, from permute kind 2, 12 bytes
+// per complex in one array); only the single block tensordot stages
+// operands that way.
+bool gemm_tile_planar(rn_mode mode, int tile);
+// The planar tile a single block tensordot uses by default for this shape,
+// or -1.
+int gemm_planar_default(rn_mode mode, int64_t M, int64_t N, int64_t K);
 
 // Grouped launches: many problems (or permutations) in one kernel launch.
 // The host builds a parameter table plus a prefix sum of workgroups per

@@ -39,6 +39,17 @@ has error <= gamma_n sum |x_i y_i| with gamma_n = n u / (1 - n u)):
          bf16 products of each of the 2K real products (6K terms, their
          magnitudes at most m_s |x||y|, m_s = (1 + 2^-8)^2 (1 + 2^-7)) are
          summed in FP32: |dC| <= sqrt(2) (e_s + m_s gamma_6K) S.
+  split BF16x3, Gauss form (the planar tile): T1 = Ar.Br, T2 = Ai.Bi and
+         T3 = sa.sb with sa = fl(Ar + Ai), sb = fl(Br + Bi), each a split
+         product of K terms (3K exact bf16 products summed in FP32), so
+         |dT1|, |dT2| <= E S with E = e_s + m_s gamma_3K, and, since
+         sum (|ar| + |ai|)(|br| + |bi|) <= 2 S and the two sums add
+         (2u + u^2) relative, |dT3| <= 2 E3 S with
+         E3 = E (1 + u)^2 + 2u + u^2; Re = T1 - T2 and Im = (T3 - T1) - T2
+         add their roundings:
+         |dRe| <= 2 E S + 2u (1 + E) S,
+         |dIm| <= (2 E3 + 2 E) S + u (7 + 4 E3 + 3 E) (1 + u)^2 S.
+         The split-BF16 mode may run either form, so its bound is the larger.
   FP32 and split-BF16 modes take the complex128 inputs rounded once to
   complex64 (relative u per part): that adds (2u + u^2) S and scales the
   bounds above by (1 + u)^2.  FP64 mode may run the 4M or the Gauss tile, so
@@ -50,8 +61,10 @@ import math
 
 import numpy as np
 
-TOL = {"fp64": 1e-12, "fp32_4m": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3}
-UNIT = {"fp64": 2.0 ** -53, "fp32_4m": 2.0 ** -24, "fp32_3m": 2.0 ** -24, "bf16x3": 2.0 ** -24}
+TOL = {"fp64": 1e-12, "fp32_4m": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3, "bf16x3_4m": 1e-3,
+       "bf16x3_3m": 1e-3}
+UNIT = {"fp64": 2.0 ** -53, "fp32_4m": 2.0 ** -24, "fp32_3m": 2.0 ** -24, "bf16x3": 2.0 ** -24,
+        "bf16x3_4m": 2.0 ** -24, "bf16x3_3m": 2.0 ** -24}
 
 
 def _gamma(n: float, u: float) -> float:
@@ -76,6 +89,17 @@ def _bound_bf16x3(K: int, u: float) -> float:
     return math.sqrt(2.0) * (e_s + m_s * _gamma(6 * K, u))
 
 
+def _bound_bf16x3_gauss(K: int, u: float) -> float:
+    b = 2.0 ** -8
+    e_s = 2.0 * b * b + b ** 4 + b * b * (1.0 + b) ** 2
+    m_s = (1.0 + b) ** 2 * (1.0 + 2.0 * b)
+    e = e_s + m_s * _gamma(3 * K, u)
+    e3 = e * (1.0 + u) ** 2 + 2.0 * u + u * u
+    d_re = 2.0 * e + 2.0 * u * (1.0 + e)
+    d_im = 2.0 * e3 + 2.0 * e + u * (7.0 + 4.0 * e3 + 3.0 * e) * (1.0 + u) ** 2
+    return math.hypot(d_re, d_im)
+
+
 def bound_factor(mode: str, K: int) -> float:
     """g(mode, K): |dC_ij| <= g * (|A||B|)_ij for K complex terms per output."""
     K = max(int(K), 1)
@@ -86,8 +110,12 @@ def bound_factor(mode: str, K: int) -> float:
         g = _bound_4m(K, u)
     elif mode == "fp32_3m":
         g = _bound_gauss(K, u)
-    else:
+    elif mode == "bf16x3_4m":  # one form alone (simulations)
         g = _bound_bf16x3(K, u)
+    elif mode == "bf16x3_3m":
+        g = _bound_bf16x3_gauss(K, u)
+    else:
+        g = max(_bound_bf16x3(K, u), _bound_bf16x3_gauss(K, u))
     return g * (1.0 + u) ** 2 + 2.0 * u + u * u
 
 

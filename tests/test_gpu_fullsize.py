@@ -1,7 +1,7 @@
 """Full-size parity of the rank-28 pairwise contraction: two rank-28 tensors
 (all dims 2, 2^28 complex entries each), 14 contracted indices in seeded
 random order, contracted through the same call and default tiles the
-benchmark times.  The oracle computes sampled outputs one by one (two 32 x 32
+benchmark times, plus split BF16's opt-in Gauss tile (planar operands).  The oracle computes sampled outputs one by one (two 32 x 32
 blocks of C viewed as M x N, plus the corners).  Complex normal inputs: e_F
 and e_max within each mode's tolerance and every sampled entry within its
 rounding bound (tests/parity.py).  Bit-exact on Gaussian-integer inputs,
@@ -23,6 +23,7 @@ pytestmark = pytest.mark.gpu
 
 RANK, K = 28, 14
 TOL = {"fp64": 1e-12, "fp32_4m": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-3}
+BF16_GAUSS_TILE = 12  # split BF16, Gauss form on planar operands (opt-in tile)
 
 
 def log(msg):
@@ -43,10 +44,13 @@ def sample_index():
 
 
 def run_modes(p, idx, check, absprod=False):
+    import tempfile
+    from pathlib import Path
     import torch
     import paper_2201_06620_amd as rn
     assert torch.cuda.is_available()
     ctx = rn.Context(0)
+    tmp_dir = Path(tempfile.mkdtemp())
     dims = [2] * RANK
     A = p.a.data.reshape(dims)
     B = p.b.data.reshape(dims)
@@ -55,14 +59,23 @@ def run_modes(p, idx, check, absprod=False):
     if absprod:
         log("oracle (|A||B|) on the same outputs")
         ref = (ref, parity.abs_product_entries(A, B, p.axes_a, p.axes_b, idx))
-    for dt, modes in ((torch.complex64, ("fp32_4m", "fp32_3m", "bf16x3")),
+    for dt, modes in ((torch.complex64, ("fp32_4m", "fp32_3m", "bf16x3", "bf16x3_gauss")),
                       (torch.complex128, ("fp64",))):
         a = torch.from_numpy(p.a.data).to(dt).cuda()
         b = torch.from_numpy(p.b.data).to(dt).cuda()
         for mode in modes:
             log(f"mode {mode}: rank-{RANK} contraction, {K} contracted axes")
+            call = mode
+            if mode == "bf16x3_gauss":  # the planar Gauss tile, through a tune file
+                call = "bf16x3"
+                tf = str(tmp_dir / "bf16_gauss_tune.txt")
+                with open(tf, "w") as f:
+                    f.write("rn_tune 1\n%d %d %d %d %d\n" % (rn.mode_id(call), RANK - K,
+                                                             RANK - K, K, BF16_GAUSS_TILE))
+                ctx.tune_load(tf)
             c, cd, cg = ctx.block_tensordot(a, dims, None, b, dims, None, p.axes_a, p.axes_b,
-                                            mode)
+                                            call)
+            ctx.tune_clear()
             torch.cuda.synchronize()
             assert cd == [2] * (2 * (RANK - K))
             got = c[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.complex128)
@@ -79,7 +92,8 @@ def test_rank28_sampled_within_tolerance():
 
     def check(mode, got, ref):
         ref, absprod = ref
-        parity.check(got, ref, absprod, 2 ** K, mode, "rank-28 sampled")
+        pm = "bf16x3" if mode == "bf16x3_gauss" else mode
+        parity.check(got, ref, absprod, 2 ** K, pm, f"rank-28 sampled {mode}")
 
     run_modes(p, idx, check, absprod=True)
 

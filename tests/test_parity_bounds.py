@@ -57,8 +57,14 @@ def sim(mode, a, b, drop=None):
                 s = s + (xh @ yl).astype(f)
             return s
 
-        re = prod(arh, arl, brh, brl) - prod(aih, ail, bih, bil)
-        im = prod(arh, arl, bih, bil) + prod(aih, ail, brh, brl)
+        if mode == "bf16x3_3m":  # Gauss form on planar splits of re, im, re + im
+            (sah, sal), (sbh, sbl) = split((ar + ai).astype(f)), split((br + bi).astype(f))
+            t1, t2 = prod(arh, arl, brh, brl), prod(aih, ail, bih, bil)
+            t3 = prod(sah, sal, sbh, sbl)
+            re, im = t1 - t2, (t3 - t1) - t2
+        else:
+            re = prod(arh, arl, brh, brl) - prod(aih, ail, bih, bil)
+            im = prod(arh, arl, bih, bil) + prod(aih, ail, brh, brl)
     return re.astype(np.float64) + 1j * im.astype(np.float64)
 
 
@@ -66,14 +72,19 @@ def normal(seed, shape):
     return rng.complex_normal(seed, int(np.prod(shape))).reshape(shape)
 
 
-@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "fp32_3m", "bf16x3"])
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "fp32_3m", "bf16x3", "bf16x3_3m"])
 @pytest.mark.parametrize("K", [1, 16, 1024])
 def test_simulated_arithmetic_within_bound(mode, K):
+    # "bf16x3" simulates the 4M split form, "bf16x3_3m" the Gauss split form;
+    # each is held to its own form's bound and to the mode's (the larger).
     a, b = normal(11 + K, (M, K)), normal(12 + K, (K, N))
     ref = a @ b
     absprod = np.abs(a) @ np.abs(b)
-    r = parity.check(sim(mode, a, b), ref, absprod, K, mode, "simulated")
+    own = {"bf16x3": "bf16x3_4m"}.get(mode, mode)
+    r = parity.check(sim(mode, a, b), ref, absprod, K, own, "simulated")
     assert r["higham"] <= r["higham_bound"]
+    if mode.startswith("bf16"):
+        parity.check(sim(mode, a, b), ref, absprod, K, "bf16x3", "simulated")
 
 
 def test_bound_constants():
@@ -83,8 +94,16 @@ def test_bound_constants():
     u = 2.0 ** -24
     assert abs(parity.bound_factor("fp32_4m", K) / (K * u) / (2 * np.sqrt(2)) - 1) < 3e-3
     assert abs(parity.bound_factor("fp32_3m", K) / (K * u) / np.sqrt(10) - 1) < 3e-3
-    g = parity.bound_factor("bf16x3", K) / (K * u)
+    g = parity.bound_factor("bf16x3_4m", K) / (K * u)
     assert 6 * np.sqrt(2) < g < 6 * np.sqrt(2) * 1.03 + 3 * np.sqrt(2) * 256 / K + 0.01
+    # Gauss split form: dRe -> 2 E, dIm -> 4 E with E -> 3 K u m_s, so
+    # sqrt(6^2 + 12^2) m_s (plus the split term); the mode takes the larger
+    # of the two forms.
+    m_s = (1 + 2.0 ** -8) ** 2 * (1 + 2.0 ** -7)
+    g3 = parity.bound_factor("bf16x3_3m", K) / (K * u)
+    assert np.hypot(6, 12) * m_s < g3 < np.hypot(6, 12) * m_s * 1.01 + 20 * 256 / K
+    assert parity.bound_factor("bf16x3", K) == max(parity.bound_factor("bf16x3_4m", K),
+                                                   parity.bound_factor("bf16x3_3m", K))
 
 
 def test_planted_single_entry_error_fails():
@@ -114,7 +133,7 @@ def test_exact_split_inputs(order):
     ref = a @ b
     wide = a if order[0] == "wide" else b
     assert np.all(bf16_round(wide.real.astype(np.float32)) != wide.real)  # lo != 0
-    for mode in ("fp64", "fp32_4m", "fp32_3m", "bf16x3"):
+    for mode in ("fp64", "fp32_4m", "fp32_3m", "bf16x3", "bf16x3_3m"):
         assert np.array_equal(sim(mode, a, b), ref), mode
     # The cross term that multiplies the wide operand's low part is needed
     # for exactness (so a kernel that drops it fails); the other one

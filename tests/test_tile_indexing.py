@@ -377,3 +377,73 @@ def test_fp64_gauss_tile_index():
     launch = launch[:launch.index("void launch_tiles_f64_grouped(")]
     assert re.search(r"else\s+cgemm_f64_3mdl<2, 2, 2, 2, 8>", launch)
     assert "tile == %d" % (bench.FP64_GAUSS_TILE - 1) in launch
+
+
+def gauss_f(r):
+    return (((r >> 2) ^ (r >> 4)) & 1) | (((r >> 3) & 1) << 1)
+
+
+def test_bf16_gauss_planar_tiles():
+    # Planar split-BF16 Gauss tile: per operand and stage, R LDS rows of 12
+    # chunks (chunk j = 2 plane + half); slot s = tid + NT j (NT threads) is row s / 12,
+    # stored chunk s % 12 holding logical chunk (s % 12) ^ f(row), at LDS
+    # word 4 s.  Every (row, logical chunk) is filled once and stays in its
+    # group of four; the fragment read of lane l (row l % 32 of a subtile,
+    # plane q, half l / 32) finds the word its slot was copied to; the
+    # global chunk (8 elements from 8 j in the row's 96-element stage group)
+    # stays inside the group.
+    shapes = instances("cgemm_bf16g_dl")
+    assert shapes
+    for wm_, wn_, tm, tn, bk in shapes:
+        assert bk == 16
+        nt = 64 * wm_ * wn_  # four or eight waves
+        assert nt in (256, 512)
+        for rows, sub, nsub in ((wm_ * tm * 32, tm, wm_), (wn_ * tn * 32, tn, wn_)):
+            v = 12 * rows
+            assert v % nt == 0
+            where = {}
+            for j in range(v // nt):
+                for tid in range(nt):
+                    s = tid + nt * j
+                    assert nt * j + 64 * (tid >> 6) + (tid & 63) == s < v
+                    r, ch = s // 12, (s % 12) ^ gauss_f(s // 12)
+                    assert 0 <= ch < 12 and ch // 4 == (s % 12) // 4
+                    assert 8 * ch + 8 <= 6 * bk
+                    where[(r, ch)] = 4 * s
+            assert len(where) == v
+            for w in range(nsub):
+                for i in range(sub):
+                    for lane in range(64):
+                        r = w * sub * 32 + i * 32 + (lane & 31)
+                        for q in range(6):
+                            ch = 2 * q + (lane >> 5)
+                            word = r * 48 + ((ch ^ gauss_f(r)) << 2)
+                            assert word == where[(r, ch)] and word + 4 <= 48 * rows
+
+
+def test_bf16_gauss_reads_spread_banks():
+    # 128-bit fragment reads of 16 (64 banks) or 32 (128 banks) consecutive
+    # lanes: consecutive rows of 12 chunks at one logical chunk; their
+    # 16-byte slots must fall on distinct bank groups.
+    for group in (16, 32):
+        for r0 in range(0, 256, group):
+            for ch in range(12):
+                got = {(12 * r + (ch ^ gauss_f(r))) % group for r in range(r0, r0 + group)}
+                assert len(got) == group
+
+
+def test_bf16_gauss_group_layout_formula():
+    # The permute's address 6 (oo - w) + q W + w (w = oo % W) equals the
+    # kernel's r 6K + 6W (k / W) + q W + k % W for oo = r K + k, W = min(16, K).
+    for K in (1, 2, 4, 8, 16, 32, 64):
+        W = min(16, K)
+        seen = set()
+        for r in range(3):
+            for k in range(K):
+                oo = r * K + k
+                w = oo % W
+                for q in range(6):
+                    a = 6 * (oo - w) + q * W + w
+                    assert a == r * 6 * K + 6 * W * (k // W) + q * W + k % W
+                    seen.add(a)
+        assert seen == set(range(3 * 6 * K))
