@@ -148,9 +148,12 @@ def run_serving(args, torch, rn, log):
 
     def sweep_loads(loads, tag):
         out = []
-        for li, load in enumerate(loads):
+        for load in loads:
             lam = load * thr
-            gaps = np.random.default_rng(2201 + li).exponential(1.0 / lam, size=len(reqs))
+            # Arrival gaps seeded by the load alone: both admission policies see
+            # the same arrival sequence at a given load.
+            gaps = np.random.default_rng(2201 + int(round(100 * load))).exponential(
+                1.0 / lam, size=len(reqs))
             tk2 = [None] * len(reqs)
 
             def client():

@@ -343,7 +343,9 @@ rn_status rn_network_release(rn_prepared p);
  * rest); policy 1, the default, admits the request with the fewest planned
  * flops first, except that a request overtaken max_overtakes times (default
  * 8) by later arrivals goes next, and while it does not fit the free memory
- * nothing else is admitted, so no request waits forever.  A request whose
+ * nothing else is admitted, so no request waits forever; while younger
+ * requests wait, such aged requests occupy at most max_active - 1 slots (with
+ * two or more), keeping one slot for the small work behind them.  A request whose
  * footprint exceeds the whole budget completes with status RN_ERR_OOM.
  * Results: amplitude, latency = completion - submit, and its split into
  * queueing and running time.  A request's amplitude does not depend on what

@@ -6,7 +6,9 @@
 // the network workspace the planner reports -- fits the HBM budget, either
 // in arrival order or smallest first (planned flops) with an aging bound: a
 // request overtaken max_overtakes times goes next, and while it does not fit
-// the free memory nothing else is admitted.  Admitted requests copy their
+// the free memory nothing else is admitted.  While younger requests wait,
+// aged ones hold at most all but one slot (with two or more slots), so a
+// burst of large aged requests cannot shut out the small ones behind them.  Admitted requests copy their
 // tensors into a device arena,
 // where they stay until the request completes, and run concurrently on
 // their slot streams, so a request arriving while others are on the GPU
@@ -77,6 +79,7 @@ struct Request {
   size_t ws_bytes = 0, tensor_bytes = 0, footprint = 0;
   double flops = 0;    // planned useful flops (admission order)
   int overtaken = 0;   // later requests admitted before this one
+  bool aged = false;   // admitted after being overtaken max_overtakes times
   NetOpts opts;  // batched-slice count fitted to the budget at submission
   std::shared_ptr<void> plan;  // made at submission, run by the worker
   Clock::time_point t_submit, t_start, t_done;
@@ -231,19 +234,28 @@ void worker_loop(rn_server* S) {
           return ra->ticket < rb->ticket;
         });
       }
+      int aged_running = 0;
+      for (const Request* a : S->active) aged_running += a->aged ? 1 : 0;
+      bool young_waiting = false;
+      for (const Request* q : S->queue) young_waiting |= q->overtaken < S->max_overtakes;
+      const bool aged_room =
+          S->max_active < 2 || !young_waiting || aged_running < S->max_active - 1;
       size_t pick = SIZE_MAX, off = 0;
       for (size_t c : cand) {
         Request* r = S->queue[c];
+        const bool aged = S->policy == 1 && r->overtaken >= S->max_overtakes;
+        if (aged && !aged_room) continue;  // all but one slot hold aged requests
         if (S->free.alloc(r->footprint, &off)) {
           pick = c;
           break;
         }
         // Arrival order, or an aged request: wait for memory, admit nothing
         // past it.
-        if (S->policy == 0 || r->overtaken >= S->max_overtakes) break;
+        if (S->policy == 0 || aged) break;
       }
       if (pick == SIZE_MAX) break;
       Request* r = S->queue[pick];
+      r->aged = S->policy == 1 && r->overtaken >= S->max_overtakes;
       for (Request* q : S->queue)
         if (q->ticket < r->ticket) ++q->overtaken;
       S->queue.erase(S->queue.begin() + pick);
