@@ -493,8 +493,9 @@ def run_config1(ctx, torch, oracle, parity, reps, log):
     """Workload 1 (rank-16 x rank-16 complex, 8 contracted axes, first three
     axes of each operand split in two: 64 coupled block pairs of 32 x 256 x
     32): latency per call (plan + relayouts + GEMM, HIP-event and host-wall
-    time over `reps` calls after 3 warm-ups, synchronised each call) and the
-    error against the oracle, in every mode."""
+    time over `reps` calls after 3 warm-ups, synchronised each call; and the
+    same contraction as a prepared, graph-replayed call) and the error
+    against the oracle, in every mode."""
     from workloads import configs
     p = configs.config1()
     t = time.perf_counter()
@@ -536,13 +537,33 @@ def run_config1(ctx, torch, oracle, parity, reps, log):
                 host.append(1e6 * (time.perf_counter() - t))
                 ev.append(1e3 * e0.elapsed_time(e1))
         r = parity.report(c.cpu().numpy().astype(np.complex128), ref, absprod, K, mode)
+        # The same contraction as a prepared call (descriptors and plan built
+        # once, a one-problem batch replayed as a HIP graph on a side stream):
+        # the latency of repeated calls on one shape.
+        c2 = torch.empty_like(c)
+        pb = ctx.prepare_batch([(a, p.a.dims, p.a.grid, b, p.b.dims, p.b.grid, p.axes_a,
+                                 p.axes_b)], mode, outs=[c2])
+        side = torch.cuda.Stream()
+        prep = []
+        for it in range(3 + reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            with torch.cuda.stream(side):
+                pb.run()
+            side.synchronize()
+            if it >= 3:
+                prep.append(1e6 * (time.perf_counter() - t))
+        r2 = parity.report(c2.cpu().numpy().astype(np.complex128), ref, absprod, K, mode)
         out[mode] = {"p50_us_host": percentile(host, 50), "p10_us_host": percentile(host, 10),
                      "p90_us_host": percentile(host, 90), "p50_us_gpu_events": percentile(ev, 50),
                      "e_F": r["e_F"], "e_max": r["e_max"], "higham_max": r["higham"],
-                     "higham_bound": r["higham_bound"], "tolerance": parity.TOL[mode]}
+                     "higham_bound": r["higham_bound"], "tolerance": parity.TOL[mode],
+                     "prepared_p50_us_host": percentile(prep, 50),
+                     "prepared_e_F": r2["e_F"], "prepared_higham_max": r2["higham"]}
         log(f"config1 {mode}: p50 {out[mode]['p50_us_host']:.1f} us host, "
-            f"{out[mode]['p50_us_gpu_events']:.1f} us events, e_F {r['e_F']:.2e}")
-        del a, b, c, wsb
+            f"{out[mode]['p50_us_gpu_events']:.1f} us events, prepared "
+            f"{out[mode]['prepared_p50_us_host']:.1f} us, e_F {r['e_F']:.2e}")
+        del a, b, c, c2, wsb, pb
     out["oracle"] = {"single_thread_s": t_single,
                      "single_thread_gflops": flops / t_single / 1e9,
                      "openmp_s": t_omp, "openmp_threads": min(threads, 8),

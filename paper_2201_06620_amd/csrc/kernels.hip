@@ -57,6 +57,9 @@ struct PermParams {
   int64_t hi_out[16];
   int32_t hi_lds[16];
   int64_t gw;  // KIND 2: k per plane group (W = min(16, K), a power of two)
+  int64_t sstride;  // nsum > 1: elements between the input's split-K partials
+  int nsum;         // partials summed (ascending) per element read
+  int pad_;
 };
 
 // Thread-fixed low parts of the tile-local index u = tid + 256 * j.
@@ -97,6 +100,16 @@ __device__ __forceinline__ void permute_tile(const PermParams& p, int64_t t, T* 
 #pragma unroll
     for (int j = 0; j < E; ++j)
       if (!PRED || (j << 8) < tsize) v[j] = in[ib + in_lo + p.hi_in[j]];
+    // Unreduced split-K partials: add the others in ascending split order.
+    for (int q = 1; q < p.nsum; ++q) {
+#pragma unroll
+      for (int j = 0; j < E; ++j)
+        if (!PRED || (j << 8) < tsize) {
+          const T w = in[ib + in_lo + p.hi_in[j] + q * p.sstride];
+          v[j].x += w.x;
+          v[j].y += w.y;
+        }
+    }
 #pragma unroll
     for (int j = 0; j < E; ++j)
       if (!PRED || (j << 8) < tsize) tile[lds_pad(tid + (j << 8))] = v[j];
@@ -202,6 +215,8 @@ static void perm_setup(const PermLaunch& L, PermParams& p) {
   p.out2 = L.out2;
   p.in_base = L.in_base;
   p.gw = L.gw;
+  p.nsum = L.nsum;
+  p.sstride = L.sstride;
   const int tlow = (L.in_es == 16) ? 5 : 6;
   bool inS[64] = {false};
   if (R <= 2 * tlow) {
@@ -929,7 +944,7 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
   }
   hipError_t e = hipGetLastError();
   if (prof) prof->end(ev, s);
-  if (e != hipSuccess || g.splitk <= 1) return e;
+  if (e != hipSuccess || g.splitk <= 1 || g.partial_only) return e;
   int64_t total = int64_t(nbatch) * g.M * g.N;
   unsigned rg = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
   const int ev2 = prof ? prof->begin(2, s) : -1;

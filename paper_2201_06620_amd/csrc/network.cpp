@@ -79,6 +79,8 @@ struct NTensor {
   int input_idx = -1;
   int64_t off = -1;            // workspace offset (intermediates)
   int64_t bytes = 0;
+  int64_t alloc = 0;           // arena bytes at off (bytes, or the unreduced partials)
+  int nsum = 1;                // split-K partials it holds (summed by its reader's permute)
 };
 
 struct NStep {
@@ -95,6 +97,7 @@ struct NStep {
   DirectStep dstep;     // its bit maps (pointers filled at enqueue time)
   int level = 0;        // dependency level of its launch (1 = inputs only)
   int cluster = -1;     // subtree run by one workgroup (index), or -1
+  bool fused = false;   // split-K partials left for the reader's permute to sum
   int height = 0;       // height inside that subtree
 };
 
@@ -474,8 +477,35 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
   // permuted copies stay live until the level ends), and the large steps'
   // GEMMs run one after another.
   auto release_operand = [&](int id) {
-    if (!P.T[id].input) arena.release(P.T[id].off, P.T[id].bytes);
+    if (!P.T[id].input) arena.release(P.T[id].off, P.T[id].alloc);
   };
+  // A large step with split K whose result is read by a large step that
+  // permutes it leaves its partial sums unreduced: the reader's permute adds
+  // them in ascending split order (the same sums as the reduction kernel) on
+  // the way, which saves the reduction's launch and a write and read of C.
+  // Only for two partials of at least 2^20 elements: the permute adds the
+  // partials one after another per element, and with fewer elements it has
+  // too few workgroups to hide that (measured: 16 partials of 2^16 elements
+  // took a permute from 6 to 127 us).
+  {
+    std::vector<int> reader(P.T.size(), -1);
+    for (int c = 0; c < (int)P.steps.size(); ++c) {
+      reader[P.steps[c].a] = c;
+      reader[P.steps[c].b] = c;
+    }
+    for (int si = 0; si < (int)P.steps.size(); ++si) {
+      NStep& st = P.steps[si];
+      const int c = reader[nt + si];
+      if (st.direct || st.splitk != 2 || c < 0 || P.steps[c].direct) continue;
+      if (P.T[nt + si].bytes / P.es < (int64_t(1) << 20)) continue;
+      const NStep& rd = P.steps[c];
+      if ((rd.a == nt + si && rd.permuteA) || (rd.b == nt + si && rd.permuteB)) {
+        st.fused = true;
+        P.T[nt + si].nsum = st.splitk;
+      }
+    }
+  }
+  for (auto& t : P.T) t.alloc = t.bytes;
   for (auto& lv : P.levels) {
     for (int si : lv)
       if (P.steps[si].direct) P.T[nt + si].off = arena.alloc(P.T[nt + si].bytes);
@@ -499,9 +529,14 @@ rn_status plan_network(int32_t nt, const rn_tensor* T, const int32_t* const* lab
     for (int si : lv) {
       NStep& st = P.steps[si];
       if (st.direct) continue;
-      if (st.splitk > 1) st.offPart = arena.alloc(st.pbytes);
-      P.T[nt + si].off = arena.alloc(P.T[nt + si].bytes);
-      if (st.splitk > 1) arena.release(st.offPart, st.pbytes);
+      if (st.fused) {
+        P.T[nt + si].alloc = st.pbytes;  // the partials are the tensor until it is read
+        P.T[nt + si].off = arena.alloc(st.pbytes);
+      } else {
+        if (st.splitk > 1) st.offPart = arena.alloc(st.pbytes);
+        P.T[nt + si].off = arena.alloc(P.T[nt + si].bytes);
+        if (st.splitk > 1) arena.release(st.offPart, st.pbytes);
+      }
       release_operand(st.a);
       release_operand(st.b);
     }
@@ -668,6 +703,8 @@ static void build_net_tables(const NetPlan& P, const rn_tensor* T, void* ws,
           if (!(side ? st.permuteB : st.permuteA)) continue;
           PermLaunch pl;
           pl.in = ptr(side ? st.b : st.a);
+          pl.nsum = P.T[side ? st.b : st.a].nsum;
+          pl.sstride = P.T[side ? st.b : st.a].bytes / P.es;
           pl.out = w + (side ? st.offB : st.offA);
           pl.out2 = split_prec ? w + (side ? st.offB2 : st.offA2) : nullptr;
           pl.perm = side ? st.permB : st.permA;
@@ -762,6 +799,8 @@ static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hi
       } else if (st.permuteA) {
         PermLaunch pl;
         pl.in = am;
+        pl.nsum = P.T[st.a].nsum;
+        pl.sstride = P.T[st.a].bytes / P.es;
         pl.out = w + st.offA;
         pl.out2 = split_prec ? w + st.offA2 : nullptr;
         pl.perm = st.permA;
@@ -778,6 +817,8 @@ static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hi
       if (!grouped_perm && st.permuteB) {
         PermLaunch pl;
         pl.in = bm;
+        pl.nsum = P.T[st.b].nsum;
+        pl.sstride = P.T[st.b].bytes / P.es;
         pl.out = w + st.offB;
         pl.out2 = split_prec ? w + st.offB2 : nullptr;
         pl.perm = st.permB;
@@ -816,8 +857,10 @@ static rn_status enqueue_pass(const NetPlan& P, const rn_tensor* T, void* ws, hi
         g.c_bstride[q] = st.c_bs[q];
       }
       g.splitk = st.splitk;
-      g.partial = st.splitk > 1 ? w + st.offPart : nullptr;
-      if (si < (int)per_level.tile.size() && per_level.tile[si] >= 0) {
+      g.partial = st.splitk > 1 ? w + (st.fused ? P.T[nt + si].off : st.offPart) : nullptr;
+      g.partial_only = st.fused;  // the reader's permute sums the partials
+      if (si < (int)per_level.tile.size() && per_level.tile[si] >= 0 &&
+          (!st.fused || gemm_tile_splits(P.mode, per_level.tile[si]))) {
         // A tuned tile; the planned split (and its partials) only if it splits.
         g.tile = per_level.tile[si];
         if (!gemm_tile_splits(P.mode, g.tile)) {

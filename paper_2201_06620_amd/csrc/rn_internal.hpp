@@ -129,6 +129,10 @@ struct PermLaunch {
   int kind = 0;              // 0 copy, 1 split complex64 -> bf16 hi/lo (packed
                              // pairs), 2 planar-group split (Gauss form)
   int64_t gw = 0;            // kind 2: k per plane group, min(16, K)
+  // The input holds nsum split-K partials sstride elements apart: each
+  // element read is their sum in ascending order.
+  int nsum = 1;
+  int64_t sstride = 0;
 };
 hipError_t launch_permute(const PermLaunch& p, hipStream_t s);
 
@@ -151,6 +155,7 @@ struct GemmLaunch {
   int tile = -1;             // tile config index, -1 = choose
   bool planar = false;       // operands in planar Gauss form (permute kind 2;
                              // tile must be a planar one)
+  bool partial_only = false; // splitk > 1: leave the partials, launch no reduction
 };
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof = nullptr);
 int gemm_tile_count(rn_mode mode);
