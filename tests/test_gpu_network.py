@@ -57,6 +57,36 @@ def test_config2_amplitude(ctx, mode):
     assert err < TOL[mode]
 
 
+@pytest.mark.parametrize("mode", ["fp64", "fp32_4m", "bf16x3"])
+def test_config2_prepared_replay_equals_plain_call(ctx, mode):
+    # The 20-qubit amplitude (subtrees of tiny steps, a large step whose split-K
+    # partials the next permute sums) as a prepared call on a side stream --
+    # direct, captured, then replayed from the graph's own parameter table --
+    # gives the plain call's bits, per-slice values included.
+    import torch
+    w = configs.config2()
+    dt = torch.complex128 if mode == "fp64" else torch.complex64
+    ts = [torch.from_numpy(np.ascontiguousarray(t.reshape(-1))).to(dt).cuda()
+          for t in w.network.tensors]
+    ns = 1 << len(w.sliced)
+    sl_c = torch.zeros(2 * ns, dtype=torch.float64, device="cuda")
+    amp_c = ctx.contract_network(ts, w.network.labels, w.path, w.sliced, mode, slices=sl_c)
+    torch.cuda.synchronize()
+    prep = ctx.prepare_network(ts, w.network.labels, w.path, w.sliced, mode)
+    s = torch.cuda.Stream()
+    amp = torch.zeros(2, dtype=torch.float64, device="cuda")
+    sl_p = torch.zeros_like(sl_c)
+    for it in range(4):
+        amp.fill_(float("nan"))
+        sl_p.fill_(float("nan"))
+        torch.cuda.synchronize()
+        prep.run(amp=amp, slices=sl_p, stream=s)
+        s.synchronize()
+        assert np.array_equal(amp.cpu().numpy(), amp_c.cpu().numpy()), it
+        assert np.array_equal(sl_p.cpu().numpy(), sl_c.cpu().numpy()), it
+    del prep
+
+
 def test_config2_per_slice_values(ctx):
     import torch
     w = configs.config2()
