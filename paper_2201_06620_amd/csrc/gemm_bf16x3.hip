@@ -389,7 +389,10 @@ __device__ __forceinline__ void cgemm_bf16x3_ri_body(const GemmParams& p, int tm
 // chunk q of row r at q ^ swz(r)) filled by global_load_lds_dwordx4 on
 // interior tiles (a wave writes 64 consecutive slots; slot s of a stage is
 // row s / (BK / 4), stored chunk s % (BK / 4)).  One array per buffer and the
-// stage loop unrolled by two, as in the FP32 direct-to-LDS tile.
+// stage loop unrolled by two, as in the FP32 direct-to-LDS tile.  The
+// operands are either two arrays (hi, lo) or one row-interleaved array
+// (p.ilv: per 16 k of a row, 16 hi words then 16 lo words), where a stage of
+// a row is one 128-byte line rather than a 64-byte half line of each array.
 template <int WM, int WN, int TM, int TN, int BK>
 __device__ __forceinline__ void cgemm_bf16x3_dl_body(const GemmParams& p, int tm, int tn,
                                                      int split, int b) {
@@ -429,6 +432,9 @@ __device__ __forceinline__ void cgemm_bf16x3_dl_body(const GemmParams& p, int tm
   const int64_t kend = min(p.K, kbeg + p.kchunk);
   const int nk = (int)((kend - kbeg + BK - 1) / BK);
   const bool interior = row0 + BM <= p.M && col0 + BN <= p.N && (kend - kbeg) % BK == 0;
+  // Row-interleaved operands (p.ilv): the 16 k of a stage start at word 2 k0
+  // of the row, hi then lo (A2 = A + 16 words); otherwise at word k0.
+  const int64_t kmul = 1 + p.ilv;
 
   auto dma = [&](auto buf, int64_t k0) {
     uint32_t* ah = pick(buf, Ah0, Ah1);
@@ -438,7 +444,7 @@ __device__ __forceinline__ void cgemm_bf16x3_dl_body(const GemmParams& p, int tm
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       const int s = tid + 256 * j, r = s / CPR, q = (s % CPR) ^ swz(r);
-      const int64_t o = (row0 + r) * p.lda + k0 + 4 * q;
+      const int64_t o = (row0 + r) * p.lda + kmul * k0 + 4 * q;
       const int d = 4 * (256 * j + 64 * wave);
       __builtin_amdgcn_global_load_lds(Agh + o, (__attribute__((address_space(3))) void*)(ah + d),
                                        16, 0, 0);
@@ -448,7 +454,7 @@ __device__ __forceinline__ void cgemm_bf16x3_dl_body(const GemmParams& p, int tm
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int s = tid + 256 * j, r = s / CPR, q = (s % CPR) ^ swz(r);
-      const int64_t o = (col0 + r) * p.ldb + k0 + 4 * q;
+      const int64_t o = (col0 + r) * p.ldb + kmul * k0 + 4 * q;
       const int d = 4 * (256 * j + 64 * wave);
       __builtin_amdgcn_global_load_lds(Bgh + o, (__attribute__((address_space(3))) void*)(bh + d),
                                        16, 0, 0);
@@ -469,11 +475,11 @@ __device__ __forceinline__ void cgemm_bf16x3_dl_body(const GemmParams& p, int tm
 #pragma unroll
     for (int j = 0; j < NA; ++j) {
       const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) * 4;
-      const int64_t gr = row0 + r, gk = k0 + c;
+      const int64_t gr = row0 + r, gk = k0 + c, o = gr * p.lda + kmul * k0 + c;
       uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
       if (gr < p.M && gk < kend) {
-        h = ld4(Agh + gr * p.lda + gk, gk);
-        l = ld4(Agl + gr * p.lda + gk, gk);
+        h = ld4(Agh + o, gk);
+        l = ld4(Agl + o, gk);
       }
       rah[j] = h;
       ral[j] = l;
@@ -481,11 +487,11 @@ __device__ __forceinline__ void cgemm_bf16x3_dl_body(const GemmParams& p, int tm
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int s = tid + 256 * j, r = s / CPR, c = (s % CPR) * 4;
-      const int64_t gr = col0 + r, gk = k0 + c;
+      const int64_t gr = col0 + r, gk = k0 + c, o = gr * p.ldb + kmul * k0 + c;
       uint4 h = make_uint4(0u, 0u, 0u, 0u), l = h;
       if (gr < p.N && gk < kend) {
-        h = ld4(Bgh + gr * p.ldb + gk, gk);
-        l = ld4(Bgl + gr * p.ldb + gk, gk);
+        h = ld4(Bgh + o, gk);
+        l = ld4(Bgl + o, gk);
       }
       rbh[j] = h;
       rbl[j] = l;

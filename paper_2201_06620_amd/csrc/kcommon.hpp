@@ -87,6 +87,8 @@ struct GemmParams {
   int crs, ccs;
   int nbb;
   int splitk;
+  int ilv;   // split-BF16 operands row-interleaved (hi, lo per 16 k); lda counts words
+  int pad_;
   int64_t kchunk;
   int tiles_m, tiles_n;
   int64_t a_bs[RN_MAX_SLICED], b_bs[RN_MAX_SLICED], c_bs[RN_MAX_SLICED];

@@ -131,6 +131,16 @@ __device__ __forceinline__ void permute_tile(const PermParams& p, int64_t t, T* 
         bf16_split(v[j].y, hi_, li_);
         reinterpret_cast<uint32_t*>(p.out)[oo] = hr | (hi_ << 16);
         reinterpret_cast<uint32_t*>(p.out2)[oo] = lr | (li_ << 16);
+      } else if constexpr (KIND == 3) {
+        // Row-interleaved split: element oo = r K + k of the K-contiguous
+        // operand (K a multiple of 16) goes to word 2 (oo - oo % 16) + oo % 16
+        // (hi) and 16 words later (lo), so each 16 k of a row are one line.
+        uint32_t hr, lr, hi_, li_;
+        bf16_split(v[j].x, hr, lr);
+        bf16_split(v[j].y, hi_, li_);
+        uint32_t* o = reinterpret_cast<uint32_t*>(p.out) + 2 * (oo & ~int64_t(15)) + (oo & 15);
+        o[0] = hr | (hi_ << 16);
+        o[16] = lr | (li_ << 16);
       } else {
         // Planar-group split for the Gauss form: element oo = r K + k of the
         // K-contiguous operand goes to 6 (oo - w) + q W + w, w = oo % W, in
@@ -292,8 +302,11 @@ hipError_t launch_permute(const PermLaunch& L, hipStream_t s) {
   unsigned grid = (unsigned)std::min<int64_t>(p.ntiles, 256 * 64);
   if (L.kind == 2 && (L.in_es != 8 || L.gw < 1 || L.gw > 16 || (L.gw & (L.gw - 1))))
     return hipErrorInvalidValue;
+  if (L.kind == 3 && (L.in_es != 8 || L.perm.nbits < 4)) return hipErrorInvalidValue;
   if (L.kind == 1)
     launch_perm_e<float2, 1>(p, E, grid, lds, s);
+  else if (L.kind == 3)
+    launch_perm_e<float2, 3>(p, E, grid, lds, s);
   else if (L.kind == 2)
     launch_perm_e<float2, 2>(p, E, grid, lds, s);
   else if (L.in_es == 16)
@@ -854,6 +867,7 @@ static void fill_params(const GemmLaunch& g, GemmParams& p) {
   }
   p.splitk = g.splitk;
   p.kchunk = (g.K + g.splitk - 1) / g.splitk;
+  p.ilv = g.interleaved ? 1 : 0;
 }
 
 static int tile_count_of(rn_mode mode) {
@@ -867,6 +881,11 @@ int gemm_tile_count(rn_mode mode) { return tile_count_of(mode); }
 
 bool gemm_tile_planar(rn_mode mode, int tile) {
   return mode == RN_BF16X3 && (tile == 11 || tile == 12);
+}
+
+// The split-BF16 direct-to-LDS tiles (9, 10).
+bool gemm_tile_interleaved(rn_mode mode, int tile) {
+  return mode == RN_BF16X3 && (tile == 9 || tile == 10);
 }
 
 // The skinny tiles run problems whose shorter output side has at most their
@@ -907,6 +926,10 @@ hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof) {
   const int tile = g.planar || gemm_tile_valid(g.mode, g.tile, g.M, g.N)
                        ? g.tile
                        : choose_tile(g.mode, g.M, g.N, g.K, int64_t(1) << g.nbb);
+  // Interleaved operands: a tile that reads them, whole 16-k groups per split.
+  if (g.interleaved && (!gemm_tile_interleaved(g.mode, tile) || g.nbb != 0 || g.K % 16 != 0 ||
+                        p.kchunk % 16 != 0 || g.lda != 2 * g.K || g.ldb != 2 * g.K))
+    return hipErrorInvalidValue;
   const TileCfg& c = tile_of(g.mode, tile);
   const unsigned nbatch = 1u << g.nbb;
   const int ev = prof ? prof->begin(1, s) : -1;

@@ -73,7 +73,7 @@ struct TdPlan {
   int pair_cbits[RN_MAX_RANK];  // refined contracted grid bits, pair order
   // Workspace sub-buffers (byte offsets; -1 when unused).
   int64_t off_a = -1, off_b = -1, off_a2 = -1, off_b2 = -1, off_part = -1;
-  bool planar_ok = false;  // workspace holds planar split-BF16 operands
+  bool planar_ok = false;  // workspace holds planar or interleaved split-BF16 operands
   int splitk = 1;
   size_t ws_bytes = 0;
   double flops = 0;
@@ -93,9 +93,10 @@ struct SplitPolicy {
 };
 
 // planar_ok: the call may stage split-BF16 operands in the planar Gauss form
-// (six bf16 planes in one array, 12 bytes per complex instead of 8): the
-// single block tensordot entry points; their workspace is sized for it (the
-// packed form's hi and lo arrays then sit inside that region).
+// (six bf16 planes in one array, 12 bytes per complex instead of 8) or
+// row-interleaved (hi and lo per 16 k of a row in one array): the single
+// block tensordot entry points; their workspace is sized for it (the packed
+// form's hi and lo arrays then sit inside that region).
 rn_status plan_tensordot(const rn_tensor* A, const rn_tensor* B, int32_t k,
                          const int32_t* axesA, const int32_t* axesB, rn_mode mode,
                          TdPlan* P, bool allow_splitk = true,
@@ -127,7 +128,8 @@ struct PermLaunch {
   BitPerm perm;              // output bit -> input bit
   int in_es = 8;             // input element bytes (8 or 16)
   int kind = 0;              // 0 copy, 1 split complex64 -> bf16 hi/lo (packed
-                             // pairs), 2 planar-group split (Gauss form)
+                             // pairs), 2 planar-group split (Gauss form),
+                             // 3 row-interleaved split (hi and lo per 16 k)
   int64_t gw = 0;            // kind 2: k per plane group, min(16, K)
   // The input holds nsum split-K partials sstride elements apart: each
   // element read is their sum in ascending order.
@@ -155,6 +157,10 @@ struct GemmLaunch {
   int tile = -1;             // tile config index, -1 = choose
   bool planar = false;       // operands in planar Gauss form (permute kind 2;
                              // tile must be a planar one)
+  bool interleaved = false;  // split-BF16 operands from permute kind 3: per row,
+                             // per 16 k, 16 packed hi words then 16 lo words
+                             // (A2 = A + 16 words, lda = 2K); the tile must be
+                             // one of gemm_tile_interleaved, K a multiple of 16
   bool partial_only = false; // splitk > 1: leave the partials, launch no reduction
 };
 hipError_t launch_gemm(const GemmLaunch& g, hipStream_t s, Profiler* prof = nullptr);
@@ -171,6 +177,11 @@ bool gemm_tile_splits(rn_mode mode, int tile);
 // per complex in one array); only the single block tensordot stages
 // operands that way.
 bool gemm_tile_planar(rn_mode mode, int tile);
+// Tiles that can also read row-interleaved split-BF16 operands (permute
+// kind 3): per 16 k of a row one 128-byte line holds the hi and lo parts, so
+// a K stage fetches whole lines instead of two half lines from two arrays.
+// Only the single block tensordot stages operands that way.
+bool gemm_tile_interleaved(rn_mode mode, int tile);
 // The planar tile a single block tensordot uses by default for this shape,
 // or -1.
 int gemm_planar_default(rn_mode mode, int64_t M, int64_t N, int64_t K);

@@ -447,3 +447,30 @@ def test_bf16_gauss_group_layout_formula():
                     assert a == r * 6 * K + 6 * W * (k // W) + q * W + k % W
                     seen.add(a)
         assert seen == set(range(3 * 6 * K))
+
+
+def test_bf16_interleaved_layout_matches_tile_reads():
+    # Permute kind 3 writes element oo = r K + k (K a multiple of 16) at word
+    # 2 (oo - oo % 16) + oo % 16 (hi) and 16 words later (lo).  The
+    # direct-to-LDS tile reads the 16-byte chunk of words c .. c + 3 of a
+    # stage k0 (a multiple of 16) at row * 2K + 2 k0 + c (hi, A) and the
+    # same plus 16 (lo, A2 = A + 16 words).  Every (row, k, part) must be
+    # read from where it was written, and the writes must tile 2 M K words.
+    assert "KIND == 3" in SRC and "kmul * k0" in SRC
+    for K in (16, 32, 64):
+        M = 3
+        written = {}
+        for r in range(M):
+            for k in range(K):
+                oo = r * K + k
+                base = 2 * (oo - oo % 16) + oo % 16
+                written[(r, k, 0)] = base
+                written[(r, k, 1)] = base + 16
+        assert sorted(written.values()) == list(range(2 * M * K))
+        for r in range(M):
+            for k0 in range(0, K, 16):
+                for c in range(0, 16, 4):
+                    for part in (0, 1):
+                        w0 = r * 2 * K + 2 * k0 + c + 16 * part
+                        for t in range(4):
+                            assert written[(r, k0 + c + t, part)] == w0 + t
