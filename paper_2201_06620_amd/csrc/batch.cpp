@@ -5,8 +5,9 @@
 // as one group per GEMM tile shape: a grouped permute of the operands its
 // problems need, then one grouped GEMM launch, problems ordered by
 // decreasing work so the largest start first; the groups are spread over up
-// to four streams, and problems with few tiles and a long K split K with one
-// grouped reduction at the end.  The per-problem parameters travel in a
+// to four streams (largest first onto the least loaded, then each stream's
+// groups issued smallest first), and problems with few tiles and a long K
+// split K with one grouped reduction at the end.  The per-problem parameters travel in a
 // small table copied into the workspace.  When the same call is repeated on
 // a non-default stream, the recorded sequence (table copy plus launches) is
 // replayed as a HIP graph, found before any planning.
@@ -95,7 +96,8 @@ struct BatchPlan {
 // One group per GEMM tile shape: the grouped permute of the operands its
 // problems need, then its grouped GEMM.  Groups are spread over up to four
 // streams, longest first onto the least loaded stream, so one group's
-// (HBM-bound) permute overlaps other groups' GEMMs.
+// (HBM-bound) permute overlaps other groups' GEMMs; `perms`, `gemms` and
+// `lane` are in issue order (smallest group first).
 struct Launches {
   std::vector<char> table;
   std::vector<GroupedLaunch> perms;  // perms[g].n == 0: no permute needed
@@ -218,16 +220,19 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
   for (auto& kv : by_tile) {
     std::vector<PermLaunch> pj;
     std::vector<GemmLaunch> gg;
-    double c = 0;
+    // Estimated time of the group, fitted to serialized kernel times of the
+    // uneven 256-problem batch: 1.5 times each problem's roofline time (MFMA
+    // flops or HBM bytes), 2 us per problem and 10 us per group (small
+    // problems are latency-bound), plus the permutes at 5 TB/s.
+    double c = 10e-6;
     for (int i : kv.second) {
       pj.insert(pj.end(), jobs[i].begin(), jobs[i].end());
       gg.push_back(gl[i]);
       const TdPlan& P = bp.plans[i];
-      // Rough time: MFMA-bound flops or HBM-bound bytes, plus the permutes.
       const double bytes = double(P.es) * double(P.M * P.K + P.N * P.K + P.M * P.N);
-      c += std::max(P.flops / 150e12, bytes / 6e12) +
-           (P.permuteA ? 2.0 * P.es * P.M * P.K / 6e12 : 0.0) +
-           (P.permuteB ? 2.0 * P.es * P.N * P.K / 6e12 : 0.0);
+      c += 1.5 * std::max(P.flops / 157.3e12, bytes / 8e12) + 2e-6 +
+           (P.permuteA ? 2.0 * P.es * P.M * P.K / 5e12 : 0.0) +
+           (P.permuteB ? 2.0 * P.es * P.N * P.K / 5e12 : 0.0);
     }
     GroupedLaunch G, PG;
     size_t base = L->table.size();
@@ -247,21 +252,29 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
     for (const GemmLaunch& g : gg)
       if (g.splitk > 1) split_probs.push_back(g);
   }
-  // Longest group first, each onto the least loaded of up to four streams.
+  // Longest group first, each onto the least loaded of up to four streams;
+  // then issued shortest first, so each stream runs its small, latency-bound
+  // groups while the others' large groups fill the GPU, and ends on its
+  // largest group instead of a serial tail of small launches.
   const int ng = (int)L->gemms.size();
   std::vector<int> idx(ng);
   std::iota(idx.begin(), idx.end(), 0);
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
   L->lanes = std::max(1, std::min(ng, 4));
   std::vector<double> load(L->lanes, 0.0);
-  std::vector<GroupedLaunch> perms, gemms;
-  L->lane.clear();
+  std::vector<int> lane_of(ng);
   for (int g : idx) {
     const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
     load[j] += cost[g];
+    lane_of[g] = j;
+  }
+  std::vector<GroupedLaunch> perms, gemms;
+  L->lane.clear();
+  for (int q = ng - 1; q >= 0; --q) {
+    const int g = idx[q];
     perms.push_back(L->perms[g]);
     gemms.push_back(L->gemms[g]);
-    L->lane.push_back(j);
+    L->lane.push_back(lane_of[g]);
   }
   L->perms.swap(perms);
   L->gemms.swap(gemms);
