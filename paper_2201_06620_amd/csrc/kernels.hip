@@ -77,6 +77,27 @@ __device__ __forceinline__ void perm_lo(const PermParams& p, int tid, int64_t& i
   }
 }
 
+// Streaming accesses of the permutes: every element is read once and written
+// once, so both go out as non-temporal (measured on the 2 GiB complex64
+// relayout: 0.84 -> 0.80 ms).
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  typedef typename std::conditional<sizeof(T) == 8, float, double>::type S;
+  typedef S nv __attribute__((ext_vector_type(2)));
+  const nv t = __builtin_nontemporal_load(reinterpret_cast<const nv*>(p));
+  T v;
+  v.x = t.x;
+  v.y = t.y;
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, const T& v) {
+  typedef typename std::conditional<sizeof(T) == 8, float, double>::type S;
+  typedef S nv __attribute__((ext_vector_type(2)));
+  const nv t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<nv*>(p));
+}
+
 // One tile t of a permutation.  E elements per thread (tile = 256 * E
 // elements, or fewer for a tile smaller than one workgroup); with PRED the
 // tile may hold fewer than 256 * E elements.  All loads of a tile are
@@ -99,7 +120,7 @@ __device__ __forceinline__ void permute_tile(const PermParams& p, int64_t t, T* 
   if (active) {
 #pragma unroll
     for (int j = 0; j < E; ++j)
-      if (!PRED || (j << 8) < tsize) v[j] = in[ib + in_lo + p.hi_in[j]];
+      if (!PRED || (j << 8) < tsize) v[j] = ld_stream(in + ib + in_lo + p.hi_in[j]);
     // Unreduced split-K partials: add the others in ascending split order.
     for (int q = 1; q < p.nsum; ++q) {
 #pragma unroll
@@ -124,7 +145,7 @@ __device__ __forceinline__ void permute_tile(const PermParams& p, int64_t t, T* 
       if (PRED && (j << 8) >= tsize) continue;
       const int64_t oo = ob + out_lo + p.hi_out[j];
       if constexpr (KIND == 0) {
-        reinterpret_cast<T*>(p.out)[oo] = v[j];
+        st_stream(reinterpret_cast<T*>(p.out) + oo, v[j]);
       } else if constexpr (KIND == 1) {
         uint32_t hr, lr, hi_, li_;
         bf16_split(v[j].x, hr, lr);
