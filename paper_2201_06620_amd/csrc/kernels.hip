@@ -59,7 +59,7 @@ struct PermParams {
   int64_t gw;  // KIND 2: k per plane group (W = min(16, K), a power of two)
   int64_t sstride;  // nsum > 1: elements between the input's split-K partials
   int nsum;         // partials summed (ascending) per element read
-  int pad_;
+  int nt_store;     // copy: non-temporal stores (outputs beyond the caches)
 };
 
 // Thread-fixed low parts of the tile-local index u = tid + 256 * j.
@@ -77,9 +77,11 @@ __device__ __forceinline__ void perm_lo(const PermParams& p, int tid, int64_t& i
   }
 }
 
-// Streaming accesses of the permutes: every element is read once and written
-// once, so both go out as non-temporal (measured on the 2 GiB complex64
-// relayout: 0.84 -> 0.80 ms).
+// Streaming accesses of the permutes: every element is read once, so loads
+// are non-temporal; stores too when the launch's outputs are larger than the
+// 256 MiB memory-side cache (a smaller output is read next by the GEMM, which
+// then finds it there: non-temporal stores cost the FP64 20-qubit amplitude
+// 7 us).  Measured: 2 GiB complex64 relayout 0.84 -> 0.80 ms.
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p) {
   typedef typename std::conditional<sizeof(T) == 8, float, double>::type S;
@@ -145,7 +147,10 @@ __device__ __forceinline__ void permute_tile(const PermParams& p, int64_t t, T* 
       if (PRED && (j << 8) >= tsize) continue;
       const int64_t oo = ob + out_lo + p.hi_out[j];
       if constexpr (KIND == 0) {
-        st_stream(reinterpret_cast<T*>(p.out) + oo, v[j]);
+        if (p.nt_store)
+          st_stream(reinterpret_cast<T*>(p.out) + oo, v[j]);
+        else
+          reinterpret_cast<T*>(p.out)[oo] = v[j];
       } else if constexpr (KIND == 1) {
         uint32_t hr, lr, hi_, li_;
         bf16_split(v[j].x, hr, lr);
@@ -247,6 +252,7 @@ static void perm_setup(const PermLaunch& L, PermParams& p) {
   p.in_base = L.in_base;
   p.gw = L.gw;
   p.nsum = L.nsum;
+  p.nt_store = (int64_t(L.in_es) << R) > (int64_t(256) << 20) ? 1 : 0;
   p.sstride = L.sstride;
   const int tlow = (L.in_es == 16) ? 5 : 6;
   bool inS[64] = {false};
@@ -347,13 +353,17 @@ size_t grouped_perm_build(const std::vector<PermLaunch>& jobs, std::vector<char>
   std::vector<PermParams> ps(jobs.size());
   std::vector<int32_t> prefix(jobs.size() + 1, 0);
   int max_tsize = 1;
-  int64_t total = 0;
+  int64_t total = 0, out_bytes = 0;
   for (size_t i = 0; i < jobs.size(); ++i) {
     perm_setup(jobs[i], ps[i]);
     max_tsize = std::max(max_tsize, 1 << ps[i].nS);
     total += ps[i].ntiles;
     prefix[i + 1] = prefix_entry(total);
+    out_bytes += int64_t(jobs[i].in_es) << jobs[i].perm.nbits;
   }
+  // The launch's outputs together decide: beyond the memory-side cache, they
+  // are evicted before the GEMMs read them anyway.
+  for (PermParams& q : ps) q.nt_store = out_bytes > (int64_t(256) << 20) ? 1 : 0;
   G.blocks = grouped_blocks(total);
   G.lds = size_t(max_tsize + (max_tsize >> 5) + 1) * G.es;
   G.params_off = 0;
