@@ -291,6 +291,9 @@ def run_weak_share(args, torch, rn, log):
     ctx = rn.Context(0)
     dev = "cuda:0"
     mb_bits, nb_inner, kb_inner = args.weak_block_bits
+    oracle = None
+    if not args.no_cpu_baseline:
+        import oracle
 
     def gen_device(n, seed):
         g = torch.Generator(device=dev)
@@ -321,15 +324,22 @@ def run_weak_share(args, torch, rn, log):
         return [2] * ua, gu, [2] * va, gv, ax_u, ax_v
 
     def sample_check(c_flat, u_rows, v_rows, m_total, n_total, k_total, blocked, bn_bits):
-        # A few outputs recomputed in float64 with numpy from the operand rows.
+        # A few outputs recomputed in complex128 from the operand rows: by the
+        # oracle (the contraction of the two rows over all their axes) in the
+        # CPU-baseline leg, else by numpy's dot product.
         rs = np.random.default_rng(13)
         worst = 0.0
+        kb = int(k_total).bit_length() - 1
         for _ in range(4):
             i = int(rs.integers(0, m_total))
             j = int(rs.integers(0, n_total))
             ur = u_rows(i).astype(np.complex128)
             vr = v_rows(j).astype(np.complex128)
-            ref = np.dot(ur, vr)
+            if oracle is not None:
+                ref = complex(oracle.tensordot(ur.reshape([2] * kb), vr.reshape([2] * kb),
+                                               list(range(kb)), list(range(kb))))
+            else:
+                ref = np.dot(ur, vr)
             if blocked:
                 bi, ii = i >> mb_bits, i & ((1 << mb_bits) - 1)
                 bj, jj = j >> nb_inner, j & ((1 << nb_inner) - 1)
@@ -438,7 +448,8 @@ def run_weak_share(args, torch, rn, log):
                     "eq1_task_elems": bk * kb_ * (m_b + n_b) + m_b * n_b,
                     "eq2_task_elems": kb_ * (m_b + n_b) + m_b * n_b,
                     "h2d_bytes": h2d, "h2d_GBps": round(h2d / total_s / 1e9, 2) if h2d else None,
-                    "max_rel_err_sampled": worst}
+                    "max_rel_err_sampled": worst,
+                    "reference": "numpy" if oracle is None else "oracle"}
             print(json.dumps(line), flush=True)
             results.append(line)
     ctx.close()
