@@ -103,6 +103,7 @@ struct Launches {
   std::vector<GroupedLaunch> perms;  // perms[g].n == 0: no permute needed
   std::vector<GroupedLaunch> gemms;
   std::vector<int> lane;             // stream slot of each group
+  std::vector<uint64_t> sig;         // signature of each group (group_signature)
   int lanes = 1;
   GroupedLaunch reduce;              // split-K partials of all groups
 };
@@ -155,6 +156,21 @@ rn_status plan_batch(int32_t n, const rn_tensor* A, const rn_tensor* B, const in
   });
   bp->table_off = off;
   return RN_OK;
+}
+
+// Identity of one tile group for its measured time: mode, tile, and each
+// problem's shape, relayouts and K splits, in launch order.
+uint64_t group_signature(const BatchPlan& bp, const std::vector<int>& probs, int tile,
+                         const std::vector<int>& splits) {
+  uint64_t h = hash_bytes(1469598103934665603ull, "group", 5);
+  h = hash_bytes(h, &tile, sizeof(tile));
+  for (size_t q = 0; q < probs.size(); ++q) {
+    const TdPlan& P = bp.plans[probs[q]];
+    const int32_t v[7] = {(int32_t)P.mode, P.mbits,         P.nbits,  P.kbits,
+                          P.permuteA,      P.permuteB,      splits[q]};
+    h = hash_bytes(h, v, sizeof(v));
+  }
+  return h;
 }
 
 // Parameter tables for the grouped launches; pointers refer to `ws`.
@@ -217,6 +233,7 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
   std::vector<char> part;
   std::vector<GemmLaunch> split_probs;
   std::vector<double> cost;
+  std::vector<uint64_t> sigs;
   for (auto& kv : by_tile) {
     std::vector<PermLaunch> pj;
     std::vector<GemmLaunch> gg;
@@ -234,6 +251,13 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
            (P.permuteA ? 2.0 * P.es * P.M * P.K / 5e12 : 0.0) +
            (P.permuteB ? 2.0 * P.es * P.N * P.K / 5e12 : 0.0);
     }
+    std::vector<int> splits;
+    for (const GemmLaunch& g : gg) splits.push_back(g.splitk);
+    const uint64_t sig = group_signature(bp, kv.second, kv.first, splits);
+    if (h) {
+      auto it = h->group_s.find(sig);
+      if (it != h->group_s.end()) c = it->second;
+    }
     GroupedLaunch G, PG;
     size_t base = L->table.size();
     if (grouped_gemm_build(gg, kv.first, part, G) == 0) continue;
@@ -249,6 +273,7 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
     L->gemms.push_back(G);
     L->perms.push_back(PG);
     cost.push_back(c);
+    sigs.push_back(sig);
     for (const GemmLaunch& g : gg)
       if (g.splitk > 1) split_probs.push_back(g);
   }
@@ -270,11 +295,13 @@ void build_launches(const rn_ctx* h, const BatchPlan& bp, const rn_tensor* A, co
   }
   std::vector<GroupedLaunch> perms, gemms;
   L->lane.clear();
+  L->sig.clear();
   for (int q = ng - 1; q >= 0; --q) {
     const int g = idx[q];
     perms.push_back(L->perms[g]);
     gemms.push_back(L->gemms[g]);
     L->lane.push_back(lane_of[g]);
+    L->sig.push_back(sigs[g]);
   }
   L->perms.swap(perms);
   L->gemms.swap(gemms);
@@ -665,6 +692,31 @@ rn_status rn_autotune_batch(rn_handle h, int32_t n, const rn_tensor* A, const rn
     if (st != RN_OK) break;
     h->tune[key] = best;
     h->tune_ms[key] = times;
+  }
+  // Then each tile group of the batch with the chosen tiles, once warm and
+  // once timed, one after another: the batch assigns streams from these times.
+  if (st == RN_OK && ws && ws_bytes >= bp.table_off + grouped_table_bound(mode, n)) {
+    Launches L;
+    build_launches(h, bp, A, B, C, static_cast<char*>(ws), &L);
+    char* table_dev = static_cast<char*>(ws) + bp.table_off;
+    st = upload_table(h, L.table, table_dev, s);
+    for (size_t g = 0; g < L.gemms.size() && st == RN_OK; ++g) {
+      for (int rep = 0; rep < 2 && st == RN_OK; ++rep) {
+        if (rep == 1) hipEventRecord(e0, s);
+        if ((e = launch_permute_grouped(L.perms[g], table_dev, s)) != hipSuccess ||
+            (e = launch_gemm_grouped(L.gemms[g], table_dev, s)) != hipSuccess)
+          st = hipf(e, "group timing launch");
+      }
+      if (st != RN_OK) break;
+      hipEventRecord(e1, s);
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+        st = hipf(e, "group timing");
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      h->group_s[L.sig[g]] = 1e-3 * double(ms);
+    }
   }
   h->prof.on = saved_prof;
   hipEventDestroy(e0);

@@ -328,6 +328,10 @@ struct rn_ctx {
   std::map<std::tuple<int, int, int, int>, int> tune;
   // Milliseconds per launch of every tile shape timed for that key.
   std::map<std::tuple<int, int, int, int>, std::vector<float>> tune_ms;
+  // Batch tile groups timed by the autotuner (seconds, one serialized run of
+  // the group's permute and GEMM), by group signature; the batch's stream
+  // assignment uses them in place of its estimate.
+  std::map<uint64_t, double> group_s;
   std::string tune_path;
   // Pinned staging for parameter tables of direct (not captured) launches.
   void* pinned = nullptr;
