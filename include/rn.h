@@ -217,10 +217,15 @@ rn_status rn_block_tensordot_batch(rn_handle h, int32_t n, const rn_tensor* A,
  * measurement.  For every problem shape (mode,
  * log2 M, log2 N, log2 K) of the batch that is not tuned yet, times each GEMM
  * tile configuration on that problem (one warm-up and three timed launches,
- * HIP events) and keeps the fastest.  Runs synchronously on `stream` and
- * writes C (arguments as rn_block_tensordot_batch).  The choices live in the
- * handle and are used by every later call on it; they never change during a
- * call, so results are reproducible.  When the environment variable
+ * HIP events) and keeps the fastest.  Then, when the workspace is the size
+ * rn_block_tensordot_batch_plan gives, times each tile group of the batch
+ * once (its grouped relayout and GEMM, one after another); later batch calls
+ * spread the groups over their streams by these times.  Runs synchronously
+ * on `stream` and writes C (arguments as rn_block_tensordot_batch; C's
+ * contents afterwards are unspecified).  The choices live in the handle and
+ * are used by every later call on it; they never change during a call, and
+ * neither tiles nor stream placement change any result bit.  When the
+ * environment variable
  * RN_TUNE_CACHE names a file, rn_create loads it and every autotune run
  * rewrites it.  save/load/clear manage the table explicitly. */
 rn_status rn_autotune_batch(rn_handle h, int32_t n, const rn_tensor* A, const rn_tensor* B,
