@@ -716,7 +716,9 @@ class PreparedBatch:
         self.wp, self.wn = ctx._workspace(ws_n.value, workspace)
 
     def autotune(self):
-        """Time the tile shapes of every untuned problem shape (synchronous)."""
+        """Time the tile shapes of every untuned problem shape, then each tile
+        group of the batch (synchronous); the outputs' contents afterwards are
+        unspecified until the next run()."""
         check(lib().rn_autotune_batch(self.ctx.h, self.n, self.As, self.Bs, self.ks.ctypes.data,
                                       self.pa, self.pb, self.Cs, mode_id(self.mode), self.wp,
                                       self.wn, self.ctx._stream()), "autotune")
