@@ -616,7 +616,9 @@ __device__ __forceinline__ void cgemm_bf16x3_dl_body(const GemmParams& p, int tm
 
 RN_GEMM_ENTRY(cgemm_bf16x3)
 RN_GEMM_ENTRY(cgemm_bf16x3_ri)
-RN_GEMM_ENTRY_OCC(cgemm_bf16x3_dl, 2)
+// Column groups of 4 row tiles: on the rank-28 pair 444-445 against 435-439
+// useful TFLOP/s with groups of 8 (2: 419, 16: 401, in one timing run).
+RN_GEMM_ENTRY_OCC_GM(cgemm_bf16x3_dl, 2, 4)
 
 // Split-BF16x3 in the Gauss (3M) form, direct-to-LDS.  Operands come from
 // permute kind 2 in the planar-group layout: per row, per group of W = min(16,

@@ -131,11 +131,11 @@ __device__ __forceinline__ void store_out(const GemmParams& p, int b, int split,
 // XCDs round-robin; renumbering them so each XCD receives one contiguous run
 // of logical tiles, and walking tiles in column groups of GROUP_M row tiles,
 // keeps the A row panels and B column panels a group shares inside one L2.
+template <int GROUP_M = 8>
 __device__ __forceinline__ void tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
   int nwg = gridDim.x;
   int bid = blockIdx.x;
   if ((nwg & 7) == 0) bid = (bid & 7) * (nwg >> 3) + (bid >> 3);
-  const int GROUP_M = 8;
   int group_size = GROUP_M * tiles_n;
   int g = bid / group_size;
   int first_m = g * GROUP_M;
@@ -186,12 +186,13 @@ __device__ __forceinline__ int group_find(const GroupTable& g, int bid) {
                                     local / per, 0);                                    \
   }
 
-// Entry points whose register use is capped for WAVES waves per SIMD.
-#define RN_GEMM_ENTRY_OCC(NAME, WAVES)                                                              \
+// Entry points whose register use is capped for WAVES waves per SIMD, and
+// whose single-problem tiles are walked in column groups of GROUP_M row tiles.
+#define RN_GEMM_ENTRY_OCC_GM(NAME, WAVES, GROUP_M)                                                  \
   template <int WM, int WN, int TM, int TN, int BK>                                     \
   __global__ __launch_bounds__(256, WAVES) void NAME(GemmParams p) {                           \
     int tm, tn;                                                                         \
-    tile_coords(p.tiles_m, p.tiles_n, tm, tn);                                          \
+    tile_coords<GROUP_M>(p.tiles_m, p.tiles_n, tm, tn);                                 \
     NAME##_body<WM, WN, TM, TN, BK>(p, tm, tn, blockIdx.y, blockIdx.z);                 \
   }                                                                                     \
   template <int WM, int WN, int TM, int TN, int BK>                                     \
@@ -203,6 +204,7 @@ __device__ __forceinline__ int group_find(const GroupTable& g, int bid) {
     NAME##_body<WM, WN, TM, TN, BK>(p, (local % per) / p.tiles_n, local % p.tiles_n,    \
                                     local / per, 0);                                    \
   }
+#define RN_GEMM_ENTRY_OCC(NAME, WAVES) RN_GEMM_ENTRY_OCC_GM(NAME, WAVES, 8)
 // Per-mode tile launchers (one kernel file per mode).
 void launch_tiles_f32_4m(int tile, dim3 grid, const GemmParams& p, hipStream_t s);
 void launch_tiles_f32_4m_grouped(int tile, dim3 grid, const GroupTable& t, hipStream_t s);
