@@ -1311,6 +1311,24 @@ constexpr int kDirectW = sizeof(DirectStep) / 4, kTinyW = sizeof(TinyStep) / 4;
 constexpr int kDirectLdsWords =
     std::max<int>(kDirectW + 2 * (int)kDirectMaxK, kClusterMaxSteps * kTinyW + kClusterMapWords);
 
+// dst[i] = src[i] for i < n by the workgroup's 256 threads.
+__device__ __forceinline__ void copy_words(uint32_t* dst, const uint32_t* __restrict__ src, int n) {
+  constexpr int U = 8;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 256 * U) {
+    uint32_t v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 256 * u;
+      v[u] = i < n ? src[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + 256 * u;
+      if (i < n) dst[i] = v[u];
+    }
+  }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
   __shared__ __align__(16) uint32_t lds[kDirectLdsWords];
@@ -1340,10 +1358,12 @@ __global__ __launch_bounds__(256) void direct_grouped(DirectTable g) {
   const TinyStep* ts = reinterpret_cast<const TinyStep*>(lds);
   int32_t* map = reinterpret_cast<int32_t*>(lds + kClusterMaxSteps * kTinyW);
   {
+    // Eight loads in flight per thread before their stores (a loop of
+    // load-then-store pays one memory latency per word a thread copies).
     const uint32_t* src = reinterpret_cast<const uint32_t*>(g.tiny + job.first);
-    for (int i = threadIdx.x; i < job.count * kTinyW; i += 256) lds[i] = src[i];
-    const int32_t* msrc = g.maps + job.map_first;
-    for (int i = threadIdx.x; i < job.map_words; i += 256) map[i] = msrc[i];
+    copy_words(lds, src, job.count * kTinyW);
+    copy_words(reinterpret_cast<uint32_t*>(map),
+               reinterpret_cast<const uint32_t*>(g.maps + job.map_first), job.map_words);
   }
   __syncthreads();
   for (int q = 0; q < job.count;) {
