@@ -1519,7 +1519,7 @@ __global__ __launch_bounds__(256) void norm2_partial(const T* x, int64_t n, doub
   for (; i + 768 < n; i += stride) {
     T v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = x[i + 256 * u];
+    for (int u = 0; u < 4; ++u) v[u] = ld_stream(x + i + 256 * u);  // read once
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const double re = (double)v[u].x, im = (double)v[u].y;
