@@ -11,6 +11,7 @@ Operand tensors are torch complex tensors on a GPU holding the stored
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -164,6 +165,16 @@ def _arr32(x):
     return a, (a.ctypes.data if a.size else None)
 
 
+def _axes(axes_a, axes_b):
+    """Paired contracted axes as int32 arrays and their pointers; the library
+    reads k = len(axes_a) entries of each, so the lengths must agree."""
+    aa, pa = _arr32(axes_a)
+    ab, pb = _arr32(axes_b)
+    if len(aa) != len(ab):
+        raise RnError(1, f"{len(aa)} axes of A paired with {len(ab)} axes of B")
+    return aa, pa, ab, pb
+
+
 def _check_tensor(t, name, dtype=None, numel=None, min_numel=None, device=None, on_gpu=True):
     """Raise RnError(RN_ERR_INVALID) unless t is a contiguous torch tensor of
     this dtype and element count on GPU `device` (every check is made before
@@ -189,7 +200,7 @@ def _check_tensor(t, name, dtype=None, numel=None, min_numel=None, device=None, 
 
 
 def _numel(dims) -> int:
-    return int(np.prod([int(d) for d in dims], dtype=np.int64)) if len(dims) else 1
+    return math.prod(int(d) for d in dims)
 
 
 def _torch_dtype(mode):
@@ -216,8 +227,7 @@ def plan_block_tensordot(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, mode="f
     """(C dims, C grid, workspace bytes, useful flops) of a block tensordot."""
     dt = dtype_of_mode(mode)
     A, B, C = descriptor(dims_a, grid_a, dt), descriptor(dims_b, grid_b, dt), RnTensor()
-    aa, pa = _arr32(axes_a)
-    ab, pb = _arr32(axes_b)
+    aa, pa, ab, pb = _axes(axes_a, axes_b)
     ws, fl = ctypes.c_size_t(), ctypes.c_double()
     check(lib().rn_block_tensordot_plan(None, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb,
                                         mode_id(mode), ctypes.byref(C), ctypes.byref(ws),
@@ -229,8 +239,7 @@ def plan_block_tensordot(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, mode="f
 def block_pairs(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, cblock, dtype=C128):
     """Coupled (A block, B block) pairs of one C block, in K-loop order."""
     A, B = descriptor(dims_a, grid_a, dtype), descriptor(dims_b, grid_b, dtype)
-    aa, pa = _arr32(axes_a)
-    ab, pb = _arr32(axes_b)
+    aa, pa, ab, pb = _axes(axes_a, axes_b)
     n = ctypes.c_int64()
     check(lib().rn_block_pairs(None, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb, cblock,
                                None, 0, ctypes.byref(n)), "pairs")
@@ -243,8 +252,7 @@ def block_pairs(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, cblock, dtype=C1
 def block_footprint(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, dtype=C64):
     """(Eq. 1, Eq. 2) element counts of Section IV.A for this contraction."""
     A, B = descriptor(dims_a, grid_a, dtype), descriptor(dims_b, grid_b, dtype)
-    aa, pa = _arr32(axes_a)
-    ab, pb = _arr32(axes_b)
+    aa, pa, ab, pb = _axes(axes_a, axes_b)
     e1, e2 = ctypes.c_double(), ctypes.c_double()
     check(lib().rn_block_footprint(ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb,
                                    ctypes.byref(e1), ctypes.byref(e2)), "footprint")
@@ -263,8 +271,7 @@ def plan_batch_workspace(ctx, problems, mode="fp32_4m"):
     for i, (a, da, ga, b, db, gb, axa, axb) in enumerate(problems):
         As[i] = descriptor(da, ga, dt, None)
         Bs[i] = descriptor(db, gb, dt, None)
-        x, px = _arr32(axa)
-        y, py = _arr32(axb)
+        x, px, y, py = _axes(axa, axb)
         keep += [x, y]
         ks[i] = len(x)
         pa_arr[i] = px
@@ -287,6 +294,8 @@ class Context:
         h = ctypes.c_void_p()
         check(lib().rn_create(ctypes.byref(h), device), "rn_create")
         self.h = h
+        # Block tensordot plans by shape (see _td_plan).
+        self._plans = {}
 
     def close(self):
         if self.h:
@@ -319,13 +328,43 @@ class Context:
         return ws.data_ptr(), nbytes
 
     # -- block tensordot -----------------------------------------------------
+    def _td_plan(self, dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, mode):
+        """The descriptors (without data), axis arrays, C shape and workspace
+        size of one block tensordot shape under this handle, planned on the
+        first call with that shape and reused after it: a repeated call then
+        costs the tensor checks and one library call.  The plan depends on
+        the shapes, the mode and the handle's split options; set_option
+        clears the cache."""
+        key = (tuple(dims_a), None if grid_a is None else tuple(grid_a), tuple(dims_b),
+               None if grid_b is None else tuple(grid_b), tuple(axes_a), tuple(axes_b), mode)
+        e = self._plans.get(key)
+        if e is not None:
+            return e
+        dt = dtype_of_mode(mode)
+        A, B, C = descriptor(dims_a, grid_a, dt), descriptor(dims_b, grid_b, dt), RnTensor()
+        aa, pa, ab, pb = _axes(axes_a, axes_b)
+        ws, fl = ctypes.c_size_t(), ctypes.c_double()
+        check(lib().rn_block_tensordot_plan(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
+                                            pa, pb, mode_id(mode), ctypes.byref(C),
+                                            ctypes.byref(ws), ctypes.byref(fl)), "plan")
+        cdims = [C.dims[j] for j in range(C.rank)]
+        cgrid = [C.grid[j] for j in range(C.rank)]
+        e = {"A": bytes(A), "B": bytes(B), "C": bytes(C), "aa": aa, "ab": ab, "pa": pa, "pb": pb,
+             "k": len(aa),
+             "cdims": cdims, "cgrid": cgrid, "n": _numel(cdims), "ws": ws.value,
+             "flops": fl.value, "na": _numel(dims_a), "nb": _numel(dims_b),
+             "want": _torch_dtype(mode), "mode": mode_id(mode)}
+        if len(self._plans) >= 1024:
+            self._plans.clear()
+        self._plans[key] = e
+        return e
+
     def plan_block_tensordot(self, dims_a, grid_a, dims_b, grid_b, axes_a, axes_b,
                              mode="fp64"):
         """As the module-level plan, under this handle's options (split policy)."""
         dt = dtype_of_mode(mode)
         A, B, C = descriptor(dims_a, grid_a, dt), descriptor(dims_b, grid_b, dt), RnTensor()
-        aa, pa = _arr32(axes_a)
-        bb, pb = _arr32(axes_b)
+        aa, pa, bb, pb = _axes(axes_a, axes_b)
         ws, fl = ctypes.c_size_t(), ctypes.c_double()
         check(lib().rn_block_tensordot_plan(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
                                             pa, pb, mode_id(mode), ctypes.byref(C),
@@ -337,34 +376,25 @@ class Context:
                         mode="fp64", out=None, workspace=None):
         """C (stored block-major, flat torch tensor), C dims, C grid."""
         import torch
-        dt = dtype_of_mode(mode)
-        want = _torch_dtype(mode)
-        _check_tensor(a, "a", want, _numel(dims_a), device=self.device)
-        _check_tensor(b, "b", want, _numel(dims_b), device=self.device)
-        A = descriptor(dims_a, grid_a, dt, a.data_ptr())
-        B = descriptor(dims_b, grid_b, dt, b.data_ptr())
-        C = RnTensor()
-        aa, pa = _arr32(axes_a)
-        ab, pb = _arr32(axes_b)
-        ws_n, fl = ctypes.c_size_t(), ctypes.c_double()
-        check(lib().rn_block_tensordot_plan(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
-                                            pa, pb, mode_id(mode), ctypes.byref(C),
-                                            ctypes.byref(ws_n), ctypes.byref(fl)), "plan")
-        cdims = [C.dims[j] for j in range(C.rank)]
-        cgrid = [C.grid[j] for j in range(C.rank)]
-        n = int(np.prod(cdims, dtype=np.int64)) if cdims else 1
+        e = self._td_plan(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, mode)
+        want = e["want"]
+        _check_tensor(a, "a", want, e["na"], device=self.device)
+        _check_tensor(b, "b", want, e["nb"], device=self.device)
         if out is None:
-            out = torch.empty(n, dtype=want, device=a.device)
-        _check_tensor(out, "out", want, n, device=self.device)
-        for x in (a, b):
-            if out.data_ptr() == x.data_ptr():
-                raise RnError(1, "out aliases an operand")
-        C.data = out.data_ptr()
-        wp, wn = self._workspace(ws_n.value, workspace)
-        check(lib().rn_block_tensordot(self.h, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb,
-                                       ctypes.byref(C), mode_id(mode), wp, wn, self._stream()),
-              "block_tensordot")
-        return out, cdims, cgrid
+            out = torch.empty(e["n"], dtype=want, device=a.device)
+        _check_tensor(out, "out", want, e["n"], device=self.device)
+        op = out.data_ptr()
+        if op == a.data_ptr() or op == b.data_ptr():
+            raise RnError(1, "out aliases an operand")
+        A = RnTensor.from_buffer_copy(e["A"])
+        B = RnTensor.from_buffer_copy(e["B"])
+        C = RnTensor.from_buffer_copy(e["C"])
+        A.data, B.data, C.data = a.data_ptr(), b.data_ptr(), op
+        wp, wn = self._workspace(e["ws"], workspace)
+        check(lib().rn_block_tensordot(self.h, ctypes.byref(A), ctypes.byref(B), e["k"],
+                                       e["pa"], e["pb"], ctypes.byref(C),
+                                       e["mode"], wp, wn, self._stream()), "block_tensordot")
+        return out, list(e["cdims"]), list(e["cgrid"])
 
     def block_tensordot_noalloc(self, a, dims_a, grid_a, b, dims_b, grid_b, axes_a, axes_b,
                                 mode="fp64", out=None):
@@ -372,36 +402,27 @@ class Context:
         fixed device scratch array is the workspace (nothing is allocated
         when `out` is given)."""
         import torch
-        dt = dtype_of_mode(mode)
-        want = _torch_dtype(mode)
-        _check_tensor(a, "a", want, _numel(dims_a), device=self.device)
-        _check_tensor(b, "b", want, _numel(dims_b), device=self.device)
-        A = descriptor(dims_a, grid_a, dt, a.data_ptr())
-        B = descriptor(dims_b, grid_b, dt, b.data_ptr())
-        C = RnTensor()
-        aa, pa = _arr32(axes_a)
-        ab, pb = _arr32(axes_b)
-        check(lib().rn_block_tensordot_plan(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
-                                            pa, pb, mode_id(mode), ctypes.byref(C), None, None),
-              "plan")
-        cdims = [C.dims[j] for j in range(C.rank)]
-        cgrid = [C.grid[j] for j in range(C.rank)]
-        n = _numel(cdims)
+        e = self._td_plan(dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, mode)
+        want = e["want"]
+        _check_tensor(a, "a", want, e["na"], device=self.device)
+        _check_tensor(b, "b", want, e["nb"], device=self.device)
         if out is None:
-            out = torch.empty(n, dtype=want, device=a.device)
-        _check_tensor(out, "out", want, n, device=self.device)
-        C.data = out.data_ptr()
-        check(lib().rn_block_tensordot_noalloc(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
-                                               pa, pb, ctypes.byref(C), mode_id(mode),
+            out = torch.empty(e["n"], dtype=want, device=a.device)
+        _check_tensor(out, "out", want, e["n"], device=self.device)
+        A = RnTensor.from_buffer_copy(e["A"])
+        B = RnTensor.from_buffer_copy(e["B"])
+        C = RnTensor.from_buffer_copy(e["C"])
+        A.data, B.data, C.data = a.data_ptr(), b.data_ptr(), out.data_ptr()
+        check(lib().rn_block_tensordot_noalloc(self.h, ctypes.byref(A), ctypes.byref(B), e["k"],
+                                               e["pa"], e["pb"], ctypes.byref(C), e["mode"],
                                                self._stream()), "block_tensordot_noalloc")
-        return out, cdims, cgrid
+        return out, list(e["cdims"]), list(e["cgrid"])
 
     def plan_streamed(self, dims_a, grid_a, dims_b, grid_b, axes_a, axes_b, mode="fp64"):
         """(C dims, C grid, workspace bytes, useful flops, host-to-device bytes)."""
         dt = dtype_of_mode(mode)
         A, B, C = descriptor(dims_a, grid_a, dt), descriptor(dims_b, grid_b, dt), RnTensor()
-        aa, pa = _arr32(axes_a)
-        bb, pb = _arr32(axes_b)
+        aa, pa, bb, pb = _axes(axes_a, axes_b)
         ws, fl, hd = ctypes.c_size_t(), ctypes.c_double(), ctypes.c_double()
         check(lib().rn_block_tensordot_streamed_plan(
             self.h, ctypes.byref(A), ctypes.byref(B), len(aa), pa, pb, mode_id(mode),
@@ -434,8 +455,7 @@ class Context:
         A = descriptor(dims_a, grid_a, dt, a_host.data_ptr())
         B = descriptor(dims_b, grid_b, dt, b_host.data_ptr())
         C = descriptor(cd, cg, dt, out.data_ptr())
-        aa, pa = _arr32(axes_a)
-        bb, pb = _arr32(axes_b)
+        aa, pa, bb, pb = _axes(axes_a, axes_b)
         wp, wn = self._workspace(ws_n, workspace)
         check(lib().rn_block_tensordot_streamed(self.h, ctypes.byref(A), ctypes.byref(B), len(aa),
                                                 pa, pb, ctypes.byref(C), mode_id(mode), wp, wn,
@@ -465,6 +485,7 @@ class Context:
 
     def set_option(self, name: str, value: int) -> None:
         """Handle option by name: graphs, pair_split_threshold, split_footprint, slice_sum."""
+        self._plans.clear()
         check(lib().rn_set_option(self.h, OPTIONS[name], int(value)), f"set_option {name}")
 
     def get_option(self, name: str) -> int:
@@ -687,8 +708,7 @@ class PreparedBatch:
             _check_tensor(b, f"problem {i} b", want, _numel(db), device=ctx.device)
             self.As[i] = descriptor(da, ga, dt, a.data_ptr())
             self.Bs[i] = descriptor(db, gb, dt, b.data_ptr())
-            x, px = _arr32(axa)
-            y, py = _arr32(axb)
+            x, px, y, py = _axes(axa, axb)
             self._keep += [x, y]
             self.ks[i] = len(x)
             self.pa[i] = px

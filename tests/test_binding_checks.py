@@ -16,6 +16,10 @@ class FakeCtx:
     device = 0
     _workspace = rn.Context._workspace
     _net_args = rn.Context._net_args
+    _td_plan = rn.Context._td_plan
+
+    def __init__(self):
+        self._plans = {}
 
 
 def td(ctx, a, b, out=None, mode="fp32_4m"):
@@ -95,3 +99,38 @@ def test_server_submit_checks_host_sizes(have_lib):
         rn.Server.submit(srv, [np.zeros(3, dtype=np.complex64)], [[1, 2]], [], (), "fp32_4m")
     assert "elements" in str(e.value)
     srv.s = None
+
+
+def test_axes_lengths_must_agree(have_lib):
+    """The library reads len(axes_a) entries of both axis arrays: a shorter
+    axes_b is refused in the binding, before any library call."""
+    with pytest.raises(rn.RnError) as e:
+        rn.plan_block_tensordot([2] * 4, None, [2] * 4, None, [3, 1], [0], "fp32_4m")
+    assert status_of(e) == 1 and "paired" in str(e.value)
+    ok = torch.zeros(16, dtype=torch.complex64)
+    with pytest.raises(rn.RnError) as e:
+        rn.Context.block_tensordot(FakeCtx(), ok, [2] * 4, None, ok, [2] * 4, None, [3, 1],
+                                   [0, 2, 1], "fp32_4m")
+    assert "paired" in str(e.value)
+
+
+def test_plan_cache_matches_uncached_plan(have_lib):
+    """Repeated block tensordots on one shape reuse the handle's cached plan;
+    the cached C shape and workspace equal a fresh plan's, distinct shapes and
+    modes get distinct entries, and the buffer checks still run on every call."""
+    ctx = FakeCtx()
+    shapes = [([2] * 4, None, [2] * 4, None, [3, 1], [0, 2], "fp32_4m"),
+              ([2] * 4, None, [2] * 4, None, [3, 1], [0, 2], "fp64"),
+              ([2] * 6, [2, 1, 1, 1, 1, 1], [2] * 5, [1, 2, 1, 1, 1], [5, 0], [1, 3], "bf16x3")]
+    for sh in shapes:
+        e1 = ctx._td_plan(*sh)
+        assert ctx._td_plan(*sh) is e1
+        cd, cg, ws, fl = rn.plan_block_tensordot(*sh)
+        assert (e1["cdims"], e1["cgrid"], e1["ws"], e1["flops"]) == (cd, cg, ws, fl)
+        assert e1["n"] == int(np.prod(cd))
+    assert len(ctx._plans) == len(shapes)
+    ok = torch.zeros(16, dtype=torch.complex64)
+    for _ in range(2):                            # cached shape, wrong operand size
+        with pytest.raises(rn.RnError) as e:
+            td(ctx, torch.zeros(8, dtype=torch.complex64), ok)
+        assert "elements" in str(e.value)
