@@ -112,6 +112,13 @@ def test_axes_lengths_must_agree(have_lib):
         rn.Context.block_tensordot(FakeCtx(), ok, [2] * 4, None, ok, [2] * 4, None, [3, 1],
                                    [0, 2, 1], "fp32_4m")
     assert "paired" in str(e.value)
+    with pytest.raises(rn.RnError) as e:          # one problem of a batch
+        rn.plan_batch_workspace(None, [(None, [2] * 4, None, None, [2] * 4, None, [3, 1], [0, 2]),
+                                       (None, [2] * 4, None, None, [2] * 4, None, [3], [0, 2])])
+    assert "paired" in str(e.value)
+    with pytest.raises(rn.RnError) as e:
+        rn.block_footprint([2] * 4, None, [2] * 4, None, [3, 1, 2], [0, 2])
+    assert "paired" in str(e.value)
 
 
 def test_plan_cache_matches_uncached_plan(have_lib):
